@@ -1,0 +1,112 @@
+"""Oracle: a plain, slow CPU reference for the Schur-reduction step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  The product
+library never calls it, links it or shares code with it.
+
+The arithmetic lives in ``oracle_schur.c`` (plain C, binary64, no BLAS):
+the practical Francis double-shift QR iteration that the paper points to for
+the theory of the Schur reduction (Sec. 2, Eq. (4); Golub & Van Loan,
+Sec. 7.5).  This module only builds that file with ``gcc`` and marshals
+numpy arrays (column-major, Fortran order) through ``ctypes``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle_schur.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile ``oracle_schur.c`` into ``liboracle.so`` (gcc -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off",
+                               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _bind(path):
+    """Load a compiled oracle library and declare its C signatures."""
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.oracle_schur.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int,
+                                 dp, dp, ctypes.c_int, ip]
+    lib.oracle_schur.restype = ctypes.c_int
+    lib.oracle_std2x2.argtypes = [ctypes.c_double] * 4 + [dp]
+    lib.oracle_std2x2.restype = None
+    lib.oracle_francis_step.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_double, ctypes.c_double]
+    lib.oracle_francis_step.restype = None
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = _bind(_LIB)
+    return _lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def schur(H, Q=None, want_q=True, itmax=30, lib=None):
+    """Real Schur form of upper Hessenberg ``H`` (paper Sec. 2, Eq. (4)).
+
+    Returns ``(S, Q, wr, wi, info, iters)`` with ``H = Q S Q^T`` (``Q`` is
+    ``Q_in @ Q2``; ``Q_in`` defaults to the identity).  Entries of ``H``
+    below the first subdiagonal are ignored.
+    """
+    lib = lib or _load()
+    H = np.array(H, dtype=np.float64, order="F", copy=True)
+    n = H.shape[0]
+    assert H.shape == (n, n)
+    if want_q:
+        Qm = np.eye(n, order="F") if Q is None else np.array(Q, dtype=np.float64, order="F", copy=True)
+        qptr, ldq = _dptr(Qm), max(1, n)
+    else:
+        Qm, qptr, ldq = None, None, 1
+    wr = np.zeros(n)
+    wi = np.zeros(n)
+    iters = ctypes.c_int(0)
+    info = lib.oracle_schur(n, _dptr(H) if n else None, max(1, n), qptr, ldq,
+                            _dptr(wr), _dptr(wi), int(itmax), ctypes.byref(iters))
+    return H, Qm, wr, wi, int(info), int(iters.value)
+
+
+def std2x2(a, b, c, d, lib=None):
+    """Standardise one 2x2 block; returns (a', b', c', d', cs, sn, wr1, wi1, wr2, wi2)."""
+    lib = lib or _load()
+    out = np.zeros(10)
+    lib.oracle_std2x2(float(a), float(b), float(c), float(d), _dptr(out))
+    return tuple(float(x) for x in out)
+
+
+def francis_step(H, l, i, s, t, Q=None, lib=None):
+    """One Francis double-shift step on block l..i (0-based) with shift sum
+    ``s`` and product ``t``; returns the new (H, Q)."""
+    lib = lib or _load()
+    H = np.array(H, dtype=np.float64, order="F", copy=True)
+    n = H.shape[0]
+    Qm = np.eye(n, order="F") if Q is None else np.array(Q, dtype=np.float64, order="F", copy=True)
+    lib.oracle_francis_step(n, _dptr(H), n, _dptr(Qm), n, int(l), int(i), float(s), float(t))
+    return H, Qm
+
+
+def eigenvalues(H, itmax=30):
+    """Eigenvalues (complex array, diagonal order) of upper Hessenberg ``H``."""
+    _, _, wr, wi, info, _ = schur(H, want_q=False, itmax=itmax)
+    return wr + 1j * wi, info

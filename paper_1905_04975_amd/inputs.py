@@ -1,0 +1,101 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+This module holds only input generation: it contains none of the Schur
+method's arithmetic, so both the HIP path and the oracle can consume it.
+
+Recipes (all numpy ``Generator(PCG64(seed))``):
+
+* ``hessenberg_normal(n, seed)`` -- upper Hessenberg with iid N(0,1) entries
+  on and above the first subdiagonal, zero below.  A full n x n draw is
+  taken and then masked, so the values do not depend on traversal order.
+* ``prescribed(n, seed)`` -- Hessenberg matrix with a known, perfectly
+  conditioned spectrum: a block-diagonal D of 1x1 blocks d ~ N(0,1) and 2x2
+  blocks [[a, b], [-b, a]] with a, b ~ U(-2, 2) (half of the eigenvalues in
+  complex pairs, blocks in shuffled order) is conjugated by a Haar-random
+  orthogonal Z (QR of a Gaussian matrix with the signs of diag(R) fixed) and
+  reduced to Hessenberg form with LAPACK's Householder reduction
+  (``scipy.linalg.hessenberg``).  The ground-truth eigenvalues are returned.
+* ``paper_like(n, seed)`` -- dense entries U(-1, 1) reduced to Hessenberg
+  form, the test-matrix recipe of the paper's experiments (Sec. 5).
+* ``batch_sizes(count, lo, hi, seed)`` -- matrix orders for batched runs.
+
+All matrices are returned column-major (Fortran order), float64.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def hessenberg_normal(n: int, seed: int) -> np.ndarray:
+    rng = _rng(seed)
+    a = rng.standard_normal((n, n))
+    return np.asfortranarray(np.triu(a, -1))
+
+
+def haar_orthogonal(n: int, rng: np.random.Generator) -> np.ndarray:
+    g = rng.standard_normal((n, n))
+    q, r = np.linalg.qr(g)
+    d = np.sign(np.diag(r))
+    d[d == 0] = 1.0
+    return q * d[None, :]
+
+
+def prescribed(n: int, seed: int, complex_fraction: float = 0.5):
+    """Return ``(H, eigs)``: Hessenberg H with the known spectrum ``eigs``."""
+    import scipy.linalg as sla
+
+    rng = _rng(seed)
+    npairs = int(round(n * complex_fraction / 2.0))
+    nreal = n - 2 * npairs
+    blocks = []
+    for _ in range(npairs):
+        a, b = rng.uniform(-2.0, 2.0, size=2)
+        blocks.append(np.array([[a, b], [-b, a]]))
+    for _ in range(nreal):
+        blocks.append(np.array([[rng.standard_normal()]]))
+    order = rng.permutation(len(blocks))
+    d = np.zeros((n, n))
+    eigs = []
+    pos = 0
+    for k in order:
+        blk = blocks[k]
+        m = blk.shape[0]
+        d[pos:pos + m, pos:pos + m] = blk
+        if m == 1:
+            eigs.append(complex(blk[0, 0], 0.0))
+        else:
+            eigs.append(complex(blk[0, 0], abs(blk[0, 1])))
+            eigs.append(complex(blk[0, 0], -abs(blk[0, 1])))
+        pos += m
+    z = haar_orthogonal(n, rng)
+    a = z @ d @ z.T
+    h = sla.hessenberg(a)
+    h = np.triu(h, -1)
+    return np.asfortranarray(h), np.array(eigs)
+
+
+def paper_like(n: int, seed: int) -> np.ndarray:
+    import scipy.linalg as sla
+
+    rng = _rng(seed)
+    a = rng.uniform(-1.0, 1.0, size=(n, n))
+    return np.asfortranarray(np.triu(sla.hessenberg(a), -1))
+
+
+def batch_sizes(count: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    rng = _rng(seed)
+    return rng.integers(lo, hi + 1, size=count)
+
+
+# Seeds of the standard workloads.
+SEED_N256 = 1          # N(0,1) Hessenberg, n = 256
+SEED_N1024 = 2         # prescribed spectrum, n = 1024
+SEED_N16384 = 3        # N(0,1) Hessenberg, n = 16384
+SEED_BATCH_SIZES = 4   # batch of 2000, orders U{32..512}
+SEED_BATCH_BASE = 40000
+SEED_SERVE = 5
+SEED_SERVE_BASE = 50000

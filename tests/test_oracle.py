@@ -1,0 +1,369 @@
+"""Pins for the oracle (CPU only).
+
+The oracle is checked against things fixed by the mathematics, never by
+re-typing its own formulas: closed-form 2x2 eigenvalues, the implicit-Q
+property of the Francis step, companion matrices with chosen roots,
+triangular and block-diagonal inputs, symmetric tridiagonal matrices,
+matrices with a prescribed spectrum, brute-force characteristic
+polynomials for n <= 8, similarity invariants, and LAPACK (run, not read).
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_04975_amd import inputs
+from tests import checks
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U = 2.0 ** -53
+
+
+# ---------------------------------------------------------------- 2x2 blocks
+
+def _grid_2x2():
+    vals = [0.0, 1.0, -1.0, 2.5, -3.0, 1e-8, -1e-8, 1e8]
+    rng = np.random.default_rng(7)
+    cases = []
+    for a in (0.0, 1.0, -2.0):
+        for d in (0.0, 1.0, 3.0):
+            for b in vals:
+                for c in vals:
+                    cases.append((a, b, c, d))
+    for _ in range(300):
+        cases.append(tuple(rng.standard_normal(4) * 10.0 ** rng.uniform(-3, 3, 4)))
+    # equal diagonal, b + c = 0, huge / tiny magnitudes
+    cases += [(1.0, 2.0, -2.0, 1.0), (0.0, 1e150, -1e150, 0.0), (1e-150, 1e-150, -1e-150, 0.0),
+              (5.0, 0.0, 3.0, 5.0), (2.0, -3.0, 0.0, 1.0), (1.0, 1e-300, -1e-300, 1.0)]
+    return cases
+
+
+def test_std2x2_closed_form():
+    """Standardised block: similarity by the returned rotation, trace and
+    determinant kept, eigenvalues = roots of the characteristic polynomial."""
+    for (a, b, c, d) in _grid_2x2():
+        na, nb, nc, nd, cs, sn, wr1, wi1, wr2, wi2 = oracle.std2x2(a, b, c, d)
+        B = np.array([[a, b], [c, d]])
+        G = np.array([[cs, -sn], [sn, cs]])
+        scale = max(np.abs(B).max(), 1e-300)
+        assert abs(cs * cs + sn * sn - 1.0) < 8 * U
+        Bp = G.T @ B @ G
+        assert np.allclose(Bp, [[na, nb], [nc, nd]], atol=64 * U * scale, rtol=0), (a, b, c, d)
+        if nc == 0.0:
+            assert wi1 == 0.0 and wi2 == 0.0 and wr1 == na and wr2 == nd
+        else:
+            # complex pair: equal diagonal and opposite-signed off-diagonals
+            assert na == nd and nb * nc < 0.0
+            assert wr1 == wr2 == na and wi1 > 0 and wi2 == -wi1
+        # eigenvalues from the characteristic polynomial x^2 - (a+d)x + (ad-bc)
+        tr, det = a + d, a * d - b * c
+        ref = np.roots([1.0, -tr, det]) if scale < 1e100 else None
+        if ref is not None and scale > 1e-100:
+            got = np.array([wr1 + 1j * wi1, wr2 + 1j * wi2])
+            dist = checks.match_eigs(got, ref)
+            # defective / nearly-defective blocks have sqrt(u)-conditioned eigenvalues
+            tol = 1e-7 * scale + 64 * U * scale
+            assert dist.max() <= tol, (a, b, c, d, got, ref)
+
+
+def test_std2x2_real_and_complex_pinned_examples():
+    # [[1, 2], [-2, 1]] is already standard: eigenvalues 1 +- 2i
+    o = oracle.std2x2(1.0, 2.0, -2.0, 1.0)
+    assert o[6] == 1.0 and abs(o[7] - 2.0) <= 16 * U and o[9] == -o[7]
+    # [[4, 1], [2, 3]] has eigenvalues 5 and 2 (characteristic polynomial x^2-7x+10)
+    o = oracle.std2x2(4.0, 1.0, 2.0, 3.0)
+    assert o[2] == 0.0
+    assert sorted([o[6], o[8]]) == pytest.approx([2.0, 5.0], abs=1e-14)
+    # symmetric [[0, 1], [1, 0]]: eigenvalues +-1
+    o = oracle.std2x2(0.0, 1.0, 1.0, 0.0)
+    assert o[2] == 0.0 and sorted([o[6], o[8]]) == pytest.approx([-1.0, 1.0], abs=1e-15)
+
+
+# ---------------------------------------------------------------- Francis step
+
+@pytest.mark.parametrize("n,seed", [(6, 1), (17, 2), (40, 3)])
+def test_francis_step_implicit_q(n, seed):
+    """One step on the whole matrix: orthogonal similarity, Hessenberg form
+    restored, and (implicit-Q theorem) Q e1 parallel to (H-s1)(H-s2) e1."""
+    H = inputs.hessenberg_normal(n, seed)
+    s, t = 0.7, 1.9  # complex pair 0.35 +- i sqrt(1.9 - 0.35^2)
+    H1, Q = oracle.francis_step(H, 0, n - 1, s, t)
+    nrm = np.linalg.norm(H)
+    assert np.linalg.norm(Q @ H1 @ Q.T - H) <= 50 * n * U * nrm
+    assert checks.orthogonality(Q) <= 50 * n * U
+    assert np.all(np.tril(H1, -2) == 0.0)
+    M = H @ H - s * H + t * np.eye(n)
+    x = M[:, 0] / np.linalg.norm(M[:, 0])
+    q0 = Q[:, 0]
+    assert abs(abs(x @ q0) - 1.0) <= 100 * n * U
+    assert np.abs(trace_diff := np.trace(H1) - np.trace(H)) <= 50 * n * U * nrm, trace_diff
+
+
+def test_francis_step_subblock_leaves_outside_structure():
+    n = 30
+    H = inputs.hessenberg_normal(n, 11)
+    H[10, 9] = 0.0
+    H[25, 24] = 0.0
+    H1, Q = oracle.francis_step(H, 10, 24, 1.0, 2.0)
+    # Q acts only on coordinates 10..24
+    Qo = Q.copy()
+    Qo[10:25, 10:25] = 0.0
+    assert np.array_equal(Qo, np.diag(np.r_[np.ones(10), np.zeros(15), np.ones(5)]))
+    assert H1[10, 9] == 0.0 and H1[25, 24] == 0.0
+    assert np.linalg.norm(Q @ H1 @ Q.T - H) <= 50 * n * U * np.linalg.norm(H)
+
+
+# ---------------------------------------------------------------- whole oracle
+
+def _companion_from_roots(roots):
+    """Upper Hessenberg companion matrix with exact (rational) coefficients."""
+    # expand prod (x - r) with Fractions over conjugate pairs -> real coefficients
+    poly = [Fraction(1)]
+    i = 0
+    rs = list(roots)
+    while i < len(rs):
+        re, im = rs[i]
+        if im == 0:
+            fac = [Fraction(1), -Fraction(re)]
+            i += 1
+        else:
+            # (x - (re + i im))(x - (re - i im)) = x^2 - 2 re x + re^2 + im^2
+            fac = [Fraction(1), -2 * Fraction(re), Fraction(re) ** 2 + Fraction(im) ** 2]
+            i += 2
+        new = [Fraction(0)] * (len(poly) + len(fac) - 1)
+        for a, pa in enumerate(poly):
+            for b, fb in enumerate(fac):
+                new[a + b] += pa * fb
+        poly = new
+    n = len(poly) - 1
+    C = np.zeros((n, n))
+    C[0, :] = [-float(c) for c in poly[1:]]
+    for k in range(1, n):
+        C[k, k - 1] = 1.0
+    return np.asfortranarray(C)
+
+
+def _golden_cases():
+    with open(os.path.join(GOLDEN, "companion_roots.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _golden_cases(), ids=lambda c: c["name"])
+def test_companion_known_roots(case):
+    roots = case["roots"]
+    if isinstance(roots, str):
+        m = int(roots.split(":")[1])
+        C = np.zeros((m, m))
+        C[0, m - 1] = 1.0
+        for k in range(1, m):
+            C[k, k - 1] = 1.0
+        exact = np.exp(2j * np.pi * np.arange(m) / m)
+    else:
+        C = _companion_from_roots(roots)
+        exact = np.array([complex(r, i) for r, i in roots])
+    S, Q, wr, wi, info, iters = oracle.schur(C)
+    assert info == 0
+    assert checks.structure_errors(S, wr, wi) == []
+    assert checks.residual(C, Q, S) <= 100 * C.shape[0] * U
+    dist = checks.match_eigs(wr + 1j * wi, exact)
+    assert dist.max() <= case["tol"] * max(1.0, np.abs(exact).max()), (dist, wr, wi)
+
+
+def test_cyclic_permutation_needs_exceptional_shifts():
+    """The cyclic shift is orthogonal with perfectly conditioned roots of
+    unity; standard shifts stagnate on it, so convergence proves that the
+    exceptional-shift path works (at least 10 steps are taken)."""
+    m = 12
+    C = np.zeros((m, m))
+    C[0, m - 1] = 1.0
+    C[np.arange(1, m), np.arange(m - 1)] = 1.0
+    S, Q, wr, wi, info, iters = oracle.schur(C)
+    assert info == 0 and iters >= 10
+    exact = np.exp(2j * np.pi * np.arange(m) / m)
+    assert checks.match_eigs(wr + 1j * wi, exact).max() <= 1e-13
+
+
+def test_upper_triangular_is_fixed_point():
+    n = 20
+    rng = np.random.default_rng(3)
+    H = np.asfortranarray(np.triu(rng.standard_normal((n, n))))
+    Qin = np.asfortranarray(inputs.haar_orthogonal(n, rng))
+    S, Q, wr, wi, info, iters = oracle.schur(H, Q=Qin)
+    assert info == 0 and iters == 0
+    assert np.array_equal(S, H) and np.array_equal(Q, Qin)
+    assert np.array_equal(wr, np.diag(H)) and np.all(wi == 0)
+
+
+def test_block_diagonal_2x2_closed_form():
+    rng = np.random.default_rng(5)
+    nb = 6
+    n = 2 * nb
+    H = np.zeros((n, n))
+    exact = []
+    for k in range(nb):
+        a, b = rng.uniform(-2, 2, 2)
+        c = -abs(rng.uniform(0.5, 2))
+        b = abs(b) + 0.5
+        d = a + rng.uniform(-0.1, 0.1)
+        H[2 * k:2 * k + 2, 2 * k:2 * k + 2] = [[a, b], [c, d]]
+        exact += list(np.roots([1.0, -(a + d), a * d - b * c]))
+    H[0, 5] = 1.0  # some coupling above the diagonal
+    S, Q, wr, wi, info, iters = oracle.schur(np.asfortranarray(H))
+    assert info == 0 and iters == 0
+    assert checks.structure_errors(S, wr, wi) == []
+    assert checks.match_eigs(wr + 1j * wi, np.array(exact)).max() <= 1e-14 * 4
+
+
+@pytest.mark.parametrize("n", [7, 50, 120])
+def test_symmetric_tridiagonal_vs_eigvalsh(n):
+    rng = np.random.default_rng(n)
+    d = rng.standard_normal(n)
+    e = rng.standard_normal(n - 1)
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    S, Q, wr, wi, info, iters = oracle.schur(np.asfortranarray(T))
+    assert info == 0
+    assert np.all(wi == 0)
+    off = S - np.diag(np.diag(S))
+    assert np.abs(off).max() <= 1e3 * n * U * np.linalg.norm(T)
+    assert np.abs(np.sort(wr) - np.linalg.eigvalsh(T)).max() <= 100 * n * U * np.linalg.norm(T)
+
+
+@pytest.mark.parametrize("n,seed", [(64, 2), (160, 12)])
+def test_prescribed_spectrum(n, seed):
+    H, exact = inputs.prescribed(n, seed)
+    S, Q, wr, wi, info, iters = oracle.schur(H)
+    assert info == 0
+    assert checks.structure_errors(S, wr, wi) == []
+    dist = checks.match_eigs(wr + 1j * wi, exact)
+    assert dist.max() <= 1e3 * n * U * np.linalg.norm(H)
+    assert np.all(dist <= checks.eig_rel_tol(exact, H, 1e-12))
+
+
+def _charpoly_roots_exact(H, dps=50):
+    """Characteristic polynomial with the float64 entries taken as exact
+    rationals (sympy), roots at 50 digits (mpmath)."""
+    import mpmath
+    import sympy
+
+    n = H.shape[0]
+    M = sympy.Matrix(n, n, lambda i, j: sympy.Rational(Fraction(float(H[i, j]))))
+    x = sympy.Symbol("x")
+    coeffs = sympy.Poly(M.charpoly(x).as_expr(), x).all_coeffs()
+    mpmath.mp.dps = dps
+    rts = mpmath.polyroots([mpmath.mpf(sympy.Rational(c).p) / mpmath.mpf(sympy.Rational(c).q)
+                            for c in coeffs], maxsteps=400, extraprec=400)
+    return np.array([complex(r) for r in rts])
+
+
+@pytest.mark.parametrize("n,seed", [(3, 1), (4, 2), (5, 3), (6, 4), (7, 5), (8, 6), (8, 7)])
+def test_brute_force_charpoly(n, seed):
+    H = inputs.hessenberg_normal(n, 100 + seed)
+    S, Q, wr, wi, info, iters = oracle.schur(H)
+    assert info == 0
+    exact = _charpoly_roots_exact(H)
+    w, kappa = checks.eig_condition(H)
+    dist = checks.match_eigs(wr + 1j * wi, exact)
+    # per-eigenvalue kappa-weighted bound, matched through scipy's ordering
+    kap = np.empty(n)
+    order = checks.match_eigs  # noqa: F841  (documentation: same matcher)
+    from scipy.optimize import linear_sum_assignment
+    cost = np.abs((wr + 1j * wi)[:, None] - w[None, :])
+    r, c = linear_sum_assignment(cost)
+    kap[r] = kappa[c]
+    assert np.all(dist <= checks.kappa_tolerance(H, exact, kap)), (dist, kap)
+
+
+@pytest.mark.parametrize("n,seed", [(30, 1), (90, 2), (256, 1)])
+def test_invariants_and_lapack(n, seed):
+    import scipy.linalg as sla
+
+    H = inputs.hessenberg_normal(n, seed)
+    S, Q, wr, wi, info, iters = oracle.schur(H)
+    assert info == 0
+    lam = wr + 1j * wi
+    nrm = np.linalg.norm(H)
+    assert abs(lam.sum().real - np.trace(H)) <= 100 * n * U * nrm
+    assert abs((lam ** 2).sum().real - np.trace(H @ H)) <= 100 * n * U * nrm ** 2
+    assert abs(np.linalg.norm(S) - nrm) <= 100 * n * U * nrm
+    assert checks.residual(H, Q, S) <= 10 * n * U
+    assert checks.orthogonality(Q) <= 10 * n * U
+    assert checks.structure_errors(S, wr, wi) == []
+    w, kappa = checks.eig_condition(H)
+    from scipy.optimize import linear_sum_assignment
+    cost = np.abs(lam[:, None] - w[None, :])
+    r, c = linear_sum_assignment(cost)
+    assert np.all(cost[r, c] <= checks.kappa_tolerance(H, w[c], kappa[c]))
+    # LAPACK's real Schur form has the same eigenvalue multiset
+    T, Z = sla.schur(H, output="real")
+    wl = sla.eigvals(T)
+    assert checks.match_eigs(lam, wl).max() <= 1e-8 * nrm
+
+
+def test_accumulates_into_given_q():
+    n = 40
+    rng = np.random.default_rng(9)
+    H = inputs.hessenberg_normal(n, 21)
+    Qin = np.asfortranarray(inputs.haar_orthogonal(n, rng))
+    S1, Q1, *_ = oracle.schur(H)
+    S2, Q2, *_ = oracle.schur(H, Q=Qin)
+    assert np.array_equal(S1, S2)
+    assert np.abs(Q2 - Qin @ Q1).max() <= 100 * n * U
+
+
+def test_trivial_sizes():
+    S, Q, wr, wi, info, it = oracle.schur(np.zeros((0, 0)))
+    assert info == 0 and S.shape == (0, 0)
+    S, Q, wr, wi, info, it = oracle.schur(np.array([[3.5]]))
+    assert info == 0 and wr[0] == 3.5 and wi[0] == 0 and Q[0, 0] == 1.0
+    S, Q, wr, wi, info, it = oracle.schur(np.array([[1.0, 2.0], [-2.0, 1.0]], order="F"))
+    assert info == 0 and it == 0 and wr[0] == 1.0 and abs(wi[0] - 2.0) < 1e-15
+
+
+def test_iteration_cap_keeps_similarity():
+    n = 60
+    H = inputs.hessenberg_normal(n, 31)
+    for itmax in (1, 3):
+        S, Q, wr, wi, info, it = oracle.schur(H, itmax=itmax)
+        assert 0 < info <= n
+        assert checks.residual(H, Q, S) <= 10 * n * U
+        assert checks.orthogonality(Q) <= 10 * n * U
+        # eigenvalues info..n-1 (0-based) were found and are exact for S's tail
+        if info < n:
+            tail = S[info:, info:]
+            got = (wr + 1j * wi)[info:]
+            assert checks.match_eigs(got, np.linalg.eigvals(tail)).max() <= 1e-12 * np.linalg.norm(H)
+
+
+def test_entries_below_subdiagonal_are_ignored():
+    n = 25
+    H = inputs.hessenberg_normal(n, 41)
+    G = np.asfortranarray(H + np.tril(np.full((n, n), 7.0), -2))
+    S1, Q1, *_ = oracle.schur(H)
+    S2, Q2, *_ = oracle.schur(G)
+    assert np.array_equal(S1, S2) and np.array_equal(Q1, Q2)
+
+
+try:
+    from hypothesis import given, settings, strategies as st
+
+    @settings(max_examples=60, deadline=None)
+    @given(n=st.integers(min_value=1, max_value=12), seed=st.integers(0, 10 ** 6),
+           scale=st.sampled_from([1e-3, 1.0, 1e3]))
+    def test_property_small(n, seed, scale):
+        H = np.asfortranarray(inputs.hessenberg_normal(n, seed) * scale)
+        S, Q, wr, wi, info, it = oracle.schur(H)
+        assert info == 0
+        assert checks.structure_errors(S, wr, wi) == []
+        assert checks.residual(H, Q, S) <= 20 * n * U
+        assert checks.orthogonality(Q) <= 20 * n * U
+        w, kappa = checks.eig_condition(H)
+        from scipy.optimize import linear_sum_assignment
+        lam = wr + 1j * wi
+        cost = np.abs(lam[:, None] - w[None, :])
+        r, c = linear_sum_assignment(cost)
+        assert np.all(cost[r, c] <= checks.kappa_tolerance(H, w[c], kappa[c], factor=100.0))
+except ImportError:  # pragma: no cover
+    pass
