@@ -1,0 +1,152 @@
+/*
+ * schur.h -- C ABI of the MI355X (gfx950) Schur-reduction engine.
+ *
+ * The library reduces an upper Hessenberg matrix H to real Schur form
+ *
+ *     H = Q2 S Q2^T,
+ *
+ * with Q2 orthogonal and S upper quasi-triangular with 1x1 and 2x2 diagonal
+ * blocks; the eigenvalues are read from the diagonal blocks (paper Sec. 2,
+ * Eq. (4), "Schur reduction").  The eigenvector step backtransforms with the
+ * product Q1 Q2 (Sec. 2, Eq. (6)), so Q is accumulated: Q <- Q_in Q2.
+ *
+ * Method (Sec. 3.2): multishift QR sweeps with small bulges.  Shifts are the
+ * eigenvalues of a trailing block; chains of 3x3 bulges are chased down the
+ * diagonal with overlapping 3x3 Householder reflectors, first inside small
+ * diagonal windows whose orthogonal factors are accumulated, then applied to
+ * the off-diagonal panels and to Q as matrix-matrix products.  All arithmetic
+ * is IEEE binary64.
+ *
+ * Conventions (LAPACK/ScaLAPACK style, which the paper keeps compatibility
+ * with, Sec. 4.2):
+ *   - matrices are column-major with a leading dimension: element (i, j) of
+ *     H is H[i + j*ldh], 0-based;
+ *   - pointers named H, Q, wr, wi are DEVICE pointers (memory of the current
+ *     HIP device, e.g. a torch tensor's data_ptr()), unless stated otherwise;
+ *   - streams are passed as `void*` holding a hipStream_t (NULL = the
+ *     handle's own stream);
+ *   - return value `info`:
+ *         0      success
+ *        -i      argument i is illegal (1-based position in the argument
+ *                list of schur_reduce: n -> -1, H -> -2, ldh -> -3, Q -> -4,
+ *                ldq -> -5, wr -> -6, wi -> -7).  A non-finite entry in the
+ *                Hessenberg part of H is reported as -2 and nothing is
+ *                modified.
+ *        >0      the QR iteration did not converge within the sweep limit;
+ *                info is the 1-based last row of the unreduced block that
+ *                failed.  wr/wi rows info+1..n hold the eigenvalues that
+ *                converged, and H_in = Q S Q^T still holds for the returned
+ *                (non-triangular) S.
+ *       <=-100   runtime failure: -101 out of device memory, -102 HIP error,
+ *                -103 pointer is not device memory, -104 bad handle.
+ *   - entries of H below the first subdiagonal are ignored on input and are
+ *     exactly zero on output; S's 2x2 blocks are standardised (equal diagonal
+ *     entries, off-diagonal entries of opposite sign, i.e. a complex pair);
+ *     real eigenvalue pairs always appear as two 1x1 blocks;
+ *   - wr/wi are in the diagonal order of S; a conjugate pair is adjacent with
+ *     the positive imaginary part first.
+ *   - ownership: the caller owns every buffer passed in; the library never
+ *     frees or keeps them beyond the call (async calls: until the stream
+ *     reaches the end of the enqueued work).  A handle owns its workspace.
+ *   - threading: a handle must not be used by two threads at once.
+ */
+#ifndef SCHUR_MI355X_H
+#define SCHUR_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct schur_handle_s* schur_handle_t;
+
+/* Tuning options; zero fields take the built-in defaults (per-n table). */
+typedef struct schur_opts {
+  int ns;          /* shifts per sweep (even); 0 = by table                    */
+  int nb;          /* bulges per window chain (group), 1..24; 0 = by table     */
+  int step;        /* chain steps per window; 0 = largest that fits 128 rows   */
+  int nmin;        /* active blocks of order <= nmin are solved in one kernel  */
+  int max_sweeps;  /* sweep limit per solve; 0 = 30 * max(10, n)/max(2, ns)    */
+  int exc_period;  /* sweeps without deflation before ad-hoc shifts; 0 = 6     */
+  int flags;       /* SCHUR_FLAG_*                                             */
+  int reserved[5];
+} schur_opts;
+
+#define SCHUR_FLAG_TIME_KERNELS 1   /* time each kernel family with HIP events */
+
+/* Counters of the last solve on a handle. */
+typedef struct schur_stats {
+  int64_t sweeps;           /* multishift sweeps                               */
+  int64_t windows;          /* diagonal windows chased                         */
+  int64_t chain_steps;      /* window chain steps (all windows)                */
+  int64_t small_solves;     /* blocks finished by the single-kernel solver      */
+  int64_t launches;         /* kernel launches                                 */
+  double gemm_flops;        /* flops of the panel matrix products               */
+  double gemm_ms;           /* summed duration of the panel kernels (TIME flag) */
+  int64_t gemm_launches;    /* number of panel kernel launches                 */
+  double chase_ms;          /* summed duration of the window kernels (TIME)    */
+  int64_t chase_launches;
+  double shift_ms;          /* summed duration of the shift kernels (TIME)     */
+  double other_ms;          /* deflation, standardisation, small solves (TIME) */
+  int64_t shifts_applied;   /* total shifts used in sweeps                     */
+  double row_flops;         /* flops of the row-panel (left) products          */
+  double row_ms;            /* summed duration of k_panel_row launches (TIME)  */
+  int64_t row_launches;
+  double colq_flops;        /* flops of the column-panel and Q (right) products */
+  double colq_ms;           /* summed duration of k_panel_colq launches (TIME) */
+  int64_t colq_launches;
+  double reserved[4];
+} schur_stats;
+
+/* --------------------------------------------------------------------------
+ * schur_reduce -- synchronous Schur reduction (paper Sec. 2, Eq. (4)).
+ *   n        order, n >= 0
+ *   H        device, ldh x n; in: upper Hessenberg; out: S
+ *   ldh      >= max(1, n)
+ *   Q        device, ldq x n or NULL; in: Q_in; out: Q_in Q2 (NULL: no
+ *            Schur vectors, the Q products are skipped)
+ *   ldq      >= max(1, n) when Q != NULL
+ *   wr, wi   device, n doubles each
+ * Uses a per-device default handle and its stream; blocks until done.
+ * ------------------------------------------------------------------------ */
+int schur_reduce(int n, double* H, int ldh, double* Q, int ldq, double* wr, double* wi);
+
+/* Handle with its own stream and workspace on `device` (opts may be NULL). */
+int schur_create(schur_handle_t* h, int device, const schur_opts* opts);
+int schur_destroy(schur_handle_t h);
+int schur_set_opts(schur_handle_t h, const schur_opts* opts);
+int schur_get_stats(schur_handle_t h, schur_stats* out);
+
+/* --------------------------------------------------------------------------
+ * schur_reduce_async -- stream-ordered Schur reduction.
+ * All device work is enqueued on `stream` after the work already there and
+ * nothing else is synchronised; the host thread drives the sweep loop and
+ * waits on `stream` for the few control integers each sweep needs, so the
+ * call returns once the last kernel has been enqueued.  The results (and
+ * *info_out, a HOST int) are final when the call returns; the output buffers
+ * are written by work on `stream`.
+ * ------------------------------------------------------------------------ */
+int schur_reduce_async(schur_handle_t h, void* stream, int n, double* H, int ldh, double* Q,
+                       int ldq, double* wr, double* wi, int* info_out);
+
+/* --------------------------------------------------------------------------
+ * schur_reduce_batched -- many independent Hessenberg matrices of uneven
+ * orders in one call.  n, ldh, ldq are HOST arrays of `count` ints; H, Q,
+ * wr, wi are HOST arrays of `count` DEVICE pointers (Q[i] may be NULL,
+ * or Q itself NULL for no Schur vectors).  info is a HOST array of `count`
+ * ints receiving each matrix's info.  Matrices of order <= 96 are solved one
+ * per workgroup in a single launch; larger ones are advanced sweep by sweep
+ * with the windows and panel tiles of all of them in shared launches.
+ * Returns 0 when every matrix succeeded, else the first nonzero info.
+ * ------------------------------------------------------------------------ */
+int schur_reduce_batched(schur_handle_t h, void* stream, int count, const int* n,
+                         double* const* H, const int* ldh, double* const* Q, const int* ldq,
+                         double* const* wr, double* const* wi, int* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCHUR_MI355X_H */

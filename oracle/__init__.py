@@ -110,3 +110,15 @@ def eigenvalues(H, itmax=30):
     """Eigenvalues (complex array, diagonal order) of upper Hessenberg ``H``."""
     _, _, wr, wi, info, _ = schur(H, want_q=False, itmax=itmax)
     return wr + 1j * wi, info
+
+
+def francis_step_inplace(H, Q, l, i, s, t, lib=None):
+    """In-place variant of ``francis_step`` on Fortran-ordered float64 arrays
+    (``Q`` may be None); used to time the oracle on large inputs."""
+    lib = lib or _load()
+    assert H.flags.f_contiguous and H.dtype == np.float64
+    n = H.shape[0]
+    if Q is not None:
+        assert Q.flags.f_contiguous and Q.dtype == np.float64
+    lib.oracle_francis_step(n, _dptr(H), n, _dptr(Q) if Q is not None else None, n,
+                            int(l), int(i), float(s), float(t))

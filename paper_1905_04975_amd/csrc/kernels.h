@@ -1,0 +1,35 @@
+// kernels.h -- host-visible launch wrappers of the device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "schur_internal.h"
+
+namespace schur {
+
+// One small block solved inside a single workgroup (LDS resident).
+struct SmallTask {
+  double* A; int lda; int m;   // block, overwritten by its Schur form (Z mode)
+  double* Z; int ldz;          // optional: Z (m x m) written column-major
+  double* Zt; int ldzt;        // optional: Z^T written into a ldzt x ldzt slot, zero padded
+  double* wr; double* wi;      // optional: eigenvalues of the block
+  int* info;                   // optional: 0, or 1-based end of a non-converged block
+  int itmax;                   // Francis steps allowed per block end (<= 0: 30)
+};
+
+void launch_small_z(const SmallTask& t, const SmallTask* tasks, int count, int maxm,
+                    hipStream_t s);
+void launch_small_eig(const SmallTask& t, hipStream_t s);
+void launch_shift_prep(const double* wr, const double* wi, int ns, const int* small_info,
+                       int exceptional, const double* H, int ldh, int ktop, int kbot, double* st,
+                       hipStream_t s);
+void launch_chase(const SweepArgs& a, hipStream_t s);
+void launch_panel_row(const SweepArgs& a, int tiles, hipStream_t s);
+void launch_panel_colq(const SweepArgs& a, int tiles, hipStream_t s);
+void launch_check_finite(const double* H, int ldh, int n, Ctrl* ctrl, hipStream_t s);
+void launch_zero_lower(double* H, int ldh, int n, hipStream_t s);
+void launch_ctrl_reset(Ctrl* ctrl, hipStream_t s);
+void launch_deflate(double* H, int ldh, int kbot, int klo, Ctrl* ctrl, hipStream_t s);
+void launch_standardize(double* H, int ldh, double* Q, int ldq, int n, int kmin, double* wr,
+                        double* wi, int* list, int* count, int cap, hipStream_t s);
+
+}  // namespace schur

@@ -1,0 +1,848 @@
+// kernels.hip -- CDNA4 (gfx950) device kernels of the Schur engine.
+//
+// Kernel families (paper Sec. 3.2; the window / right-update / left-update
+// task types of Sec. 3.2 become kernel roles here):
+//   k_small_*     whole Francis double-shift QR of a small block in LDS, used
+//                 for the shifts (eigenvalues of a trailing block), for the
+//                 last small active blocks and for whole small matrices
+//   k_chase       the window task: bulge introduction and chasing with
+//                 overlapping 3x3 Householder reflectors inside an LDS window,
+//                 then accumulation of the window's orthogonal factor U
+//   k_panel_row   left update of the row panel  H(win, right) <- U^T H(win, right)
+//   k_panel_colq  right update of the column panel and of Q  X <- X U
+//                 (both as FP64 MFMA matrix products)
+//   k_deflate     negligible-subdiagonal scan and bottom deflation
+//   k_std_*       2x2 standardisation of the converged blocks and (wr, wi)
+#include "schur_internal.h"
+#include "device_common.h"
+#include "kernels.h"
+
+namespace schur {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// ============================================================================
+// Small-block Francis double-shift QR (one wavefront, block in LDS)
+// ============================================================================
+
+// Column-major LDS block with odd leading dimension (spreads banks).
+template <int MAXM>
+struct SmallSmem {
+  static constexpr int LD = MAXM | 1;
+};
+
+template <bool WANTZ, int MAXM>
+__device__ void small_qr(const SmallTask& T, double* S, double* Zs) {
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  const int m = T.m;
+  const int lane = threadIdx.x;
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
+
+  for (int c = 0; c < m; ++c)
+    for (int r = lane; r < m; r += 64)
+      Sx(r, c) = (r <= c + 1) ? T.A[r + (size_t)c * T.lda] : 0.0;
+  if (WANTZ)
+    for (int c = 0; c < m; ++c)
+      for (int r = lane; r < m; r += 64) Zx(r, c) = (r == c) ? 1.0 : 0.0;
+  __syncthreads();
+
+  int i = m - 1, its = 0, info = 0;
+  const int itmax = T.itmax > 0 ? T.itmax : 30;
+  while (i >= 0) {
+    // ---- deflation search: largest k in [1, i] with a negligible subdiagonal
+    int l = 0;
+    for (int top = i; top >= 1; top -= 64) {
+      const int k = top - lane;
+      bool neg = false;
+      if (k >= 1) {
+        const double sub = fabs(Sx(k, k - 1));
+        double tst = fabs(Sx(k - 1, k - 1)) + fabs(Sx(k, k));
+        if (tst == 0.0) {
+          tst = fabs(Sx(k - 1, k));
+          if (k >= 2) tst += fabs(Sx(k - 1, k - 2));
+          if (k + 1 <= i) tst += fabs(Sx(k + 1, k));
+        }
+        neg = (sub <= kUlp * tst);
+      }
+      const unsigned long long mask = __ballot(neg);
+      if (mask) {
+        l = top - __builtin_ctzll(mask);
+        break;
+      }
+    }
+    __syncthreads();
+    if (l > 0 && lane == 0) Sx(l, l - 1) = 0.0;
+    __syncthreads();
+
+    if (l == i) {
+      if (lane == 0 && T.wr) { T.wr[i] = Sx(i, i); T.wi[i] = 0.0; }
+      i -= 1; its = 0;
+      continue;
+    }
+    if (l == i - 1) {
+      const Std2 o = standardize2(Sx(i - 1, i - 1), Sx(i - 1, i), Sx(i, i - 1), Sx(i, i));
+      __syncthreads();
+      if (WANTZ && !(o.cs == 1.0 && o.sn == 0.0)) {
+        for (int c = i + 1 + lane; c < m; c += 64) {
+          const double x = Sx(i - 1, c), y = Sx(i, c);
+          Sx(i - 1, c) = o.cs * x + o.sn * y;
+          Sx(i, c) = o.cs * y - o.sn * x;
+        }
+        for (int r = lane; r < i - 1; r += 64) {
+          const double x = Sx(r, i - 1), y = Sx(r, i);
+          Sx(r, i - 1) = o.cs * x + o.sn * y;
+          Sx(r, i) = o.cs * y - o.sn * x;
+        }
+        for (int r = lane; r < m; r += 64) {
+          const double x = Zx(r, i - 1), y = Zx(r, i);
+          Zx(r, i - 1) = o.cs * x + o.sn * y;
+          Zx(r, i) = o.cs * y - o.sn * x;
+        }
+      }
+      if (lane == 0) {
+        if (WANTZ) {
+          Sx(i - 1, i - 1) = o.a; Sx(i - 1, i) = o.b;
+          Sx(i, i - 1) = o.c;     Sx(i, i) = o.d;
+        }
+        if (T.wr) {
+          T.wr[i - 1] = o.wr1; T.wi[i - 1] = o.wi1;
+          T.wr[i] = o.wr2;     T.wi[i] = o.wi2;
+        }
+      }
+      __syncthreads();
+      i -= 2; its = 0;
+      continue;
+    }
+    its += 1;
+    if (its > itmax) { info = i + 1; break; }
+
+    // ---- shifts: trailing 2x2 (Francis) or the ad-hoc exceptional pair
+    double s, t;
+    if (its == 10 || its == 20) {
+      double w, e;
+      if (its == 10) {
+        w = fabs(Sx(i, i - 1)) + fabs(Sx(i - 1, i - 2));
+        e = Sx(i, i) + 0.75 * w;
+      } else {
+        w = fabs(Sx(l + 1, l)) + fabs(Sx(l + 2, l + 1));
+        e = Sx(l, l) + 0.75 * w;
+      }
+      s = e + e;
+      t = e * e + 0.4375 * w * w;
+    } else {
+      const double a = Sx(i - 1, i - 1), b = Sx(i - 1, i), c = Sx(i, i - 1), d = Sx(i, i);
+      s = a + d;
+      t = a * d - b * c;
+    }
+
+    // ---- one double-shift step on rows/cols l..i
+    const int cend = WANTZ ? m - 1 : i;    // last column of left updates
+    const int rbeg = WANTZ ? 0 : l;        // first row of right updates
+    double x, y, z;
+    first_column(Sx(l, l), Sx(l, l + 1), Sx(l + 1, l), Sx(l + 1, l + 1), Sx(l + 2, l + 1), s, t,
+                 x, y, z);
+    for (int r = l; r <= i - 1; ++r) {
+      const int nr = (r <= i - 2) ? 3 : 2;
+      if (r > l) {
+        x = Sx(r, r - 1);
+        y = Sx(r + 1, r - 1);
+        z = (nr == 3) ? Sx(r + 2, r - 1) : 0.0;
+      }
+      const Refl h = make_reflector(nr, x, y, z);
+      __syncthreads();
+      if (h.tau == 0.0) continue;
+      const double tv2 = h.tau * h.v2, tv3 = h.tau * h.v3;
+      for (int c = r + lane; c <= cend; c += 64) {
+        const double a1 = Sx(r, c), a2 = Sx(r + 1, c);
+        const double a3 = (nr == 3) ? Sx(r + 2, c) : 0.0;
+        const double w = a1 + h.v2 * a2 + h.v3 * a3;
+        Sx(r, c) = a1 - h.tau * w;
+        Sx(r + 1, c) = a2 - tv2 * w;
+        if (nr == 3) Sx(r + 2, c) = a3 - tv3 * w;
+      }
+      if (r > l && lane == 0) {
+        Sx(r, r - 1) = h.beta;
+        Sx(r + 1, r - 1) = 0.0;
+        if (nr == 3) Sx(r + 2, r - 1) = 0.0;
+      }
+      __syncthreads();
+      const int rlast = (r + 3 < i) ? r + 3 : i;
+      for (int q = rbeg + lane; q <= rlast; q += 64) {
+        const double a1 = Sx(q, r), a2 = Sx(q, r + 1);
+        const double a3 = (nr == 3) ? Sx(q, r + 2) : 0.0;
+        const double w = a1 + h.v2 * a2 + h.v3 * a3;
+        Sx(q, r) = a1 - h.tau * w;
+        Sx(q, r + 1) = a2 - tv2 * w;
+        if (nr == 3) Sx(q, r + 2) = a3 - tv3 * w;
+      }
+      if (WANTZ) {
+        for (int q = lane; q < m; q += 64) {
+          const double a1 = Zx(q, r), a2 = Zx(q, r + 1);
+          const double a3 = (nr == 3) ? Zx(q, r + 2) : 0.0;
+          const double w = a1 + h.v2 * a2 + h.v3 * a3;
+          Zx(q, r) = a1 - h.tau * w;
+          Zx(q, r + 1) = a2 - tv2 * w;
+          if (nr == 3) Zx(q, r + 2) = a3 - tv3 * w;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (lane == 0 && T.info) *T.info = info;
+  if (WANTZ) {
+    // Schur form of the block back to global memory, Z^T into the U slot layout
+    for (int c = 0; c < m; ++c)
+      for (int r = lane; r < m; r += 64) T.A[r + (size_t)c * T.lda] = Sx(r, c);
+    if (T.Zt) {
+      for (int c = 0; c < T.ldzt; ++c)
+        for (int r = lane; r < T.ldzt; r += 64)
+          T.Zt[r + (size_t)c * T.ldzt] = (r < m && c < m) ? Zx(c, r) : 0.0;
+    }
+    if (T.Z) {
+      for (int c = 0; c < m; ++c)
+        for (int r = lane; r < m; r += 64) T.Z[r + (size_t)c * T.ldz] = Zx(r, c);
+    }
+  }
+}
+
+template <int MAXM>
+__global__ __launch_bounds__(64) void k_small_z(SmallTask t0, const SmallTask* tasks) {
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  __shared__ double S[LD * MAXM];
+  __shared__ double Z[LD * MAXM];
+  const SmallTask T = tasks ? tasks[blockIdx.x] : t0;
+  if (T.m <= 0 || T.m > MAXM) return;
+  small_qr<true, MAXM>(T, S, Z);
+}
+
+template <int MAXM>
+__global__ __launch_bounds__(64) void k_small_eig(SmallTask t0, const SmallTask* tasks) {
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  __shared__ double S[LD * MAXM];
+  const SmallTask T = tasks ? tasks[blockIdx.x] : t0;
+  if (T.m <= 0 || T.m > MAXM) return;
+  small_qr<false, MAXM>(T, S, nullptr);
+}
+
+// ============================================================================
+// Shift preparation: sort the trailing-block eigenvalues by decreasing
+// modulus (conjugate pairs stay together), pair the real ones, and emit one
+// (sum, product) pair per bulge.  Missing pairs (if the small solve did not
+// converge) are filled with ad-hoc shifts from the bottom of the block.
+// ============================================================================
+__global__ __launch_bounds__(256) void k_shift_prep(const double* wr, const double* wi, int ns,
+                                                    const int* small_info, int exceptional,
+                                                    const double* H, int ldh, int ktop, int kbot,
+                                                    double* st) {
+  __shared__ double key[512];
+  __shared__ int kind[512];   // 0 real, 1 first of a conjugate pair, 2 second (skipped)
+  __shared__ int rank[512];
+  __shared__ int order[512];
+  const int tid = threadIdx.x;
+  const int npair = ns / 2;
+  int valid0 = 0;  // eigenvalues [valid0, ns) converged
+  if (!exceptional && small_info) {
+    const int inf = *small_info;
+    valid0 = inf;  // 1-based end of the failed block -> entries >= inf are valid
+  }
+  if (exceptional) valid0 = ns;
+  for (int e = tid; e < ns; e += blockDim.x) {
+    const bool ok = e >= valid0;
+    key[e] = ok ? hypot(wr[e], wi[e]) : -1.0;
+    int kd = 0;
+    if (ok && wi[e] > 0.0) kd = 1;
+    else if (ok && wi[e] < 0.0) kd = 2;
+    else if (!ok) kd = 3;
+    kind[e] = kd;
+  }
+  __syncthreads();
+  // rank of each unit (real or first-of-pair) by decreasing modulus, stable
+  for (int e = tid; e < ns; e += blockDim.x) {
+    int rk = 0;
+    if (kind[e] <= 1) {
+      for (int f = 0; f < ns; ++f) {
+        if (kind[f] > 1) continue;
+        if (key[f] > key[e] || (key[f] == key[e] && f < e)) ++rk;
+      }
+      rank[e] = rk;
+    } else {
+      rank[e] = -1;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < ns; e += blockDim.x)
+    if (rank[e] >= 0) order[rank[e]] = e;
+  __syncthreads();
+  if (tid == 0) {
+    int nunits = 0;
+    for (int e = 0; e < ns; ++e) nunits += (rank[e] >= 0);
+    int np = 0;
+    int pend = -1;
+    for (int u = 0; u < nunits && np < npair; ++u) {
+      const int e = order[u];
+      if (kind[e] == 1) {
+        st[2 * np] = 2.0 * wr[e];
+        st[2 * np + 1] = wr[e] * wr[e] + wi[e] * wi[e];
+        ++np;
+      } else if (pend < 0) {
+        pend = e;
+      } else {
+        st[2 * np] = wr[pend] + wr[e];
+        st[2 * np + 1] = wr[pend] * wr[e];
+        ++np;
+        pend = -1;
+      }
+    }
+    // fill: ad-hoc pairs from 2x2 windows at the bottom of the block
+    int row = kbot;
+    while (np < npair) {
+      if (row - 2 < ktop) row = kbot;
+      const double w = fabs(H[row + (size_t)(row - 1) * ldh]) +
+                       fabs(H[(row - 1) + (size_t)(row - 2) * ldh]);
+      const double e = H[row + (size_t)row * ldh] + 0.75 * w;
+      st[2 * np] = e + e;
+      st[2 * np + 1] = e * e + 0.4375 * w * w;
+      ++np;
+      row -= 2;
+    }
+  }
+}
+
+// ============================================================================
+// Window chase (the window task).  One workgroup per diagonal window.
+// ============================================================================
+constexpr int CHASE_THREADS = 512;
+constexpr int NO_BULGE = -0x40000000;   // rk[] marker of an inactive bulge
+
+__global__ __launch_bounds__(CHASE_THREADS) void k_chase(SweepArgs a) {
+  __shared__ double W[LDW * WMAX];
+  __shared__ double rv[NBMAX][4];
+  __shared__ int rk[NBMAX];
+  const Win d = a.win[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int p = d.p, ws = d.ws, nb = d.nb;
+  const int ktop = a.ktop, kbot = a.kbot;
+  double* refl = a.refl + (size_t)d.slot * a.refl_stride;
+  auto Wx = [&](int r, int c) -> double& { return W[r + c * LDW]; };
+
+  // load the window
+  for (int idx = tid; idx < ws * ws; idx += CHASE_THREADS) {
+    const int c = idx / ws, r = idx - c * ws;
+    Wx(r, c) = a.H[(size_t)(p + r) + (size_t)(p + c) * a.ldh];
+  }
+  __syncthreads();
+
+  for (int tau = d.tau0; tau < d.tau1; ++tau) {
+    // phase A: one reflector per active bulge (from the bulge column, or from
+    // the shifts when the bulge is introduced at the top of the block)
+    if (tid < nb) {
+      const int b = tid;
+      const int K = ktop - 1 + tau - 3 * b;
+      double* out = refl + ((size_t)(tau - d.tau0) * nb + b) * 3;
+      if (K < ktop - 1 || K > kbot - 2) {
+        rk[b] = NO_BULGE;
+        out[0] = 0.0; out[1] = 0.0; out[2] = 0.0;
+      } else {
+        const int nr = (K <= kbot - 3) ? 3 : 2;
+        double x, y, z;
+        if (K == ktop - 1) {
+          const int o = ktop - p;
+          first_column(Wx(o, o), Wx(o, o + 1), Wx(o + 1, o), Wx(o + 1, o + 1),
+                       (nr == 3) ? Wx(o + 2, o + 1) : 0.0,
+                       a.st[2 * (d.shift0 + b)], a.st[2 * (d.shift0 + b) + 1], x, y, z);
+        } else {
+          const int k = K - p;
+          x = Wx(k + 1, k);
+          y = Wx(k + 2, k);
+          z = (nr == 3) ? Wx(k + 3, k) : 0.0;
+        }
+        const Refl h = make_reflector(nr, x, y, z);
+        rv[b][0] = h.v2; rv[b][1] = h.v3; rv[b][2] = h.tau; rv[b][3] = h.beta;
+        rk[b] = (h.tau == 0.0) ? NO_BULGE : K;
+        out[0] = h.v2; out[1] = (nr == 3) ? h.v3 : 0.0; out[2] = h.tau;
+      }
+    }
+    __syncthreads();
+    // phase B: left updates, rows K+1..K+nr, columns from the bulge column on
+    for (int idx = tid; idx < nb * ws; idx += CHASE_THREADS) {
+      const int b = idx / ws, c = idx - b * ws;
+      const int K = rk[b];
+      if (K == NO_BULGE) continue;
+      const int k = K - p;                  // local bulge column (may be -1)
+      if (c < k) continue;
+      const int nr = (K <= kbot - 3) ? 3 : 2;
+      if (c == k) {
+        Wx(k + 1, k) = rv[b][3];
+        Wx(k + 2, k) = 0.0;
+        if (nr == 3) Wx(k + 3, k) = 0.0;
+        continue;
+      }
+      const double v2 = rv[b][0], v3 = rv[b][1], tv = rv[b][2];
+      const double a1 = Wx(k + 1, c), a2 = Wx(k + 2, c);
+      const double a3 = (nr == 3) ? Wx(k + 3, c) : 0.0;
+      const double w = tv * (a1 + v2 * a2 + v3 * a3);
+      Wx(k + 1, c) = a1 - w;
+      Wx(k + 2, c) = a2 - w * v2;
+      if (nr == 3) Wx(k + 3, c) = a3 - w * v3;
+    }
+    __syncthreads();
+    // phase C: right updates, columns K+1..K+nr, rows from the window top
+    for (int idx = tid; idx < nb * ws; idx += CHASE_THREADS) {
+      const int b = idx / ws, r = idx - b * ws;
+      const int K = rk[b];
+      if (K == NO_BULGE) continue;
+      const int k = K - p;
+      const int rl = ((K + 4 < kbot) ? K + 4 : kbot) - p;
+      if (r > rl) continue;
+      const int nr = (K <= kbot - 3) ? 3 : 2;
+      const double v2 = rv[b][0], v3 = rv[b][1], tv = rv[b][2];
+      const double a1 = Wx(r, k + 1), a2 = Wx(r, k + 2);
+      const double a3 = (nr == 3) ? Wx(r, k + 3) : 0.0;
+      const double w = tv * (a1 + v2 * a2 + v3 * a3);
+      Wx(r, k + 1) = a1 - w;
+      Wx(r, k + 2) = a2 - w * v2;
+      if (nr == 3) Wx(r, k + 3) = a3 - w * v3;
+    }
+    __syncthreads();
+  }
+
+  // window back to HBM
+  for (int idx = tid; idx < ws * ws; idx += CHASE_THREADS) {
+    const int c = idx / ws, r = idx - c * ws;
+    a.H[(size_t)(p + r) + (size_t)(p + c) * a.ldh] = Wx(r, c);
+  }
+  __syncthreads();
+
+  // accumulate U = P_1 P_2 ... in LDS (the window space is free now)
+  for (int idx = tid; idx < ws * ws; idx += CHASE_THREADS) {
+    const int c = idx / ws, r = idx - c * ws;
+    Wx(r, c) = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int tau = d.tau0; tau < d.tau1; ++tau) {
+    // rows below the leading bulge's reach are still zero in the touched columns
+    int klead = ktop - 1 + tau;
+    if (klead > kbot - 2) klead = kbot - 2;
+    int rmax = klead + 3 - p;
+    if (rmax > ws - 1) rmax = ws - 1;
+    const int nrow = rmax + 1;
+    const double* rt = refl + (size_t)(tau - d.tau0) * nb * 3;
+    for (int idx = tid; idx < nb * nrow; idx += CHASE_THREADS) {
+      const int b = idx / nrow, r = idx - b * nrow;
+      const double tv = rt[3 * b + 2];
+      if (tv == 0.0) continue;
+      const int K = ktop - 1 + tau - 3 * b;
+      const int k = K - p;
+      const int nr = (K <= kbot - 3) ? 3 : 2;
+      const double v2 = rt[3 * b], v3 = rt[3 * b + 1];
+      const double a1 = Wx(r, k + 1), a2 = Wx(r, k + 2);
+      const double a3 = (nr == 3) ? Wx(r, k + 3) : 0.0;
+      const double w = tv * (a1 + v2 * a2 + v3 * a3);
+      Wx(r, k + 1) = a1 - w;
+      Wx(r, k + 2) = a2 - w * v2;
+      if (nr == 3) Wx(r, k + 3) = a3 - w * v3;
+    }
+    __syncthreads();
+  }
+  // U^T (column-major, ld UPAD, zero padded) -> the slot read by the panel kernels
+  double* Ut = a.U + (size_t)d.slot * UPAD * UPAD;
+  for (int idx = tid; idx < UPAD * UPAD; idx += CHASE_THREADS) {
+    const int c = idx / UPAD, r = idx - c * UPAD;   // Ut(r, c) = U(c, r)
+    Ut[idx] = (r < ws && c < ws) ? Wx(c, r) : 0.0;
+  }
+}
+
+// ============================================================================
+// Panel updates with FP64 MFMA (v_mfma_f64_16x16x4f64).
+// Fragment layout of the 16x16x4 FP64 MFMA (wave64), measured on gfx950:
+//   A(i, k): lane = i + 16 k      B(k, j): lane = j + 16 k
+//   D(i, j): lane = j + 16 (i % 4), element i / 4
+// ============================================================================
+constexpr int PT = GEMM_T;       // 64
+constexpr int LDT = PT + 4;      // padded LDS leading dimension of panel tiles
+
+__device__ __forceinline__ int find_window(const SweepArgs& a, int bid, bool row) {
+  int w = 0;
+  if (row) {
+    while (w + 1 < a.nwin && a.win[w + 1].base_r <= bid) ++w;
+  } else {
+    while (w + 1 < a.nwin && a.win[w + 1].base_cq <= bid) ++w;
+  }
+  return w;
+}
+
+// Y(ws x 64) = U^T X for one 64-column tile of a window's row panel, in place.
+__global__ __launch_bounds__(256) void k_panel_row(SweepArgs a) {
+  __shared__ double Xs[WMAX * LDT];   // row-major tile: Xs[c + r*LDT]
+  const int w = find_window(a, blockIdx.x, true);
+  const Win& d = a.win[w];
+  const int tile = blockIdx.x - d.base_r;
+  const int p = d.p, ws = d.ws;
+  const int c0 = p + ws + tile * PT;
+  const int nc = min(PT, a.cend - c0);
+  const int kpad = (ws + 3) & ~3;
+  const double* Ut = a.U + (size_t)d.slot * UPAD * UPAD;
+  const int tid = threadIdx.x;
+
+  for (int idx = tid; idx < kpad * PT; idx += 256) {
+    const int c = idx / kpad, r = idx - c * kpad;
+    double v = 0.0;
+    if (r < ws && c < nc) v = a.H[(size_t)(p + r) + (size_t)(c0 + c) * a.ldh];
+    Xs[c + r * LDT] = v;
+  }
+  __syncthreads();
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int i0 = wave * 32;
+  if (i0 >= ws) return;
+  d4 acc[2][4];
+  for (int ib = 0; ib < 2; ++ib)
+    for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < kpad; k0 += 4) {
+    const int k = k0 + lk;
+    const double a0 = Ut[(i0 + li) + (size_t)k * UPAD];
+    const double a1 = Ut[(i0 + 16 + li) + (size_t)k * UPAD];
+    for (int jb = 0; jb < 4; ++jb) {
+      const double b = Xs[(jb * 16 + li) + k * LDT];
+      acc[0][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][jb], 0, 0, 0);
+      acc[1][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][jb], 0, 0, 0);
+    }
+  }
+  for (int ib = 0; ib < 2; ++ib)
+    for (int jb = 0; jb < 4; ++jb) {
+      const int col = jb * 16 + li;
+      if (col >= nc) continue;
+      for (int e = 0; e < 4; ++e) {
+        const int row = i0 + ib * 16 + lk + 4 * e;
+        if (row < ws) a.H[(size_t)(p + row) + (size_t)(c0 + col) * a.ldh] = acc[ib][jb][e];
+      }
+    }
+}
+
+// Y(64 x ws) = X U for one 64-row tile of a window's column panel or of Q.
+__global__ __launch_bounds__(256) void k_panel_colq(SweepArgs a) {
+  __shared__ double Xs[WMAX * LDT];   // column-major tile: Xs[r + c*LDT]
+  const int w = find_window(a, blockIdx.x, false);
+  const Win& d = a.win[w];
+  int tile = blockIdx.x - d.base_cq;
+  const int p = d.p, ws = d.ws;
+  double* M;
+  int ld, r0, rend;
+  if (tile < d.tiles_c) {
+    M = a.H; ld = a.ldh; r0 = a.rtop + tile * PT; rend = p;
+  } else {
+    tile -= d.tiles_c;
+    M = a.Q; ld = a.ldq; r0 = tile * PT; rend = a.n;
+  }
+  const int nr = min(PT, rend - r0);
+  const int kpad = (ws + 3) & ~3;
+  const double* Ut = a.U + (size_t)d.slot * UPAD * UPAD;
+  const int tid = threadIdx.x;
+
+  for (int idx = tid; idx < kpad * PT; idx += 256) {
+    const int c = idx / PT, r = idx - c * PT;
+    double v = 0.0;
+    if (r < nr && c < ws) v = M[(size_t)(r0 + r) + (size_t)(p + c) * ld];
+    Xs[r + c * LDT] = v;
+  }
+  __syncthreads();
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int j0 = wave * 32;
+  if (j0 >= ws) return;
+  d4 acc[4][2];
+  for (int ib = 0; ib < 4; ++ib)
+    for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < kpad; k0 += 4) {
+    const int k = k0 + lk;
+    const double b0 = Ut[(j0 + li) + (size_t)k * UPAD];
+    const double b1 = Ut[(j0 + 16 + li) + (size_t)k * UPAD];
+    for (int ib = 0; ib < 4; ++ib) {
+      const double av = Xs[(ib * 16 + li) + k * LDT];
+      acc[ib][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc[ib][0], 0, 0, 0);
+      acc[ib][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc[ib][1], 0, 0, 0);
+    }
+  }
+  for (int ib = 0; ib < 4; ++ib)
+    for (int jb = 0; jb < 2; ++jb) {
+      const int col = j0 + jb * 16 + li;
+      if (col >= ws) continue;
+      for (int e = 0; e < 4; ++e) {
+        const int row = ib * 16 + lk + 4 * e;
+        if (row < nr) M[(size_t)(r0 + row) + (size_t)(p + col) * ld] = acc[ib][jb][e];
+      }
+    }
+}
+
+// ============================================================================
+// Input check and clean-up: flag non-finite entries of the Hessenberg part,
+// then (separate launch) zero everything below the first subdiagonal.
+// ============================================================================
+__global__ void k_check_finite(const double* H, int ldh, int n, Ctrl* ctrl) {
+  const size_t total = (size_t)n * n;
+  int bad = 0;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(idx / n), r = (int)(idx - (size_t)c * n);
+    if (r <= c + 1) {
+      const double v = H[r + (size_t)c * ldh];
+      if (!isfinite(v)) bad = 1;
+    }
+  }
+  if (bad) atomicOr(&ctrl->bad, 1);
+}
+
+__global__ void k_zero_lower(double* H, int ldh, int n) {
+  const size_t total = (size_t)n * n;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(idx / n), r = (int)(idx - (size_t)c * n);
+    if (r > c + 1) H[r + (size_t)c * ldh] = 0.0;
+  }
+}
+
+__global__ void k_ctrl_reset(Ctrl* ctrl) {
+  if (threadIdx.x == 0) {
+    ctrl->bad = 0;
+    ctrl->small_info = 0;
+    ctrl->ndefl = 0;
+  }
+}
+
+// ============================================================================
+// Deflation scan of the bottom unreduced block (one workgroup).
+// Negligible subdiagonal entries of rows 1..kbot are set to exactly zero;
+// converged 1x1 / 2x2 blocks at the bottom are peeled off.
+// ============================================================================
+constexpr int DEFL_THREADS = 1024;
+constexpr int DEFL_WORDS = 16384;   // bitmap words: n <= 524288
+
+__global__ __launch_bounds__(DEFL_THREADS) void k_deflate(double* H, int ldh, int kbot, int klo,
+                                                          Ctrl* ctrl) {
+  __shared__ unsigned bits[DEFL_WORDS];
+  const int tid = threadIdx.x;
+  const int nwords = (kbot >> 5) + 1;
+  for (int wv = tid; wv < nwords; wv += DEFL_THREADS) bits[wv] = 0u;
+  __syncthreads();
+  for (int k = klo + 1 + tid; k <= kbot; k += DEFL_THREADS) {
+    const double sub = fabs(H[k + (size_t)(k - 1) * ldh]);
+    double tst = fabs(H[(k - 1) + (size_t)(k - 1) * ldh]) + fabs(H[k + (size_t)k * ldh]);
+    if (tst == 0.0) {
+      tst = fabs(H[(k - 1) + (size_t)k * ldh]);
+      if (k >= 2) tst += fabs(H[(k - 1) + (size_t)(k - 2) * ldh]);
+      if (k + 1 <= kbot) tst += fabs(H[(k + 1) + (size_t)k * ldh]);
+    }
+    if (sub <= kUlp * tst) {
+      if (sub != 0.0) H[k + (size_t)(k - 1) * ldh] = 0.0;
+      atomicOr(&bits[k >> 5], 1u << (k & 31));
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int lane = tid;
+    int kb = kbot, kt = 0, peeled = 0;
+    while (kb >= 0) {
+      // largest flagged k <= kb (k >= klo+1), else klo
+      kt = klo;
+      const int wtop = kb >> 5;
+      for (int wbase = wtop; wbase >= 0; wbase -= 64) {
+        const int wv = wbase - lane;
+        unsigned word = 0u;
+        if (wv >= 0) {
+          word = bits[wv];
+          if (wv == wtop) {
+            const int sh = kb & 31;
+            word &= (sh == 31) ? 0xffffffffu : ((2u << sh) - 1u);
+          }
+        }
+        const unsigned long long mask = __ballot(word != 0u);
+        if (mask) {
+          const int src = __builtin_ctzll(mask);
+          const unsigned wsel = __shfl(word, src);
+          const int wi = wbase - src;
+          kt = wi * 32 + 31 - __builtin_clz(wsel);
+          break;
+        }
+      }
+      if (kt < klo) kt = klo;
+      if (kb - kt + 1 <= 2) {
+        peeled += kb - kt + 1;
+        kb = kt - 1;
+        if (kb < klo) { kb = klo - 1; break; }
+        continue;
+      }
+      break;
+    }
+    if (lane == 0) {
+      ctrl->kbot = kb;
+      ctrl->ktop = (kb < klo) ? klo : kt;
+      ctrl->ndefl = peeled;
+    }
+  }
+}
+
+// ============================================================================
+// Final standardisation of the 2x2 blocks and eigenvalue extraction.
+// Blocks are found as nonzero subdiagonal entries; each block's rotation is
+// recomputed from its four (untouched) entries by every thread that needs it.
+// Phase 1 rotates block rows (columns to the right), phase 2 block columns
+// (rows above) and Q, phase 3 writes the standard blocks and (wr, wi).
+// ============================================================================
+__global__ void k_find_blocks(const double* H, int ldh, int n, int kmin, int* list, int* count,
+                              int cap) {
+  for (int k = kmin + blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    if (H[k + (size_t)(k - 1) * ldh] != 0.0) {
+      const int pos = atomicAdd(count, 1);
+      if (pos < cap) list[pos] = k;
+    }
+  }
+}
+
+__global__ void k_clamp_count(int* count, int cap) {
+  if (threadIdx.x == 0 && *count > cap) *count = cap;
+}
+
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
+__global__ void k_std_rows(double* H, int ldh, int n, const int* list, const int* count) {
+  const int nbk = *count;
+  for (int e = blockIdx.x; e < nbk; e += gridDim.x) {
+    const int k = list[e];
+    const Std2 o = standardize2(H[(k - 1) + (size_t)(k - 1) * ldh], H[(k - 1) + (size_t)k * ldh],
+                                H[k + (size_t)(k - 1) * ldh], H[k + (size_t)k * ldh]);
+    if (o.cs == 1.0 && o.sn == 0.0) continue;
+    for (int c = k + 1 + threadIdx.x; c < n; c += blockDim.x) {
+      const double x = H[(k - 1) + (size_t)c * ldh], y = H[k + (size_t)c * ldh];
+      H[(k - 1) + (size_t)c * ldh] = o.cs * x + o.sn * y;
+      H[k + (size_t)c * ldh] = o.cs * y - o.sn * x;
+    }
+  }
+}
+
+__global__ void k_std_cols(double* H, int ldh, double* Q, int ldq, int n, const int* list,
+                           const int* count) {
+  const int nbk = *count;
+  for (int e = blockIdx.x; e < nbk; e += gridDim.x) {
+    const int k = list[e];
+    const Std2 o = standardize2(H[(k - 1) + (size_t)(k - 1) * ldh], H[(k - 1) + (size_t)k * ldh],
+                                H[k + (size_t)(k - 1) * ldh], H[k + (size_t)k * ldh]);
+    if (o.cs == 1.0 && o.sn == 0.0) continue;
+    for (int r = threadIdx.x; r < k - 1; r += blockDim.x) {
+      const double x = H[r + (size_t)(k - 1) * ldh], y = H[r + (size_t)k * ldh];
+      H[r + (size_t)(k - 1) * ldh] = o.cs * x + o.sn * y;
+      H[r + (size_t)k * ldh] = o.cs * y - o.sn * x;
+    }
+    if (Q) {
+      for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        const double x = Q[r + (size_t)(k - 1) * ldq], y = Q[r + (size_t)k * ldq];
+        Q[r + (size_t)(k - 1) * ldq] = o.cs * x + o.sn * y;
+        Q[r + (size_t)k * ldq] = o.cs * y - o.sn * x;
+      }
+    }
+  }
+}
+
+__global__ void k_std_finish(double* H, int ldh, int n, double* wr, double* wi) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const bool top = (k + 1 < n) && H[(k + 1) + (size_t)k * ldh] != 0.0;   // k is first of a block
+    const bool bottom = (k >= 1) && H[k + (size_t)(k - 1) * ldh] != 0.0;   // k is second
+    if (!top && !bottom) {
+      wr[k] = H[k + (size_t)k * ldh];
+      wi[k] = 0.0;
+    }
+  }
+}
+
+__global__ void k_std_blocks(double* H, int ldh, int n, const int* list, const int* count,
+                             double* wr, double* wi) {
+  const int nbk = *count;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nbk; e += gridDim.x * blockDim.x) {
+    const int k = list[e];
+    const Std2 o = standardize2(H[(k - 1) + (size_t)(k - 1) * ldh], H[(k - 1) + (size_t)k * ldh],
+                                H[k + (size_t)(k - 1) * ldh], H[k + (size_t)k * ldh]);
+    H[(k - 1) + (size_t)(k - 1) * ldh] = o.a;
+    H[(k - 1) + (size_t)k * ldh] = o.b;
+    H[k + (size_t)(k - 1) * ldh] = o.c;
+    H[k + (size_t)k * ldh] = o.d;
+    wr[k - 1] = o.wr1; wi[k - 1] = o.wi1;
+    wr[k] = o.wr2;     wi[k] = o.wi2;
+  }
+}
+
+// ============================================================================
+// Host-side launch wrappers
+// ============================================================================
+void launch_small_z(const SmallTask& t, const SmallTask* tasks, int count, int maxm,
+                    hipStream_t s) {
+  if (maxm <= 32)
+    hipLaunchKernelGGL((k_small_z<32>), dim3(count), dim3(64), 0, s, t, tasks);
+  else if (maxm <= 64)
+    hipLaunchKernelGGL((k_small_z<64>), dim3(count), dim3(64), 0, s, t, tasks);
+  else
+    hipLaunchKernelGGL((k_small_z<SMALL_Z_MAX>), dim3(count), dim3(64), 0, s, t, tasks);
+}
+
+void launch_small_eig(const SmallTask& t, hipStream_t s) {
+  if (t.m <= 32)
+    hipLaunchKernelGGL((k_small_eig<32>), dim3(1), dim3(64), 0, s, t, (const SmallTask*)nullptr);
+  else if (t.m <= 64)
+    hipLaunchKernelGGL((k_small_eig<64>), dim3(1), dim3(64), 0, s, t, (const SmallTask*)nullptr);
+  else
+    hipLaunchKernelGGL((k_small_eig<SMALL_EIG_MAX>), dim3(1), dim3(64), 0, s, t,
+                       (const SmallTask*)nullptr);
+}
+
+void launch_shift_prep(const double* wr, const double* wi, int ns, const int* small_info,
+                       int exceptional, const double* H, int ldh, int ktop, int kbot, double* st,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_shift_prep, dim3(1), dim3(256), 0, s, wr, wi, ns, small_info, exceptional,
+                     H, ldh, ktop, kbot, st);
+}
+
+void launch_chase(const SweepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_chase, dim3(a.nwin), dim3(CHASE_THREADS), 0, s, a);
+}
+
+void launch_panel_row(const SweepArgs& a, int tiles, hipStream_t s) {
+  if (tiles > 0) hipLaunchKernelGGL(k_panel_row, dim3(tiles), dim3(256), 0, s, a);
+}
+
+void launch_panel_colq(const SweepArgs& a, int tiles, hipStream_t s) {
+  if (tiles > 0) hipLaunchKernelGGL(k_panel_colq, dim3(tiles), dim3(256), 0, s, a);
+}
+
+void launch_check_finite(const double* H, int ldh, int n, Ctrl* ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, H, ldh, n, ctrl);
+}
+
+void launch_zero_lower(double* H, int ldh, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_lower, dim3(2048), dim3(256), 0, s, H, ldh, n);
+}
+
+void launch_ctrl_reset(Ctrl* ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, ctrl);
+}
+
+void launch_deflate(double* H, int ldh, int kbot, int klo, Ctrl* ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_deflate, dim3(1), dim3(DEFL_THREADS), 0, s, H, ldh, kbot, klo, ctrl);
+}
+
+void launch_standardize(double* H, int ldh, double* Q, int ldq, int n, int kmin, double* wr,
+                        double* wi, int* list, int* count, int cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, count);
+  if (kmin < 1) kmin = 1;
+  hipLaunchKernelGGL(k_find_blocks, dim3(64), dim3(256), 0, s, H, ldh, n, kmin, list, count, cap);
+  hipLaunchKernelGGL(k_clamp_count, dim3(1), dim3(64), 0, s, count, cap);
+  hipLaunchKernelGGL(k_std_rows, dim3(1024), dim3(256), 0, s, H, ldh, n, list, count);
+  hipLaunchKernelGGL(k_std_cols, dim3(1024), dim3(256), 0, s, H, ldh, Q, ldq, n, list, count);
+  hipLaunchKernelGGL(k_std_finish, dim3(64), dim3(256), 0, s, H, ldh, n, wr, wi);
+  hipLaunchKernelGGL(k_std_blocks, dim3(64), dim3(256), 0, s, H, ldh, n, list, count, wr, wi);
+}
+
+}  // namespace schur

@@ -1,0 +1,189 @@
+"""Python binding of the C ABI declared in ``include/schur.h``.
+
+Argument marshalling only: every step of the Schur reduction runs in the
+HIP library ``libschur_mi355x.so`` (built in-tree by ``build.py``).  PyTorch
+supplies device memory and streams.  There is no CPU fallback: loading fails
+loudly when the built library is missing.
+
+Matrices are column-major.  A torch tensor ``T`` is used in place when
+``T.stride(0) == 1`` (its memory is column-major with ``ld = T.stride(1)``);
+otherwise ``reduce`` works on a column-major copy.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libschur_mi355x.so")
+
+_lib = None
+
+
+class SchurOpts(ctypes.Structure):
+    _fields_ = [("ns", ctypes.c_int), ("nb", ctypes.c_int), ("step", ctypes.c_int),
+                ("nmin", ctypes.c_int), ("max_sweeps", ctypes.c_int),
+                ("exc_period", ctypes.c_int), ("flags", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
+
+
+class SchurStats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("windows", ctypes.c_int64),
+                ("chain_steps", ctypes.c_int64), ("small_solves", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("gemm_flops", ctypes.c_double),
+                ("gemm_ms", ctypes.c_double), ("gemm_launches", ctypes.c_int64),
+                ("chase_ms", ctypes.c_double), ("chase_launches", ctypes.c_int64),
+                ("shift_ms", ctypes.c_double), ("other_ms", ctypes.c_double),
+                ("shifts_applied", ctypes.c_int64),
+                ("row_flops", ctypes.c_double), ("row_ms", ctypes.c_double),
+                ("row_launches", ctypes.c_int64),
+                ("colq_flops", ctypes.c_double), ("colq_ms", ctypes.c_double),
+                ("colq_launches", ctypes.c_int64),
+                ("reserved", ctypes.c_double * 4)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+FLAG_TIME_KERNELS = 1
+
+EXPORTS = ("schur_reduce", "schur_create", "schur_destroy", "schur_set_opts",
+           "schur_get_stats", "schur_reduce_async", "schur_reduce_batched")
+
+
+def load():
+    """Load the built HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("HIP library %s is missing: run `python -m paper_1905_04975_amd.build`"
+                           % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p
+    lib.schur_reduce.argtypes = [ip, dp, ip, dp, ip, dp, dp]
+    lib.schur_reduce.restype = ctypes.c_int
+    lib.schur_create.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(SchurOpts)]
+    lib.schur_create.restype = ctypes.c_int
+    lib.schur_destroy.argtypes = [vp]
+    lib.schur_destroy.restype = ctypes.c_int
+    lib.schur_set_opts.argtypes = [vp, ctypes.POINTER(SchurOpts)]
+    lib.schur_set_opts.restype = ctypes.c_int
+    lib.schur_get_stats.argtypes = [vp, ctypes.POINTER(SchurStats)]
+    lib.schur_get_stats.restype = ctypes.c_int
+    lib.schur_reduce_async.argtypes = [vp, vp, ip, dp, ip, dp, ip, dp, dp, ctypes.POINTER(ip)]
+    lib.schur_reduce_async.restype = ctypes.c_int
+    pint = ctypes.POINTER(ctypes.c_int)
+    pptr = ctypes.POINTER(ctypes.c_void_p)
+    lib.schur_reduce_batched.argtypes = [vp, vp, ip, pint, pptr, pint, pptr, pint, pptr, pptr, pint]
+    lib.schur_reduce_batched.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def schur_reduce(n, H, ldh, Q, ldq, wr, wi):
+    """C ``schur_reduce`` with raw device pointers (ints); returns info."""
+    return load().schur_reduce(int(n), H, int(ldh), Q, int(ldq), wr, wi)
+
+
+class Handle:
+    """A library handle (its own HIP stream and workspace on one device)."""
+
+    def __init__(self, device: int = 0, **opts):
+        lib = load()
+        self._h = ctypes.c_void_p()
+        o = make_opts(**opts)
+        rc = lib.schur_create(ctypes.byref(self._h), int(device), ctypes.byref(o))
+        if rc != 0:
+            raise RuntimeError("schur_create failed: %d" % rc)
+
+    def set_opts(self, **opts):
+        o = make_opts(**opts)
+        load().schur_set_opts(self._h, ctypes.byref(o))
+
+    def stats(self):
+        st = SchurStats()
+        load().schur_get_stats(self._h, ctypes.byref(st))
+        return st.as_dict()
+
+    def reduce_async(self, stream, n, H, ldh, Q, ldq, wr, wi):
+        info = ctypes.c_int(0)
+        rc = load().schur_reduce_async(self._h, stream, int(n), H, int(ldh), Q, int(ldq), wr, wi,
+                                       ctypes.byref(info))
+        return rc
+
+    def reduce_batched(self, stream, ns, Hs, ldhs, Qs, ldqs, wrs, wis):
+        count = len(ns)
+        IA = ctypes.c_int * count
+        PA = ctypes.c_void_p * count
+        info = IA()
+        q_arr = PA(*[q or 0 for q in Qs]) if Qs is not None else None
+        ldq_arr = IA(*ldqs) if ldqs is not None else None
+        rc = load().schur_reduce_batched(self._h, stream, count, IA(*ns), PA(*Hs), IA(*ldhs),
+                                         q_arr, ldq_arr, PA(*wrs), PA(*wis), info)
+        return rc, list(info)
+
+    def close(self):
+        if self._h:
+            load().schur_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_opts(ns=0, nb=0, step=0, nmin=0, max_sweeps=0, exc_period=0, flags=0):
+    o = SchurOpts()
+    o.ns, o.nb, o.step, o.nmin = int(ns), int(nb), int(step), int(nmin)
+    o.max_sweeps, o.exc_period, o.flags = int(max_sweeps), int(exc_period), int(flags)
+    return o
+
+
+def _colmajor(T):
+    """Column-major view (or copy) of a 2-D CUDA float64 tensor and its ld."""
+    import torch
+
+    if T.dtype != torch.float64:
+        raise TypeError("FP64 tensors only")
+    if T.stride(0) == 1 and T.stride(1) >= max(1, T.shape[0]):
+        return T, T.stride(1)
+    C = T.t().contiguous().t()
+    return C, max(1, C.stride(1))
+
+
+def reduce(H, Q=None, want_q=True, handle=None, stream=None):
+    """Schur form of the upper Hessenberg CUDA/HIP tensor ``H`` (float64).
+
+    Returns ``(S, Q, w, info)`` with ``w`` complex (torch complex128 on the
+    device).  ``H`` is overwritten when it is already column-major; ``Q``
+    (if given, column-major float64) is accumulated in place.
+    """
+    import torch
+
+    n = H.shape[0]
+    S, ldh = _colmajor(H)
+    dev = S.device
+    if want_q:
+        if Q is None:
+            Qm = torch.eye(n, dtype=torch.float64, device=dev).t()
+        else:
+            Qm = Q
+        Qm, ldq = _colmajor(Qm)
+        qptr = Qm.data_ptr()
+    else:
+        Qm, ldq, qptr = None, 1, None
+    wr = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    wi = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    if handle is None:
+        torch.cuda.synchronize(dev)
+        info = schur_reduce(n, S.data_ptr(), ldh, qptr, ldq, wr.data_ptr(), wi.data_ptr())
+    else:
+        if stream is None:
+            stream = torch.cuda.current_stream(dev).cuda_stream
+        info = handle.reduce_async(stream, n, S.data_ptr(), ldh, qptr, ldq, wr.data_ptr(),
+                                   wi.data_ptr())
+    w = torch.complex(wr[:n], wi[:n])
+    return S, Qm, w, info
