@@ -22,7 +22,8 @@ __device__ __forceinline__ Refl make_reflector(int nr, double x, double y, doubl
     return h;
   }
   const double sc = fabs(x) + tail;           // scaling keeps the squares finite
-  const double xs = x / sc, ys = y / sc, zs = z / sc;
+  const double isc = 1.0 / sc;
+  const double xs = x * isc, ys = y * isc, zs = z * isc;
   const double len = sc * sqrt(xs * xs + ys * ys + zs * zs);
   const double beta = (x < 0.0) ? len : -len;
   const double den = 1.0 / (x - beta);

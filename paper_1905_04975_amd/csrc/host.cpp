@@ -90,9 +90,15 @@ struct Timer {
 
 }  // namespace
 
+constexpr int NBUF = 4;   // ring of U-slot buffers shared by the two streams
+
 struct schur_handle_s {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t aux = nullptr;     // Q products run here, overlapping the window chase
+  hipEvent_t ev_u[NBUF] = {};    // U slots of a buffer written (main stream)
+  hipEvent_t ev_q[NBUF] = {};    // U slots of a buffer read by the Q products (aux stream)
+  hipEvent_t ev_join = nullptr;
   schur_opts opts{};
   double* U = nullptr;
   double* refl = nullptr;
@@ -106,6 +112,13 @@ struct schur_handle_s {
   int* bcount = nullptr;
   schur_stats stats{};
   Timer timer;
+  // batched workspace (grow-only)
+  struct Grow {
+    void* dev = nullptr;
+    void* host = nullptr;   // pinned staging
+    size_t cap = 0;
+  };
+  Grow b_ctrl, b_defl, b_small, b_shift, b_win, b_u, b_sh;
 };
 
 namespace {
@@ -153,7 +166,8 @@ Params resolve(const schur_opts& o, int n) {
 
 int alloc_ws(schur_handle_s* h, int n) {
   if (!h->U) {
-    if (hipMalloc(&h->U, sizeof(double) * (size_t)MAXWIN * UPAD * UPAD) != hipSuccess) return -101;
+    if (hipMalloc(&h->U, sizeof(double) * (size_t)NBUF * MAXWIN * UPAD * UPAD) != hipSuccess)
+      return -101;
     if (hipMalloc(&h->refl, sizeof(double) * (size_t)MAXWIN * REFL_STRIDE) != hipSuccess) return -101;
     if (hipMalloc(&h->st, sizeof(double) * NSMAX) != hipSuccess) return -101;
     if (hipMalloc(&h->ewr, sizeof(double) * NSMAX) != hipSuccess) return -101;
@@ -173,7 +187,34 @@ int alloc_ws(schur_handle_s* h, int n) {
   return 0;
 }
 
+// grow-only device buffer with a pinned host mirror
+void* grow(schur_handle_s::Grow& g, size_t bytes, bool staging) {
+  if (g.cap < bytes) {
+    if (g.dev) HCHECK(hipFree(g.dev));
+    if (g.host) HCHECK(hipHostFree(g.host));
+    g.dev = nullptr;
+    g.host = nullptr;
+    g.cap = 0;
+    const size_t cap = bytes + bytes / 2 + 4096;
+    HCHECK(hipMalloc(&g.dev, cap));
+    if (staging) HCHECK(hipHostMalloc(&g.host, cap, hipHostMallocDefault));
+    g.cap = cap;
+  }
+  if (staging && !g.host) HCHECK(hipHostMalloc(&g.host, g.cap, hipHostMallocDefault));
+  return g.dev;
+}
+
+void free_grow(schur_handle_s::Grow& g) {
+  if (g.dev) (void)hipFree(g.dev);
+  if (g.host) (void)hipHostFree(g.host);
+  g.dev = nullptr;
+  g.host = nullptr;
+  g.cap = 0;
+}
+
 void free_ws(schur_handle_s* h) {
+  free_grow(h->b_ctrl); free_grow(h->b_defl); free_grow(h->b_small);
+  free_grow(h->b_shift); free_grow(h->b_win); free_grow(h->b_u); free_grow(h->b_sh);
   if (h->U) (void)hipFree(h->U);
   if (h->refl) (void)hipFree(h->refl);
   if (h->st) (void)hipFree(h->st);
@@ -210,6 +251,7 @@ void plan_sweep(int ktop, int kbot, int npair, int nbmax, int step_opt,
   }
   const int nbm = nbj[0];
   int step = WMAX - 3 * nbm - 1;
+  step = std::min(step, REFL_LDS / nbm);   // reflector log of one window fits LDS
   if (step_opt > 0) step = std::min(step, step_opt);
   if (step < 3) step = 3;
   step_out = step;
@@ -253,19 +295,24 @@ struct Solver {
   double* Q; int ldq;
   double* wr; double* wi;
 
-  void fill_gemm(SweepArgs& a, int& tr, int& tcq) {
+  int64_t tslot = 0;   // time steps issued so far (ring position of the U slots)
+
+  // Tile counts of the row panel and column panel (main stream) in `a`, and
+  // of the Q products (aux stream) in `aq`, a copy of `a`.
+  void fill_gemm(SweepArgs& a, SweepArgs& aq, int& tr, int& tc, int& tq) {
     tr = 0;
-    tcq = 0;
+    tc = 0;
+    tq = 0;
     for (int w = 0; w < a.nwin; ++w) {
       Win& d = a.win[w];
       const int pe = d.p + d.ws - 1;
       d.tiles_r = std::max(0, (a.cend - pe - 1 + GEMM_T - 1) / GEMM_T);
       d.tiles_c = std::max(0, (d.p - a.rtop + GEMM_T - 1) / GEMM_T);
-      d.tiles_q = a.Q ? (n + GEMM_T - 1) / GEMM_T : 0;
+      d.tiles_q = 0;
       d.base_r = tr;
-      d.base_cq = tcq;
+      d.base_cq = tc;
       tr += d.tiles_r;
-      tcq += d.tiles_c + d.tiles_q;
+      tc += d.tiles_c;
       const double ws = d.ws;
       const double fr = 2.0 * ws * ws * (double)std::max(0, a.cend - pe - 1);
       const double fc = 2.0 * ws * ws * ((double)(d.p - a.rtop) + (a.Q ? (double)n : 0.0));
@@ -273,6 +320,47 @@ struct Solver {
       h->stats.colq_flops += fc;
       h->stats.gemm_flops += fr + fc;
     }
+    aq = a;
+    for (int w = 0; w < aq.nwin; ++w) {
+      Win& d = aq.win[w];
+      d.tiles_r = 0;
+      d.tiles_c = 0;
+      d.tiles_q = a.Q ? (n + GEMM_T - 1) / GEMM_T : 0;
+      d.base_cq = tq;
+      tq += d.tiles_q;
+    }
+  }
+
+  // ring buffer of U slots for the next time step: wait until the Q products
+  // that last read this buffer are done
+  int acquire_buffer() {
+    const int buf = (int)(tslot % NBUF);
+    if (tslot >= NBUF) HCHECK(hipStreamWaitEvent(s, h->ev_q[buf], 0));
+    ++tslot;
+    return buf;
+  }
+
+  // Q products of one time step on the aux stream, after the U slots are ready
+  void launch_q(const SweepArgs& aq, int tq, int buf) {
+    HCHECK(hipEventRecord(h->ev_u[buf], s));
+    if (tq > 0) {
+      HCHECK(hipStreamWaitEvent(h->aux, h->ev_u[buf], 0));
+      hipEvent_t e0 = nullptr;
+      if (P.time) h->timer.begin(h->aux, e0);
+      launch_panel_colq(aq, tq, h->aux);
+      HCHECK(hipGetLastError());
+      if (P.time) h->timer.end(h->aux, e0, &h->stats.colq_ms);
+      h->stats.colq_launches += 1;
+      h->stats.gemm_launches += 1;
+      h->stats.launches += 1;
+    }
+    HCHECK(hipEventRecord(h->ev_q[buf], h->aux));
+  }
+
+  // main stream waits for everything issued on the aux stream
+  void join_aux() {
+    HCHECK(hipEventRecord(h->ev_join, h->aux));
+    HCHECK(hipStreamWaitEvent(s, h->ev_join, 0));
   }
 
   void base_args(SweepArgs& a, int ktop, int kbot) {
@@ -309,18 +397,22 @@ struct Solver {
   void sync_ctrl() {
     HCHECK(hipMemcpyAsync(h->ctrl_h, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HCHECK(hipStreamSynchronize(s));
-    if (P.time) h->timer.harvest();
+    if (P.time) {
+      HCHECK(hipStreamSynchronize(h->aux));
+      h->timer.harvest();
+    }
   }
 
   // finish a small active block [ktop, kbot] in one kernel, then apply its
   // Z to the row panel, the column panel and Q
   void small_block(int ktop, int kbot) {
     const int m = kbot - ktop + 1;
+    const int buf = acquire_buffer();
     SmallTask t{};
     t.A = H + ktop + (size_t)ktop * ldh;
     t.lda = ldh;
     t.m = m;
-    t.Zt = h->U;
+    t.Zt = h->U + (size_t)buf * MAXWIN * UPAD * UPAD;
     t.ldzt = UPAD;
     t.info = &h->ctrl->small_info;
     t.itmax = 30;
@@ -331,15 +423,16 @@ struct Solver {
     if (P.time) h->timer.end(s, e0, &h->stats.other_ms);
     h->stats.small_solves += 1;
     h->stats.launches += 1;
-    SweepArgs a;
+    SweepArgs a, aq;
     base_args(a, ktop, kbot);
     a.nwin = 1;
     a.win[0].p = ktop;
     a.win[0].ws = m;
-    a.win[0].slot = 0;
-    int tr, tcq;
-    fill_gemm(a, tr, tcq);
-    launch_gemms(a, tr, tcq);
+    a.win[0].slot = buf * MAXWIN;
+    int tr, tc, tq;
+    fill_gemm(a, aq, tr, tc, tq);
+    launch_q(aq, tq, buf);
+    launch_gemms(a, tr, tc);
   }
 
   void compute_shifts(int ktop, int kbot, int ns, bool exceptional) {
@@ -373,20 +466,22 @@ struct Solver {
     h->stats.shifts_applied += ns;
     for (const auto& ws : steps) {
       if (ws.empty()) continue;   // gap between groups on short blocks
-      SweepArgs a;
+      SweepArgs a, aq;
       base_args(a, ktop, kbot);
       a.nwin = (int)ws.size();
       if (a.nwin > MAXWIN) throw HipErr{hipErrorInvalidValue};
+      const int buf = acquire_buffer();
       int prev_end = -1;
       for (int w = 0; w < a.nwin; ++w) {
         const WinPlan& pl = ws[w];
         if (pl.ws > WMAX || pl.ws < 3 || pl.p <= prev_end || pl.p < ktop ||
-            pl.p + pl.ws - 1 > kbot || pl.nb > NBMAX || pl.tau1 - pl.tau0 > WMAX)
+            pl.p + pl.ws - 1 > kbot || pl.nb > NBMAX || pl.tau1 - pl.tau0 > WMAX ||
+            (pl.tau1 - pl.tau0) * pl.nb > REFL_LDS)
           throw HipErr{hipErrorInvalidValue};
         prev_end = pl.p + pl.ws - 1;
         Win& d = a.win[w];
         d.p = pl.p; d.ws = pl.ws; d.tau0 = pl.tau0; d.tau1 = pl.tau1;
-        d.nb = pl.nb; d.shift0 = pl.shift0; d.slot = w;
+        d.nb = pl.nb; d.shift0 = pl.shift0; d.slot = buf * MAXWIN + w;
         h->stats.windows += 1;
         h->stats.chain_steps += pl.tau1 - pl.tau0;
       }
@@ -397,13 +492,17 @@ struct Solver {
       if (P.time) h->timer.end(s, e0, &h->stats.chase_ms);
       h->stats.chase_launches += 1;
       h->stats.launches += 1;
-      int tr, tcq;
-      fill_gemm(a, tr, tcq);
-      launch_gemms(a, tr, tcq);
+      int tr, tc, tq;
+      fill_gemm(a, aq, tr, tc, tq);
+      launch_q(aq, tq, buf);
+      launch_gemms(a, tr, tc);
     }
   }
 
   int run() {
+    // the aux stream starts after the work already queued on the solve stream
+    HCHECK(hipEventRecord(h->ev_join, s));
+    HCHECK(hipStreamWaitEvent(h->aux, h->ev_join, 0));
     launch_ctrl_reset(h->ctrl, s);
     launch_check_finite(H, ldh, n, h->ctrl, s);
     sync_ctrl();
@@ -435,9 +534,7 @@ struct Solver {
       if (m <= P.nmin) {
         // small_info is rebased to the global row by the next check
         small_block(ktop, kbot);
-        HCHECK(hipMemcpyAsync(h->ctrl_h, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-        HCHECK(hipStreamSynchronize(s));
-        if (P.time) h->timer.harvest();
+        sync_ctrl();
         if (h->ctrl_h->small_info != 0) {
           info = ktop + h->ctrl_h->small_info;
           break;
@@ -458,6 +555,7 @@ struct Solver {
       ++nodefl;
     }
     const int kmin = info > 0 ? info + 1 : 1;
+    join_aux();   // the standardisation rotates columns of Q
     hipEvent_t e0 = nullptr;
     if (P.time) h->timer.begin(s, e0);
     launch_standardize(H, ldh, Q, ldq, n, kmin, wr, wi, h->blist, h->bcount, h->blist_cap, s);
@@ -501,12 +599,345 @@ int solve(schur_handle_s* h, hipStream_t s, int n, double* H, int ldh, double* Q
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched solver: independent matrices advance in rounds.  A round is one
+// batched deflation scan (one workgroup per matrix, with converged bottom
+// blocks peeled and standardised at once), one batched small-block solve
+// for the matrices whose active block is small, one batched shift solve, and
+// one sweep for every other matrix -- the sweeps' time steps are merged so
+// that each launch carries the windows (or panel tiles) of all matrices.
+// ---------------------------------------------------------------------------
+struct BatchSolver {
+  schur_handle_s* h;
+  hipStream_t s;
+  int count;
+  struct Mat {
+    int n, ldh, ldq;
+    double *H, *Q, *wr, *wi;
+    int kbot, ktop, info, nodefl;
+    int last_small_top;   // ktop of the last small-block solve (-1: none)
+    int64_t sweeps;
+    bool active;
+    Params P;
+  };
+  std::vector<Mat> M;
+
+  template <class T>
+  T* dev_of(schur_handle_s::Grow& g) { return (T*)g.dev; }
+  template <class T>
+  T* host_of(schur_handle_s::Grow& g) { return (T*)g.host; }
+
+  void upload(schur_handle_s::Grow& g, size_t bytes) {
+    if (bytes) HCHECK(hipMemcpyAsync(g.dev, g.host, bytes, hipMemcpyHostToDevice, s));
+  }
+
+  int run() {
+    const int nm = count;
+    grow(h->b_ctrl, sizeof(Ctrl) * nm, true);
+    grow(h->b_defl, sizeof(DeflB) * nm, true);
+    grow(h->b_sh, sizeof(double) * 3 * SMALL_EIG_MAX * (size_t)nm, false);
+    Ctrl* ctrl_d = dev_of<Ctrl>(h->b_ctrl);
+    Ctrl* ctrl_h = host_of<Ctrl>(h->b_ctrl);
+    double* shbuf = dev_of<double>(h->b_sh);
+    // input check, then zero below the subdiagonal
+    {
+      HCHECK(hipMemsetAsync(ctrl_d, 0, sizeof(Ctrl) * nm, s));
+      for (int i = 0; i < nm; ++i)
+        if (M[i].active) launch_check_finite(M[i].H, M[i].ldh, M[i].n, ctrl_d + i, s);
+      HCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl) * nm, hipMemcpyDeviceToHost, s));
+      HCHECK(hipStreamSynchronize(s));
+      for (int i = 0; i < nm; ++i) {
+        if (!M[i].active) continue;
+        if (ctrl_h[i].bad) { M[i].info = -2; M[i].active = false; continue; }
+        launch_zero_lower(M[i].H, M[i].ldh, M[i].n, s);
+      }
+      HCHECK(hipMemsetAsync(ctrl_d, 0, sizeof(Ctrl) * nm, s));
+    }
+    std::vector<int> idx;
+    int64_t rounds = 0, round_cap = 0;
+    for (int i = 0; i < nm; ++i)
+      round_cap = std::max<int64_t>(round_cap, M[i].P.max_sweeps + M[i].n + 16);
+    while (true) {
+      if (++rounds > round_cap) throw HipErr{hipErrorUnknown};   // no progress: report, never spin
+      // ---- deflation scan of every active matrix
+      idx.clear();
+      for (int i = 0; i < nm; ++i) if (M[i].active) idx.push_back(i);
+      if (idx.empty()) break;
+      DeflB* dh = host_of<DeflB>(h->b_defl);
+      for (size_t q = 0; q < idx.size(); ++q) {
+        Mat& m = M[idx[q]];
+        dh[q] = DeflB{m.H, m.Q, m.wr, m.wi, m.ldh, m.ldq, m.n, m.kbot, ctrl_d + idx[q]};
+      }
+      upload(h->b_defl, sizeof(DeflB) * idx.size());
+      launch_deflate_b(dev_of<DeflB>(h->b_defl), (int)idx.size(), s);
+      HCHECK(hipGetLastError());
+      h->stats.launches += 1;
+      HCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl) * nm, hipMemcpyDeviceToHost, s));
+      HCHECK(hipStreamSynchronize(s));
+      // ---- classify
+      std::vector<int> small, big;
+      for (int i : idx) {
+        Mat& m = M[i];
+        if (ctrl_h[i].small_info != 0) {       // a small-block solve of the last round failed
+          m.info = m.last_small_top + ctrl_h[i].small_info;
+          m.active = false;
+          continue;
+        }
+        const int nk = ctrl_h[i].kbot;
+        if (nk < m.kbot) m.nodefl = 0;
+        m.kbot = nk;
+        m.ktop = ctrl_h[i].ktop;
+        if (m.kbot < 0) { m.active = false; continue; }
+        const int len = m.kbot - m.ktop + 1;
+        if (len <= m.P.nmin) small.push_back(i);
+        else if (++m.sweeps > m.P.max_sweeps) { m.info = m.kbot + 1; m.active = false; }
+        else big.push_back(i);
+      }
+      if (small.empty() && big.empty()) continue;
+      // U slots: one per small block, and one per window of the widest time step
+      std::vector<std::vector<std::vector<WinPlan>>> plans(big.size());
+      std::vector<int> nsv(big.size());
+      size_t maxw = 0, tmax = 0;
+      for (size_t q = 0; q < big.size(); ++q) {
+        Mat& m = M[big[q]];
+        const int len = m.kbot - m.ktop + 1;
+        int ns = std::min(m.P.ns, 2 * ((len - 2) / 6));
+        if (ns < 2) ns = 2;
+        nsv[q] = ns;
+        int step = 0;
+        plan_sweep(m.ktop, m.kbot, ns / 2, m.P.nb, m.P.step, plans[q], step);
+        tmax = std::max(tmax, plans[q].size());
+      }
+      std::vector<size_t> per_t(tmax, 0);
+      for (size_t q = 0; q < big.size(); ++q)
+        for (size_t t = 0; t < plans[q].size(); ++t) per_t[t] += plans[q][t].size();
+      for (size_t t = 0; t < tmax; ++t) maxw = std::max(maxw, per_t[t]);
+      const size_t nslots = std::max(maxw, small.size());
+      double* Ubase = (double*)grow(h->b_u, sizeof(double) * UPAD * UPAD * std::max<size_t>(1, nslots),
+                                    false);
+      // ---- small blocks: one workgroup each; whole small matrices accumulate Q
+      // in the kernel, blocks of larger matrices apply Z as panel products
+      if (!small.empty()) {
+        grow(h->b_small, sizeof(SmallTask) * small.size(), true);
+        grow(h->b_win, sizeof(WinB) * small.size(), true);
+        SmallTask* th = host_of<SmallTask>(h->b_small);
+        WinB* wh = host_of<WinB>(h->b_win);
+        int nwin = 0, tr = 0, tcq = 0;
+        int maxm = 0;
+        for (size_t q = 0; q < small.size(); ++q) {
+          Mat& m = M[small[q]];
+          const int len = m.kbot - m.ktop + 1;
+          maxm = std::max(maxm, len);
+          const bool whole = (m.ktop == 0 && m.kbot == m.n - 1);
+          m.last_small_top = m.ktop;
+          SmallTask t{};
+          t.A = m.H + m.ktop + (size_t)m.ktop * m.ldh;
+          t.lda = m.ldh;
+          t.m = len;
+          t.wr = m.wr + m.ktop;
+          t.wi = m.wi + m.ktop;
+          t.info = &ctrl_d[small[q]].small_info;
+          t.itmax = 30;
+          double* slot = Ubase + (size_t)q * UPAD * UPAD;
+          if (whole) {
+            t.Qacc = m.Q;
+            t.ldqacc = m.ldq;
+          } else {
+            t.Zt = slot;
+            t.ldzt = UPAD;
+            WinB& w = wh[nwin++];
+            std::memset(&w, 0, sizeof(w));
+            w.c.H = m.H; w.c.Q = m.Q; w.c.U = slot; w.c.st = nullptr;
+            w.c.ldh = m.ldh; w.c.ldq = m.ldq; w.c.n = m.n;
+            w.c.ktop = m.ktop; w.c.kbot = m.kbot; w.c.rtop = 0; w.c.cend = m.n;
+            w.c.p = m.ktop; w.c.ws = len;
+            fill_tiles(w, tr, tcq);
+          }
+          th[q] = t;
+          m.kbot = m.ktop - 1;     // the block is finished by this round's launches
+          if (m.kbot < 0) m.active = false;   // (a failure is still read from its ctrl below)
+          h->stats.small_solves += 1;
+        }
+        upload(h->b_small, sizeof(SmallTask) * small.size());
+        launch_small_tasks(dev_of<SmallTask>(h->b_small), (int)small.size(), maxm, true, s);
+        HCHECK(hipGetLastError());
+        h->stats.launches += 1;
+        if (nwin > 0) {
+          upload(h->b_win, sizeof(WinB) * nwin);
+          launch_panel_row_b(dev_of<WinB>(h->b_win), nwin, tr, s);
+          launch_panel_colq_b(dev_of<WinB>(h->b_win), nwin, tcq, s);
+          HCHECK(hipGetLastError());
+          h->stats.launches += (tr > 0) + (tcq > 0);
+        }
+        if (!big.empty()) HCHECK(hipStreamSynchronize(s));   // slots and staging reused below
+      }
+      if (big.empty()) continue;
+      // ---- shifts: eigenvalues of the trailing blocks (or ad-hoc pairs)
+      {
+        grow(h->b_small, sizeof(SmallTask) * big.size(), true);
+        grow(h->b_shift, sizeof(ShiftB) * big.size(), true);
+        SmallTask* th = host_of<SmallTask>(h->b_small);
+        ShiftB* sh = host_of<ShiftB>(h->b_shift);
+        int ne = 0, maxns = 0;
+        for (size_t q = 0; q < big.size(); ++q) {
+          Mat& m = M[big[q]];
+          const int ns = nsv[q];
+          double* base = shbuf + (size_t)big[q] * 3 * SMALL_EIG_MAX;
+          const bool exc = (m.nodefl > 0 && m.nodefl % m.P.exc_period == 0);
+          if (!exc) {
+            SmallTask t{};
+            const int b0 = m.kbot - ns + 1;
+            t.A = m.H + b0 + (size_t)b0 * m.ldh;
+            t.lda = m.ldh;
+            t.m = ns;
+            t.wr = base;
+            t.wi = base + SMALL_EIG_MAX;
+            t.info = &ctrl_d[big[q]].nshift;   // per-matrix scratch for the shift solve
+            t.itmax = 30;
+            th[ne++] = t;
+            maxns = std::max(maxns, ns);
+          }
+          sh[q] = ShiftB{base, base + SMALL_EIG_MAX, exc ? nullptr : &ctrl_d[big[q]].nshift,
+                         m.H, base + 2 * SMALL_EIG_MAX, ns, exc ? 1 : 0, m.ldh, m.ktop, m.kbot, 0};
+          ++m.nodefl;
+          h->stats.sweeps += 1;
+          h->stats.shifts_applied += ns;
+        }
+        upload(h->b_small, sizeof(SmallTask) * ne);
+        upload(h->b_shift, sizeof(ShiftB) * big.size());
+        launch_small_tasks(dev_of<SmallTask>(h->b_small), ne, maxns, false, s);
+        launch_shift_prep_b(dev_of<ShiftB>(h->b_shift), (int)big.size(), s);
+        HCHECK(hipGetLastError());
+        h->stats.launches += 2;
+      }
+      // ---- merged sweeps: time step t carries the windows of every matrix
+      {
+        size_t total = 0;
+        for (size_t t = 0; t < tmax; ++t) total += per_t[t];
+        grow(h->b_win, sizeof(WinB) * std::max<size_t>(1, total), true);
+        WinB* wh = host_of<WinB>(h->b_win);
+        std::vector<size_t> off(tmax + 1, 0);
+        std::vector<int> tr_t(tmax, 0), tcq_t(tmax, 0);
+        for (size_t t = 0; t < tmax; ++t) {
+          off[t + 1] = off[t] + per_t[t];
+          size_t k = off[t];
+          int tr = 0, tcq = 0;
+          for (size_t q = 0; q < big.size(); ++q) {
+            if (t >= plans[q].size()) continue;
+            Mat& m = M[big[q]];
+            const double* st = shbuf + (size_t)big[q] * 3 * SMALL_EIG_MAX + 2 * SMALL_EIG_MAX;
+            for (const WinPlan& pl : plans[q][t]) {
+              if (pl.ws > WMAX || pl.ws < 3 || pl.p < m.ktop || pl.p + pl.ws - 1 > m.kbot ||
+                  (pl.tau1 - pl.tau0) * pl.nb > REFL_LDS || pl.nb > NBMAX)
+                throw HipErr{hipErrorInvalidValue};
+              WinB& w = wh[k];
+              std::memset(&w, 0, sizeof(w));
+              w.c.H = m.H; w.c.Q = m.Q;
+              w.c.U = Ubase + (k - off[t]) * (size_t)UPAD * UPAD;
+              w.c.st = st + 2 * pl.shift0;
+              w.c.ldh = m.ldh; w.c.ldq = m.ldq; w.c.n = m.n;
+              w.c.ktop = m.ktop; w.c.kbot = m.kbot; w.c.rtop = 0; w.c.cend = m.n;
+              w.c.p = pl.p; w.c.ws = pl.ws; w.c.tau0 = pl.tau0; w.c.tau1 = pl.tau1;
+              w.c.nb = pl.nb;
+              fill_tiles(w, tr, tcq);
+              ++k;
+              h->stats.windows += 1;
+              h->stats.chain_steps += pl.tau1 - pl.tau0;
+            }
+          }
+          tr_t[t] = tr;
+          tcq_t[t] = tcq;
+        }
+        upload(h->b_win, sizeof(WinB) * total);
+        WinB* wd = dev_of<WinB>(h->b_win);
+        for (size_t t = 0; t < tmax; ++t) {
+          const int nw = (int)per_t[t];
+          if (nw == 0) continue;
+          launch_chase_b(wd + off[t], nw, s);
+          launch_panel_row_b(wd + off[t], nw, tr_t[t], s);
+          launch_panel_colq_b(wd + off[t], nw, tcq_t[t], s);
+          HCHECK(hipGetLastError());
+          h->stats.chase_launches += 1;
+          h->stats.launches += 1 + (tr_t[t] > 0) + (tcq_t[t] > 0);
+        }
+      }
+    }
+    HCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl) * nm, hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    for (int i = 0; i < nm; ++i)   // small-block failures of the last launches
+      if (M[i].info == 0 && M[i].last_small_top >= 0 && ctrl_h[i].small_info != 0)
+        M[i].info = M[i].last_small_top + ctrl_h[i].small_info;
+    int first = 0;
+    for (int i = 0; i < nm; ++i) if (M[i].info != 0 && first == 0) first = M[i].info;
+    return first;
+  }
+
+  void fill_tiles(WinB& w, int& tr, int& tcq) {
+    const int pe = w.c.p + w.c.ws - 1;
+    w.tiles_r = std::max(0, (w.c.cend - pe - 1 + GEMM_T - 1) / GEMM_T);
+    w.tiles_c = std::max(0, (w.c.p - w.c.rtop + GEMM_T - 1) / GEMM_T);
+    w.tiles_q = w.c.Q ? (w.c.n + GEMM_T - 1) / GEMM_T : 0;
+    w.base_r = tr;
+    w.base_cq = tcq;
+    tr += w.tiles_r;
+    tcq += w.tiles_c + w.tiles_q;
+    const double ws = w.c.ws;
+    const double fr = 2.0 * ws * ws * (double)std::max(0, w.c.cend - pe - 1);
+    const double fc = 2.0 * ws * ws * ((double)(w.c.p - w.c.rtop) + (w.c.Q ? (double)w.c.n : 0.0));
+    h->stats.row_flops += fr;
+    h->stats.colq_flops += fc;
+    h->stats.gemm_flops += fr + fc;
+  }
+};
+
+int solve_batched(schur_handle_s* h, hipStream_t s, int count, const int* n, double* const* H,
+                  const int* ldh, double* const* Q, const int* ldq, double* const* wr,
+                  double* const* wi, int* info) {
+  try {
+    HCHECK(hipSetDevice(h->device));
+    const int rc = alloc_ws(h, 2);
+    if (rc) return rc;
+    std::memset(&h->stats, 0, sizeof(h->stats));
+    BatchSolver b{h, s ? s : h->stream, count, {}};
+    b.M.resize(count);
+    for (int i = 0; i < count; ++i) {
+      auto& m = b.M[i];
+      double* qi = Q ? Q[i] : nullptr;
+      m.n = n[i]; m.H = H[i]; m.ldh = ldh[i]; m.Q = qi; m.ldq = (qi && ldq) ? ldq[i] : 1;
+      m.wr = wr[i]; m.wi = wi[i];
+      m.info = check_args(m.n, m.H, m.ldh, m.Q, m.ldq, m.wr, m.wi);
+      m.active = (m.info == 0 && m.n > 0);
+      if (m.n > 65536) { m.info = -1; m.active = false; }
+      m.kbot = m.n - 1; m.ktop = 0; m.nodefl = 0; m.sweeps = 0; m.last_small_top = -1;
+      m.P = resolve(h->opts, std::max(1, m.n));
+    }
+    const int rc2 = b.run();
+    for (int i = 0; i < count; ++i) if (info) info[i] = b.M[i].info;
+    return rc2;
+  } catch (const HipErr& e) {
+    (void)hipGetLastError();
+    return e.e == hipErrorOutOfMemory ? -101 : -102;
+  }
+}
+
 int create_handle(schur_handle_s** out, int device, const schur_opts* opts) {
   schur_handle_s* h = new schur_handle_s();
   h->device = device;
   if (opts) h->opts = *opts;
   if (hipSetDevice(device) != hipSuccess) { delete h; return -102; }
-  if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+  if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) {
+    delete h;
+    return -102;
+  }
+  for (int i = 0; i < NBUF; ++i) {
+    if (hipEventCreateWithFlags(&h->ev_u[i], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_q[i], hipEventDisableTiming) != hipSuccess) {
+      delete h;
+      return -102;
+    }
+  }
+  if (hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
     delete h;
     return -102;
   }
@@ -530,6 +961,15 @@ int schur_destroy(schur_handle_t h) {
     (void)hipStreamSynchronize(h->stream);
     (void)hipStreamDestroy(h->stream);
   }
+  if (h->aux) {
+    (void)hipStreamSynchronize(h->aux);
+    (void)hipStreamDestroy(h->aux);
+  }
+  for (int i = 0; i < NBUF; ++i) {
+    if (h->ev_u[i]) (void)hipEventDestroy(h->ev_u[i]);
+    if (h->ev_q[i]) (void)hipEventDestroy(h->ev_q[i]);
+  }
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   free_ws(h);
   delete h;
   return 0;
@@ -575,14 +1015,9 @@ int schur_reduce_batched(schur_handle_t h, void* stream, int count, const int* n
                          double* const* wr, double* const* wi, int* info) {
   if (!h) return -104;
   if (count < 0) return -3;
-  int first = 0;
-  for (int i = 0; i < count; ++i) {
-    const int rc = solve(h, (hipStream_t)stream, n[i], H[i], ldh[i], Q ? Q[i] : nullptr,
-                         ldq ? ldq[i] : 1, wr[i], wi[i]);
-    if (info) info[i] = rc;
-    if (rc != 0 && first == 0) first = rc;
-  }
-  return first;
+  if (count == 0) return 0;
+  if (!n || !H || !ldh || !wr || !wi) return -4;
+  return solve_batched(h, (hipStream_t)stream, count, n, H, ldh, Q, ldq, wr, wi, info);
 }
 
 }  // extern "C"

@@ -14,6 +14,22 @@ struct SmallTask {
   double* wr; double* wi;      // optional: eigenvalues of the block
   int* info;                   // optional: 0, or 1-based end of a non-converged block
   int itmax;                   // Francis steps allowed per block end (<= 0: 30)
+  double* Qacc; int ldqacc;    // optional: Qacc(0:m, 0:m) <- Qacc(0:m, 0:m) Z
+};
+
+// One matrix of a batched deflation scan.
+struct DeflB {
+  double* H; double* Q; double* wr; double* wi;
+  int ldh, ldq, n, kbot;       // kbot: current bottom of the unreduced part
+  Ctrl* out;                   // kbot / ktop after the converged bottom blocks are peeled
+};
+
+// One matrix of a batched shift preparation.
+struct ShiftB {
+  const double* wr; const double* wi;   // eigenvalues of the trailing block
+  const int* info;                      // its small-solve info (may be null)
+  const double* H; double* st;
+  int ns, exceptional, ldh, ktop, kbot, pad;
 };
 
 void launch_small_z(const SmallTask& t, const SmallTask* tasks, int count, int maxm,
@@ -31,5 +47,13 @@ void launch_ctrl_reset(Ctrl* ctrl, hipStream_t s);
 void launch_deflate(double* H, int ldh, int kbot, int klo, Ctrl* ctrl, hipStream_t s);
 void launch_standardize(double* H, int ldh, double* Q, int ldq, int n, int kmin, double* wr,
                         double* wi, int* list, int* count, int cap, hipStream_t s);
+
+// batched (descriptor arrays in device memory)
+void launch_small_tasks(const SmallTask* tasks, int count, int maxm, bool wantz, hipStream_t s);
+void launch_chase_b(const WinB* wins, int nwin, hipStream_t s);
+void launch_panel_row_b(const WinB* wins, int nwin, int tiles, hipStream_t s);
+void launch_panel_colq_b(const WinB* wins, int nwin, int tiles, hipStream_t s);
+void launch_deflate_b(const DeflB* tasks, int count, hipStream_t s);
+void launch_shift_prep_b(const ShiftB* tasks, int count, hipStream_t s);
 
 }  // namespace schur

@@ -204,6 +204,30 @@ __device__ void small_qr(const SmallTask& T, double* S, double* Zs) {
       for (int c = 0; c < m; ++c)
         for (int r = lane; r < m; r += 64) T.Z[r + (size_t)c * T.ldz] = Zx(r, c);
     }
+    if (T.Qacc) {
+      // Qacc <- Qacc Z, rows by lanes, 16 columns at a time; the block's LDS
+      // copy (already written back) is the staging area
+      __syncthreads();
+      for (int r = lane; r < m; r += 64) {
+        for (int c0 = 0; c0 < m; c0 += 16) {
+          double acc[16];
+#pragma unroll
+          for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+          for (int k = 0; k < m; ++k) {
+            const double q = T.Qacc[r + (size_t)k * T.ldqacc];
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+              if (c0 + j < m) acc[j] += q * Zx(k, c0 + j);
+          }
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (c0 + j < m) Sx(r, c0 + j) = acc[j];
+        }
+      }
+      __syncthreads();
+      for (int c = 0; c < m; ++c)
+        for (int r = lane; r < m; r += 64) T.Qacc[r + (size_t)c * T.ldqacc] = Sx(r, c);
+    }
   }
 }
 
@@ -232,10 +256,9 @@ __global__ __launch_bounds__(64) void k_small_eig(SmallTask t0, const SmallTask*
 // (sum, product) pair per bulge.  Missing pairs (if the small solve did not
 // converge) are filled with ad-hoc shifts from the bottom of the block.
 // ============================================================================
-__global__ __launch_bounds__(256) void k_shift_prep(const double* wr, const double* wi, int ns,
-                                                    const int* small_info, int exceptional,
-                                                    const double* H, int ldh, int ktop, int kbot,
-                                                    double* st) {
+__device__ void shift_prep(const double* wr, const double* wi, int ns, const int* small_info,
+                           int exceptional, const double* H, int ldh, int ktop, int kbot,
+                           double* st) {
   __shared__ double key[512];
   __shared__ int kind[512];   // 0 real, 1 first of a conjugate pair, 2 second (skipped)
   __shared__ int rank[512];
@@ -310,148 +333,259 @@ __global__ __launch_bounds__(256) void k_shift_prep(const double* wr, const doub
   }
 }
 
+__global__ __launch_bounds__(256) void k_shift_prep(const double* wr, const double* wi, int ns,
+                                                    const int* small_info, int exceptional,
+                                                    const double* H, int ldh, int ktop, int kbot,
+                                                    double* st) {
+  shift_prep(wr, wi, ns, small_info, exceptional, H, ldh, ktop, kbot, st);
+}
+
+__global__ __launch_bounds__(256) void k_shift_prep_b(const ShiftB* tasks) {
+  const ShiftB T = tasks[blockIdx.x];
+  shift_prep(T.wr, T.wi, T.ns, T.info, T.exceptional, T.H, T.ldh, T.ktop, T.kbot, T.st);
+}
+
 // ============================================================================
 // Window chase (the window task).  One workgroup per diagonal window.
+//
+// Thread layout: 1024 threads; group b (TPB = 64 or 32 consecutive threads,
+// inside one wavefront) owns bulge b of the window's chain.  One chain step
+// advances every bulge by one row:
+//   B  left update of rows K+1..K+3 from the bulge column to the window end;
+//   C  right update of columns K+1..K+3 from the window top to row K+4;
+//   A  the group forms bulge b's reflector for the next step from column
+//      K+1, rows K+2..K+4, which only its own B and C of this step touched,
+//      so no workgroup barrier is needed before it.  A bulge entering the
+//      block takes its reflector from the shift pair after the barrier.
+// Bulges sit three rows apart, so all left updates of a step precede all
+// right updates (B, barrier, C, barrier).  Each thread issues all loads of
+// a phase before its stores.  The reflectors are logged in LDS; after the
+// window is written back, U is accumulated in the freed LDS with eight
+// lanes of one wavefront per row (rows are independent).
 // ============================================================================
-constexpr int CHASE_THREADS = 512;
-constexpr int NO_BULGE = -0x40000000;   // rk[] marker of an inactive bulge
+constexpr int CHASE_THREADS = 1024;
 
-__global__ __launch_bounds__(CHASE_THREADS) void k_chase(SweepArgs a) {
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ WinCtx ctx_of(const SweepArgs& a, const Win& w) {
+  WinCtx c;
+  c.H = a.H; c.Q = a.Q; c.U = a.U + (size_t)w.slot * UPAD * UPAD;
+  c.st = a.st + 2 * w.shift0;
+  c.ldh = a.ldh; c.ldq = a.ldq; c.n = a.n;
+  c.ktop = a.ktop; c.kbot = a.kbot; c.rtop = a.rtop; c.cend = a.cend;
+  c.p = w.p; c.ws = w.ws; c.tau0 = w.tau0; c.tau1 = w.tau1; c.nb = w.nb;
+  return c;
+}
+
+__device__ void chase_window(const WinCtx& d) {
   __shared__ double W[LDW * WMAX];
-  __shared__ double rv[NBMAX][4];
-  __shared__ int rk[NBMAX];
-  const Win d = a.win[blockIdx.x];
+  __shared__ double R[REFL_LDS * 3];
   const int tid = threadIdx.x;
   const int p = d.p, ws = d.ws, nb = d.nb;
-  const int ktop = a.ktop, kbot = a.kbot;
-  double* refl = a.refl + (size_t)d.slot * a.refl_stride;
+  const int ktop = d.ktop, kbot = d.kbot;
+  const WinCtx& a = d;   // matrix fields
   auto Wx = [&](int r, int c) -> double& { return W[r + c * LDW]; };
 
-  // load the window
-  for (int idx = tid; idx < ws * ws; idx += CHASE_THREADS) {
-    const int c = idx / ws, r = idx - c * ws;
-    Wx(r, c) = a.H[(size_t)(p + r) + (size_t)(p + c) * a.ldh];
+  // load the window: 8 columns per pass, all loads issued before the stores
+  {
+    const int r = tid & 127, c0 = tid >> 7;
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int c = c0 + 8 * q;
+      v[q] = (r < ws && c < ws) ? a.H[(size_t)(p + r) + (size_t)(p + c) * a.ldh] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int c = c0 + 8 * q;
+      if (r < ws && c < ws) Wx(r, c) = v[q];
+    }
   }
+  const int lgt = (nb <= 16) ? 6 : 5;
+  const int tpb = 1 << lgt;
+  const int b = tid >> lgt;
+  const int t = tid & (tpb - 1);
+  const bool mine = b < nb;
+  const double s_sum = mine ? d.st[2 * b] : 0.0;
+  const double s_prod = mine ? d.st[2 * b + 1] : 0.0;
   __syncthreads();
 
-  for (int tau = d.tau0; tau < d.tau1; ++tau) {
-    // phase A: one reflector per active bulge (from the bulge column, or from
-    // the shifts when the bulge is introduced at the top of the block)
-    if (tid < nb) {
-      const int b = tid;
-      const int K = ktop - 1 + tau - 3 * b;
-      double* out = refl + ((size_t)(tau - d.tau0) * nb + b) * 3;
-      if (K < ktop - 1 || K > kbot - 2) {
-        rk[b] = NO_BULGE;
-        out[0] = 0.0; out[1] = 0.0; out[2] = 0.0;
+  // reflector of bulge b at chain step tau (reads column K, or the shifts)
+  auto form = [&](int tau, int& K, int& nr, bool& act, Refl& h) {
+    K = ktop - 1 + tau - 3 * b;
+    act = mine && K >= ktop - 1 && K <= kbot - 2;
+    nr = (K <= kbot - 3) ? 3 : 2;
+    h = Refl{0.0, 0.0, 0.0, 0.0};
+    if (act) {
+      double x, y, z;
+      if (K == ktop - 1) {
+        const int o = ktop - p;
+        first_column(Wx(o, o), Wx(o, o + 1), Wx(o + 1, o), Wx(o + 1, o + 1),
+                     (nr == 3) ? Wx(o + 2, o + 1) : 0.0, s_sum, s_prod, x, y, z);
       } else {
-        const int nr = (K <= kbot - 3) ? 3 : 2;
-        double x, y, z;
-        if (K == ktop - 1) {
-          const int o = ktop - p;
-          first_column(Wx(o, o), Wx(o, o + 1), Wx(o + 1, o), Wx(o + 1, o + 1),
-                       (nr == 3) ? Wx(o + 2, o + 1) : 0.0,
-                       a.st[2 * (d.shift0 + b)], a.st[2 * (d.shift0 + b) + 1], x, y, z);
-        } else {
-          const int k = K - p;
-          x = Wx(k + 1, k);
-          y = Wx(k + 2, k);
-          z = (nr == 3) ? Wx(k + 3, k) : 0.0;
+        const int k = K - p;
+        x = Wx(k + 1, k);
+        y = Wx(k + 2, k);
+        z = (nr == 3) ? Wx(k + 3, k) : 0.0;
+      }
+      h = make_reflector(nr, x, y, z);
+      if (h.tau == 0.0) act = false;
+    }
+  };
+
+  int K, nr;
+  bool act;
+  Refl h;
+  form(d.tau0, K, nr, act, h);
+  for (int tau = d.tau0; tau < d.tau1; ++tau) {
+    if (K == ktop - 1) form(tau, K, nr, act, h);   // entering bulge: after the barrier
+    const int k = K - p;
+    if (mine && t == 0) {
+      double* rr = &R[3 * ((tau - d.tau0) * nb + b)];
+      rr[0] = h.v2;
+      rr[1] = (nr == 3) ? h.v3 : 0.0;
+      rr[2] = act ? h.tau : 0.0;
+    }
+    // ---- B: left update (at most 2 columns per thread with TPB = 64)
+    if (act) {
+      const int c0 = (k < 0) ? 0 : k;
+      double x1[4], x2[4], x3[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = c0 + t + q * tpb;
+        if (c < ws && c != k) {
+          const double* col = &Wx(k + 1, c);
+          x1[q] = col[0]; x2[q] = col[1]; x3[q] = (nr == 3) ? col[2] : 0.0;
         }
-        const Refl h = make_reflector(nr, x, y, z);
-        rv[b][0] = h.v2; rv[b][1] = h.v3; rv[b][2] = h.tau; rv[b][3] = h.beta;
-        rk[b] = (h.tau == 0.0) ? NO_BULGE : K;
-        out[0] = h.v2; out[1] = (nr == 3) ? h.v3 : 0.0; out[2] = h.tau;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = c0 + t + q * tpb;
+        if (c >= ws) continue;
+        if (c == k) {
+          Wx(k + 1, k) = h.beta;
+          Wx(k + 2, k) = 0.0;
+          if (nr == 3) Wx(k + 3, k) = 0.0;
+          continue;
+        }
+        const double w = h.tau * (x1[q] + h.v2 * x2[q] + h.v3 * x3[q]);
+        double* col = &Wx(k + 1, c);
+        col[0] = x1[q] - w;
+        col[1] = x2[q] - w * h.v2;
+        if (nr == 3) col[2] = x3[q] - w * h.v3;
       }
     }
     __syncthreads();
-    // phase B: left updates, rows K+1..K+nr, columns from the bulge column on
-    for (int idx = tid; idx < nb * ws; idx += CHASE_THREADS) {
-      const int b = idx / ws, c = idx - b * ws;
-      const int K = rk[b];
-      if (K == NO_BULGE) continue;
-      const int k = K - p;                  // local bulge column (may be -1)
-      if (c < k) continue;
-      const int nr = (K <= kbot - 3) ? 3 : 2;
-      if (c == k) {
-        Wx(k + 1, k) = rv[b][3];
-        Wx(k + 2, k) = 0.0;
-        if (nr == 3) Wx(k + 3, k) = 0.0;
-        continue;
-      }
-      const double v2 = rv[b][0], v3 = rv[b][1], tv = rv[b][2];
-      const double a1 = Wx(k + 1, c), a2 = Wx(k + 2, c);
-      const double a3 = (nr == 3) ? Wx(k + 3, c) : 0.0;
-      const double w = tv * (a1 + v2 * a2 + v3 * a3);
-      Wx(k + 1, c) = a1 - w;
-      Wx(k + 2, c) = a2 - w * v2;
-      if (nr == 3) Wx(k + 3, c) = a3 - w * v3;
-    }
-    __syncthreads();
-    // phase C: right updates, columns K+1..K+nr, rows from the window top
-    for (int idx = tid; idx < nb * ws; idx += CHASE_THREADS) {
-      const int b = idx / ws, r = idx - b * ws;
-      const int K = rk[b];
-      if (K == NO_BULGE) continue;
-      const int k = K - p;
+    // ---- C: right update, then the next reflector of this bulge
+    if (act) {
       const int rl = ((K + 4 < kbot) ? K + 4 : kbot) - p;
-      if (r > rl) continue;
-      const int nr = (K <= kbot - 3) ? 3 : 2;
-      const double v2 = rv[b][0], v3 = rv[b][1], tv = rv[b][2];
-      const double a1 = Wx(r, k + 1), a2 = Wx(r, k + 2);
-      const double a3 = (nr == 3) ? Wx(r, k + 3) : 0.0;
-      const double w = tv * (a1 + v2 * a2 + v3 * a3);
-      Wx(r, k + 1) = a1 - w;
-      Wx(r, k + 2) = a2 - w * v2;
-      if (nr == 3) Wx(r, k + 3) = a3 - w * v3;
+      double y1[2], y2[2], y3[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int r = t + q * tpb;
+        if (r <= rl) {
+          y1[q] = Wx(r, k + 1); y2[q] = Wx(r, k + 2); y3[q] = (nr == 3) ? Wx(r, k + 3) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int r = t + q * tpb;
+        if (r > rl) continue;
+        const double w = h.tau * (y1[q] + h.v2 * y2[q] + h.v3 * y3[q]);
+        Wx(r, k + 1) = y1[q] - w;
+        Wx(r, k + 2) = y2[q] - w * h.v2;
+        if (nr == 3) Wx(r, k + 3) = y3[q] - w * h.v3;
+      }
+      // rows beyond two per thread (TPB = 32 only)
+      for (int r = t + 2 * tpb; r <= rl; r += tpb) {
+        const double a1 = Wx(r, k + 1), a2 = Wx(r, k + 2);
+        const double a3 = (nr == 3) ? Wx(r, k + 3) : 0.0;
+        const double w = h.tau * (a1 + h.v2 * a2 + h.v3 * a3);
+        Wx(r, k + 1) = a1 - w;
+        Wx(r, k + 2) = a2 - w * h.v2;
+        if (nr == 3) Wx(r, k + 3) = a3 - w * h.v3;
+      }
     }
+    wave_sync();
+    if (tau + 1 < d.tau1 && K + 1 != ktop - 1) form(tau + 1, K, nr, act, h);
+    else { K = ktop - 1 + tau + 1 - 3 * b; }
     __syncthreads();
   }
 
   // window back to HBM
-  for (int idx = tid; idx < ws * ws; idx += CHASE_THREADS) {
-    const int c = idx / ws, r = idx - c * ws;
-    a.H[(size_t)(p + r) + (size_t)(p + c) * a.ldh] = Wx(r, c);
+  {
+    const int r = tid & 127, c0 = tid >> 7;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int c = c0 + 8 * q;
+      if (r < ws && c < ws) a.H[(size_t)(p + r) + (size_t)(p + c) * a.ldh] = Wx(r, c);
+    }
   }
   __syncthreads();
 
-  // accumulate U = P_1 P_2 ... in LDS (the window space is free now)
-  for (int idx = tid; idx < ws * ws; idx += CHASE_THREADS) {
-    const int c = idx / ws, r = idx - c * ws;
-    Wx(r, c) = (r == c) ? 1.0 : 0.0;
+  // ---- accumulate U = P_1 P_2 ... ; row r by lanes j = 0..7 of its wave,
+  // lane j applying the reflectors of bulges j, j+8, j+16 of each chain step
+  {
+    const int r = tid >> 3, j = tid & 7;
+    if (r < ws)
+      for (int c = j; c < ws; c += 8) Wx(r, c) = (r == c) ? 1.0 : 0.0;
+    wave_sync();
+    for (int tau = d.tau0; tau < d.tau1; ++tau) {
+      int klead = ktop - 1 + tau;
+      if (klead > kbot - 2) klead = kbot - 2;
+      const bool rowact = (r < ws) && (r <= klead + 3 - p);
+      const double* rt = &R[3 * (tau - d.tau0) * nb];
+      if (rowact) {
+        double u1[3], u2[3], u3[3], tv[3], v2[3], v3[3];
+        int kk[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const int bb = j + 8 * q;
+          tv[q] = (bb < nb) ? rt[3 * bb + 2] : 0.0;
+          if (tv[q] != 0.0) {
+            v2[q] = rt[3 * bb];
+            v3[q] = rt[3 * bb + 1];
+            kk[q] = ktop - 1 + tau - 3 * bb - p;
+            const double* row = &Wx(r, kk[q] + 1);
+            u1[q] = row[0]; u2[q] = row[LDW]; u3[q] = row[2 * LDW];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          if (tv[q] == 0.0) continue;
+          const double w = tv[q] * (u1[q] + v2[q] * u2[q] + v3[q] * u3[q]);
+          double* row = &Wx(r, kk[q] + 1);
+          row[0] = u1[q] - w;
+          row[LDW] = u2[q] - w * v2[q];
+          row[2 * LDW] = u3[q] - w * v3[q];
+        }
+      }
+      wave_sync();
+    }
   }
   __syncthreads();
-  for (int tau = d.tau0; tau < d.tau1; ++tau) {
-    // rows below the leading bulge's reach are still zero in the touched columns
-    int klead = ktop - 1 + tau;
-    if (klead > kbot - 2) klead = kbot - 2;
-    int rmax = klead + 3 - p;
-    if (rmax > ws - 1) rmax = ws - 1;
-    const int nrow = rmax + 1;
-    const double* rt = refl + (size_t)(tau - d.tau0) * nb * 3;
-    for (int idx = tid; idx < nb * nrow; idx += CHASE_THREADS) {
-      const int b = idx / nrow, r = idx - b * nrow;
-      const double tv = rt[3 * b + 2];
-      if (tv == 0.0) continue;
-      const int K = ktop - 1 + tau - 3 * b;
-      const int k = K - p;
-      const int nr = (K <= kbot - 3) ? 3 : 2;
-      const double v2 = rt[3 * b], v3 = rt[3 * b + 1];
-      const double a1 = Wx(r, k + 1), a2 = Wx(r, k + 2);
-      const double a3 = (nr == 3) ? Wx(r, k + 3) : 0.0;
-      const double w = tv * (a1 + v2 * a2 + v3 * a3);
-      Wx(r, k + 1) = a1 - w;
-      Wx(r, k + 2) = a2 - w * v2;
-      if (nr == 3) Wx(r, k + 3) = a3 - w * v3;
-    }
-    __syncthreads();
-  }
   // U^T (column-major, ld UPAD, zero padded) -> the slot read by the panel kernels
-  double* Ut = a.U + (size_t)d.slot * UPAD * UPAD;
-  for (int idx = tid; idx < UPAD * UPAD; idx += CHASE_THREADS) {
-    const int c = idx / UPAD, r = idx - c * UPAD;   // Ut(r, c) = U(c, r)
-    Ut[idx] = (r < ws && c < ws) ? Wx(c, r) : 0.0;
+  double* Ut = d.U;
+  {
+    const int r = tid & 127, c0 = tid >> 7;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {   // Ut(r, c) = U(c, r)
+      const int c = c0 + 8 * q;
+      Ut[r + (size_t)c * UPAD] = (r < ws && c < ws) ? Wx(c, r) : 0.0;
+    }
   }
+}
+
+__global__ __launch_bounds__(CHASE_THREADS) void k_chase(SweepArgs a) {
+  chase_window(ctx_of(a, a.win[blockIdx.x]));
+}
+
+__global__ __launch_bounds__(CHASE_THREADS) void k_chase_b(const WinB* wins) {
+  chase_window(wins[blockIdx.x].c);
 }
 
 // ============================================================================
@@ -473,23 +607,31 @@ __device__ __forceinline__ int find_window(const SweepArgs& a, int bid, bool row
   return w;
 }
 
+// last window whose prefix is <= bid (zero-tile windows share the next prefix)
+__device__ __forceinline__ int find_window_b(const WinB* wins, int nwin, int bid, bool row) {
+  int lo = 0, hi = nwin - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int base = row ? wins[mid].base_r : wins[mid].base_cq;
+    if (base <= bid) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Y(ws x 64) = U^T X for one 64-column tile of a window's row panel, in place.
-__global__ __launch_bounds__(256) void k_panel_row(SweepArgs a) {
+__device__ void panel_row_tile(const WinCtx& d, int tile) {
   __shared__ double Xs[WMAX * LDT];   // row-major tile: Xs[c + r*LDT]
-  const int w = find_window(a, blockIdx.x, true);
-  const Win& d = a.win[w];
-  const int tile = blockIdx.x - d.base_r;
   const int p = d.p, ws = d.ws;
   const int c0 = p + ws + tile * PT;
-  const int nc = min(PT, a.cend - c0);
+  const int nc = min(PT, d.cend - c0);
   const int kpad = (ws + 3) & ~3;
-  const double* Ut = a.U + (size_t)d.slot * UPAD * UPAD;
+  const double* Ut = d.U;
   const int tid = threadIdx.x;
 
   for (int idx = tid; idx < kpad * PT; idx += 256) {
     const int c = idx / kpad, r = idx - c * kpad;
     double v = 0.0;
-    if (r < ws && c < nc) v = a.H[(size_t)(p + r) + (size_t)(c0 + c) * a.ldh];
+    if (r < ws && c < nc) v = d.H[(size_t)(p + r) + (size_t)(c0 + c) * d.ldh];
     Xs[c + r * LDT] = v;
   }
   __syncthreads();
@@ -517,29 +659,27 @@ __global__ __launch_bounds__(256) void k_panel_row(SweepArgs a) {
       if (col >= nc) continue;
       for (int e = 0; e < 4; ++e) {
         const int row = i0 + ib * 16 + lk + 4 * e;
-        if (row < ws) a.H[(size_t)(p + row) + (size_t)(c0 + col) * a.ldh] = acc[ib][jb][e];
+        if (row < ws) d.H[(size_t)(p + row) + (size_t)(c0 + col) * d.ldh] = acc[ib][jb][e];
       }
     }
 }
 
-// Y(64 x ws) = X U for one 64-row tile of a window's column panel or of Q.
-__global__ __launch_bounds__(256) void k_panel_colq(SweepArgs a) {
+// Y(64 x ws) = X U for one 64-row tile of a window's column panel (tile <
+// tiles_c) or of Q (the remaining tiles).
+__device__ void panel_colq_tile(const WinCtx& d, int tile, int tiles_c) {
   __shared__ double Xs[WMAX * LDT];   // column-major tile: Xs[r + c*LDT]
-  const int w = find_window(a, blockIdx.x, false);
-  const Win& d = a.win[w];
-  int tile = blockIdx.x - d.base_cq;
   const int p = d.p, ws = d.ws;
   double* M;
   int ld, r0, rend;
-  if (tile < d.tiles_c) {
-    M = a.H; ld = a.ldh; r0 = a.rtop + tile * PT; rend = p;
+  if (tile < tiles_c) {
+    M = d.H; ld = d.ldh; r0 = d.rtop + tile * PT; rend = p;
   } else {
-    tile -= d.tiles_c;
-    M = a.Q; ld = a.ldq; r0 = tile * PT; rend = a.n;
+    tile -= tiles_c;
+    M = d.Q; ld = d.ldq; r0 = tile * PT; rend = d.n;
   }
   const int nr = min(PT, rend - r0);
   const int kpad = (ws + 3) & ~3;
-  const double* Ut = a.U + (size_t)d.slot * UPAD * UPAD;
+  const double* Ut = d.U;
   const int tid = threadIdx.x;
 
   for (int idx = tid; idx < kpad * PT; idx += 256) {
@@ -576,6 +716,26 @@ __global__ __launch_bounds__(256) void k_panel_colq(SweepArgs a) {
         if (row < nr) M[(size_t)(r0 + row) + (size_t)(p + col) * ld] = acc[ib][jb][e];
       }
     }
+}
+
+__global__ __launch_bounds__(256) void k_panel_row(SweepArgs a) {
+  const int w = find_window(a, blockIdx.x, true);
+  panel_row_tile(ctx_of(a, a.win[w]), blockIdx.x - a.win[w].base_r);
+}
+
+__global__ __launch_bounds__(256) void k_panel_colq(SweepArgs a) {
+  const int w = find_window(a, blockIdx.x, false);
+  panel_colq_tile(ctx_of(a, a.win[w]), blockIdx.x - a.win[w].base_cq, a.win[w].tiles_c);
+}
+
+__global__ __launch_bounds__(256) void k_panel_row_b(const WinB* wins, int nwin) {
+  const int w = find_window_b(wins, nwin, blockIdx.x, true);
+  panel_row_tile(wins[w].c, blockIdx.x - wins[w].base_r);
+}
+
+__global__ __launch_bounds__(256) void k_panel_colq_b(const WinB* wins, int nwin) {
+  const int w = find_window_b(wins, nwin, blockIdx.x, false);
+  panel_colq_tile(wins[w].c, blockIdx.x - wins[w].base_cq, wins[w].tiles_c);
 }
 
 // ============================================================================
@@ -682,6 +842,104 @@ __global__ __launch_bounds__(DEFL_THREADS) void k_deflate(double* H, int ldh, in
       ctrl->ktop = (kb < klo) ? klo : kt;
       ctrl->ndefl = peeled;
     }
+  }
+}
+
+// ============================================================================
+// Batched deflation scan: one workgroup per matrix.  Negligible subdiagonal
+// entries of rows 1..kbot are set to zero; converged 1x1 and 2x2 blocks at
+// the bottom are peeled off at once: (wr, wi) are written, and each 2x2
+// block is standardised with its rotation applied to the rest of H and to Q.
+// ============================================================================
+constexpr int DB_WORDS = 2048;   // n <= 65536
+
+__global__ __launch_bounds__(256) void k_deflate_b(const DeflB* tasks) {
+  const DeflB T = tasks[blockIdx.x];
+  __shared__ unsigned bits[DB_WORDS];
+  __shared__ int s_kt;
+  const int tid = threadIdx.x;
+  double* H = T.H;
+  const int ldh = T.ldh, n = T.n;
+  int kbot = T.kbot;
+  if (kbot < 0) {
+    if (tid == 0) { T.out->kbot = -1; T.out->ktop = 0; }
+    return;
+  }
+  for (int wv = tid; wv <= (kbot >> 5); wv += 256) bits[wv] = 0u;
+  __syncthreads();
+  for (int k = 1 + tid; k <= kbot; k += 256) {
+    const double sub = fabs(H[k + (size_t)(k - 1) * ldh]);
+    double tst = fabs(H[(k - 1) + (size_t)(k - 1) * ldh]) + fabs(H[k + (size_t)k * ldh]);
+    if (tst == 0.0) {
+      tst = fabs(H[(k - 1) + (size_t)k * ldh]);
+      if (k >= 2) tst += fabs(H[(k - 1) + (size_t)(k - 2) * ldh]);
+      if (k + 1 <= kbot) tst += fabs(H[(k + 1) + (size_t)k * ldh]);
+    }
+    if (sub <= kUlp * tst) {
+      if (sub != 0.0) H[k + (size_t)(k - 1) * ldh] = 0.0;
+      atomicOr(&bits[k >> 5], 1u << (k & 31));
+    }
+  }
+  __syncthreads();
+  int kt = 0;
+  while (kbot >= 0) {
+    if (tid == 0) {
+      int f = 0;
+      for (int wv = kbot >> 5; wv >= 0; --wv) {
+        unsigned word = bits[wv];
+        if (wv == (kbot >> 5)) {
+          const int sh = kbot & 31;
+          word &= (sh == 31) ? 0xffffffffu : ((2u << sh) - 1u);
+        }
+        if (word) { f = wv * 32 + 31 - __builtin_clz(word); break; }
+      }
+      s_kt = f;
+    }
+    __syncthreads();
+    kt = s_kt;
+    const int m = kbot - kt + 1;
+    if (m == 1) {
+      if (tid == 0) { T.wr[kbot] = H[kbot + (size_t)kbot * ldh]; T.wi[kbot] = 0.0; }
+      kbot -= 1;
+    } else if (m == 2) {
+      const int i = kbot;
+      const Std2 o = standardize2(H[(i - 1) + (size_t)(i - 1) * ldh], H[(i - 1) + (size_t)i * ldh],
+                                  H[i + (size_t)(i - 1) * ldh], H[i + (size_t)i * ldh]);
+      if (!(o.cs == 1.0 && o.sn == 0.0)) {
+        for (int c = i + 1 + tid; c < n; c += 256) {
+          const double x = H[(i - 1) + (size_t)c * ldh], y = H[i + (size_t)c * ldh];
+          H[(i - 1) + (size_t)c * ldh] = o.cs * x + o.sn * y;
+          H[i + (size_t)c * ldh] = o.cs * y - o.sn * x;
+        }
+        for (int r = tid; r < i - 1; r += 256) {
+          const double x = H[r + (size_t)(i - 1) * ldh], y = H[r + (size_t)i * ldh];
+          H[r + (size_t)(i - 1) * ldh] = o.cs * x + o.sn * y;
+          H[r + (size_t)i * ldh] = o.cs * y - o.sn * x;
+        }
+        if (T.Q) {
+          for (int r = tid; r < n; r += 256) {
+            const double x = T.Q[r + (size_t)(i - 1) * T.ldq], y = T.Q[r + (size_t)i * T.ldq];
+            T.Q[r + (size_t)(i - 1) * T.ldq] = o.cs * x + o.sn * y;
+            T.Q[r + (size_t)i * T.ldq] = o.cs * y - o.sn * x;
+          }
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        H[(i - 1) + (size_t)(i - 1) * ldh] = o.a; H[(i - 1) + (size_t)i * ldh] = o.b;
+        H[i + (size_t)(i - 1) * ldh] = o.c;       H[i + (size_t)i * ldh] = o.d;
+        T.wr[i - 1] = o.wr1; T.wi[i - 1] = o.wi1;
+        T.wr[i] = o.wr2;     T.wi[i] = o.wi2;
+      }
+      kbot -= 2;
+    } else {
+      break;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    T.out->kbot = kbot;
+    T.out->ktop = (kbot < 0) ? 0 : kt;
   }
 }
 
@@ -815,6 +1073,40 @@ void launch_panel_row(const SweepArgs& a, int tiles, hipStream_t s) {
 
 void launch_panel_colq(const SweepArgs& a, int tiles, hipStream_t s) {
   if (tiles > 0) hipLaunchKernelGGL(k_panel_colq, dim3(tiles), dim3(256), 0, s, a);
+}
+
+void launch_small_tasks(const SmallTask* tasks, int count, int maxm, bool wantz, hipStream_t s) {
+  if (count <= 0) return;
+  SmallTask none{};
+  if (wantz) {
+    launch_small_z(none, tasks, count, maxm, s);
+  } else if (maxm <= 32) {
+    hipLaunchKernelGGL((k_small_eig<32>), dim3(count), dim3(64), 0, s, none, tasks);
+  } else if (maxm <= 64) {
+    hipLaunchKernelGGL((k_small_eig<64>), dim3(count), dim3(64), 0, s, none, tasks);
+  } else {
+    hipLaunchKernelGGL((k_small_eig<SMALL_EIG_MAX>), dim3(count), dim3(64), 0, s, none, tasks);
+  }
+}
+
+void launch_chase_b(const WinB* wins, int nwin, hipStream_t s) {
+  if (nwin > 0) hipLaunchKernelGGL(k_chase_b, dim3(nwin), dim3(CHASE_THREADS), 0, s, wins);
+}
+
+void launch_panel_row_b(const WinB* wins, int nwin, int tiles, hipStream_t s) {
+  if (tiles > 0) hipLaunchKernelGGL(k_panel_row_b, dim3(tiles), dim3(256), 0, s, wins, nwin);
+}
+
+void launch_panel_colq_b(const WinB* wins, int nwin, int tiles, hipStream_t s) {
+  if (tiles > 0) hipLaunchKernelGGL(k_panel_colq_b, dim3(tiles), dim3(256), 0, s, wins, nwin);
+}
+
+void launch_deflate_b(const DeflB* tasks, int count, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_deflate_b, dim3(count), dim3(256), 0, s, tasks);
+}
+
+void launch_shift_prep_b(const ShiftB* tasks, int count, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_shift_prep_b, dim3(count), dim3(256), 0, s, tasks);
 }
 
 void launch_check_finite(const double* H, int ldh, int n, Ctrl* ctrl, hipStream_t s) {

@@ -25,6 +25,7 @@ constexpr int UPAD = WMAX;         // leading dimension of the U slots
 constexpr int SMALL_Z_MAX = 96;    // block order solved in LDS with its Z
 constexpr int SMALL_EIG_MAX = 128; // block order solved in LDS, eigenvalues only
 constexpr int GEMM_T = 64;         // panel tile edge (rows or columns)
+constexpr int REFL_LDS = 1280;     // reflectors (chain step x bulge) logged in LDS per window
 
 // ---- one diagonal window of a sweep (a "window task") -----------------------
 struct Win {
@@ -53,6 +54,26 @@ struct SweepArgs {
   int refl_stride;          // doubles per reflector slot
   int nwin;
   Win win[MAXWIN];
+};
+
+// ---- everything one window task (and its panel tiles) needs ----------------
+struct WinCtx {
+  double* H;                // matrix, column-major
+  double* Q;                // Schur vectors or null
+  double* U;                // this window's U^T slot (UPAD x UPAD, zero padded)
+  const double* st;         // shift pairs of the window's group, first pair
+  int ldh, ldq, n;
+  int ktop, kbot;           // active block of the sweep
+  int rtop, cend;           // column-panel first row, row-panel end column
+  int p, ws, tau0, tau1, nb;
+};
+
+// ---- batched form: windows of many matrices in one launch ------------------
+struct WinB {
+  WinCtx c;
+  int tiles_r, tiles_c, tiles_q;
+  int base_r, base_cq;      // prefixes over the launch's windows (ascending)
+  int pad;
 };
 
 // ---- small control block kept in device memory ----------------------------

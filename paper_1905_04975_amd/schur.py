@@ -187,3 +187,38 @@ def reduce(H, Q=None, want_q=True, handle=None, stream=None):
                                    wi.data_ptr())
     w = torch.complex(wr[:n], wi[:n])
     return S, Qm, w, info
+
+
+def reduce_batched(Hs, want_q=True, handle=None, stream=None):
+    """Batched Schur reduction of a list of column-major float64 CUDA tensors.
+
+    Each ``H`` is overwritten by its Schur form when it is column-major
+    (otherwise a column-major copy is used).  Returns ``(Ss, Qs, ws, infos,
+    rc)``.  Argument marshalling only: all matrices go to one
+    ``schur_reduce_batched`` call.
+    """
+    import torch
+
+    if handle is None:
+        handle = Handle(Hs[0].device.index or 0) if Hs else Handle(0)
+    Ss, lds, Qs, ldqs, wrs, wis = [], [], [], [], [], []
+    for H in Hs:
+        S, ld = _colmajor(H)
+        n = S.shape[0]
+        Ss.append(S)
+        lds.append(max(1, ld))
+        if want_q:
+            Qm = torch.eye(n, dtype=torch.float64, device=S.device).t()
+            Qm, ldq = _colmajor(Qm)
+            Qs.append(Qm)
+            ldqs.append(max(1, ldq))
+        wrs.append(torch.empty(max(n, 1), dtype=torch.float64, device=S.device))
+        wis.append(torch.empty(max(n, 1), dtype=torch.float64, device=S.device))
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    rc, infos = handle.reduce_batched(
+        stream, [S.shape[0] for S in Ss], [S.data_ptr() for S in Ss], lds,
+        [Q.data_ptr() for Q in Qs] if want_q else None, ldqs if want_q else None,
+        [w.data_ptr() for w in wrs], [w.data_ptr() for w in wis])
+    ws = [torch.complex(wr[:S.shape[0]], wi[:S.shape[0]]) for wr, wi, S in zip(wrs, wis, Ss)]
+    return Ss, (Qs if want_q else None), ws, infos, rc

@@ -1,0 +1,106 @@
+"""Batched Schur reduction: many matrices of uneven orders in one call.
+
+Each matrix of the batch must meet the same bar as a solo solve (backward
+error, orthogonality, structure, eigenvalues against the oracle), and its
+eigenvalues must agree with the solo solve of the same matrix.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_04975_amd import inputs
+from tests import checks
+
+pytestmark = pytest.mark.gpu
+
+
+def _to_dev(H):
+    import torch
+
+    return torch.from_numpy(np.asfortranarray(H)).to("cuda:0")
+
+
+def test_batched_mixed_sizes(gpu_lib):
+    import torch
+
+    sizes = [1, 2, 3, 5, 31, 32, 33, 64, 65, 95, 96, 97, 130, 200, 257, 300, 512]
+    rng = np.random.default_rng(4)
+    sizes += list(rng.integers(32, 400, size=23))
+    print("case batched %d matrices, orders %d..%d" % (len(sizes), min(sizes), max(sizes)),
+          flush=True)
+    mats = [inputs.hessenberg_normal(int(n), 40000 + i) for i, n in enumerate(sizes)]
+    h = gpu_lib.Handle(0)
+    Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(H) for H in mats], handle=h)
+    torch.cuda.synchronize()
+    st = h.stats()
+    assert rc == 0 and all(i == 0 for i in infos), infos
+    assert st["small_solves"] > 0 and st["windows"] > 0
+    for H, S, Q, w in zip(mats, Ss, Qs, ws):
+        S, Q, w = S.cpu().numpy(), Q.cpu().numpy(), w.cpu().numpy()
+        n = H.shape[0]
+        assert checks.structure_errors(S, w.real, w.imag) == [], n
+        assert checks.residual(H, Q, S) <= 1e-12, n
+        assert checks.orthogonality(Q) <= 1e-12, n
+        _, _, wr, wi, oinfo, _ = oracle.schur(H)
+        assert oinfo == 0
+        wref, kappa = checks.eig_condition(H)
+        from scipy.optimize import linear_sum_assignment
+        cost = np.abs(w[:, None] - wref[None, :])
+        r, c = linear_sum_assignment(cost)
+        assert np.all(cost[r, c] <= checks.kappa_tolerance(H, wref[c], kappa[c], factor=100.0)), n
+        assert checks.match_eigs(w, wr + 1j * wi).max() <= 1e-9 * max(1.0, np.linalg.norm(H)), n
+    h.close()
+
+
+def test_batched_equals_solo(gpu_lib):
+    """Batched and solo solves of the same matrices give the same eigenvalues
+    (to rounding) and both meet the accuracy bar."""
+    import torch
+
+    sizes = [40, 150, 333, 96, 700]
+    mats = [inputs.hessenberg_normal(n, 777 + n) for n in sizes]
+    print("case batched vs solo", flush=True)
+    h = gpu_lib.Handle(0)
+    Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(H) for H in mats], handle=h)
+    assert rc == 0
+    for H, wb in zip(mats, ws):
+        Hd = _to_dev(H)
+        S, Q, w, info = gpu_lib.reduce(Hd, handle=h)
+        torch.cuda.synchronize()
+        assert info == 0
+        d = checks.match_eigs(wb.cpu().numpy(), w.cpu().numpy())
+        assert d.max() <= 1e-10 * np.linalg.norm(H)
+    h.close()
+
+
+def test_batched_prescribed_and_no_q(gpu_lib):
+    import torch
+
+    print("case batched prescribed, no Q", flush=True)
+    cases = [inputs.prescribed(n, 60 + n) for n in (48, 120, 256, 410)]
+    h = gpu_lib.Handle(0)
+    Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(H) for H, _ in cases], want_q=False,
+                                                    handle=h)
+    torch.cuda.synchronize()
+    assert rc == 0 and Qs is None
+    for (H, exact), S, w in zip(cases, Ss, ws):
+        w = w.cpu().numpy()
+        assert checks.structure_errors(S.cpu().numpy(), w.real, w.imag) == []
+        assert np.all(checks.match_eigs(w, exact) <= checks.eig_rel_tol(exact, H, 1e-9))
+    h.close()
+
+
+def test_batched_bad_member_reported(gpu_lib):
+    import torch
+
+    print("case batched with a non-finite member", flush=True)
+    good = inputs.hessenberg_normal(50, 1)
+    bad = inputs.hessenberg_normal(60, 2)
+    bad[5, 7] = np.inf
+    h = gpu_lib.Handle(0)
+    Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(good), _to_dev(bad)], handle=h)
+    torch.cuda.synchronize()
+    assert infos[0] == 0 and infos[1] == -2 and rc == -2
+    S = Ss[0].cpu().numpy()
+    assert checks.residual(good, Qs[0].cpu().numpy(), S) <= 1e-12
+    h.close()
