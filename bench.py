@@ -45,6 +45,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle sample")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--workload", choices=["n16384", "batch", "serve"], default="n16384")
+    ap.add_argument("--count", type=int, default=2000, help="batch: number of matrices")
+    ap.add_argument("--plain-sample", type=int, default=60,
+                    help="batch/serve: requests timed with per-matrix plain launches")
+    ap.add_argument("--requests", type=int, default=240, help="serve: requests (first 10%% warm-up)")
+    ap.add_argument("--rate", type=float, default=0.0, help="serve: arrivals/s (0: 0.7 x saturation)")
+    ap.add_argument("--budget-gb", type=float, default=64.0)
     return ap.parse_args()
 
 
@@ -97,8 +104,181 @@ def oracle_sample(H_np, budget_s):
     }
 
 
+def bench_batch(args):
+    """Batched solves: 2000 random Hessenberg matrices, orders U{32..512}."""
+    import numpy as np
+    import torch
+
+    from paper_1905_04975_amd import inputs, schur
+
+    dev = torch.device("cuda:0")
+    sizes = inputs.batch_sizes(args.count, 32, 512, inputs.SEED_BATCH_SIZES)
+    mats = [inputs.hessenberg_normal(int(n), inputs.SEED_BATCH_BASE + i) for i, n in enumerate(sizes)]
+    H0 = [torch.from_numpy(H).to(dev) for H in mats]
+    h = schur.Handle(0)
+
+    def run_batch():
+        Hs = [H.clone() for H in H0]
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        Ss, Qs, ws, infos, rc = schur.reduce_batched(Hs, handle=h)
+        torch.cuda.synchronize(dev)
+        t = time.perf_counter() - t0
+        if rc != 0:
+            raise RuntimeError("batched solve failed: %d" % rc)
+        return t, Ss, Qs
+
+    for _ in range(args.warmup):
+        run_batch()
+    times = []
+    for _ in range(args.steps):
+        t, Ss, Qs = run_batch()
+        times.append(t)
+        print("batch step: %.3f s" % t, file=sys.stderr, flush=True)
+    st = h.stats()
+    # accuracy of a sample of the batch (checker)
+    worst_res = worst_orth = 0.0
+    for i in range(0, args.count, max(1, args.count // 50)):
+        Hh = torch.triu(H0[i], -1)
+        S, Q = Ss[i], Qs[i]
+        n = Hh.shape[0]
+        r = (torch.linalg.norm(Hh - Q @ S @ Q.t()) / torch.linalg.norm(Hh)).item()
+        o = torch.linalg.norm(Q.t() @ Q - torch.eye(n, dtype=torch.float64, device=dev)).item()
+        worst_res, worst_orth = max(worst_res, r), max(worst_orth, o)
+    # per-matrix plain launches (one schur_reduce per matrix) on a sample
+    k = min(args.plain_sample, args.count)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for i in range(k):
+        H = H0[i].clone()
+        S, Q, w, info = schur.reduce(H, handle=h)
+    torch.cuda.synchronize(dev)
+    tp = time.perf_counter() - t0
+    cost = sum(int(n) ** 3 for n in sizes)
+    cost_k = sum(int(n) ** 3 for n in sizes[:k])
+    plain_rate = k / tp
+    plain_scaled = args.count / (tp * cost / cost_k)
+    t = sum(times) / len(times)
+    out = {
+        "metric": "batched solves/s (2000 random Hessenberg, orders U{32..512})",
+        "value": args.count / t, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "schur_batched_random_hessenberg", "count": args.count,
+                   "orders": "U{32..512}", "seed_sizes": inputs.SEED_BATCH_SIZES,
+                   "schur_vectors": True},
+        "plain_launches": {"sample": k, "solves_per_s_sample": plain_rate,
+                           "solves_per_s_cost_scaled": plain_scaled,
+                           "speedup_cost_scaled": (args.count / t) / plain_scaled},
+        "check": {"max_residual": worst_res, "max_orthogonality": worst_orth},
+        "stats": {k2: st[k2] for k2 in ("sweeps", "windows", "launches", "small_solves")},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Serving loop: Poisson arrivals, orders log-uniform in [64, 4096]."""
+    import numpy as np
+
+    from paper_1905_04975_amd import inputs, schur
+
+    rng = np.random.Generator(np.random.PCG64(inputs.SEED_SERVE))
+    pool = []
+    for i in range(48):   # pre-generated request pool, reused round-robin
+        r2 = np.random.Generator(np.random.PCG64(inputs.SEED_SERVE_BASE + i))
+        n = int(round(np.exp(r2.uniform(np.log(64), np.log(4096)))))
+        if i % 2 == 0:
+            pool.append(inputs.hessenberg_normal(n, inputs.SEED_SERVE_BASE + i))
+        else:
+            pool.append(inputs.prescribed(n, inputs.SEED_SERVE_BASE + i)[0])
+    srv = schur.Server(0, budget_bytes=int(args.budget_gb * (1 << 30)))
+
+    def drain(pending, done, t_end=None):
+        for tk in list(pending):
+            r = srv.poll(tk, pending[tk][0])
+            if r is not None:
+                done[tk] = (pending[tk][1], r[3], r[4])
+                del pending[tk]
+
+    # saturation: submit a block of requests at once
+    if args.rate <= 0:
+        pending, done = {}, {}
+        t0 = time.perf_counter()
+        for i in range(24):
+            tk, n = srv.submit(pool[i % len(pool)])
+            pending[tk] = (n, i)
+        while pending:
+            drain(pending, done)
+            time.sleep(0.001)
+        mu = 24 / (time.perf_counter() - t0)
+        rate = 0.7 * mu
+    else:
+        mu, rate = None, args.rate
+    gaps = rng.exponential(1.0 / rate, size=args.requests)
+    arrivals = np.cumsum(gaps)
+    pending, done = {}, {}
+    t0 = time.perf_counter()
+    for i in range(args.requests):
+        while time.perf_counter() - t0 < arrivals[i]:
+            drain(pending, done)
+            time.sleep(0.0005)
+        tk, n = srv.submit(pool[i % len(pool)])
+        pending[tk] = (n, i)
+    while pending:
+        drain(pending, done)
+        time.sleep(0.001)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    warm = args.requests // 10
+    lat = np.array(sorted(v[2] for v in done.values() if v[0] >= warm))
+    infos = [v[1] for v in done.values()]
+    # FIFO plain launches on the same arrivals (sample): one request at a time
+    import torch
+
+    k = min(args.plain_sample, args.requests)
+    h = schur.Handle(0)
+    dev = torch.device("cuda:0")
+    t_free = 0.0
+    lat_plain = []
+    tp0 = time.perf_counter()
+    for i in range(k):
+        H = pool[i % len(pool)]
+        start = max(arrivals[i], t_free)
+        s0 = time.perf_counter()
+        Hd = torch.from_numpy(np.asfortranarray(H)).to(dev)
+        S, Q, w, info = schur.reduce(Hd, handle=h)
+        S.cpu(); Q.cpu(); w.cpu()
+        svc = time.perf_counter() - s0
+        t_free = start + svc
+        lat_plain.append(t_free - arrivals[i])
+    lat_plain = np.array(sorted(lat_plain))
+    out = {
+        "metric": "served solves/s and p50/p99 latency (Poisson arrivals, orders log-uniform [64, 4096])",
+        "value": args.requests / wall, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * wall, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "schur_serving_mix", "requests": args.requests,
+                   "rate_per_s": rate, "saturation_per_s": mu, "budget_gb": args.budget_gb,
+                   "mix": "half random N(0,1), half prescribed spectrum"},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "mean": float(lat.mean())},
+        "fifo_plain_launches": {"sample": k,
+                                "p50": float(np.percentile(lat_plain, 50)),
+                                "p99": float(np.percentile(lat_plain, 99)),
+                                "solves_per_s": k / max(t_free, 1e-9)},
+        "all_info_zero": all(i == 0 for i in infos),
+        "server": st,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)

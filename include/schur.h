@@ -145,6 +145,62 @@ int schur_reduce_batched(schur_handle_t h, void* stream, int count, const int* n
                          double* const* H, const int* ldh, double* const* Q, const int* ldq,
                          double* const* wr, double* const* wi, int* info);
 
+/* --------------------------------------------------------------------------
+ * Tuning table (written by the autotuner).  For a matrix (or active block)
+ * of order n, the first entry with n <= nmax[i] supplies the shifts per
+ * sweep, bulges per window chain and chain steps per window (0 = largest
+ * that fits) whenever the handle's options leave them 0.  Process-wide;
+ * count = 0 restores the built-in table.  Host-only, no device work.
+ * ------------------------------------------------------------------------ */
+int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, const int* step);
+
+/* --------------------------------------------------------------------------
+ * Sweep schedule (host-only diagnostic of the planner, no device work):
+ * the lock-step window plan of one sweep over the active block
+ * [ktop, kbot] (0-based) with npair bulges in groups of at most nb and at
+ * most `step` chain steps per window (0 = largest that fits).  Writes up to
+ * `cap` records of 7 ints (time step, group, first row p, order ws, first
+ * and one-past-last chain step, bulges) to `out`; returns the number of
+ * windows (which may exceed cap), or a negative value on bad arguments.
+ * ------------------------------------------------------------------------ */
+int schur_plan_sweep(int ktop, int kbot, int npair, int nb, int step, int* out, int cap);
+
+/* --------------------------------------------------------------------------
+ * Serving loop (continuous batching).  A server owns a device handle and a
+ * background thread.  Requests (HOST matrices) queue FIFO; between rounds of
+ * the batched engine (one sweep per resident matrix per round) the thread
+ * admits queued requests while the device bytes of the resident ones (H, Q,
+ * wr, wi) stay within `hbm_budget_bytes`, so requests that arrive while
+ * others are on the GPU join the next round.  Finished results are copied
+ * to pinned host memory; latency = submit to results on the host.
+ * ------------------------------------------------------------------------ */
+typedef struct schur_server_s* schur_server_t;
+
+typedef struct schur_server_stats {
+  int64_t submitted, completed, rounds;
+  int64_t resident, queued, peak_resident;
+  double bytes_in_use, peak_bytes;
+  double reserved[4];
+} schur_server_stats;
+
+/* opts may be NULL; budget 0 = 64 GiB. */
+int schur_server_create(schur_server_t* srv, int device, size_t hbm_budget_bytes,
+                        const schur_opts* opts);
+/* Finishes queued and resident requests, then stops the thread and frees. */
+int schur_server_destroy(schur_server_t srv);
+/* H_host: HOST, column-major ldh x n (copied before return).  want_q != 0
+ * returns Schur vectors.  *ticket identifies the request.  A request whose
+ * device bytes exceed the whole budget completes with info -101. */
+int schur_submit(schur_server_t srv, int n, const double* H_host, int ldh, int want_q,
+                 uint64_t* ticket);
+/* Returns 1 while the request is not done.  When done (return 0) copies S
+ * (HOST, lds >= n), Q (HOST, ldq >= n; ignored when NULL or not requested),
+ * wr/wi (HOST, n each; may be NULL), *info and *latency_s (may be NULL),
+ * and forgets the ticket.  Unknown ticket: -2. */
+int schur_poll(schur_server_t srv, uint64_t ticket, double* S_host, int lds, double* Q_host,
+               int ldq, double* wr, double* wi, int* info, double* latency_s);
+int schur_server_get_stats(schur_server_t srv, schur_server_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,16 +21,19 @@ __device__ __forceinline__ Refl make_reflector(int nr, double x, double y, doubl
     h.v2 = 0.0; h.v3 = 0.0; h.tau = 0.0; h.beta = x;
     return h;
   }
-  const double sc = fabs(x) + tail;           // scaling keeps the squares finite
-  const double isc = 1.0 / sc;
-  const double xs = x * isc, ys = y * isc, zs = z * isc;
-  const double len = sc * sqrt(xs * xs + ys * ys + zs * zs);
-  const double beta = (x < 0.0) ? len : -len;
-  const double den = 1.0 / (x - beta);
-  h.beta = beta;
-  h.tau = (beta - x) / beta;
-  h.v2 = y * den;
-  h.v3 = z * den;
+  // exact power-of-two scaling (no division) keeps every square and product
+  // below in range; the scaled quantities are O(1)
+  const int e = ilogb(fabs(x) + tail);
+  const double xs = ldexp(x, -e), ys = ldexp(y, -e), zs = ldexp(z, -e);
+  const double ls = sqrt(xs * xs + ys * ys + zs * zs);
+  const double bs = (xs < 0.0) ? ls : -ls;     // beta / 2^e
+  const double ds = xs - bs;                   // (x - beta) / 2^e
+  // one reciprocal r = 1 / (bs ds) gives 1/beta and 1/(x - beta)
+  const double r = 1.0 / (bs * ds);
+  h.beta = ldexp(bs, e);
+  h.tau = -ds * (ds * r);                      // (beta - x) / beta
+  h.v2 = ys * (bs * r);                        // y / (x - beta)
+  h.v3 = zs * (bs * r);
   return h;
 }
 

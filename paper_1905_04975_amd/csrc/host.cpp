@@ -23,7 +23,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/schur.h"
@@ -136,12 +141,22 @@ bool is_device_ptr(const void* p) {
   return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
 }
 
-// ---- defaults ------------------------------------------------------------
-int default_ns(int n) {
-  if (n < 300) return 2;       // plain Francis double-shift steps
-  if (n < 3000) return 32;
-  if (n < 6000) return 64;
-  return 128;
+// ---- defaults and the tuning table -----------------------------------------
+struct TuneRow {
+  int nmax, ns, nb, step;
+};
+// built-in table: plain double-shift sweeps for small orders, then more
+// shifts per sweep as the order grows
+const TuneRow kBuiltinTune[] = {
+    {299, 2, 1, 0}, {2999, 32, 16, 0}, {5999, 64, 16, 0}, {1 << 30, 128, 16, 0}};
+std::mutex g_tune_mu;
+std::vector<TuneRow> g_tune(std::begin(kBuiltinTune), std::end(kBuiltinTune));
+
+TuneRow tune_for(int n) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const TuneRow& r : g_tune)
+    if (n <= r.nmax) return r;
+  return g_tune.back();
 }
 
 struct Params {
@@ -151,12 +166,13 @@ struct Params {
 
 Params resolve(const schur_opts& o, int n) {
   Params p;
-  p.ns = o.ns > 0 ? (o.ns & ~1) : default_ns(n);
+  const TuneRow tr = tune_for(n);
+  p.ns = o.ns > 0 ? (o.ns & ~1) : tr.ns;
   if (p.ns < 2) p.ns = 2;
   if (p.ns > SMALL_EIG_MAX) p.ns = SMALL_EIG_MAX;
-  p.nb = o.nb > 0 ? o.nb : 16;
+  p.nb = o.nb > 0 ? o.nb : (tr.nb > 0 ? tr.nb : 16);
   if (p.nb > NBMAX) p.nb = NBMAX;
-  p.step = o.step;
+  p.step = o.step > 0 ? o.step : tr.step;
   p.nmin = o.nmin > 0 ? std::min(o.nmin, SMALL_Z_MAX) : SMALL_Z_MAX;
   p.max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30 * std::max(10, n) / std::max(2, p.ns) + 100;
   p.exc_period = o.exc_period > 0 ? o.exc_period : 6;
@@ -600,27 +616,34 @@ int solve(schur_handle_s* h, hipStream_t s, int n, double* H, int ldh, double* Q
 }
 
 // ---------------------------------------------------------------------------
-// Batched solver: independent matrices advance in rounds.  A round is one
+// Batched engine: independent matrices advance in rounds.  A round is one
 // batched deflation scan (one workgroup per matrix, with converged bottom
 // blocks peeled and standardised at once), one batched small-block solve
 // for the matrices whose active block is small, one batched shift solve, and
 // one sweep for every other matrix -- the sweeps' time steps are merged so
 // that each launch carries the windows (or panel tiles) of all matrices.
+// Matrices can be added between rounds (continuous batching); each matrix
+// owns a fixed slot (control block and shift buffers) until it retires.
 // ---------------------------------------------------------------------------
-struct BatchSolver {
-  schur_handle_s* h;
-  hipStream_t s;
-  int count;
+struct BatchEngine {
+  schur_handle_s* h = nullptr;
+  hipStream_t s = nullptr;
+  int cap = 0;                       // slots
   struct Mat {
-    int n, ldh, ldq;
-    double *H, *Q, *wr, *wi;
-    int kbot, ktop, info, nodefl;
-    int last_small_top;   // ktop of the last small-block solve (-1: none)
-    int64_t sweeps;
-    bool active;
-    Params P;
+    int n = 0, ldh = 1, ldq = 1;
+    double *H = nullptr, *Q = nullptr, *wr = nullptr, *wi = nullptr;
+    int kbot = -1, ktop = 0, info = 0, nodefl = 0;
+    int last_small_top = -1;         // ktop of the last small-block solve (-1: none)
+    int64_t sweeps = 0;
+    bool used = false, active = false, checked = false;
+    Params P{};
+    uint64_t tag = 0;
   };
   std::vector<Mat> M;
+  Ctrl* ctrl_d = nullptr;
+  Ctrl* ctrl_h = nullptr;
+  double* shbuf = nullptr;
+  int64_t rounds = 0;
 
   template <class T>
   T* dev_of(schur_handle_s::Grow& g) { return (T*)g.dev; }
@@ -631,245 +654,290 @@ struct BatchSolver {
     if (bytes) HCHECK(hipMemcpyAsync(g.dev, g.host, bytes, hipMemcpyHostToDevice, s));
   }
 
-  int run() {
-    const int nm = count;
-    grow(h->b_ctrl, sizeof(Ctrl) * nm, true);
-    grow(h->b_defl, sizeof(DeflB) * nm, true);
-    grow(h->b_sh, sizeof(double) * 3 * SMALL_EIG_MAX * (size_t)nm, false);
-    Ctrl* ctrl_d = dev_of<Ctrl>(h->b_ctrl);
-    Ctrl* ctrl_h = host_of<Ctrl>(h->b_ctrl);
-    double* shbuf = dev_of<double>(h->b_sh);
-    // input check, then zero below the subdiagonal
-    {
-      HCHECK(hipMemsetAsync(ctrl_d, 0, sizeof(Ctrl) * nm, s));
-      for (int i = 0; i < nm; ++i)
-        if (M[i].active) launch_check_finite(M[i].H, M[i].ldh, M[i].n, ctrl_d + i, s);
-      HCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl) * nm, hipMemcpyDeviceToHost, s));
-      HCHECK(hipStreamSynchronize(s));
-      for (int i = 0; i < nm; ++i) {
-        if (!M[i].active) continue;
-        if (ctrl_h[i].bad) { M[i].info = -2; M[i].active = false; continue; }
-        launch_zero_lower(M[i].H, M[i].ldh, M[i].n, s);
-      }
-      HCHECK(hipMemsetAsync(ctrl_d, 0, sizeof(Ctrl) * nm, s));
+  void init(schur_handle_s* hh, hipStream_t ss, int slots) {
+    h = hh;
+    s = ss;
+    cap = slots;
+    M.assign(slots, Mat{});
+    grow(h->b_ctrl, sizeof(Ctrl) * slots, true);
+    grow(h->b_defl, sizeof(DeflB) * slots, true);
+    grow(h->b_sh, sizeof(double) * 3 * SMALL_EIG_MAX * (size_t)slots, false);
+    ctrl_d = dev_of<Ctrl>(h->b_ctrl);
+    ctrl_h = host_of<Ctrl>(h->b_ctrl);
+    shbuf = dev_of<double>(h->b_sh);
+    HCHECK(hipMemsetAsync(ctrl_d, 0, sizeof(Ctrl) * slots, s));
+    rounds = 0;
+  }
+
+  int free_slot() const {
+    for (int i = 0; i < cap; ++i) if (!M[i].used) return i;
+    return -1;
+  }
+
+  // Register a matrix in slot i (device buffers owned by the caller).  The
+  // input check runs with the next round.
+  void add(int i, int n, double* H, int ldh, double* Q, int ldq, double* wr, double* wi,
+           uint64_t tag) {
+    Mat& m = M[i];
+    m = Mat{};
+    m.used = true;
+    m.n = n; m.H = H; m.ldh = ldh; m.Q = Q; m.ldq = Q ? ldq : 1; m.wr = wr; m.wi = wi;
+    m.tag = tag;
+    m.info = 0;
+    m.active = n > 0;
+    m.kbot = n - 1;
+    m.P = resolve(h->opts, std::max(1, n));
+    HCHECK(hipMemsetAsync(ctrl_d + i, 0, sizeof(Ctrl), s));
+  }
+
+  void release(int i) { M[i] = Mat{}; }
+
+  bool any_active() const {
+    for (const Mat& m : M) if (m.used && m.active) return true;
+    return false;
+  }
+
+  // input check (non-finite entries -> info -2) and zeroing below the
+  // subdiagonal for matrices added since the last round
+  void check_new() {
+    bool any = false;
+    for (int i = 0; i < cap; ++i) {
+      Mat& m = M[i];
+      if (!m.used || !m.active || m.checked) continue;
+      launch_check_finite(m.H, m.ldh, m.n, ctrl_d + i, s);
+      any = true;
     }
+    if (!any) return;
+    HCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl) * cap, hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    for (int i = 0; i < cap; ++i) {
+      Mat& m = M[i];
+      if (!m.used || !m.active || m.checked) continue;
+      m.checked = true;
+      if (ctrl_h[i].bad) { m.info = -2; m.active = false; continue; }
+      launch_zero_lower(m.H, m.ldh, m.n, s);
+    }
+  }
+
+  // One round.  Afterwards, matrices with used && !active are finished
+  // (info set) once the stream has drained; the caller retires them.
+  void round() {
+    check_new();
+    if (++rounds > (int64_t)1 << 40) throw HipErr{hipErrorUnknown};
     std::vector<int> idx;
-    int64_t rounds = 0, round_cap = 0;
-    for (int i = 0; i < nm; ++i)
-      round_cap = std::max<int64_t>(round_cap, M[i].P.max_sweeps + M[i].n + 16);
-    while (true) {
-      if (++rounds > round_cap) throw HipErr{hipErrorUnknown};   // no progress: report, never spin
-      // ---- deflation scan of every active matrix
-      idx.clear();
-      for (int i = 0; i < nm; ++i) if (M[i].active) idx.push_back(i);
-      if (idx.empty()) break;
-      DeflB* dh = host_of<DeflB>(h->b_defl);
-      for (size_t q = 0; q < idx.size(); ++q) {
-        Mat& m = M[idx[q]];
-        dh[q] = DeflB{m.H, m.Q, m.wr, m.wi, m.ldh, m.ldq, m.n, m.kbot, ctrl_d + idx[q]};
+    for (int i = 0; i < cap; ++i) if (M[i].used && M[i].active) idx.push_back(i);
+    if (idx.empty()) return;
+    // ---- deflation scan of every active matrix
+    DeflB* dh = host_of<DeflB>(h->b_defl);
+    for (size_t q = 0; q < idx.size(); ++q) {
+      Mat& m = M[idx[q]];
+      dh[q] = DeflB{m.H, m.Q, m.wr, m.wi, m.ldh, m.ldq, m.n, m.kbot, ctrl_d + idx[q]};
+    }
+    upload(h->b_defl, sizeof(DeflB) * idx.size());
+    launch_deflate_b(dev_of<DeflB>(h->b_defl), (int)idx.size(), s);
+    HCHECK(hipGetLastError());
+    h->stats.launches += 1;
+    HCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl) * cap, hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    // ---- classify
+    std::vector<int> small, big;
+    for (int i : idx) {
+      Mat& m = M[i];
+      if (ctrl_h[i].small_info != 0) {       // the last small-block solve failed
+        m.info = m.last_small_top + ctrl_h[i].small_info;
+        m.active = false;
+        continue;
       }
-      upload(h->b_defl, sizeof(DeflB) * idx.size());
-      launch_deflate_b(dev_of<DeflB>(h->b_defl), (int)idx.size(), s);
+      const int nk = ctrl_h[i].kbot;
+      if (nk < m.kbot) m.nodefl = 0;
+      m.kbot = nk;
+      m.ktop = ctrl_h[i].ktop;
+      if (m.kbot < 0) { m.active = false; continue; }
+      const int len = m.kbot - m.ktop + 1;
+      if (len <= m.P.nmin) small.push_back(i);
+      else if (++m.sweeps > m.P.max_sweeps) { m.info = m.kbot + 1; m.active = false; }
+      else big.push_back(i);
+    }
+    if (small.empty() && big.empty()) return;
+    // U slots: one per small block, and one per window of the widest time step
+    std::vector<std::vector<std::vector<WinPlan>>> plans(big.size());
+    std::vector<int> nsv(big.size());
+    size_t maxw = 0, tmax = 0;
+    for (size_t q = 0; q < big.size(); ++q) {
+      Mat& m = M[big[q]];
+      const int len = m.kbot - m.ktop + 1;
+      int ns = std::min(m.P.ns, 2 * ((len - 2) / 6));
+      if (ns < 2) ns = 2;
+      nsv[q] = ns;
+      int step = 0;
+      plan_sweep(m.ktop, m.kbot, ns / 2, m.P.nb, m.P.step, plans[q], step);
+      tmax = std::max(tmax, plans[q].size());
+    }
+    std::vector<size_t> per_t(tmax, 0);
+    for (size_t q = 0; q < big.size(); ++q)
+      for (size_t t = 0; t < plans[q].size(); ++t) per_t[t] += plans[q][t].size();
+    for (size_t t = 0; t < tmax; ++t) maxw = std::max(maxw, per_t[t]);
+    const size_t nslots = std::max(maxw, small.size());
+    double* Ubase =
+        (double*)grow(h->b_u, sizeof(double) * UPAD * UPAD * std::max<size_t>(1, nslots), false);
+    // ---- small blocks: one workgroup each; whole small matrices accumulate Q
+    // in the kernel, blocks of larger matrices apply Z as panel products
+    if (!small.empty()) {
+      grow(h->b_small, sizeof(SmallTask) * small.size(), true);
+      grow(h->b_win, sizeof(WinB) * small.size(), true);
+      SmallTask* th = host_of<SmallTask>(h->b_small);
+      WinB* wh = host_of<WinB>(h->b_win);
+      int nwin = 0, tr = 0, tcq = 0;
+      int maxm = 0;
+      for (size_t q = 0; q < small.size(); ++q) {
+        Mat& m = M[small[q]];
+        const int len = m.kbot - m.ktop + 1;
+        maxm = std::max(maxm, len);
+        const bool whole = (m.ktop == 0 && m.kbot == m.n - 1);
+        m.last_small_top = m.ktop;
+        SmallTask t{};
+        t.A = m.H + m.ktop + (size_t)m.ktop * m.ldh;
+        t.lda = m.ldh;
+        t.m = len;
+        t.wr = m.wr + m.ktop;
+        t.wi = m.wi + m.ktop;
+        t.info = &ctrl_d[small[q]].small_info;
+        t.itmax = 30;
+        double* slot = Ubase + (size_t)q * UPAD * UPAD;
+        if (whole) {
+          t.Qacc = m.Q;
+          t.ldqacc = m.ldq;
+        } else {
+          t.Zt = slot;
+          t.ldzt = UPAD;
+          WinB& w = wh[nwin++];
+          std::memset(&w, 0, sizeof(w));
+          w.c.H = m.H; w.c.Q = m.Q; w.c.U = slot; w.c.st = nullptr;
+          w.c.ldh = m.ldh; w.c.ldq = m.ldq; w.c.n = m.n;
+          w.c.ktop = m.ktop; w.c.kbot = m.kbot; w.c.rtop = 0; w.c.cend = m.n;
+          w.c.p = m.ktop; w.c.ws = len;
+          fill_tiles(w, tr, tcq);
+        }
+        th[q] = t;
+        m.kbot = m.ktop - 1;     // the block is finished by this round's launches
+        if (m.kbot < 0) m.active = false;   // a failure is read from its ctrl later
+        h->stats.small_solves += 1;
+      }
+      upload(h->b_small, sizeof(SmallTask) * small.size());
+      launch_small_tasks(dev_of<SmallTask>(h->b_small), (int)small.size(), maxm, true, s);
       HCHECK(hipGetLastError());
       h->stats.launches += 1;
-      HCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl) * nm, hipMemcpyDeviceToHost, s));
-      HCHECK(hipStreamSynchronize(s));
-      // ---- classify
-      std::vector<int> small, big;
-      for (int i : idx) {
-        Mat& m = M[i];
-        if (ctrl_h[i].small_info != 0) {       // a small-block solve of the last round failed
-          m.info = m.last_small_top + ctrl_h[i].small_info;
-          m.active = false;
-          continue;
-        }
-        const int nk = ctrl_h[i].kbot;
-        if (nk < m.kbot) m.nodefl = 0;
-        m.kbot = nk;
-        m.ktop = ctrl_h[i].ktop;
-        if (m.kbot < 0) { m.active = false; continue; }
-        const int len = m.kbot - m.ktop + 1;
-        if (len <= m.P.nmin) small.push_back(i);
-        else if (++m.sweeps > m.P.max_sweeps) { m.info = m.kbot + 1; m.active = false; }
-        else big.push_back(i);
+      if (nwin > 0) {
+        upload(h->b_win, sizeof(WinB) * nwin);
+        launch_panel_row_b(dev_of<WinB>(h->b_win), nwin, tr, s);
+        launch_panel_colq_b(dev_of<WinB>(h->b_win), nwin, tcq, s);
+        HCHECK(hipGetLastError());
+        h->stats.launches += (tr > 0) + (tcq > 0);
       }
-      if (small.empty() && big.empty()) continue;
-      // U slots: one per small block, and one per window of the widest time step
-      std::vector<std::vector<std::vector<WinPlan>>> plans(big.size());
-      std::vector<int> nsv(big.size());
-      size_t maxw = 0, tmax = 0;
+      if (!big.empty()) HCHECK(hipStreamSynchronize(s));   // slots and staging reused below
+    }
+    if (big.empty()) return;
+    // ---- shifts: eigenvalues of the trailing blocks (or ad-hoc pairs)
+    {
+      grow(h->b_small, sizeof(SmallTask) * big.size(), true);
+      grow(h->b_shift, sizeof(ShiftB) * big.size(), true);
+      SmallTask* th = host_of<SmallTask>(h->b_small);
+      ShiftB* sh = host_of<ShiftB>(h->b_shift);
+      int ne = 0, maxns = 0;
       for (size_t q = 0; q < big.size(); ++q) {
         Mat& m = M[big[q]];
-        const int len = m.kbot - m.ktop + 1;
-        int ns = std::min(m.P.ns, 2 * ((len - 2) / 6));
-        if (ns < 2) ns = 2;
-        nsv[q] = ns;
-        int step = 0;
-        plan_sweep(m.ktop, m.kbot, ns / 2, m.P.nb, m.P.step, plans[q], step);
-        tmax = std::max(tmax, plans[q].size());
-      }
-      std::vector<size_t> per_t(tmax, 0);
-      for (size_t q = 0; q < big.size(); ++q)
-        for (size_t t = 0; t < plans[q].size(); ++t) per_t[t] += plans[q][t].size();
-      for (size_t t = 0; t < tmax; ++t) maxw = std::max(maxw, per_t[t]);
-      const size_t nslots = std::max(maxw, small.size());
-      double* Ubase = (double*)grow(h->b_u, sizeof(double) * UPAD * UPAD * std::max<size_t>(1, nslots),
-                                    false);
-      // ---- small blocks: one workgroup each; whole small matrices accumulate Q
-      // in the kernel, blocks of larger matrices apply Z as panel products
-      if (!small.empty()) {
-        grow(h->b_small, sizeof(SmallTask) * small.size(), true);
-        grow(h->b_win, sizeof(WinB) * small.size(), true);
-        SmallTask* th = host_of<SmallTask>(h->b_small);
-        WinB* wh = host_of<WinB>(h->b_win);
-        int nwin = 0, tr = 0, tcq = 0;
-        int maxm = 0;
-        for (size_t q = 0; q < small.size(); ++q) {
-          Mat& m = M[small[q]];
-          const int len = m.kbot - m.ktop + 1;
-          maxm = std::max(maxm, len);
-          const bool whole = (m.ktop == 0 && m.kbot == m.n - 1);
-          m.last_small_top = m.ktop;
+        const int ns = nsv[q];
+        double* base = shbuf + (size_t)big[q] * 3 * SMALL_EIG_MAX;
+        const bool exc = (m.nodefl > 0 && m.nodefl % m.P.exc_period == 0);
+        if (!exc) {
           SmallTask t{};
-          t.A = m.H + m.ktop + (size_t)m.ktop * m.ldh;
+          const int b0 = m.kbot - ns + 1;
+          t.A = m.H + b0 + (size_t)b0 * m.ldh;
           t.lda = m.ldh;
-          t.m = len;
-          t.wr = m.wr + m.ktop;
-          t.wi = m.wi + m.ktop;
-          t.info = &ctrl_d[small[q]].small_info;
+          t.m = ns;
+          t.wr = base;
+          t.wi = base + SMALL_EIG_MAX;
+          t.info = &ctrl_d[big[q]].nshift;   // per-matrix scratch for the shift solve
           t.itmax = 30;
-          double* slot = Ubase + (size_t)q * UPAD * UPAD;
-          if (whole) {
-            t.Qacc = m.Q;
-            t.ldqacc = m.ldq;
-          } else {
-            t.Zt = slot;
-            t.ldzt = UPAD;
-            WinB& w = wh[nwin++];
+          th[ne++] = t;
+          maxns = std::max(maxns, ns);
+        }
+        sh[q] = ShiftB{base, base + SMALL_EIG_MAX, exc ? nullptr : &ctrl_d[big[q]].nshift,
+                       m.H, base + 2 * SMALL_EIG_MAX, ns, exc ? 1 : 0, m.ldh, m.ktop, m.kbot, 0};
+        ++m.nodefl;
+        h->stats.sweeps += 1;
+        h->stats.shifts_applied += ns;
+      }
+      upload(h->b_small, sizeof(SmallTask) * ne);
+      upload(h->b_shift, sizeof(ShiftB) * big.size());
+      launch_small_tasks(dev_of<SmallTask>(h->b_small), ne, maxns, false, s);
+      launch_shift_prep_b(dev_of<ShiftB>(h->b_shift), (int)big.size(), s);
+      HCHECK(hipGetLastError());
+      h->stats.launches += 2;
+    }
+    // ---- merged sweeps: time step t carries the windows of every matrix
+    {
+      size_t total = 0;
+      for (size_t t = 0; t < tmax; ++t) total += per_t[t];
+      grow(h->b_win, sizeof(WinB) * std::max<size_t>(1, total), true);
+      WinB* wh = host_of<WinB>(h->b_win);
+      std::vector<size_t> off(tmax + 1, 0);
+      std::vector<int> tr_t(tmax, 0), tcq_t(tmax, 0);
+      for (size_t t = 0; t < tmax; ++t) {
+        off[t + 1] = off[t] + per_t[t];
+        size_t k = off[t];
+        int tr = 0, tcq = 0;
+        for (size_t q = 0; q < big.size(); ++q) {
+          if (t >= plans[q].size()) continue;
+          Mat& m = M[big[q]];
+          const double* st = shbuf + (size_t)big[q] * 3 * SMALL_EIG_MAX + 2 * SMALL_EIG_MAX;
+          for (const WinPlan& pl : plans[q][t]) {
+            if (pl.ws > WMAX || pl.ws < 3 || pl.p < m.ktop || pl.p + pl.ws - 1 > m.kbot ||
+                (pl.tau1 - pl.tau0) * pl.nb > REFL_LDS || pl.nb > NBMAX)
+              throw HipErr{hipErrorInvalidValue};
+            WinB& w = wh[k];
             std::memset(&w, 0, sizeof(w));
-            w.c.H = m.H; w.c.Q = m.Q; w.c.U = slot; w.c.st = nullptr;
+            w.c.H = m.H; w.c.Q = m.Q;
+            w.c.U = Ubase + (k - off[t]) * (size_t)UPAD * UPAD;
+            w.c.st = st + 2 * pl.shift0;
             w.c.ldh = m.ldh; w.c.ldq = m.ldq; w.c.n = m.n;
             w.c.ktop = m.ktop; w.c.kbot = m.kbot; w.c.rtop = 0; w.c.cend = m.n;
-            w.c.p = m.ktop; w.c.ws = len;
+            w.c.p = pl.p; w.c.ws = pl.ws; w.c.tau0 = pl.tau0; w.c.tau1 = pl.tau1;
+            w.c.nb = pl.nb;
             fill_tiles(w, tr, tcq);
+            ++k;
+            h->stats.windows += 1;
+            h->stats.chain_steps += pl.tau1 - pl.tau0;
           }
-          th[q] = t;
-          m.kbot = m.ktop - 1;     // the block is finished by this round's launches
-          if (m.kbot < 0) m.active = false;   // (a failure is still read from its ctrl below)
-          h->stats.small_solves += 1;
         }
-        upload(h->b_small, sizeof(SmallTask) * small.size());
-        launch_small_tasks(dev_of<SmallTask>(h->b_small), (int)small.size(), maxm, true, s);
-        HCHECK(hipGetLastError());
-        h->stats.launches += 1;
-        if (nwin > 0) {
-          upload(h->b_win, sizeof(WinB) * nwin);
-          launch_panel_row_b(dev_of<WinB>(h->b_win), nwin, tr, s);
-          launch_panel_colq_b(dev_of<WinB>(h->b_win), nwin, tcq, s);
-          HCHECK(hipGetLastError());
-          h->stats.launches += (tr > 0) + (tcq > 0);
-        }
-        if (!big.empty()) HCHECK(hipStreamSynchronize(s));   // slots and staging reused below
+        tr_t[t] = tr;
+        tcq_t[t] = tcq;
       }
-      if (big.empty()) continue;
-      // ---- shifts: eigenvalues of the trailing blocks (or ad-hoc pairs)
-      {
-        grow(h->b_small, sizeof(SmallTask) * big.size(), true);
-        grow(h->b_shift, sizeof(ShiftB) * big.size(), true);
-        SmallTask* th = host_of<SmallTask>(h->b_small);
-        ShiftB* sh = host_of<ShiftB>(h->b_shift);
-        int ne = 0, maxns = 0;
-        for (size_t q = 0; q < big.size(); ++q) {
-          Mat& m = M[big[q]];
-          const int ns = nsv[q];
-          double* base = shbuf + (size_t)big[q] * 3 * SMALL_EIG_MAX;
-          const bool exc = (m.nodefl > 0 && m.nodefl % m.P.exc_period == 0);
-          if (!exc) {
-            SmallTask t{};
-            const int b0 = m.kbot - ns + 1;
-            t.A = m.H + b0 + (size_t)b0 * m.ldh;
-            t.lda = m.ldh;
-            t.m = ns;
-            t.wr = base;
-            t.wi = base + SMALL_EIG_MAX;
-            t.info = &ctrl_d[big[q]].nshift;   // per-matrix scratch for the shift solve
-            t.itmax = 30;
-            th[ne++] = t;
-            maxns = std::max(maxns, ns);
-          }
-          sh[q] = ShiftB{base, base + SMALL_EIG_MAX, exc ? nullptr : &ctrl_d[big[q]].nshift,
-                         m.H, base + 2 * SMALL_EIG_MAX, ns, exc ? 1 : 0, m.ldh, m.ktop, m.kbot, 0};
-          ++m.nodefl;
-          h->stats.sweeps += 1;
-          h->stats.shifts_applied += ns;
-        }
-        upload(h->b_small, sizeof(SmallTask) * ne);
-        upload(h->b_shift, sizeof(ShiftB) * big.size());
-        launch_small_tasks(dev_of<SmallTask>(h->b_small), ne, maxns, false, s);
-        launch_shift_prep_b(dev_of<ShiftB>(h->b_shift), (int)big.size(), s);
+      upload(h->b_win, sizeof(WinB) * total);
+      WinB* wd = dev_of<WinB>(h->b_win);
+      for (size_t t = 0; t < tmax; ++t) {
+        const int nw = (int)per_t[t];
+        if (nw == 0) continue;
+        launch_chase_b(wd + off[t], nw, s);
+        launch_panel_row_b(wd + off[t], nw, tr_t[t], s);
+        launch_panel_colq_b(wd + off[t], nw, tcq_t[t], s);
         HCHECK(hipGetLastError());
-        h->stats.launches += 2;
-      }
-      // ---- merged sweeps: time step t carries the windows of every matrix
-      {
-        size_t total = 0;
-        for (size_t t = 0; t < tmax; ++t) total += per_t[t];
-        grow(h->b_win, sizeof(WinB) * std::max<size_t>(1, total), true);
-        WinB* wh = host_of<WinB>(h->b_win);
-        std::vector<size_t> off(tmax + 1, 0);
-        std::vector<int> tr_t(tmax, 0), tcq_t(tmax, 0);
-        for (size_t t = 0; t < tmax; ++t) {
-          off[t + 1] = off[t] + per_t[t];
-          size_t k = off[t];
-          int tr = 0, tcq = 0;
-          for (size_t q = 0; q < big.size(); ++q) {
-            if (t >= plans[q].size()) continue;
-            Mat& m = M[big[q]];
-            const double* st = shbuf + (size_t)big[q] * 3 * SMALL_EIG_MAX + 2 * SMALL_EIG_MAX;
-            for (const WinPlan& pl : plans[q][t]) {
-              if (pl.ws > WMAX || pl.ws < 3 || pl.p < m.ktop || pl.p + pl.ws - 1 > m.kbot ||
-                  (pl.tau1 - pl.tau0) * pl.nb > REFL_LDS || pl.nb > NBMAX)
-                throw HipErr{hipErrorInvalidValue};
-              WinB& w = wh[k];
-              std::memset(&w, 0, sizeof(w));
-              w.c.H = m.H; w.c.Q = m.Q;
-              w.c.U = Ubase + (k - off[t]) * (size_t)UPAD * UPAD;
-              w.c.st = st + 2 * pl.shift0;
-              w.c.ldh = m.ldh; w.c.ldq = m.ldq; w.c.n = m.n;
-              w.c.ktop = m.ktop; w.c.kbot = m.kbot; w.c.rtop = 0; w.c.cend = m.n;
-              w.c.p = pl.p; w.c.ws = pl.ws; w.c.tau0 = pl.tau0; w.c.tau1 = pl.tau1;
-              w.c.nb = pl.nb;
-              fill_tiles(w, tr, tcq);
-              ++k;
-              h->stats.windows += 1;
-              h->stats.chain_steps += pl.tau1 - pl.tau0;
-            }
-          }
-          tr_t[t] = tr;
-          tcq_t[t] = tcq;
-        }
-        upload(h->b_win, sizeof(WinB) * total);
-        WinB* wd = dev_of<WinB>(h->b_win);
-        for (size_t t = 0; t < tmax; ++t) {
-          const int nw = (int)per_t[t];
-          if (nw == 0) continue;
-          launch_chase_b(wd + off[t], nw, s);
-          launch_panel_row_b(wd + off[t], nw, tr_t[t], s);
-          launch_panel_colq_b(wd + off[t], nw, tcq_t[t], s);
-          HCHECK(hipGetLastError());
-          h->stats.chase_launches += 1;
-          h->stats.launches += 1 + (tr_t[t] > 0) + (tcq_t[t] > 0);
-        }
+        h->stats.chase_launches += 1;
+        h->stats.launches += 1 + (tr_t[t] > 0) + (tcq_t[t] > 0);
       }
     }
-    HCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl) * nm, hipMemcpyDeviceToHost, s));
+  }
+
+  // Wait for the stream, then report small-block failures of matrices that
+  // finished inside the last launches.
+  void settle() {
+    HCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl) * cap, hipMemcpyDeviceToHost, s));
     HCHECK(hipStreamSynchronize(s));
-    for (int i = 0; i < nm; ++i)   // small-block failures of the last launches
-      if (M[i].info == 0 && M[i].last_small_top >= 0 && ctrl_h[i].small_info != 0)
-        M[i].info = M[i].last_small_top + ctrl_h[i].small_info;
-    int first = 0;
-    for (int i = 0; i < nm; ++i) if (M[i].info != 0 && first == 0) first = M[i].info;
-    return first;
+    for (int i = 0; i < cap; ++i) {
+      Mat& m = M[i];
+      if (m.used && !m.active && m.info == 0 && m.last_small_top >= 0 && ctrl_h[i].small_info != 0)
+        m.info = m.last_small_top + ctrl_h[i].small_info;
+    }
   }
 
   void fill_tiles(WinB& w, int& tr, int& tcq) {
@@ -898,22 +966,29 @@ int solve_batched(schur_handle_s* h, hipStream_t s, int count, const int* n, dou
     const int rc = alloc_ws(h, 2);
     if (rc) return rc;
     std::memset(&h->stats, 0, sizeof(h->stats));
-    BatchSolver b{h, s ? s : h->stream, count, {}};
-    b.M.resize(count);
+    BatchEngine b;
+    b.init(h, s ? s : h->stream, count);
+    std::vector<int> pre(count, 0);
     for (int i = 0; i < count; ++i) {
-      auto& m = b.M[i];
       double* qi = Q ? Q[i] : nullptr;
-      m.n = n[i]; m.H = H[i]; m.ldh = ldh[i]; m.Q = qi; m.ldq = (qi && ldq) ? ldq[i] : 1;
-      m.wr = wr[i]; m.wi = wi[i];
-      m.info = check_args(m.n, m.H, m.ldh, m.Q, m.ldq, m.wr, m.wi);
-      m.active = (m.info == 0 && m.n > 0);
-      if (m.n > 65536) { m.info = -1; m.active = false; }
-      m.kbot = m.n - 1; m.ktop = 0; m.nodefl = 0; m.sweeps = 0; m.last_small_top = -1;
-      m.P = resolve(h->opts, std::max(1, m.n));
+      const int lq = (qi && ldq) ? ldq[i] : 1;
+      pre[i] = check_args(n[i], H[i], ldh[i], qi, lq, wr[i], wi[i]);
+      if (pre[i] == 0 && n[i] > 65536) pre[i] = -1;
+      if (pre[i] == 0) b.add(i, n[i], H[i], ldh[i], qi, lq, wr[i], wi[i], (uint64_t)i);
     }
-    const int rc2 = b.run();
-    for (int i = 0; i < count; ++i) if (info) info[i] = b.M[i].info;
-    return rc2;
+    int64_t guard = 0;
+    while (b.any_active()) {
+      b.round();
+      if (++guard > (int64_t)4 * 1000 * 1000) throw HipErr{hipErrorUnknown};
+    }
+    b.settle();
+    int first = 0;
+    for (int i = 0; i < count; ++i) {
+      const int r = pre[i] != 0 ? pre[i] : b.M[i].info;
+      if (info) info[i] = r;
+      if (r != 0 && first == 0) first = r;
+    }
+    return first;
   } catch (const HipErr& e) {
     (void)hipGetLastError();
     return e.e == hipErrorOutOfMemory ? -101 : -102;
@@ -946,6 +1021,195 @@ int create_handle(schur_handle_s** out, int device, const schur_opts* opts) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Serving loop
+// ---------------------------------------------------------------------------
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+  uint64_t ticket = 0;
+  int n = 0;
+  bool want_q = false;
+  double* hH = nullptr;     // pinned: the input, then S
+  double* hQ = nullptr;     // pinned: Q
+  double* hw = nullptr;     // pinned: wr (n), wi (n)
+  Ctrl* hctrl = nullptr;    // pinned: the slot's control block at retirement
+  double *dH = nullptr, *dQ = nullptr, *dw = nullptr;
+  size_t bytes = 0;
+  int slot = -1;
+  int info = 0;
+  int last_small_top = -1;
+  double t_submit = 0, t_done = 0;
+  hipEvent_t ev = nullptr;
+  enum State { QUEUED, RESIDENT, DRAINING, DONE } state = QUEUED;
+};
+
+}  // namespace
+
+struct schur_server_s {
+  schur_handle_s* h = nullptr;
+  size_t budget = 0, in_use = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request*> queue;
+  std::map<uint64_t, Request*> all;
+  std::vector<Request*> resident;     // by engine slot
+  std::vector<Request*> draining;
+  std::thread th;
+  bool stop = false;
+  int error = 0;
+  BatchEngine eng;
+  int slots = 1024;
+  uint64_t next_ticket = 1;
+  schur_server_stats st{};
+};
+
+namespace {
+
+size_t request_bytes(int n, bool want_q) {
+  const size_t nn = (size_t)n * n;
+  return sizeof(double) * (nn + (want_q ? nn : 0) + 2 * (size_t)n) + sizeof(Ctrl);
+}
+
+void free_request_host(Request* r) {
+  if (r->hH) (void)hipHostFree(r->hH);
+  if (r->hQ) (void)hipHostFree(r->hQ);
+  if (r->hw) (void)hipHostFree(r->hw);
+  if (r->hctrl) (void)hipHostFree(r->hctrl);
+  if (r->ev) (void)hipEventDestroy(r->ev);
+  r->hH = r->hQ = r->hw = nullptr;
+  r->hctrl = nullptr;
+  r->ev = nullptr;
+}
+
+void server_loop(schur_server_s* S) {
+  hipStream_t s = S->h->stream;
+  try {
+    HCHECK(hipSetDevice(S->h->device));
+    while (true) {
+      std::vector<Request*> admitted;
+      {
+        std::unique_lock<std::mutex> lk(S->mu);
+        const bool idle = S->queue.empty() && !S->eng.any_active() && S->draining.empty();
+        if (idle) {
+          if (S->stop) break;
+          S->cv.wait_for(lk, std::chrono::milliseconds(2));
+          continue;
+        }
+        // FIFO admission by device-memory budget, as slots free up
+        while (!S->queue.empty()) {
+          Request* r = S->queue.front();
+          const bool empty_gpu = S->in_use == 0;
+          if (r->bytes > S->budget) {          // can never fit
+            S->queue.pop_front();
+            r->info = -101;
+            r->state = Request::DONE;
+            r->t_done = now_s();
+            S->st.completed += 1;
+            continue;
+          }
+          if (S->in_use + r->bytes > S->budget && !empty_gpu) break;
+          const int slot = S->eng.free_slot();
+          if (slot < 0) break;
+          S->queue.pop_front();
+          r->slot = slot;
+          S->eng.M[slot].used = true;          // reserve; filled below
+          S->in_use += r->bytes;
+          r->state = Request::RESIDENT;
+          admitted.push_back(r);
+        }
+      }
+      // device state of the admitted requests (stream-ordered allocations)
+      for (Request* r : admitted) {
+        const int n = r->n;
+        const size_t nn = (size_t)n * n;
+        HCHECK(hipMallocAsync((void**)&r->dH, sizeof(double) * std::max<size_t>(1, nn), s));
+        if (r->want_q)
+          HCHECK(hipMallocAsync((void**)&r->dQ, sizeof(double) * std::max<size_t>(1, nn), s));
+        HCHECK(hipMallocAsync((void**)&r->dw, sizeof(double) * 2 * std::max(1, n), s));
+        HCHECK(hipMemcpyAsync(r->dH, r->hH, sizeof(double) * nn, hipMemcpyHostToDevice, s));
+        if (r->want_q) launch_set_identity(r->dQ, n, n, s);
+        S->eng.add(r->slot, n, r->dH, std::max(1, n), r->dQ, std::max(1, n), r->dw,
+                   r->dw + std::max(1, n), r->ticket);
+        S->resident[r->slot] = r;
+      }
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        const int64_t res = (int64_t)std::count_if(S->resident.begin(), S->resident.end(),
+                                                   [](Request* r) { return r != nullptr; });
+        S->st.resident = res;
+        S->st.peak_resident = std::max(S->st.peak_resident, res);
+        S->st.bytes_in_use = (double)S->in_use;
+        S->st.peak_bytes = std::max(S->st.peak_bytes, (double)S->in_use);
+      }
+      if (S->eng.any_active()) {
+        S->eng.round();
+        S->st.rounds += 1;
+      }
+      // retire finished requests: results to pinned host memory, free device memory
+      for (int i = 0; i < S->eng.cap; ++i) {
+        Request* r = S->resident[i];
+        if (!r || S->eng.M[i].active) continue;
+        const int n = r->n;
+        const size_t nn = (size_t)n * n;
+        r->info = S->eng.M[i].info;
+        r->last_small_top = S->eng.M[i].last_small_top;
+        HCHECK(hipMemcpyAsync(r->hH, r->dH, sizeof(double) * nn, hipMemcpyDeviceToHost, s));
+        if (r->want_q)
+          HCHECK(hipMemcpyAsync(r->hQ, r->dQ, sizeof(double) * nn, hipMemcpyDeviceToHost, s));
+        HCHECK(hipMemcpyAsync(r->hw, r->dw, sizeof(double) * 2 * std::max(1, n),
+                              hipMemcpyDeviceToHost, s));
+        HCHECK(hipMemcpyAsync(r->hctrl, S->eng.ctrl_d + i, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+        HCHECK(hipEventRecord(r->ev, s));
+        HCHECK(hipFreeAsync(r->dH, s));
+        if (r->dQ) HCHECK(hipFreeAsync(r->dQ, s));
+        HCHECK(hipFreeAsync(r->dw, s));
+        r->dH = r->dQ = r->dw = nullptr;
+        S->eng.release(i);
+        S->resident[i] = nullptr;
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->in_use -= r->bytes;
+        r->state = Request::DRAINING;
+        S->draining.push_back(r);
+      }
+      // completions
+      std::vector<Request*> keep;
+      for (Request* r : S->draining) {
+        const hipError_t q = hipEventQuery(r->ev);
+        if (q == hipErrorNotReady) { keep.push_back(r); continue; }
+        HCHECK(q);
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (r->info == 0 && r->last_small_top >= 0 && r->hctrl->small_info != 0)
+          r->info = r->last_small_top + r->hctrl->small_info;
+        r->t_done = now_s();
+        r->state = Request::DONE;
+        S->st.completed += 1;
+      }
+      S->draining.swap(keep);
+      if (!S->draining.empty() && !S->eng.any_active()) {
+        std::unique_lock<std::mutex> lk(S->mu);
+        if (S->queue.empty()) S->cv.wait_for(lk, std::chrono::microseconds(200));
+      }
+      S->cv.notify_all();
+    }
+  } catch (const HipErr& e) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->error = e.e == hipErrorOutOfMemory ? -101 : -102;
+    for (auto& kv : S->all) {
+      Request* r = kv.second;
+      if (r->state != Request::DONE) { r->state = Request::DONE; r->info = S->error; r->t_done = now_s(); }
+    }
+  }
+  S->cv.notify_all();
+}
+
+}  // namespace
+
 
 extern "C" {
 
@@ -1018,6 +1282,166 @@ int schur_reduce_batched(schur_handle_t h, void* stream, int count, const int* n
   if (count == 0) return 0;
   if (!n || !H || !ldh || !wr || !wi) return -4;
   return solve_batched(h, (hipStream_t)stream, count, n, H, ldh, Q, ldq, wr, wi, info);
+}
+
+int schur_server_create(schur_server_t* out, int device, size_t hbm_budget_bytes,
+                        const schur_opts* opts) {
+  if (!out) return -1;
+  schur_server_s* S = new schur_server_s();
+  if (create_handle(&S->h, device, opts) != 0) { delete S; return -102; }
+  S->budget = hbm_budget_bytes ? hbm_budget_bytes : ((size_t)64 << 30);
+  try {
+    HCHECK(hipSetDevice(device));
+    if (alloc_ws(S->h, 2) != 0) throw HipErr{hipErrorOutOfMemory};
+    S->eng.init(S->h, S->h->stream, S->slots);
+    S->resident.assign(S->slots, nullptr);
+    HCHECK(hipStreamSynchronize(S->h->stream));
+  } catch (const HipErr&) {
+    schur_destroy(S->h);
+    delete S;
+    return -101;
+  }
+  S->th = std::thread(server_loop, S);
+  *out = S;
+  return 0;
+}
+
+int schur_server_destroy(schur_server_t S) {
+  if (!S) return -104;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv.notify_all();
+  if (S->th.joinable()) S->th.join();
+  for (auto& kv : S->all) { free_request_host(kv.second); delete kv.second; }
+  S->all.clear();
+  schur_destroy(S->h);
+  delete S;
+  return 0;
+}
+
+int schur_submit(schur_server_t S, int n, const double* H_host, int ldh, int want_q,
+                 uint64_t* ticket) {
+  if (!S) return -104;
+  if (n < 0 || n > 65536) return -2;
+  if (n > 0 && !H_host) return -3;
+  if (ldh < std::max(1, n)) return -4;
+  if (!ticket) return -6;
+  Request* r = new Request();
+  r->n = n;
+  r->want_q = want_q != 0;
+  r->bytes = request_bytes(n, r->want_q);
+  const size_t nn = (size_t)n * n;
+  if (hipHostMalloc((void**)&r->hH, sizeof(double) * std::max<size_t>(1, nn), hipHostMallocDefault) != hipSuccess ||
+      (r->want_q && hipHostMalloc((void**)&r->hQ, sizeof(double) * std::max<size_t>(1, nn), hipHostMallocDefault) != hipSuccess) ||
+      hipHostMalloc((void**)&r->hw, sizeof(double) * 2 * std::max(1, n), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&r->hctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
+    free_request_host(r);
+    delete r;
+    return -101;
+  }
+  std::memset(r->hctrl, 0, sizeof(Ctrl));
+  for (int c = 0; c < n; ++c)
+    std::memcpy(r->hH + (size_t)c * n, H_host + (size_t)c * ldh, sizeof(double) * n);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->error) { free_request_host(r); delete r; return S->error; }
+    r->ticket = S->next_ticket++;
+    r->t_submit = now_s();
+    if (n == 0) { r->state = Request::DONE; r->t_done = r->t_submit; S->st.completed += 1; }
+    else S->queue.push_back(r);
+    S->all[r->ticket] = r;
+    S->st.submitted += 1;
+    S->st.queued = (int64_t)S->queue.size();
+    *ticket = r->ticket;
+  }
+  S->cv.notify_all();
+  return 0;
+}
+
+int schur_poll(schur_server_t S, uint64_t ticket, double* S_host, int lds, double* Q_host, int ldq,
+               double* wr, double* wi, int* info, double* latency_s) {
+  if (!S) return -104;
+  Request* r = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return -2;
+    r = it->second;
+    if (r->state != Request::DONE) return 1;
+    S->all.erase(it);
+  }
+  const int n = r->n;
+  if (r->info >= 0 && r->hH) {
+    if (S_host && lds >= n)
+      for (int c = 0; c < n; ++c)
+        std::memcpy(S_host + (size_t)c * lds, r->hH + (size_t)c * n, sizeof(double) * n);
+    if (Q_host && r->want_q && ldq >= n)
+      for (int c = 0; c < n; ++c)
+        std::memcpy(Q_host + (size_t)c * ldq, r->hQ + (size_t)c * n, sizeof(double) * n);
+    if (wr) std::memcpy(wr, r->hw, sizeof(double) * n);
+    if (wi) std::memcpy(wi, r->hw + std::max(1, n), sizeof(double) * n);
+  }
+  if (info) *info = r->info;
+  if (latency_s) *latency_s = r->t_done - r->t_submit;
+  free_request_host(r);
+  delete r;
+  return 0;
+}
+
+int schur_server_get_stats(schur_server_t S, schur_server_stats* out) {
+  if (!S || !out) return -104;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->st.queued = (int64_t)S->queue.size();
+  *out = S->st;
+  return 0;
+}
+
+int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, const int* step) {
+  if (count < 0) return -1;
+  std::vector<TuneRow> t;
+  if (count == 0) {
+    t.assign(std::begin(kBuiltinTune), std::end(kBuiltinTune));
+  } else {
+    if (!nmax || !ns || !nb || !step) return -2;
+    for (int i = 0; i < count; ++i) {
+      if (ns[i] < 2 || ns[i] > SMALL_EIG_MAX || nb[i] < 1 || nb[i] > NBMAX || step[i] < 0 ||
+          (i > 0 && nmax[i] <= nmax[i - 1]))
+        return -2;
+      t.push_back(TuneRow{nmax[i], ns[i] & ~1, nb[i], step[i]});
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.swap(t);
+  return 0;
+}
+
+int schur_plan_sweep(int ktop, int kbot, int npair, int nb, int step, int* out, int cap) {
+  if (ktop < 0 || kbot - ktop + 1 < 3 || npair < 1 || nb < 1 || nb > NBMAX || step < 0 ||
+      cap < 0 || (cap > 0 && !out))
+    return -1;
+  std::vector<std::vector<WinPlan>> steps;
+  int st = 0;
+  plan_sweep(ktop, kbot, npair, nb, step, steps, st);
+  int k = 0;
+  for (size_t t = 0; t < steps.size(); ++t) {
+    for (const WinPlan& w : steps[t]) {
+      if (k < cap) {
+        int* o = out + 7 * k;
+        o[0] = (int)t;
+        o[1] = w.shift0;   // groups are identified by their first bulge
+        o[2] = w.p;
+        o[3] = w.ws;
+        o[4] = w.tau0;
+        o[5] = w.tau1;
+        o[6] = w.nb;
+      }
+      ++k;
+    }
+  }
+  return k;
 }
 
 }  // extern "C"

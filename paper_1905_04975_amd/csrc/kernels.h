@@ -44,6 +44,7 @@ void launch_panel_colq(const SweepArgs& a, int tiles, hipStream_t s);
 void launch_check_finite(const double* H, int ldh, int n, Ctrl* ctrl, hipStream_t s);
 void launch_zero_lower(double* H, int ldh, int n, hipStream_t s);
 void launch_ctrl_reset(Ctrl* ctrl, hipStream_t s);
+void launch_set_identity(double* Q, int ldq, int n, hipStream_t s);
 void launch_deflate(double* H, int ldh, int kbot, int klo, Ctrl* ctrl, hipStream_t s);
 void launch_standardize(double* H, int ldh, double* Q, int ldq, int n, int kmin, double* wr,
                         double* wi, int* list, int* count, int cap, hipStream_t s);

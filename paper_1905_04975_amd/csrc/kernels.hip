@@ -31,21 +31,16 @@ struct SmallSmem {
   static constexpr int LD = MAXM | 1;
 };
 
+// Francis double-shift iteration on the m x m block already in LDS (S, and Z
+// when WANTZ), one wavefront.  Writes T.wr / T.wi of converged blocks when
+// given; returns 0 or the 1-based end of a block that did not converge.
 template <bool WANTZ, int MAXM>
-__device__ void small_qr(const SmallTask& T, double* S, double* Zs) {
+__device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
   constexpr int LD = SmallSmem<MAXM>::LD;
   const int m = T.m;
   const int lane = threadIdx.x;
   auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
   auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
-
-  for (int c = 0; c < m; ++c)
-    for (int r = lane; r < m; r += 64)
-      Sx(r, c) = (r <= c + 1) ? T.A[r + (size_t)c * T.lda] : 0.0;
-  if (WANTZ)
-    for (int c = 0; c < m; ++c)
-      for (int r = lane; r < m; r += 64) Zx(r, c) = (r == c) ? 1.0 : 0.0;
-  __syncthreads();
 
   int i = m - 1, its = 0, info = 0;
   const int itmax = T.itmax > 0 ? T.itmax : 30;
@@ -190,6 +185,32 @@ __device__ void small_qr(const SmallTask& T, double* S, double* Zs) {
     }
   }
   __syncthreads();
+  return info;
+}
+
+template <bool WANTZ, int MAXM>
+__device__ void small_load(const SmallTask& T, double* S, double* Zs) {
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  const int m = T.m;
+  const int lane = threadIdx.x;
+  for (int c = 0; c < m; ++c)
+    for (int r = lane; r < m; r += 64)
+      S[r + c * LD] = (r <= c + 1) ? T.A[r + (size_t)c * T.lda] : 0.0;
+  if (WANTZ)
+    for (int c = 0; c < m; ++c)
+      for (int r = lane; r < m; r += 64) Zs[r + c * LD] = (r == c) ? 1.0 : 0.0;
+  __syncthreads();
+}
+
+template <bool WANTZ, int MAXM>
+__device__ void small_qr(const SmallTask& T, double* S, double* Zs) {
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  const int m = T.m;
+  const int lane = threadIdx.x;
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
+  small_load<WANTZ, MAXM>(T, S, Zs);
+  const int info = small_iter<WANTZ, MAXM>(T, S, Zs);
   if (lane == 0 && T.info) *T.info = info;
   if (WANTZ) {
     // Schur form of the block back to global memory, Z^T into the U slot layout
@@ -765,6 +786,15 @@ __global__ void k_zero_lower(double* H, int ldh, int n) {
   }
 }
 
+__global__ void k_set_identity(double* Q, int ldq, int n) {
+  const size_t total = (size_t)n * n;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(idx / n), r = (int)(idx - (size_t)c * n);
+    Q[r + (size_t)c * ldq] = (r == c) ? 1.0 : 0.0;
+  }
+}
+
 __global__ void k_ctrl_reset(Ctrl* ctrl) {
   if (threadIdx.x == 0) {
     ctrl->bad = 0;
@@ -1115,6 +1145,10 @@ void launch_check_finite(const double* H, int ldh, int n, Ctrl* ctrl, hipStream_
 
 void launch_zero_lower(double* H, int ldh, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_lower, dim3(2048), dim3(256), 0, s, H, ldh, n);
+}
+
+void launch_set_identity(double* Q, int ldq, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_set_identity, dim3(1024), dim3(256), 0, s, Q, ldq, n);
 }
 
 void launch_ctrl_reset(Ctrl* ctrl, hipStream_t s) {

@@ -48,7 +48,22 @@ class SchurStats(ctypes.Structure):
 FLAG_TIME_KERNELS = 1
 
 EXPORTS = ("schur_reduce", "schur_create", "schur_destroy", "schur_set_opts",
-           "schur_get_stats", "schur_reduce_async", "schur_reduce_batched")
+           "schur_get_stats", "schur_reduce_async", "schur_reduce_batched",
+           "schur_server_create", "schur_server_destroy", "schur_submit", "schur_poll",
+           "schur_server_get_stats", "schur_set_tuning", "schur_plan_sweep")
+
+TUNING_PATH = os.path.join(HERE, "tuning.json")
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rounds", ctypes.c_int64), ("resident", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("peak_resident", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_double), ("peak_bytes", ctypes.c_double),
+                ("reserved", ctypes.c_double * 4)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 def load():
@@ -77,7 +92,28 @@ def load():
     pptr = ctypes.POINTER(ctypes.c_void_p)
     lib.schur_reduce_batched.argtypes = [vp, vp, ip, pint, pptr, pint, pptr, pint, pptr, pptr, pint]
     lib.schur_reduce_batched.restype = ctypes.c_int
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.schur_server_create.argtypes = [ctypes.POINTER(vp), ip, ctypes.c_size_t,
+                                        ctypes.POINTER(SchurOpts)]
+    lib.schur_server_create.restype = ctypes.c_int
+    lib.schur_server_destroy.argtypes = [vp]
+    lib.schur_server_destroy.restype = ctypes.c_int
+    lib.schur_submit.argtypes = [vp, ip, dp, ip, ip, u64p]
+    lib.schur_submit.restype = ctypes.c_int
+    lib.schur_poll.argtypes = [vp, ctypes.c_uint64, dp, ip, dp, ip, dp, dp,
+                               ctypes.POINTER(ip), ctypes.POINTER(ctypes.c_double)]
+    lib.schur_poll.restype = ctypes.c_int
+    lib.schur_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.schur_server_get_stats.restype = ctypes.c_int
+    pi = ctypes.POINTER(ctypes.c_int)
+    lib.schur_set_tuning.argtypes = [ip, pi, pi, pi, pi]
+    lib.schur_set_tuning.restype = ctypes.c_int
+    lib.schur_plan_sweep.argtypes = [ip, ip, ip, ip, ip, pi, ip]
+    lib.schur_plan_sweep.restype = ctypes.c_int
     _lib = lib
+    path = os.environ.get("SCHUR_TUNE_TABLE", TUNING_PATH)
+    if os.path.exists(path):
+        load_tuning(path)
     return lib
 
 
@@ -222,3 +258,98 @@ def reduce_batched(Hs, want_q=True, handle=None, stream=None):
         [w.data_ptr() for w in wrs], [w.data_ptr() for w in wis])
     ws = [torch.complex(wr[:S.shape[0]], wi[:S.shape[0]]) for wr, wi, S in zip(wrs, wis, Ss)]
     return Ss, (Qs if want_q else None), ws, infos, rc
+
+
+class Server:
+    """Continuous-batching Schur server (C ``schur_server_*``), host arrays in/out."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, **opts):
+        lib = load()
+        self._s = ctypes.c_void_p()
+        o = make_opts(**opts)
+        rc = lib.schur_server_create(ctypes.byref(self._s), int(device), int(budget_bytes),
+                                     ctypes.byref(o))
+        if rc != 0:
+            raise RuntimeError("schur_server_create failed: %d" % rc)
+
+    def submit(self, H, want_q=True):
+        """Queue a host numpy matrix (any layout; sent column-major)."""
+        import numpy as np
+
+        A = np.asfortranarray(H, dtype=np.float64)
+        n = A.shape[0]
+        t = ctypes.c_uint64(0)
+        rc = load().schur_submit(self._s, n, A.ctypes.data if n else None, max(1, n),
+                                 1 if want_q else 0, ctypes.byref(t))
+        if rc != 0:
+            raise RuntimeError("schur_submit failed: %d" % rc)
+        return t.value, n
+
+    def poll(self, ticket, n, want_q=True):
+        """None while pending, else (S, Q, w, info, latency_s) as numpy arrays."""
+        import numpy as np
+
+        S = np.empty((n, n), order="F")
+        Q = np.empty((n, n), order="F") if want_q else None
+        wr = np.empty(max(n, 1))
+        wi = np.empty(max(n, 1))
+        info = ctypes.c_int(0)
+        lat = ctypes.c_double(0.0)
+        rc = load().schur_poll(self._s, ctypes.c_uint64(ticket),
+                               S.ctypes.data if n else None, max(1, n),
+                               Q.ctypes.data if (want_q and n) else None, max(1, n),
+                               wr.ctypes.data, wi.ctypes.data, ctypes.byref(info),
+                               ctypes.byref(lat))
+        if rc == 1:
+            return None
+        if rc != 0:
+            raise RuntimeError("schur_poll failed: %d" % rc)
+        return S, Q, wr[:n] + 1j * wi[:n], info.value, lat.value
+
+    def stats(self):
+        st = ServerStats()
+        load().schur_server_get_stats(self._s, ctypes.byref(st))
+        return st.as_dict()
+
+    def close(self):
+        if self._s:
+            load().schur_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def set_tuning(rows):
+    """Install a tuning table: rows of dicts with nmax, ns, nb, step (ascending nmax)."""
+    lib = load()
+    k = len(rows)
+    IA = ctypes.c_int * max(k, 1)
+    rc = lib.schur_set_tuning(k, IA(*[r["nmax"] for r in rows]), IA(*[r["ns"] for r in rows]),
+                              IA(*[r["nb"] for r in rows]), IA(*[r.get("step", 0) for r in rows]))
+    if rc != 0:
+        raise ValueError("invalid tuning table (rc=%d)" % rc)
+
+
+def load_tuning(path):
+    """Read a tuning table written by the autotuner and install it."""
+    import json
+
+    with open(path) as f:
+        rows = json.load(f)["table"]
+    set_tuning(rows)
+    return rows
+
+
+def plan_sweep(ktop, kbot, npair, nb, step=0):
+    """Host-only window schedule of one sweep: list of (t, group, p, ws, tau0, tau1, nb)."""
+    lib = load()
+    k = lib.schur_plan_sweep(int(ktop), int(kbot), int(npair), int(nb), int(step), None, 0)
+    if k < 0:
+        raise ValueError("bad schedule arguments")
+    buf = (ctypes.c_int * (7 * max(k, 1)))()
+    lib.schur_plan_sweep(int(ktop), int(kbot), int(npair), int(nb), int(step), buf, k)
+    return [tuple(buf[7 * i:7 * i + 7]) for i in range(k)]

@@ -1,0 +1,91 @@
+"""Serving loop (continuous batching): results in the mix equal results alone.
+
+Requests of different orders and kinds are submitted while others are on
+the GPU; each result must meet the accuracy bar and agree with the same
+matrix solved alone (eigenvalues to rounding; backward error and
+orthogonality to the stated tolerance).  A tiny HBM budget forces requests
+to wait for admission; results stay correct.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1905_04975_amd import inputs
+from tests import checks
+
+pytestmark = pytest.mark.gpu
+
+
+def _wait(srv, tickets, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t, n in tickets:
+            if t in out:
+                continue
+            r = srv.poll(t, n)
+            if r is not None:
+                out[t] = r
+        if time.time() - t0 > timeout:
+            raise TimeoutError("server did not finish")
+        time.sleep(0.002)
+    return out
+
+
+def _check(H, S, Q, w, info):
+    assert info == 0
+    assert checks.structure_errors(S, w.real, w.imag) == []
+    assert checks.residual(H, Q, S) <= 1e-12
+    assert checks.orthogonality(Q) <= 1e-12
+
+
+def test_served_mix_equals_alone(gpu_lib):
+    rng = np.random.default_rng(5)
+    sizes = [64, 700, 90, 300, 1024, 128, 40, 500]
+    mats = []
+    for i, n in enumerate(sizes):
+        if i % 2 == 0:
+            mats.append(inputs.hessenberg_normal(n, 50000 + i))
+        else:
+            mats.append(inputs.prescribed(n, 50000 + i)[0])
+    print("case served mix of %d requests" % len(mats), flush=True)
+    srv = gpu_lib.Server(0)
+    tickets = []
+    for H in mats:                      # staggered arrivals while others run
+        tickets.append(srv.submit(H))
+        time.sleep(float(rng.uniform(0.0, 0.01)))
+    res = _wait(srv, tickets)
+    st = srv.stats()
+    assert st["completed"] == len(mats) and st["peak_resident"] >= 2
+    mixed = [res[t] for t, _ in tickets]
+    # the same matrices, one at a time
+    alone = []
+    for H in mats:
+        t = srv.submit(H)
+        alone.append(_wait(srv, [t])[t[0]])
+    srv.close()
+    for H, (S, Q, w, info, lat), (S1, Q1, w1, info1, lat1) in zip(mats, mixed, alone):
+        _check(H, S, Q, w, info)
+        _check(H, S1, Q1, w1, info1)
+        assert checks.match_eigs(w, w1).max() <= 1e-10 * np.linalg.norm(H)
+        assert lat > 0.0
+
+
+def test_budget_forces_queueing(gpu_lib):
+    mats = [inputs.hessenberg_normal(n, 70 + n) for n in (200, 180, 160, 220)]
+    # room for about one request at a time
+    budget = 8 * (2 * 220 * 220 + 2 * 220) + 4096
+    print("case served with a tiny budget", flush=True)
+    srv = gpu_lib.Server(0, budget_bytes=budget)
+    tickets = [srv.submit(H) for H in mats]
+    big = inputs.hessenberg_normal(400, 3)
+    tbig = srv.submit(big)            # larger than the whole budget
+    res = _wait(srv, tickets + [tbig])
+    st = srv.stats()
+    srv.close()
+    assert st["peak_resident"] == 1
+    for (t, n), H in zip(tickets, mats):
+        S, Q, w, info, lat = res[t]
+        _check(H, S, Q, w, info)
+    assert res[tbig[0]][3] == -101

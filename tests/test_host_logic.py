@@ -1,0 +1,165 @@
+"""Host logic of the library, on the CPU (no GPU calls).
+
+The sweep planner (``schur_plan_sweep``, the same C++ code the solver uses)
+is checked for the properties the windowed multishift sweep relies on:
+windows of one time step are disjoint and ordered, each bulge group's chain
+steps are tiled exactly once, every reflector (and the row below it that its
+right update reaches) lies inside its window, and the reflector log fits.
+A numpy model of the window chase driven by that schedule must reproduce
+the oracle's sequential Francis double-shift steps with the same shifts
+(the multishift sweep and the sequence of double-shift steps agree in exact
+arithmetic; paper Sec. 3.2 describes the windowed, accumulated form).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_04975_amd import inputs, schur
+
+WMAX = 128
+REFL_LDS = 1280
+
+
+def _groups(npair, nb):
+    g = (npair + nb - 1) // nb
+    sizes = [npair // g + (1 if j < npair % g else 0) for j in range(g)]
+    first = np.cumsum([0] + sizes[:-1])
+    return dict(zip(first.tolist(), sizes))
+
+
+@pytest.mark.parametrize("ktop,kbot,npair,nb,step", [
+    (0, 299, 1, 1, 0), (0, 299, 8, 3, 0), (5, 1000, 64, 16, 0), (10, 140, 4, 2, 0),
+    (0, 96, 15, 16, 0), (3, 700, 32, 5, 40), (0, 4095, 64, 24, 0), (0, 511, 16, 16, 30)])
+def test_plan_invariants(ktop, kbot, npair, nb, step):
+    plan = schur.plan_sweep(ktop, kbot, npair, nb, step)
+    groups = _groups(npair, nb)
+    by_t = {}
+    for (t, g, p, ws, t0, t1, b) in plan:
+        by_t.setdefault(t, []).append((p, ws))
+        assert 3 <= ws <= WMAX and p >= ktop and p + ws - 1 <= kbot
+        assert (t1 - t0) * b <= REFL_LDS and b == groups[g]
+    for t, ws_ in by_t.items():
+        ws_.sort()
+        for (p0, w0), (p1, w1) in zip(ws_, ws_[1:]):
+            assert p0 + w0 - 1 < p1, "windows of one time step overlap"
+    for g, b in groups.items():
+        mine = sorted((t0, t1, p, ws, t) for (t, gg, p, ws, t0, t1, bb) in plan if gg == g)
+        tend = kbot - ktop + 3 * b - 3
+        assert mine[0][0] == 0 and mine[-1][1] == tend
+        for a, c in zip(mine, mine[1:]):
+            assert a[1] == c[0] and c[4] == a[4] + 1
+        # every active reflector of every bulge inside its window
+        for (t0, t1, p, ws, _) in mine:
+            for tau in range(t0, t1):
+                for j in range(b):
+                    K = ktop - 1 + tau - 3 * j
+                    if K < ktop - 1 or K > kbot - 2:
+                        continue
+                    lo = max(K, ktop)
+                    hi = min(K + 4, kbot)
+                    assert p <= lo and hi <= p + ws - 1, (tau, j, K, p, ws)
+
+
+def _house(nr, x, y, z):
+    if nr == 2:
+        z = 0.0
+    tail = abs(y) + abs(z)
+    if tail == 0:
+        return None
+    nrm = np.sqrt(x * x + y * y + z * z)
+    beta = nrm if x < 0 else -nrm
+    return np.array([1.0, y / (x - beta), z / (x - beta)])[:nr], (beta - x) / beta, beta
+
+
+def _model_sweep(H, Q, ktop, kbot, shifts, nb):
+    """Window chase + accumulated U + panel products, driven by the planner."""
+    n = H.shape[0]
+    npair = len(shifts)
+    plan = schur.plan_sweep(ktop, kbot, npair, nb, 0)
+    for t in sorted({r[0] for r in plan}):
+        wins = [r for r in plan if r[0] == t]
+        Us = []
+        for (_, g, p, ws, t0, t1, b) in wins:
+            W = H[p:p + ws, p:p + ws].copy()
+            refl = []
+            for tau in range(t0, t1):
+                step_refl = []
+                for j in range(b):
+                    K = ktop - 1 + tau - 3 * j
+                    if K < ktop - 1 or K > kbot - 2:
+                        continue
+                    nr = 3 if K <= kbot - 3 else 2
+                    if K == ktop - 1:
+                        o = ktop - p
+                        s, tt = shifts[g + j]
+                        x = W[o, o] ** 2 + W[o, o + 1] * W[o + 1, o] - s * W[o, o] + tt
+                        y = W[o + 1, o] * (W[o, o] + W[o + 1, o + 1] - s)
+                        z = W[o + 1, o] * W[o + 2, o + 1] if nr == 3 else 0.0
+                    else:
+                        k = K - p
+                        x, y = W[k + 1, k], W[k + 2, k]
+                        z = W[k + 3, k] if nr == 3 else 0.0
+                    r = _house(nr, x, y, z)
+                    if r is not None:
+                        step_refl.append((K, nr) + r)
+                for (K, nr, v, tv, beta) in step_refl:   # all left updates first
+                    k = K - p
+                    c0 = max(k, 0)
+                    blk = W[k + 1:k + 1 + nr, c0:]
+                    blk -= tv * np.outer(v, v @ blk)
+                    if k >= 0:
+                        W[k + 1:k + 1 + nr, k] = 0.0
+                        W[k + 1, k] = beta
+                for (K, nr, v, tv, beta) in step_refl:   # then the right updates
+                    k = K - p
+                    rl = min(K + 4, kbot) - p
+                    blk = W[:rl + 1, k + 1:k + 1 + nr]
+                    blk -= tv * np.outer(blk @ v, v)
+                refl += step_refl
+            H[p:p + ws, p:p + ws] = W
+            U = np.eye(ws)
+            for (K, nr, v, tv, beta) in refl:
+                k = K - p
+                blk = U[:, k + 1:k + 1 + nr]
+                blk -= tv * np.outer(blk @ v, v)
+            Us.append(U)
+        for (_, g, p, ws, t0, t1, b), U in zip(wins, Us):   # left (row panel) first
+            H[p:p + ws, p + ws:] = U.T @ H[p:p + ws, p + ws:]
+        for (_, g, p, ws, t0, t1, b), U in zip(wins, Us):   # then right (column panel, Q)
+            H[:p, p:p + ws] = H[:p, p:p + ws] @ U
+            Q[:, p:p + ws] = Q[:, p:p + ws] @ U
+
+
+@pytest.mark.parametrize("n,ktop,kbot,npair,nb", [(160, 0, 159, 1, 1), (220, 0, 219, 6, 3),
+                                                 (260, 20, 240, 10, 4), (300, 0, 299, 8, 8)])
+def test_planned_sweep_equals_sequential_double_shift_steps(n, ktop, kbot, npair, nb):
+    H0 = inputs.hessenberg_normal(n, 9 + n)
+    if ktop > 0:
+        H0[ktop, ktop - 1] = 0.0
+    if kbot < n - 1:
+        H0[kbot + 1, kbot] = 0.0
+    rng = np.random.default_rng(1)
+    shifts = []
+    for _ in range(npair):
+        a, b = rng.uniform(-1, 1, 2)
+        shifts.append((2 * a, a * a + b * b))
+    H = H0.copy()
+    Q = np.eye(n)
+    _model_sweep(H, Q, ktop, kbot, shifts, nb)
+    Hs = np.asfortranarray(H0.copy())
+    Qs = np.asfortranarray(np.eye(n))
+    for (s, t) in shifts:
+        oracle.francis_step_inplace(Hs, Qs, ktop, kbot, s, t)
+    # same similarity up to signs of the reflector columns
+    assert np.abs(np.abs(H) - np.abs(Hs)).max() <= 1e-11 * np.linalg.norm(H0)
+    assert np.linalg.norm(Q @ H @ Q.T - H0) <= 1e-13 * n * np.linalg.norm(H0)
+    assert np.abs(np.tril(H, -2)).max() == 0.0
+
+
+def test_tuning_table_roundtrip():
+    rows = [{"nmax": 500, "ns": 8, "nb": 4, "step": 0},
+            {"nmax": 1 << 30, "ns": 64, "nb": 16, "step": 0}]
+    schur.set_tuning(rows)
+    with pytest.raises(ValueError):
+        schur.set_tuning([{"nmax": 10, "ns": 1, "nb": 1, "step": 0}])
+    schur.set_tuning([])   # built-in table back
