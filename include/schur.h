@@ -71,7 +71,9 @@ typedef struct schur_opts {
   int max_sweeps;  /* sweep limit per solve; 0 = 30 * max(10, n)/max(2, ns)    */
   int exc_period;  /* sweeps without deflation before ad-hoc shifts; 0 = 6     */
   int flags;       /* SCHUR_FLAG_*                                             */
-  int reserved[5];
+  int aed_window;  /* early-deflation window order (<= 96); 0 = from ns,       */
+                   /* < 0 = no early deflation (shifts from the trailing block) */
+  int reserved[4];
 } schur_opts;
 
 #define SCHUR_FLAG_TIME_KERNELS 1   /* time each kernel family with HIP events */
@@ -97,7 +99,10 @@ typedef struct schur_stats {
   double colq_flops;        /* flops of the column-panel and Q (right) products */
   double colq_ms;           /* summed duration of k_panel_colq launches (TIME) */
   int64_t colq_launches;
-  double reserved[4];
+  double aed_ms;            /* summed duration of the early-deflation kernels   */
+  int64_t aed_windows;      /* early-deflation windows processed               */
+  int64_t aed_deflated;     /* eigenvalues deflated by them                    */
+  double reserved[1];
 } schur_stats;
 
 /* --------------------------------------------------------------------------

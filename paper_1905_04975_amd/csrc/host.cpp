@@ -123,7 +123,7 @@ struct schur_handle_s {
     void* host = nullptr;   // pinned staging
     size_t cap = 0;
   };
-  Grow b_ctrl, b_defl, b_small, b_shift, b_win, b_u, b_sh;
+  Grow b_ctrl, b_defl, b_small, b_shift, b_win, b_u, b_sh, b_aedt, b_aedw;
 };
 
 namespace {
@@ -161,8 +161,13 @@ TuneRow tune_for(int n) {
 
 struct Params {
   int ns, nb, step, nmin, max_sweeps, exc_period;
+  int nw;      // early-deflation window order (0: none)
   bool time;
 };
+
+// early deflation: skip the next sweep when a window deflated more than
+// this percentage of its order (the remaining shifts are then stale)
+constexpr int kAedSkipPct = 14;
 
 Params resolve(const schur_opts& o, int n) {
   Params p;
@@ -177,6 +182,9 @@ Params resolve(const schur_opts& o, int n) {
   p.max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30 * std::max(10, n) / std::max(2, p.ns) + 100;
   p.exc_period = o.exc_period > 0 ? o.exc_period : 6;
   p.time = (o.flags & SCHUR_FLAG_TIME_KERNELS) != 0;
+  if (o.aed_window < 0) p.nw = 0;
+  else if (o.aed_window > 0) p.nw = std::min(o.aed_window, SMALL_Z_MAX);
+  else p.nw = std::min(SMALL_Z_MAX, std::max(16, p.ns + p.ns / 2));
   return p;
 }
 
@@ -231,6 +239,7 @@ void free_grow(schur_handle_s::Grow& g) {
 void free_ws(schur_handle_s* h) {
   free_grow(h->b_ctrl); free_grow(h->b_defl); free_grow(h->b_small);
   free_grow(h->b_shift); free_grow(h->b_win); free_grow(h->b_u); free_grow(h->b_sh);
+  free_grow(h->b_aedt); free_grow(h->b_aedw);
   if (h->U) (void)hipFree(h->U);
   if (h->refl) (void)hipFree(h->refl);
   if (h->st) (void)hipFree(h->st);
@@ -451,6 +460,50 @@ struct Solver {
     launch_gemms(a, tr, tc);
   }
 
+  // Early deflation on the bottom nw rows of [ktop, kbot]; applies the
+  // window's orthogonal factor to the rest of H and to Q when something
+  // deflated.  Returns the number deflated; *nu receives the number of
+  // undeflated window eigenvalues left in ewr/ewi (0 if the window's Schur
+  // form did not converge).
+  int aed(int ktop, int kbot, int nw, int* nu) {
+    const int buf = acquire_buffer();
+    AedTask t{};
+    t.H = H; t.ldh = ldh;
+    t.ktop = ktop; t.kbot = kbot; t.nw = nw;
+    t.Ut = h->U + (size_t)buf * MAXWIN * UPAD * UPAD;
+    t.ldut = UPAD;
+    t.sr = h->ewr; t.si = h->ewi;
+    t.ctrl = h->ctrl;
+    t.itmax = 30;
+    hipEvent_t e0 = nullptr;
+    if (P.time) h->timer.begin(s, e0);
+    launch_aed(t, s);
+    HCHECK(hipGetLastError());
+    if (P.time) h->timer.end(s, e0, &h->stats.aed_ms);
+    h->stats.launches += 1;
+    h->stats.aed_windows += 1;
+    sync_ctrl();
+    const int nd = h->ctrl_h->aed_nd;
+    *nu = h->ctrl_h->aed_nu;
+    SweepArgs a, aq;
+    base_args(a, ktop, kbot);
+    int tr = 0, tc = 0, tq = 0;
+    if (nd > 0) {
+      a.nwin = 1;
+      a.win[0].p = kbot - nw + 1;
+      a.win[0].ws = nw;
+      a.win[0].slot = buf * MAXWIN;
+      fill_gemm(a, aq, tr, tc, tq);
+    } else {
+      a.nwin = 0;
+      aq = a;
+    }
+    launch_q(aq, tq, buf);   // records the slot's events even when idle
+    launch_gemms(a, tr, tc);
+    h->stats.aed_deflated += nd;
+    return nd;
+  }
+
   void compute_shifts(int ktop, int kbot, int ns, bool exceptional) {
     hipEvent_t e0 = nullptr;
     if (P.time) h->timer.begin(s, e0);
@@ -566,6 +619,34 @@ struct Solver {
       int ns = std::min(P.ns, 2 * ((m - 2) / 6));
       if (ns < 2) ns = 2;
       const bool exc = (nodefl > 0 && nodefl % P.exc_period == 0);
+      const int nw = std::min(P.nw, m - 1);
+      if (nw >= 4) {
+        int nu = 0;
+        const int nd = aed(ktop, kbot, nw, &nu);
+        if (nd > 0) {
+          kbot -= nd;
+          nodefl = 0;
+          // many deflations: look again before spending a sweep; a block
+          // that became small goes to the single-kernel solver
+          if (100 * nd > kAedSkipPct * nw || kbot - ktop + 1 <= P.nmin) continue;
+        }
+        const int m2 = kbot - ktop + 1;
+        ns = std::max(2, std::min(P.ns, 2 * ((m2 - 2) / 6)));
+        if (!exc && nu >= 2 && 2 * nu >= ns) {
+          // the undeflated window eigenvalues closest to the deflated part
+          const int use = std::min(ns, nu) & ~1;
+          hipEvent_t e0 = nullptr;
+          if (P.time) h->timer.begin(s, e0);
+          launch_shift_prep(h->ewr + (nu - use), h->ewi + (nu - use), use, nullptr, 0, H, ldh,
+                            ktop, kbot, h->st, s);
+          HCHECK(hipGetLastError());
+          if (P.time) h->timer.end(s, e0, &h->stats.shift_ms);
+          h->stats.launches += 1;
+          sweep(ktop, kbot, use);
+          ++nodefl;
+          continue;
+        }
+      }
       compute_shifts(ktop, kbot, ns, exc);
       sweep(ktop, kbot, ns);
       ++nodefl;
@@ -759,25 +840,16 @@ struct BatchEngine {
       else big.push_back(i);
     }
     if (small.empty() && big.empty()) return;
-    // U slots: one per small block, and one per window of the widest time step
-    std::vector<std::vector<std::vector<WinPlan>>> plans(big.size());
-    std::vector<int> nsv(big.size());
-    size_t maxw = 0, tmax = 0;
-    for (size_t q = 0; q < big.size(); ++q) {
-      Mat& m = M[big[q]];
+    // U slots: one per small block, per early-deflation window, and per
+    // window of the widest sweep time step (at most one per bulge group)
+    size_t gsum = 0;
+    for (int i : big) {
+      const Mat& m = M[i];
       const int len = m.kbot - m.ktop + 1;
-      int ns = std::min(m.P.ns, 2 * ((len - 2) / 6));
-      if (ns < 2) ns = 2;
-      nsv[q] = ns;
-      int step = 0;
-      plan_sweep(m.ktop, m.kbot, ns / 2, m.P.nb, m.P.step, plans[q], step);
-      tmax = std::max(tmax, plans[q].size());
+      const int ns = std::max(2, std::min(m.P.ns, 2 * ((len - 2) / 6)));
+      gsum += (size_t)((ns / 2 + m.P.nb - 1) / m.P.nb);
     }
-    std::vector<size_t> per_t(tmax, 0);
-    for (size_t q = 0; q < big.size(); ++q)
-      for (size_t t = 0; t < plans[q].size(); ++t) per_t[t] += plans[q][t].size();
-    for (size_t t = 0; t < tmax; ++t) maxw = std::max(maxw, per_t[t]);
-    const size_t nslots = std::max(maxw, small.size());
+    const size_t nslots = std::max(std::max(gsum, small.size()), big.size());
     double* Ubase =
         (double*)grow(h->b_u, sizeof(double) * UPAD * UPAD * std::max<size_t>(1, nslots), false);
     // ---- small blocks: one workgroup each; whole small matrices accumulate Q
@@ -837,43 +909,142 @@ struct BatchEngine {
       if (!big.empty()) HCHECK(hipStreamSynchronize(s));   // slots and staging reused below
     }
     if (big.empty()) return;
-    // ---- shifts: eigenvalues of the trailing blocks (or ad-hoc pairs)
+    // ---- early deflation: one workgroup per matrix, then V applied to the
+    // rest of each matrix and to its Q by the panel kernels
+    std::vector<int> aed_nu(big.size(), 0), sweep_it(big.size(), 1);
+    {
+      std::vector<int> who;
+      grow(h->b_aedt, sizeof(AedTask) * big.size(), true);
+      AedTask* ah = host_of<AedTask>(h->b_aedt);
+      std::vector<int> nwv(big.size(), 0);
+      for (size_t q = 0; q < big.size(); ++q) {
+        Mat& m = M[big[q]];
+        const int len = m.kbot - m.ktop + 1;
+        const int nw = std::min(m.P.nw, len - 1);
+        if (nw < 4) continue;
+        nwv[q] = nw;
+        double* base = shbuf + (size_t)big[q] * 3 * SMALL_EIG_MAX;
+        AedTask t{};
+        t.H = m.H; t.ldh = m.ldh;
+        t.ktop = m.ktop; t.kbot = m.kbot; t.nw = nw;
+        t.Ut = Ubase + who.size() * (size_t)UPAD * UPAD;
+        t.ldut = UPAD;
+        t.sr = base; t.si = base + SMALL_EIG_MAX;
+        t.ctrl = ctrl_d + big[q];
+        t.itmax = 30;
+        ah[who.size()] = t;
+        who.push_back((int)q);
+      }
+      if (!who.empty()) {
+        upload(h->b_aedt, sizeof(AedTask) * who.size());
+        launch_aed_b(dev_of<AedTask>(h->b_aedt), (int)who.size(), s);
+        HCHECK(hipGetLastError());
+        h->stats.launches += 1;
+        h->stats.aed_windows += (int64_t)who.size();
+        HCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl) * cap, hipMemcpyDeviceToHost, s));
+        HCHECK(hipStreamSynchronize(s));
+        grow(h->b_aedw, sizeof(WinB) * who.size(), true);
+        WinB* wh = host_of<WinB>(h->b_aedw);
+        int nwin = 0, tr = 0, tcq = 0;
+        for (size_t j = 0; j < who.size(); ++j) {
+          const int q = who[j];
+          Mat& m = M[big[q]];
+          const int nd = ctrl_h[big[q]].aed_nd;
+          aed_nu[q] = ctrl_h[big[q]].aed_nu;
+          if (nd <= 0) continue;
+          WinB& w = wh[nwin++];
+          std::memset(&w, 0, sizeof(w));
+          w.c.H = m.H; w.c.Q = m.Q; w.c.U = Ubase + j * (size_t)UPAD * UPAD; w.c.st = nullptr;
+          w.c.ldh = m.ldh; w.c.ldq = m.ldq; w.c.n = m.n;
+          w.c.ktop = m.ktop; w.c.kbot = m.kbot; w.c.rtop = 0; w.c.cend = m.n;
+          w.c.p = m.kbot - nwv[q] + 1; w.c.ws = nwv[q];
+          fill_tiles(w, tr, tcq);
+          m.kbot -= nd;
+          m.nodefl = 0;
+          h->stats.aed_deflated += nd;
+          if (100 * nd > kAedSkipPct * nwv[q] || m.kbot - m.ktop + 1 <= m.P.nmin) sweep_it[q] = 0;
+        }
+        if (nwin > 0) {
+          upload(h->b_aedw, sizeof(WinB) * nwin);
+          launch_panel_row_b(dev_of<WinB>(h->b_aedw), nwin, tr, s);
+          launch_panel_colq_b(dev_of<WinB>(h->b_aedw), nwin, tcq, s);
+          HCHECK(hipGetLastError());
+          h->stats.launches += (tr > 0) + (tcq > 0);
+        }
+      }
+    }
+    // ---- sweep plans with the (possibly shrunk) active blocks
+    std::vector<std::vector<std::vector<WinPlan>>> plans(big.size());
+    std::vector<int> nsv(big.size(), 0), use_aed(big.size(), 0);
+    size_t maxw = 0, tmax = 0;
+    for (size_t q = 0; q < big.size(); ++q) {
+      if (!sweep_it[q]) continue;
+      Mat& m = M[big[q]];
+      const int len = m.kbot - m.ktop + 1;
+      int ns = std::min(m.P.ns, 2 * ((len - 2) / 6));
+      if (ns < 2) ns = 2;
+      const bool exc = (m.nodefl > 0 && m.nodefl % m.P.exc_period == 0);
+      if (!exc && aed_nu[q] >= 2 && 2 * aed_nu[q] >= ns) {
+        ns = std::min(ns, aed_nu[q]) & ~1;
+        use_aed[q] = 1;
+      }
+      nsv[q] = ns;
+      int step = 0;
+      plan_sweep(m.ktop, m.kbot, ns / 2, m.P.nb, m.P.step, plans[q], step);
+      tmax = std::max(tmax, plans[q].size());
+    }
+    std::vector<size_t> per_t(tmax, 0);
+    for (size_t q = 0; q < big.size(); ++q)
+      for (size_t t = 0; t < plans[q].size(); ++t) per_t[t] += plans[q][t].size();
+    for (size_t t = 0; t < tmax; ++t) maxw = std::max(maxw, per_t[t]);
+    if (maxw > nslots) throw HipErr{hipErrorInvalidValue};
+    if (tmax == 0) return;
+    // ---- shifts: undeflated window eigenvalues, else eigenvalues of the
+    // trailing blocks (or ad-hoc pairs)
     {
       grow(h->b_small, sizeof(SmallTask) * big.size(), true);
       grow(h->b_shift, sizeof(ShiftB) * big.size(), true);
       SmallTask* th = host_of<SmallTask>(h->b_small);
       ShiftB* sh = host_of<ShiftB>(h->b_shift);
-      int ne = 0, maxns = 0;
+      int ne = 0, maxns = 0, nsh = 0;
       for (size_t q = 0; q < big.size(); ++q) {
+        if (!sweep_it[q]) continue;
         Mat& m = M[big[q]];
         const int ns = nsv[q];
         double* base = shbuf + (size_t)big[q] * 3 * SMALL_EIG_MAX;
         const bool exc = (m.nodefl > 0 && m.nodefl % m.P.exc_period == 0);
-        if (!exc) {
-          SmallTask t{};
-          const int b0 = m.kbot - ns + 1;
-          t.A = m.H + b0 + (size_t)b0 * m.ldh;
-          t.lda = m.ldh;
-          t.m = ns;
-          t.wr = base;
-          t.wi = base + SMALL_EIG_MAX;
-          t.info = &ctrl_d[big[q]].nshift;   // per-matrix scratch for the shift solve
-          t.itmax = 30;
-          th[ne++] = t;
-          maxns = std::max(maxns, ns);
+        if (use_aed[q]) {
+          const int off = aed_nu[q] - ns;
+          sh[nsh++] = ShiftB{base + off, base + SMALL_EIG_MAX + off, nullptr, m.H,
+                             base + 2 * SMALL_EIG_MAX, ns, 0, m.ldh, m.ktop, m.kbot, 0};
+        } else {
+          if (!exc) {
+            SmallTask t{};
+            const int b0 = m.kbot - ns + 1;
+            t.A = m.H + b0 + (size_t)b0 * m.ldh;
+            t.lda = m.ldh;
+            t.m = ns;
+            t.wr = base;
+            t.wi = base + SMALL_EIG_MAX;
+            t.info = &ctrl_d[big[q]].nshift;   // per-matrix scratch for the shift solve
+            t.itmax = 30;
+            th[ne++] = t;
+            maxns = std::max(maxns, ns);
+          }
+          sh[nsh++] = ShiftB{base, base + SMALL_EIG_MAX, exc ? nullptr : &ctrl_d[big[q]].nshift,
+                             m.H, base + 2 * SMALL_EIG_MAX, ns, exc ? 1 : 0, m.ldh, m.ktop, m.kbot,
+                             0};
         }
-        sh[q] = ShiftB{base, base + SMALL_EIG_MAX, exc ? nullptr : &ctrl_d[big[q]].nshift,
-                       m.H, base + 2 * SMALL_EIG_MAX, ns, exc ? 1 : 0, m.ldh, m.ktop, m.kbot, 0};
         ++m.nodefl;
         h->stats.sweeps += 1;
         h->stats.shifts_applied += ns;
       }
       upload(h->b_small, sizeof(SmallTask) * ne);
-      upload(h->b_shift, sizeof(ShiftB) * big.size());
-      launch_small_tasks(dev_of<SmallTask>(h->b_small), ne, maxns, false, s);
-      launch_shift_prep_b(dev_of<ShiftB>(h->b_shift), (int)big.size(), s);
+      upload(h->b_shift, sizeof(ShiftB) * nsh);
+      if (ne > 0) launch_small_tasks(dev_of<SmallTask>(h->b_small), ne, maxns, false, s);
+      launch_shift_prep_b(dev_of<ShiftB>(h->b_shift), nsh, s);
       HCHECK(hipGetLastError());
-      h->stats.launches += 2;
+      h->stats.launches += 1 + (ne > 0);
     }
     // ---- merged sweeps: time step t carries the windows of every matrix
     {

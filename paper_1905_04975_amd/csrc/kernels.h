@@ -17,6 +17,17 @@ struct SmallTask {
   double* Qacc; int ldqacc;    // optional: Qacc(0:m, 0:m) <- Qacc(0:m, 0:m) Z
 };
 
+// Aggressive early deflation on the window H(kbot-nw+1:kbot, same) of the
+// active block [ktop, kbot]; nw <= SMALL_Z_MAX.
+struct AedTask {
+  double* H; int ldh;
+  int ktop, kbot, nw;
+  double* Ut; int ldut;        // V^T of the window, zero padded to ldut x ldut
+  double* sr; double* si;      // eigenvalues of the undeflated part (nu entries)
+  Ctrl* ctrl;                  // aed_nd, aed_nu
+  int itmax;
+};
+
 // One matrix of a batched deflation scan.
 struct DeflB {
   double* H; double* Q; double* wr; double* wi;
@@ -35,6 +46,8 @@ struct ShiftB {
 void launch_small_z(const SmallTask& t, const SmallTask* tasks, int count, int maxm,
                     hipStream_t s);
 void launch_small_eig(const SmallTask& t, hipStream_t s);
+void launch_aed(const AedTask& t, hipStream_t s);
+void launch_aed_b(const AedTask* tasks, int count, hipStream_t s);
 void launch_shift_prep(const double* wr, const double* wi, int ns, const int* small_info,
                        int exceptional, const double* H, int ldh, int ktop, int kbot, double* st,
                        hipStream_t s);

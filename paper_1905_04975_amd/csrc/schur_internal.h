@@ -84,7 +84,8 @@ struct Ctrl {
   int bad;         // non-finite entry seen in the input scan
   int small_info;  // convergence failure in a small-block solve (1-based), 0 ok
   int nshift;      // shifts produced for the next sweep
-  int pad[2];
+  int aed_nd;      // eigenvalues deflated by the last early-deflation window
+  int aed_nu;      // undeflated eigenvalues of that window (shift candidates)
 };
 
 }  // namespace schur

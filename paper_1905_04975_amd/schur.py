@@ -24,7 +24,7 @@ class SchurOpts(ctypes.Structure):
     _fields_ = [("ns", ctypes.c_int), ("nb", ctypes.c_int), ("step", ctypes.c_int),
                 ("nmin", ctypes.c_int), ("max_sweeps", ctypes.c_int),
                 ("exc_period", ctypes.c_int), ("flags", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("aed_window", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
 
 class SchurStats(ctypes.Structure):
@@ -39,7 +39,8 @@ class SchurStats(ctypes.Structure):
                 ("row_launches", ctypes.c_int64),
                 ("colq_flops", ctypes.c_double), ("colq_ms", ctypes.c_double),
                 ("colq_launches", ctypes.c_int64),
-                ("reserved", ctypes.c_double * 4)]
+                ("aed_ms", ctypes.c_double), ("aed_windows", ctypes.c_int64),
+                ("aed_deflated", ctypes.c_int64), ("reserved", ctypes.c_double * 1)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -171,10 +172,11 @@ class Handle:
             pass
 
 
-def make_opts(ns=0, nb=0, step=0, nmin=0, max_sweeps=0, exc_period=0, flags=0):
+def make_opts(ns=0, nb=0, step=0, nmin=0, max_sweeps=0, exc_period=0, flags=0, aed_window=0):
     o = SchurOpts()
     o.ns, o.nb, o.step, o.nmin = int(ns), int(nb), int(step), int(nmin)
     o.max_sweeps, o.exc_period, o.flags = int(max_sweeps), int(exc_period), int(flags)
+    o.aed_window = int(aed_window)
     return o
 
 

@@ -221,3 +221,35 @@ def test_sweep_limit_keeps_similarity(gpu_lib):
     assert 0 < info <= n
     assert checks.residual(H, Q, S) <= RES_TOL
     assert checks.orthogonality(Q) <= ORTH_TOL
+
+
+@pytest.mark.parametrize("n,ns,nw,seed", [(600, 32, 0, 31), (450, 16, 96, 32), (380, 8, 37, 33),
+                                          (300, 4, 4, 34)])
+def test_early_deflation_windows(gpu_lib, n, ns, nw, seed):
+    """Aggressive early deflation (paper Sec. 3.2) on and off: both give a
+    valid Schur form with the same spectrum; with it on, windows deflate."""
+    print("case aed n=%d ns=%d nw=%d seed=%d" % (n, ns, nw, seed), flush=True)
+    H = inputs.hessenberg_normal(n, seed)
+    S, Q, w, info, st = _run(gpu_lib, H, ns=ns, aed_window=nw)
+    _check_schur(H, S, Q, w, info)
+    assert st["aed_windows"] > 0 and st["aed_deflated"] > 0
+    S0, Q0, w0, info0, st0 = _run(gpu_lib, H, ns=ns, aed_window=-1)
+    _check_schur(H, S0, Q0, w0, info0)
+    assert st0["aed_windows"] == 0
+    _kappa_match(H, w)
+    _kappa_match(H, w0)
+
+
+def test_early_deflation_graded(gpu_lib):
+    """A nearly converged bottom (graded subdiagonal): the first window
+    deflates most of its rows, then the reduction finishes."""
+    print("case aed graded n=400", flush=True)
+    n = 400
+    H = inputs.hessenberg_normal(n, 35)
+    sub = np.ones(n - 1)
+    sub[-120:] = np.logspace(-3, -13, 120)
+    H[np.arange(1, n), np.arange(n - 1)] *= sub
+    S, Q, w, info, st = _run(gpu_lib, H, ns=32, aed_window=64)
+    _check_schur(H, S, Q, w, info)
+    _kappa_match(H, w)
+    assert st["aed_deflated"] >= 40
