@@ -473,6 +473,7 @@ struct Solver {
     t.Ut = h->U + (size_t)buf * MAXWIN * UPAD * UPAD;
     t.ldut = UPAD;
     t.sr = h->ewr; t.si = h->ewi;
+    t.wr = wr + (kbot - nw + 1); t.wi = wi + (kbot - nw + 1);
     t.ctrl = h->ctrl;
     t.itmax = 30;
     hipEvent_t e0 = nullptr;
@@ -930,6 +931,7 @@ struct BatchEngine {
         t.Ut = Ubase + who.size() * (size_t)UPAD * UPAD;
         t.ldut = UPAD;
         t.sr = base; t.si = base + SMALL_EIG_MAX;
+        t.wr = m.wr + (m.kbot - nw + 1); t.wi = m.wi + (m.kbot - nw + 1);
         t.ctrl = ctrl_d + big[q];
         t.itmax = 30;
         ah[who.size()] = t;

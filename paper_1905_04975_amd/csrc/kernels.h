@@ -24,6 +24,7 @@ struct AedTask {
   int ktop, kbot, nw;
   double* Ut; int ldut;        // V^T of the window, zero padded to ldut x ldut
   double* sr; double* si;      // eigenvalues of the undeflated part (nu entries)
+  double* wr; double* wi;      // optional: final eigenvalues, indexed from the window top
   Ctrl* ctrl;                  // aed_nd, aed_nu
   int itmax;
 };

@@ -660,15 +660,21 @@ __global__ __launch_bounds__(64) void k_aed(AedTask t0, const AedTask* tasks) {
   const int nu = bot + 1;
   const int nd = nw - nu;
 
-  // ---- eigenvalues of the undeflated blocks (the next shifts)
-  for (int e = lane; e < nu; e += 64) {
-    const bool first = (e + 1 < nu) && Sx(e + 1, e) != 0.0;
+  // ---- eigenvalues: undeflated blocks give the next shifts, deflated ones
+  // are final (written when the caller asks for them)
+  for (int e = lane; e < nw; e += 64) {
+    const bool first = (e + 1 < nw) && Sx(e + 1, e) != 0.0;
     const bool second = (e >= 1) && Sx(e, e - 1) != 0.0;
     double wr = Sx(e, e), wi = 0.0;
     if (first) wi = sqrt(fabs(Sx(e, e + 1))) * sqrt(fabs(Sx(e + 1, e)));
     if (second) wi = -sqrt(fabs(Sx(e - 1, e))) * sqrt(fabs(Sx(e, e - 1)));
-    T.sr[e] = wr;
-    T.si[e] = wi;
+    if (e < nu) {
+      T.sr[e] = wr;
+      T.si[e] = wi;
+    } else if (T.wr) {
+      T.wr[e] = wr;
+      T.wi[e] = wi;
+    }
   }
   if (lane == 0) { T.ctrl->aed_nd = nd; T.ctrl->aed_nu = nu; }
   if (nd == 0) return;   // nothing deflated: H stays as it was
@@ -1118,6 +1124,21 @@ __device__ void panel_row_tile(const WinCtx& d, int tile) {
   const int kpad = (ws + 3) & ~3;
   const double* Ut = d.U;
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int i0 = wave * 32;
+  // this wave's A operands (rows i0..i0+31 of U^T, all k) go to registers
+  // before the tile load so that their latency hides behind it; the slot is
+  // zero padded to UPAD x UPAD, so the full K = UPAD is read
+  double ua[UPAD / 4][2];
+  if (i0 < ws) {
+#pragma unroll
+    for (int ks = 0; ks < UPAD / 4; ++ks) {
+      const int k = 4 * ks + lk;
+      ua[ks][0] = Ut[(i0 + li) + (size_t)k * UPAD];
+      ua[ks][1] = Ut[(i0 + 16 + li) + (size_t)k * UPAD];
+    }
+  }
 
   for (int idx = tid; idx < kpad * PT; idx += 256) {
     const int c = idx / kpad, r = idx - c * kpad;
@@ -1127,21 +1148,19 @@ __device__ void panel_row_tile(const WinCtx& d, int tile) {
   }
   __syncthreads();
 
-  const int wave = tid >> 6, lane = tid & 63;
-  const int li = lane & 15, lk = lane >> 4;
-  const int i0 = wave * 32;
   if (i0 >= ws) return;
   d4 acc[2][4];
   for (int ib = 0; ib < 2; ++ib)
     for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < kpad; k0 += 4) {
-    const int k = k0 + lk;
-    const double a0 = Ut[(i0 + li) + (size_t)k * UPAD];
-    const double a1 = Ut[(i0 + 16 + li) + (size_t)k * UPAD];
+#pragma unroll
+  for (int ks = 0; ks < UPAD / 4; ++ks) {
+    if (4 * ks >= kpad) break;
+    const int k = 4 * ks + lk;
+#pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
       const double b = Xs[(jb * 16 + li) + k * LDT];
-      acc[0][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][jb], 0, 0, 0);
-      acc[1][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][jb], 0, 0, 0);
+      acc[0][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][0], b, acc[0][jb], 0, 0, 0);
+      acc[1][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][1], b, acc[1][jb], 0, 0, 0);
     }
   }
   for (int ib = 0; ib < 2; ++ib)
@@ -1172,6 +1191,20 @@ __device__ void panel_colq_tile(const WinCtx& d, int tile, int tiles_c) {
   const int kpad = (ws + 3) & ~3;
   const double* Ut = d.U;
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int j0 = wave * 32;
+  // this wave's B operands (columns j0..j0+31 of U, all k) go to registers
+  // before the tile load (zero-padded slot, full K = UPAD)
+  double ub[UPAD / 4][2];
+  if (j0 < ws) {
+#pragma unroll
+    for (int ks = 0; ks < UPAD / 4; ++ks) {
+      const int k = 4 * ks + lk;
+      ub[ks][0] = Ut[(j0 + li) + (size_t)k * UPAD];
+      ub[ks][1] = Ut[(j0 + 16 + li) + (size_t)k * UPAD];
+    }
+  }
 
   for (int idx = tid; idx < kpad * PT; idx += 256) {
     const int c = idx / PT, r = idx - c * PT;
@@ -1181,21 +1214,19 @@ __device__ void panel_colq_tile(const WinCtx& d, int tile, int tiles_c) {
   }
   __syncthreads();
 
-  const int wave = tid >> 6, lane = tid & 63;
-  const int li = lane & 15, lk = lane >> 4;
-  const int j0 = wave * 32;
   if (j0 >= ws) return;
   d4 acc[4][2];
   for (int ib = 0; ib < 4; ++ib)
     for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < kpad; k0 += 4) {
-    const int k = k0 + lk;
-    const double b0 = Ut[(j0 + li) + (size_t)k * UPAD];
-    const double b1 = Ut[(j0 + 16 + li) + (size_t)k * UPAD];
+#pragma unroll
+  for (int ks = 0; ks < UPAD / 4; ++ks) {
+    if (4 * ks >= kpad) break;
+    const int k = 4 * ks + lk;
+#pragma unroll
     for (int ib = 0; ib < 4; ++ib) {
       const double av = Xs[(ib * 16 + li) + k * LDT];
-      acc[ib][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc[ib][0], 0, 0, 0);
-      acc[ib][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc[ib][1], 0, 0, 0);
+      acc[ib][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ub[ks][0], acc[ib][0], 0, 0, 0);
+      acc[ib][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ub[ks][1], acc[ib][1], 0, 0, 0);
     }
   }
   for (int ib = 0; ib < 4; ++ib)
@@ -1209,22 +1240,22 @@ __device__ void panel_colq_tile(const WinCtx& d, int tile, int tiles_c) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_panel_row(SweepArgs a) {
+__global__ __launch_bounds__(256, 2) void k_panel_row(SweepArgs a) {
   const int w = find_window(a, blockIdx.x, true);
   panel_row_tile(ctx_of(a, a.win[w]), blockIdx.x - a.win[w].base_r);
 }
 
-__global__ __launch_bounds__(256) void k_panel_colq(SweepArgs a) {
+__global__ __launch_bounds__(256, 2) void k_panel_colq(SweepArgs a) {
   const int w = find_window(a, blockIdx.x, false);
   panel_colq_tile(ctx_of(a, a.win[w]), blockIdx.x - a.win[w].base_cq, a.win[w].tiles_c);
 }
 
-__global__ __launch_bounds__(256) void k_panel_row_b(const WinB* wins, int nwin) {
+__global__ __launch_bounds__(256, 2) void k_panel_row_b(const WinB* wins, int nwin) {
   const int w = find_window_b(wins, nwin, blockIdx.x, true);
   panel_row_tile(wins[w].c, blockIdx.x - wins[w].base_r);
 }
 
-__global__ __launch_bounds__(256) void k_panel_colq_b(const WinB* wins, int nwin) {
+__global__ __launch_bounds__(256, 2) void k_panel_colq_b(const WinB* wins, int nwin) {
   const int w = find_window_b(wins, nwin, blockIdx.x, false);
   panel_colq_tile(wins[w].c, blockIdx.x - wins[w].base_cq, wins[w].tiles_c);
 }
