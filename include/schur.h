@@ -38,7 +38,9 @@
  *                converged, and H_in = Q S Q^T still holds for the returned
  *                (non-triangular) S.
  *       <=-100   runtime failure: -101 out of device memory, -102 HIP error,
- *                -103 pointer is not device memory, -104 bad handle.
+ *                -103 pointer is not device memory, -104 bad handle,
+ *                -105 a non-finite value appeared during the iteration
+ *                (an internal failure; H and Q are then unspecified).
  *   - entries of H below the first subdiagonal are ignored on input and are
  *     exactly zero on output; S's 2x2 blocks are standardised (equal diagonal
  *     entries, off-diagonal entries of opposite sign, i.e. a complex pair);

@@ -165,6 +165,10 @@ struct Params {
   bool time;
 };
 
+// info code of a solve in which a non-finite value appeared (never for
+// finite input; reported instead of a Schur form)
+constexpr int kErrNonFinite = -105;
+
 // early deflation: skip the next sweep when a window deflated more than
 // this percentage of its order (the remaining shifts are then stale)
 constexpr int kAedSkipPct = 14;
@@ -516,11 +520,13 @@ struct Solver {
       t.m = ns;
       t.wr = h->ewr;
       t.wi = h->ewi;
-      t.info = &h->ctrl->small_info;
+      // a shift solve that does not converge only costs shifts: its own
+      // status slot, read by the shift preparation
+      t.info = &h->ctrl->nshift;
       t.itmax = 30;
       launch_small_eig(t, s);
     }
-    launch_shift_prep(h->ewr, h->ewi, ns, &h->ctrl->small_info, exceptional ? 1 : 0, H, ldh, ktop,
+    launch_shift_prep(h->ewr, h->ewi, ns, &h->ctrl->nshift, exceptional ? 1 : 0, H, ldh, ktop,
                       kbot, h->st, s);
     HCHECK(hipGetLastError());
     if (P.time) h->timer.end(s, e0, &h->stats.shift_ms);
@@ -590,9 +596,8 @@ struct Solver {
       if (P.time) h->timer.end(s, e0, &h->stats.other_ms);
       h->stats.launches += 1;
       sync_ctrl();
-      if (h->ctrl_h->small_info != 0) {
-        // a single-kernel block solve failed: report its block end
-        info = h->ctrl_h->small_info;
+      if (h->ctrl_h->bad) {   // a non-finite value appeared during the iteration
+        info = kErrNonFinite;
         break;
       }
       const int nk = h->ctrl_h->kbot;
@@ -602,7 +607,7 @@ struct Solver {
       const int ktop = h->ctrl_h->ktop;
       const int m = kbot - ktop + 1;
       if (m <= P.nmin) {
-        // small_info is rebased to the global row by the next check
+        // a failure is reported as the global end of the non-converged block
         small_block(ktop, kbot);
         sync_ctrl();
         if (h->ctrl_h->small_info != 0) {
@@ -652,8 +657,12 @@ struct Solver {
       sweep(ktop, kbot, ns);
       ++nodefl;
     }
-    const int kmin = info > 0 ? info + 1 : 1;
     join_aux();   // the standardisation rotates columns of Q
+    if (info < 0) {
+      HCHECK(hipStreamSynchronize(s));
+      return info;
+    }
+    const int kmin = info > 0 ? info + 1 : 1;
     hipEvent_t e0 = nullptr;
     if (P.time) h->timer.begin(s, e0);
     launch_standardize(H, ldh, Q, ldq, n, kmin, wr, wi, h->blist, h->bcount, h->blist_cap, s);
@@ -825,6 +834,11 @@ struct BatchEngine {
     std::vector<int> small, big;
     for (int i : idx) {
       Mat& m = M[i];
+      if (ctrl_h[i].bad) {                   // a non-finite value appeared
+        m.info = kErrNonFinite;
+        m.active = false;
+        continue;
+      }
       if (ctrl_h[i].small_info != 0) {       // the last small-block solve failed
         m.info = m.last_small_top + ctrl_h[i].small_info;
         m.active = false;

@@ -1,0 +1,668 @@
+// wave_solvers.h -- one-wavefront LDS solvers of the Schur engine: the
+// small-block Francis double-shift QR and the aggressive-early-deflation
+// window step.  Included by kernels.hip; written against the HIP device
+// API only (threadIdx, __syncthreads, __shfl_xor, __ballot), so the same
+// source also runs under a CPU emulation of one wavefront in the tests.
+#pragma once
+#include "schur_internal.h"
+#include "device_common.h"
+#include "kernels.h"
+
+namespace schur {
+
+// ============================================================================
+// Small-block Francis double-shift QR (one wavefront, block in LDS)
+// ============================================================================
+
+// Column-major LDS block with odd leading dimension (spreads banks).
+template <int MAXM>
+struct SmallSmem {
+  static constexpr int LD = MAXM | 1;
+};
+
+// Francis double-shift iteration on the m x m block already in LDS (S, and Z
+// when WANTZ), one wavefront.  Writes T.wr / T.wi of converged blocks when
+// given; returns 0 or the 1-based end of a block that did not converge.
+template <bool WANTZ, int MAXM>
+__device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  const int m = T.m;
+  const int lane = threadIdx.x;
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
+
+  int i = m - 1, its = 0, info = 0;
+  const int itmax = T.itmax > 0 ? T.itmax : 30;
+  while (i >= 0) {
+    // ---- deflation search: largest k in [1, i] with a negligible subdiagonal
+    int l = 0;
+    for (int top = i; top >= 1; top -= 64) {
+      const int k = top - lane;
+      bool neg = false;
+      if (k >= 1) {
+        const double sub = fabs(Sx(k, k - 1));
+        double tst = fabs(Sx(k - 1, k - 1)) + fabs(Sx(k, k));
+        if (tst == 0.0) {
+          tst = fabs(Sx(k - 1, k));
+          if (k >= 2) tst += fabs(Sx(k - 1, k - 2));
+          if (k + 1 <= i) tst += fabs(Sx(k + 1, k));
+        }
+        neg = (sub <= kUlp * tst);
+      }
+      const unsigned long long mask = __ballot(neg);
+      if (mask) {
+        l = top - __builtin_ctzll(mask);
+        break;
+      }
+    }
+    __syncthreads();
+    if (l > 0 && lane == 0) Sx(l, l - 1) = 0.0;
+    __syncthreads();
+
+    if (l == i) {
+      if (lane == 0 && T.wr) { T.wr[i] = Sx(i, i); T.wi[i] = 0.0; }
+      i -= 1; its = 0;
+      continue;
+    }
+    if (l == i - 1) {
+      const Std2 o = standardize2(Sx(i - 1, i - 1), Sx(i - 1, i), Sx(i, i - 1), Sx(i, i));
+      __syncthreads();
+      if (WANTZ && !(o.cs == 1.0 && o.sn == 0.0)) {
+        for (int c = i + 1 + lane; c < m; c += 64) {
+          const double x = Sx(i - 1, c), y = Sx(i, c);
+          Sx(i - 1, c) = o.cs * x + o.sn * y;
+          Sx(i, c) = o.cs * y - o.sn * x;
+        }
+        for (int r = lane; r < i - 1; r += 64) {
+          const double x = Sx(r, i - 1), y = Sx(r, i);
+          Sx(r, i - 1) = o.cs * x + o.sn * y;
+          Sx(r, i) = o.cs * y - o.sn * x;
+        }
+        for (int r = lane; r < m; r += 64) {
+          const double x = Zx(r, i - 1), y = Zx(r, i);
+          Zx(r, i - 1) = o.cs * x + o.sn * y;
+          Zx(r, i) = o.cs * y - o.sn * x;
+        }
+      }
+      if (lane == 0) {
+        if (WANTZ) {
+          Sx(i - 1, i - 1) = o.a; Sx(i - 1, i) = o.b;
+          Sx(i, i - 1) = o.c;     Sx(i, i) = o.d;
+        }
+        if (T.wr) {
+          T.wr[i - 1] = o.wr1; T.wi[i - 1] = o.wi1;
+          T.wr[i] = o.wr2;     T.wi[i] = o.wi2;
+        }
+      }
+      __syncthreads();
+      i -= 2; its = 0;
+      continue;
+    }
+    its += 1;
+    if (its > itmax) { info = i + 1; break; }
+
+    // ---- shifts: trailing 2x2 (Francis) or the ad-hoc exceptional pair
+    double s, t;
+    if (its == 10 || its == 20) {
+      double w, e;
+      if (its == 10) {
+        w = fabs(Sx(i, i - 1)) + fabs(Sx(i - 1, i - 2));
+        e = Sx(i, i) + 0.75 * w;
+      } else {
+        w = fabs(Sx(l + 1, l)) + fabs(Sx(l + 2, l + 1));
+        e = Sx(l, l) + 0.75 * w;
+      }
+      s = e + e;
+      t = e * e + 0.4375 * w * w;
+    } else {
+      const double a = Sx(i - 1, i - 1), b = Sx(i - 1, i), c = Sx(i, i - 1), d = Sx(i, i);
+      s = a + d;
+      t = a * d - b * c;
+    }
+
+    // ---- one double-shift step on rows/cols l..i
+    const int cend = WANTZ ? m - 1 : i;    // last column of left updates
+    const int rbeg = WANTZ ? 0 : l;        // first row of right updates
+    double x, y, z;
+    first_column(Sx(l, l), Sx(l, l + 1), Sx(l + 1, l), Sx(l + 1, l + 1), Sx(l + 2, l + 1), s, t,
+                 x, y, z);
+    for (int r = l; r <= i - 1; ++r) {
+      const int nr = (r <= i - 2) ? 3 : 2;
+      if (r > l) {
+        x = Sx(r, r - 1);
+        y = Sx(r + 1, r - 1);
+        z = (nr == 3) ? Sx(r + 2, r - 1) : 0.0;
+      }
+      const Refl h = make_reflector(nr, x, y, z);
+      __syncthreads();
+      if (h.tau == 0.0) continue;
+      const double tv2 = h.tau * h.v2, tv3 = h.tau * h.v3;
+      for (int c = r + lane; c <= cend; c += 64) {
+        const double a1 = Sx(r, c), a2 = Sx(r + 1, c);
+        const double a3 = (nr == 3) ? Sx(r + 2, c) : 0.0;
+        const double w = a1 + h.v2 * a2 + h.v3 * a3;
+        Sx(r, c) = a1 - h.tau * w;
+        Sx(r + 1, c) = a2 - tv2 * w;
+        if (nr == 3) Sx(r + 2, c) = a3 - tv3 * w;
+      }
+      if (r > l && lane == 0) {
+        Sx(r, r - 1) = h.beta;
+        Sx(r + 1, r - 1) = 0.0;
+        if (nr == 3) Sx(r + 2, r - 1) = 0.0;
+      }
+      __syncthreads();
+      const int rlast = (r + 3 < i) ? r + 3 : i;
+      for (int q = rbeg + lane; q <= rlast; q += 64) {
+        const double a1 = Sx(q, r), a2 = Sx(q, r + 1);
+        const double a3 = (nr == 3) ? Sx(q, r + 2) : 0.0;
+        const double w = a1 + h.v2 * a2 + h.v3 * a3;
+        Sx(q, r) = a1 - h.tau * w;
+        Sx(q, r + 1) = a2 - tv2 * w;
+        if (nr == 3) Sx(q, r + 2) = a3 - tv3 * w;
+      }
+      if (WANTZ) {
+        for (int q = lane; q < m; q += 64) {
+          const double a1 = Zx(q, r), a2 = Zx(q, r + 1);
+          const double a3 = (nr == 3) ? Zx(q, r + 2) : 0.0;
+          const double w = a1 + h.v2 * a2 + h.v3 * a3;
+          Zx(q, r) = a1 - h.tau * w;
+          Zx(q, r + 1) = a2 - tv2 * w;
+          if (nr == 3) Zx(q, r + 2) = a3 - tv3 * w;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  return info;
+}
+
+template <bool WANTZ, int MAXM>
+__device__ void small_load(const SmallTask& T, double* S, double* Zs) {
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  const int m = T.m;
+  const int lane = threadIdx.x;
+  for (int c = 0; c < m; ++c)
+    for (int r = lane; r < m; r += 64)
+      S[r + c * LD] = (r <= c + 1) ? T.A[r + (size_t)c * T.lda] : 0.0;
+  if (WANTZ)
+    for (int c = 0; c < m; ++c)
+      for (int r = lane; r < m; r += 64) Zs[r + c * LD] = (r == c) ? 1.0 : 0.0;
+  __syncthreads();
+}
+
+// ============================================================================
+// Aggressive early deflation (paper Sec. 3.2: the algorithm alternates AED
+// steps with bulge-chasing sweeps).  One wavefront owns a bottom window
+// W = H(kwtop:kbot, kwtop:kbot) of order nw <= SMALL_Z_MAX and its spike
+// s = H(kwtop, kwtop-1):
+//   1. real Schur form W = V T V^T in LDS (the small Francis iteration);
+//   2. from the bottom of T, a diagonal block whose spike entries s V(0, .)
+//      are negligible next to it is deflated; a block that is not is moved
+//      to the top of the unchecked part by orthogonal swaps of adjacent
+//      diagonal blocks (direct swapping: a Sylvester equation for the
+//      invariant subspace, then its QR factor);
+//   3. the spike of the undeflated part is reflected onto its first entry
+//      and the undeflated part is brought back to Hessenberg form;
+//   4. T goes back into H, V^T into a panel slot; the caller applies V to
+//      the rows right of the window, the rows above it and to Q.
+// The eigenvalues of the undeflated blocks are the next sweep's shifts.
+// ============================================================================
+
+// 64-lane sums and maxima (all lanes receive the result)
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+// Solve M x = b (N <= 4) by Givens QR; a diagonal entry of R below smin in
+// magnitude is replaced by +-smin.  b is overwritten by x.
+template <int N>
+__device__ inline void tiny_solve(double (&M)[N][N], double (&b)[N], double smin) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      const double a = M[j][j], c = M[i][j];
+      const double r = hypot(a, c);
+      const double cs = (r == 0.0) ? 1.0 : a / r;
+      const double sn = (r == 0.0) ? 0.0 : c / r;
+#pragma unroll
+      for (int k = j; k < N; ++k) {
+        const double x = M[j][k], y = M[i][k];
+        M[j][k] = cs * x + sn * y;
+        M[i][k] = cs * y - sn * x;
+      }
+      const double x = b[j], y = b[i];
+      b[j] = cs * x + sn * y;
+      b[i] = cs * y - sn * x;
+    }
+  }
+#pragma unroll
+  for (int j = N - 1; j >= 0; --j) {
+    double acc = b[j];
+#pragma unroll
+    for (int k = j + 1; k < N; ++k) acc -= M[j][k] * b[k];
+    double d = M[j][j];
+    if (fabs(d) < smin) d = (d < 0.0) ? -smin : smin;
+    b[j] = acc / d;
+  }
+}
+
+// Householder reflectors of one swap: reflector h is I - tau[h] v[h] v[h]^T
+// on rows/columns k .. k+N-1 (v[h][i] = 0 for i < h, v[h][h] = 1).
+struct SwapPlan {
+  double v[2][4];
+  double tau[2];
+};
+
+// Plan the swap of the adjacent diagonal blocks A (P x P, at k) and
+// B (R x R, at k + P) of the quasi-triangular T (LDS, leading dimension LD).
+// With A X - X B = -C (C the coupling block) the columns of [X; I] span the
+// invariant subspace of B; the orthogonal factor of their QR factorisation
+// moves B to the top.  Returns false when the transformed block fails the
+// backward-stability test (the swap is then not done).
+template <int P, int R>
+__device__ bool plan_swap(const double* S, int LD, int k, SwapPlan& pl) {
+  constexpr int N = P + R;
+  constexpr int M = P * R;
+  double T[N][N];
+  double dnorm = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      T[i][j] = (i <= j + 1) ? S[(k + i) + (k + j) * LD] : 0.0;
+      dnorm = fmax(dnorm, fabs(T[i][j]));
+    }
+  const double tiny = 2.2250738585072014e-308;
+  const double smin = fmax(kUlp * dnorm, tiny);
+  // Kronecker form of A X - X B = -C, unknown x[i + P j] = X(i, j)
+  double K[M][M], x[M];
+#pragma unroll
+  for (int j = 0; j < R; ++j)
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+#pragma unroll
+      for (int jj = 0; jj < R; ++jj)
+#pragma unroll
+        for (int ii = 0; ii < P; ++ii)
+          K[i + P * j][ii + P * jj] = (jj == j ? T[i][ii] : 0.0) - (ii == i ? T[P + jj][P + j] : 0.0);
+      x[i + P * j] = -T[i][P + j];
+    }
+  tiny_solve<M>(K, x, smin);
+  // W = [X; I] (N x R), QR by R Householder reflectors
+  double W[N][R];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) W[i][j] = (i < P) ? x[i + P * j] : (i - P == j ? 1.0 : 0.0);
+#pragma unroll
+  for (int h = 0; h < R; ++h) {
+    double tail = 0.0;
+#pragma unroll
+    for (int i = h + 1; i < N; ++i) tail = fmax(tail, fabs(W[i][h]));
+    const double alpha = W[h][h];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pl.v[h][i] = 0.0;
+    pl.v[h][h] = 1.0;
+    pl.tau[h] = 0.0;
+    if (tail == 0.0 || !isfinite(tail) || !isfinite(alpha)) {
+      if (!(tail == 0.0)) return false;
+      continue;
+    }
+    const int e = ilogb(fmax(fabs(alpha), tail));
+    double ss = 0.0;
+#pragma unroll
+    for (int i = h + 1; i < N; ++i) {
+      const double t = ldexp(W[i][h], -e);
+      ss += t * t;
+    }
+    const double as = ldexp(alpha, -e);
+    const double nrm = sqrt(as * as + ss);
+    const double bs = (as < 0.0) ? nrm : -nrm;
+    const double ds = as - bs;
+    const double r = 1.0 / (bs * ds);
+    pl.tau[h] = -ds * (ds * r);
+#pragma unroll
+    for (int i = h + 1; i < N; ++i) pl.v[h][i] = ldexp(W[i][h], -e) * (bs * r);
+    // apply to the remaining columns of W
+#pragma unroll
+    for (int j = h + 1; j < R; ++j) {
+      double w = 0.0;
+#pragma unroll
+      for (int i = h; i < N; ++i) w += pl.v[h][i] * W[i][j];
+#pragma unroll
+      for (int i = h; i < N; ++i) W[i][j] -= pl.tau[h] * pl.v[h][i] * w;
+    }
+  }
+  // T' = Q^T T Q with Q = H_0 H_1 ...; accept if its lower-left block is tiny
+#pragma unroll
+  for (int h = 0; h < R; ++h) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double w = 0.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) w += pl.v[h][i] * T[i][j];
+#pragma unroll
+      for (int i = 0; i < N; ++i) T[i][j] -= pl.tau[h] * pl.v[h][i] * w;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double w = 0.0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) w += T[i][j] * pl.v[h][j];
+#pragma unroll
+      for (int j = 0; j < N; ++j) T[i][j] -= pl.tau[h] * w * pl.v[h][j];
+    }
+  }
+  double low = 0.0;
+#pragma unroll
+  for (int i = R; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) low = fmax(low, fabs(T[i][j]));
+  const double thresh = fmax(20.0 * kUlp * dnorm, tiny);
+  return low <= thresh;   // false for NaN as well
+}
+
+// Rotate rows/columns i, i+1 of the m x m quasi-triangular S (and columns of
+// Z) so that the 2x2 block at i is in standard form.  Returns whether the
+// block stayed a complex pair.
+__device__ bool aed_std_block(double* S, double* Zs, int LD, int m, int i) {
+  const int lane = threadIdx.x;
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
+  const Std2 o = standardize2(Sx(i, i), Sx(i, i + 1), Sx(i + 1, i), Sx(i + 1, i + 1));
+  __syncthreads();
+  if (!(o.cs == 1.0 && o.sn == 0.0)) {
+    for (int c = i + 2 + lane; c < m; c += 64) {
+      const double x = Sx(i, c), y = Sx(i + 1, c);
+      Sx(i, c) = o.cs * x + o.sn * y;
+      Sx(i + 1, c) = o.cs * y - o.sn * x;
+    }
+    for (int r = lane; r < i; r += 64) {
+      const double x = Sx(r, i), y = Sx(r, i + 1);
+      Sx(r, i) = o.cs * x + o.sn * y;
+      Sx(r, i + 1) = o.cs * y - o.sn * x;
+    }
+    for (int r = lane; r < m; r += 64) {
+      const double x = Zx(r, i), y = Zx(r, i + 1);
+      Zx(r, i) = o.cs * x + o.sn * y;
+      Zx(r, i + 1) = o.cs * y - o.sn * x;
+    }
+  }
+  if (lane == 0) {
+    Sx(i, i) = o.a; Sx(i, i + 1) = o.b;
+    Sx(i + 1, i) = o.c; Sx(i + 1, i + 1) = o.d;
+  }
+  __syncthreads();
+  return o.c != 0.0;
+}
+
+// Swap the adjacent diagonal blocks of orders p (at k) and r (at k + p) of
+// the m x m quasi-triangular S, updating the columns of Z.  Returns 0 when
+// done, 1 when the swap was rejected (nothing changed), 2 when the moved
+// block (now at k) split into two real eigenvalues.
+__device__ int aed_swap(double* S, double* Zs, int LD, int m, int k, int p, int r,
+                        SwapPlan* plds) {
+  const int lane = threadIdx.x;
+  auto Sx = [&](int rr, int c) -> double& { return S[rr + c * LD]; };
+  __shared__ int ok_lds;
+  __shared__ double dA, dB;
+  if (lane == 0) {
+    SwapPlan pl;
+    bool ok;
+    if (p == 1 && r == 1) ok = plan_swap<1, 1>(S, LD, k, pl);
+    else if (p == 1) ok = plan_swap<1, 2>(S, LD, k, pl);
+    else if (r == 1) ok = plan_swap<2, 1>(S, LD, k, pl);
+    else ok = plan_swap<2, 2>(S, LD, k, pl);
+    *plds = pl;
+    ok_lds = ok ? 1 : 0;
+    dA = Sx(k, k);           // the 1x1 eigenvalues are restored exactly
+    dB = Sx(k + p + r - 1, k + p + r - 1);
+  }
+  __syncthreads();
+  if (!ok_lds) return 1;
+  const int N = p + r;
+  // left: rows k .. k+N-1, columns k .. m-1
+  for (int c = k + lane; c < m; c += 64) {
+    double a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = (i < N) ? Sx(k + i, c) : 0.0;
+    for (int h = 0; h < r; ++h) {
+      double w = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w += plds->v[h][i] * a[i];
+      w *= plds->tau[h];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] -= plds->v[h][i] * w;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i < N) Sx(k + i, c) = a[i];
+  }
+  __syncthreads();
+  // right: columns k .. k+N-1 of rows 0 .. k+N-1 of S and all rows of Z
+  for (int q = lane; q < m + k + N; q += 64) {
+    const bool inS = q < k + N;
+    double* base = inS ? S : Zs;
+    const int row = inS ? q : q - (k + N);
+    double a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = (i < N) ? base[row + (k + i) * LD] : 0.0;
+    for (int h = 0; h < r; ++h) {
+      double w = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w += a[i] * plds->v[h][i];
+      w *= plds->tau[h];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] -= w * plds->v[h][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i < N) base[row + (k + i) * LD] = a[i];
+  }
+  __syncthreads();
+  if (lane == 0) {
+    for (int i = r; i < N; ++i)
+      for (int j = 0; j < r; ++j) Sx(k + i, k + j) = 0.0;
+    if (r == 1) Sx(k, k) = dB;
+    if (p == 1) Sx(k + r, k + r) = dA;
+  }
+  __syncthreads();
+  int ret = 0;
+  if (r == 2 && !aed_std_block(S, Zs, LD, m, k)) ret = 2;
+  if (p == 2) (void)aed_std_block(S, Zs, LD, m, k + r);
+  return ret;
+}
+
+// Householder reflector from a column held one entry per lane-slot:
+// x0 = alpha (scalar), tail entries x[i] for i in [1, L) at LDS vv[i].
+// On return vv[0] = 1, vv[1..L) = v, and the function yields (tau, beta).
+// tau = 0 (identity) when the tail is zero.
+__device__ void aed_reflector(double alpha, double* vv, int L, double& tau, double& beta) {
+  const int lane = threadIdx.x;
+  double tmax = 0.0;
+  for (int i = 1 + lane; i < L; i += 64) tmax = fmax(tmax, fabs(vv[i]));
+  tmax = wave_max(tmax);
+  if (tmax == 0.0) {
+    tau = 0.0;
+    beta = alpha;
+    __syncthreads();
+    if (lane == 0) vv[0] = 1.0;
+    __syncthreads();
+    return;
+  }
+  const int e = ilogb(fmax(fabs(alpha), tmax));
+  double ss = 0.0;
+  for (int i = 1 + lane; i < L; i += 64) {
+    const double t = ldexp(vv[i], -e);
+    ss += t * t;
+  }
+  ss = wave_sum(ss);
+  const double as = ldexp(alpha, -e);
+  const double nrm = sqrt(as * as + ss);
+  const double bs = (as < 0.0) ? nrm : -nrm;
+  const double ds = as - bs;
+  const double r = 1.0 / (bs * ds);
+  tau = -ds * (ds * r);
+  beta = ldexp(bs, e);
+  const double f = bs * r;
+  __syncthreads();
+  for (int i = 1 + lane; i < L; i += 64) vv[i] = ldexp(vv[i], -e) * f;
+  if (lane == 0) vv[0] = 1.0;
+  __syncthreads();
+}
+
+// The whole early-deflation step on one window; S, Z (LD x MAXM each), vv
+// (MAXM) and plan live in LDS and belong to the calling wavefront.
+template <int MAXM>
+__device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, SwapPlan& plan) {
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  const int lane = threadIdx.x;
+  const int nw = T.nw;
+  const int kwtop = T.kbot - nw + 1;
+  if (nw < 1 || nw > MAXM || kwtop < T.ktop) return;
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  auto Zx = [&](int r, int c) -> double& { return Z[r + c * LD]; };
+  double* Hw = T.H + kwtop + (size_t)kwtop * T.ldh;
+  const double s = (kwtop > T.ktop) ? T.H[kwtop + (size_t)(kwtop - 1) * T.ldh] : 0.0;
+
+  SmallTask st{};
+  st.A = Hw; st.lda = T.ldh; st.m = nw; st.itmax = T.itmax;
+  small_load<true, MAXM>(st, S, Z);
+  const int info = small_iter<true, MAXM>(st, S, Z);
+  if (info != 0) {   // window not in Schur form: no deflation, no shifts
+    if (lane == 0) { T.ctrl->aed_nd = 0; T.ctrl->aed_nu = 0; }
+    return;
+  }
+
+  // ---- deflation checks from the bottom, undeflatable blocks moved up
+  const double tiny = 2.2250738585072014e-308;
+  const double smlnum = tiny * ((double)nw / kUlp);
+  int bot = nw - 1, ilst = 0;
+  bool stop = false;
+  while (!stop && ilst <= bot) {
+    const int bs = (bot > ilst && Sx(bot, bot - 1) != 0.0) ? 2 : 1;
+    double foo, spk;
+    if (bs == 1) {
+      foo = fabs(Sx(bot, bot));
+      spk = fabs(s * Zx(0, bot));
+    } else {
+      foo = fabs(Sx(bot, bot)) + sqrt(fabs(Sx(bot, bot - 1))) * sqrt(fabs(Sx(bot - 1, bot)));
+      spk = fmax(fabs(s * Zx(0, bot)), fabs(s * Zx(0, bot - 1)));
+    }
+    if (foo == 0.0) foo = fabs(s);
+    __syncthreads();
+    if (spk <= fmax(smlnum, kUlp * foo)) {
+      bot -= bs;
+      continue;
+    }
+    int pos = bot - bs + 1;
+    while (pos > ilst) {
+      const int above = (pos - 2 >= ilst && Sx(pos - 1, pos - 2) != 0.0) ? 2 : 1;
+      __syncthreads();
+      const int k = pos - above;
+      if (aed_swap(S, Z, LD, nw, k, above, bs, &plan) != 0) { stop = true; break; }
+      pos = k;
+    }
+    if (!stop) ilst += bs;
+  }
+  const int nu = bot + 1;
+  const int nd = nw - nu;
+
+  // ---- eigenvalues: undeflated blocks give the next shifts, deflated ones
+  // are final (written when the caller asks for them)
+  for (int e = lane; e < nw; e += 64) {
+    const bool first = (e + 1 < nw) && Sx(e + 1, e) != 0.0;
+    const bool second = (e >= 1) && Sx(e, e - 1) != 0.0;
+    double wr = Sx(e, e), wi = 0.0;
+    if (first) wi = sqrt(fabs(Sx(e, e + 1))) * sqrt(fabs(Sx(e + 1, e)));
+    if (second) wi = -sqrt(fabs(Sx(e - 1, e))) * sqrt(fabs(Sx(e, e - 1)));
+    if (e < nu) {
+      T.sr[e] = wr;
+      T.si[e] = wi;
+    } else if (T.wr) {
+      T.wr[e] = wr;
+      T.wi[e] = wi;
+    }
+  }
+  if (lane == 0) { T.ctrl->aed_nd = nd; T.ctrl->aed_nu = nu; }
+  if (nd == 0) return;   // nothing deflated: H stays as it was
+
+  // ---- reflect the spike of the undeflated part onto its first entry
+  double spike = 0.0;
+  if (nu == 1) {
+    spike = s * Zx(0, 0);
+  } else if (nu > 1) {
+    for (int i = lane; i < nu; i += 64) vv[i] = s * Zx(0, i);
+    __syncthreads();
+    const double alpha = vv[0];
+    double tau, beta;
+    aed_reflector(alpha, vv, nu, tau, beta);
+    spike = beta;
+    if (tau != 0.0) {
+      for (int c = lane; c < nw; c += 64) {          // rows 0..nu-1, all columns
+        double w = 0.0;
+        for (int i = 0; i < nu; ++i) w += vv[i] * Sx(i, c);
+        w *= tau;
+        for (int i = 0; i < nu; ++i) Sx(i, c) -= vv[i] * w;
+      }
+      __syncthreads();
+      for (int q = lane; q < nu + nw; q += 64) {     // columns 0..nu-1 of S rows < nu, and of Z
+        double* base = (q < nu) ? S : Z;
+        const int row = (q < nu) ? q : q - nu;
+        double w = 0.0;
+        for (int j = 0; j < nu; ++j) w += base[row + j * LD] * vv[j];
+        w *= tau;
+        for (int j = 0; j < nu; ++j) base[row + j * LD] -= w * vv[j];
+      }
+      __syncthreads();
+    }
+    // ---- Hessenberg form of the undeflated part
+    for (int j = 0; j + 2 < nu; ++j) {
+      const int L = nu - j - 1;                       // rows j+1 .. nu-1
+      const double a0 = Sx(j + 1, j);
+      for (int i = 1 + lane; i < L; i += 64) vv[i] = Sx(j + 1 + i, j);
+      __syncthreads();
+      double tj, bj;
+      aed_reflector(a0, vv, L, tj, bj);
+      if (tj == 0.0) continue;
+      if (lane == 0) Sx(j + 1, j) = bj;
+      for (int i = 2 + lane; i <= L; i += 64) Sx(j + i, j) = 0.0;
+      for (int c = j + 1 + lane; c < nw; c += 64) {  // left: rows j+1..nu-1
+        double w = 0.0;
+        for (int i = 0; i < L; ++i) w += vv[i] * Sx(j + 1 + i, c);
+        w *= tj;
+        for (int i = 0; i < L; ++i) Sx(j + 1 + i, c) -= vv[i] * w;
+      }
+      __syncthreads();
+      for (int q = lane; q < nu + nw; q += 64) {     // right: columns j+1..nu-1
+        double* base = (q < nu) ? S : Z;
+        const int row = (q < nu) ? q : q - nu;
+        double w = 0.0;
+        for (int i = 0; i < L; ++i) w += base[row + (j + 1 + i) * LD] * vv[i];
+        w *= tj;
+        for (int i = 0; i < L; ++i) base[row + (j + 1 + i) * LD] -= w * vv[i];
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- write back: the window, its spike, and V^T into the panel slot
+  for (int c = 0; c < nw; ++c)
+    for (int r = lane; r <= c + 1 && r < nw; r += 64) Hw[r + (size_t)c * T.ldh] = Sx(r, c);
+  if (lane == 0 && kwtop > T.ktop) T.H[kwtop + (size_t)(kwtop - 1) * T.ldh] = spike;
+  for (int c = 0; c < T.ldut; ++c)
+    for (int r = lane; r < T.ldut; r += 64)
+      T.Ut[r + (size_t)c * T.ldut] = (r < nw && c < nw) ? Zx(c, r) : 0.0;
+}
+
+
+}  // namespace schur

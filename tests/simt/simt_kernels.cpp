@@ -1,0 +1,152 @@
+// Host driver that runs the device source of two LDS kernels on the CPU
+// (see hip/hip_runtime.h): the window chase of a sweep time step and the
+// early-deflation window step.  Test infrastructure.
+//
+//   simt_kernels chase in.bin out.bin
+//     in : int n, ktop, kbot, nst, nwin; double H[n*n] (column-major);
+//          double st[nst]; nwin x int (p, ws, tau0, tau1, nb, shift0)
+//     out: double H[n*n]; nwin x double Ut[128*128]
+//   simt_kernels aed in.bin out.bin
+//     in : int n, ktop, kbot, nw; double H[n*n]
+//     out: int nd, nu; double H[n*n]; double Ut[128*128]; double sr[96], si[96];
+//          double wr[n], wi[n]
+#include "hip/hip_runtime.h"
+#include "wave_solvers.h"
+#include "window_chase.h"
+
+#include <pthread.h>
+
+#include <cstdio>
+#include <string>
+#include <thread>
+#include <vector>
+
+thread_local simt_dim3 threadIdx;
+thread_local simt_dim3 blockIdx;
+simt_dim3 blockDim{64, 1, 1};
+
+namespace {
+pthread_barrier_t g_all, g_wave[16];
+int g_threads = 64;
+double g_shfl[1024];
+int g_ball[1024];
+}  // namespace
+
+void __syncthreads() { pthread_barrier_wait(&g_all); }
+void simt_wave_barrier() { pthread_barrier_wait(&g_wave[threadIdx.x >> 6]); }
+
+// only used by one-wavefront kernels (workgroup = one wavefront)
+double __shfl_xor(double x, int o, int) {
+  const int l = threadIdx.x;
+  g_shfl[l] = x;
+  __syncthreads();
+  const double r = g_shfl[l ^ o];
+  __syncthreads();
+  return r;
+}
+
+unsigned long long __ballot(int p) {
+  const int l = threadIdx.x;
+  g_ball[l] = p != 0;
+  __syncthreads();
+  unsigned long long m = 0;
+  for (int i = 0; i < 64; ++i)
+    if (g_ball[i]) m |= 1ull << i;
+  __syncthreads();
+  return m;
+}
+
+extern char __start_simt_lds[], __stop_simt_lds[];
+
+template <class F>
+void run_workgroup(int threads, int block, F f) {
+  memset(__start_simt_lds, 0xff, (size_t)(__stop_simt_lds - __start_simt_lds));   // NaN
+  g_threads = threads;
+  blockDim = simt_dim3{(unsigned)threads, 1, 1};
+  pthread_barrier_init(&g_all, nullptr, threads);
+  for (int w = 0; w < threads / 64; ++w) pthread_barrier_init(&g_wave[w], nullptr, 64);
+  std::vector<std::thread> th;
+  for (int l = 0; l < threads; ++l)
+    th.emplace_back([=] {
+      threadIdx = simt_dim3{(unsigned)l, 0, 0};
+      blockIdx = simt_dim3{(unsigned)block, 0, 0};
+      f();
+    });
+  for (auto& t : th) t.join();
+  pthread_barrier_destroy(&g_all);
+  for (int w = 0; w < threads / 64; ++w) pthread_barrier_destroy(&g_wave[w]);
+}
+
+template <class T>
+bool rd(FILE* f, T* p, size_t n) { return fread(p, sizeof(T), n, f) == n; }
+
+using namespace schur;
+
+int main(int argc, char** argv) {
+  if (argc != 4) return 2;
+  const std::string mode = argv[1];
+  FILE* f = fopen(argv[2], "rb");
+  if (!f) return 2;
+  if (mode == "chase") {
+    int hdr[5];
+    if (!rd(f, hdr, 5)) return 2;
+    const int n = hdr[0], ktop = hdr[1], kbot = hdr[2], nst = hdr[3], nwin = hdr[4];
+    std::vector<double> H((size_t)n * n), st(nst);
+    std::vector<int> wd(6 * (size_t)nwin);
+    if (!rd(f, H.data(), H.size()) || !rd(f, st.data(), st.size()) || !rd(f, wd.data(), wd.size()))
+      return 2;
+    fclose(f);
+    std::vector<double> U((size_t)nwin * UPAD * UPAD, NAN);
+    for (int w = 0; w < nwin; ++w) {
+      WinCtx c{};
+      c.H = H.data(); c.Q = nullptr; c.U = U.data() + (size_t)w * UPAD * UPAD;
+      c.st = st.data() + 2 * wd[6 * w + 5];
+      c.ldh = n; c.ldq = n; c.n = n; c.ktop = ktop; c.kbot = kbot; c.rtop = 0; c.cend = n;
+      c.p = wd[6 * w]; c.ws = wd[6 * w + 1]; c.tau0 = wd[6 * w + 2]; c.tau1 = wd[6 * w + 3];
+      c.nb = wd[6 * w + 4];
+      run_workgroup(CHASE_THREADS, w, [c] { chase_window(c); });
+    }
+    FILE* g = fopen(argv[3], "wb");
+    fwrite(H.data(), sizeof(double), H.size(), g);
+    fwrite(U.data(), sizeof(double), U.size(), g);
+    fclose(g);
+    return 0;
+  }
+  if (mode == "aed") {
+    constexpr int MAXM = SMALL_Z_MAX;
+    constexpr int LD = SmallSmem<MAXM>::LD;
+    int hdr[4];
+    if (!rd(f, hdr, 4)) return 2;
+    const int n = hdr[0];
+    std::vector<double> H((size_t)n * n), Ut(UPAD * UPAD, NAN), sr(MAXM, NAN), si(MAXM, NAN),
+        wr(n, NAN), wi(n, NAN);
+    if (!rd(f, H.data(), H.size())) return 2;
+    fclose(f);
+    static std::vector<double> S(LD * MAXM), Z(LD * MAXM), vv(MAXM);
+    static SwapPlan plan;
+    for (auto* v : {&S, &Z, &vv})
+      for (double& x : *v) x = NAN;
+    Ctrl ctrl{};
+    ctrl.aed_nd = -99;
+    ctrl.aed_nu = -99;
+    AedTask T{};
+    T.H = H.data(); T.ldh = n; T.ktop = hdr[1]; T.kbot = hdr[2]; T.nw = hdr[3];
+    T.Ut = Ut.data(); T.ldut = UPAD; T.sr = sr.data(); T.si = si.data();
+    const int kwtop = T.kbot - T.nw + 1;
+    T.wr = wr.data() + kwtop; T.wi = wi.data() + kwtop;
+    T.ctrl = &ctrl; T.itmax = 30;
+    run_workgroup(64, 0, [T] { aed_window<MAXM>(T, S.data(), Z.data(), vv.data(), plan); });
+    FILE* g = fopen(argv[3], "wb");
+    const int o[2] = {ctrl.aed_nd, ctrl.aed_nu};
+    fwrite(o, sizeof(int), 2, g);
+    fwrite(H.data(), sizeof(double), H.size(), g);
+    fwrite(Ut.data(), sizeof(double), Ut.size(), g);
+    fwrite(sr.data(), sizeof(double), MAXM, g);
+    fwrite(si.data(), sizeof(double), MAXM, g);
+    fwrite(wr.data(), sizeof(double), n, g);
+    fwrite(wi.data(), sizeof(double), n, g);
+    fclose(g);
+    return 0;
+  }
+  return 2;
+}

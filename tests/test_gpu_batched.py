@@ -48,7 +48,13 @@ def test_batched_mixed_sizes(gpu_lib):
         cost = np.abs(w[:, None] - wref[None, :])
         r, c = linear_sum_assignment(cost)
         assert np.all(cost[r, c] <= checks.kappa_tolerance(H, wref[c], kappa[c], factor=100.0)), n
-        assert checks.match_eigs(w, wr + 1j * wi).max() <= 1e-9 * max(1.0, np.linalg.norm(H)), n
+        # against the oracle: random spectra are not well conditioned, so the
+        # bound is condition weighted (both sides carry a backward error)
+        lam_o = wr + 1j * wi
+        cost_o = np.abs(w[:, None] - lam_o[None, :])
+        ro, co = linear_sum_assignment(cost_o)
+        ko = kappa[np.argmin(np.abs(lam_o[co][:, None] - wref[None, :]), axis=1)]
+        assert np.all(cost_o[ro, co] <= checks.kappa_tolerance(H, lam_o[co], ko, factor=200.0)), n
     h.close()
 
 

@@ -1,0 +1,224 @@
+"""Device source of the LDS kernels run on the CPU (no GPU needed).
+
+``tests/simt/`` compiles the HIP source of the window chase and of the
+early-deflation window step with g++ against a small stand-in for the
+device API: a workgroup is a set of host threads with real barriers, LDS is
+filled with NaN before every workgroup, and AddressSanitizer watches every
+access.  So a read of LDS the kernel never wrote, an out-of-range index or a
+missing barrier shows up here, on the CPU.
+
+* window chase: whole sweeps (the sweep planner's windows, time step by time
+  step, with the panel products done in numpy) must reproduce the oracle's
+  sequential Francis double-shift steps with the same shifts (paper Sec. 3.2:
+  the multishift sweep is that sequence, applied window by window);
+* early deflation (paper Sec. 3.2): the returned V is orthogonal and
+  V^T W V is the returned window; the undeflated part is Hessenberg, the
+  deflated part quasi-triangular with no coupling back; the spike is
+  reflected onto one entry; dropped spike entries are below the deflation
+  threshold; the eigenvalues reported for both parts are those of their
+  diagonal blocks and the window's spectrum is preserved.
+"""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_04975_amd import inputs, schur
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+UPAD = 128
+ULP = 2.0 ** -52
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    out = str(tmp_path_factory.mktemp("simt") / "simt_kernels")
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined",
+           "-I", os.path.join(HERE, "simt"), "-I", os.path.join(ROOT, "paper_1905_04975_amd", "csrc"),
+           "-I", os.path.join(ROOT, "include"), os.path.join(HERE, "simt", "simt_kernels.cpp"),
+           "-o", out, "-lpthread"]
+    subprocess.check_call(cmd)
+    return out
+
+
+def _call(driver, mode, payload, tmp_path):
+    fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    with open(fin, "wb") as f:
+        for a in payload:
+            a.tofile(f)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    r = subprocess.run([driver, mode, fin, fout], capture_output=True, text=True, timeout=600,
+                       env=env)
+    assert r.returncode == 0, r.stderr[-3000:]
+    return np.fromfile(fout, dtype=np.uint8).tobytes()
+
+
+def _chase_step(driver, tmp_path, H, ktop, kbot, st, wins):
+    n = H.shape[0]
+    raw = _call(driver, "chase", [np.array([n, ktop, kbot, len(st), len(wins)], dtype=np.int32),
+                                  np.asfortranarray(H).ravel(order="F"),
+                                  np.asarray(st, dtype=np.float64),
+                                  np.array([v for w in wins for v in w], dtype=np.int32)], tmp_path)
+    x = np.frombuffer(raw, dtype=np.float64)
+    H2 = x[:n * n].reshape(n, n, order="F").copy()
+    Us = x[n * n:].reshape(len(wins), UPAD, UPAD)   # [w, i, j] = U(i, j) (slot holds U^T)
+    return H2, Us
+
+
+@pytest.mark.parametrize("n,ktop,kbot,npair,nb,seed", [
+    (160, 0, 159, 1, 1, 3), (220, 0, 219, 6, 3, 4), (300, 10, 280, 8, 8, 5),
+    (200, 0, 199, 16, 16, 6), (190, 0, 189, 20, 20, 7)])
+def test_chase_sweep_equals_sequential_double_shift_steps(driver, tmp_path, n, ktop, kbot, npair,
+                                                          nb, seed):
+    H0 = inputs.hessenberg_normal(n, seed)
+    if ktop > 0:
+        H0[ktop, ktop - 1] = 0.0
+    if kbot < n - 1:
+        H0[kbot + 1, kbot] = 0.0
+    rng = np.random.default_rng(seed)
+    shifts = []
+    for _ in range(npair):
+        a, b = rng.uniform(-1, 1, 2)
+        shifts.append((2 * a, a * a + b * b))
+    st = [v for s in shifts for v in s]
+    plan = schur.plan_sweep(ktop, kbot, npair, nb, 0)
+    H = H0.copy()
+    for t in sorted({r[0] for r in plan}):
+        wins = [(p, ws, t0, t1, b, g) for (tt, g, p, ws, t0, t1, b) in plan if tt == t]
+        H2, Us = _chase_step(driver, tmp_path, H, ktop, kbot, st, wins)
+        assert not np.isnan(H2).any()
+        for (p, ws, t0, t1, b, g), U in zip(wins, Us):
+            assert not np.isnan(U).any(), "unwritten LDS reached the U slot"
+            assert not U[ws:, :].any() and not U[:, ws:].any(), "slot not zero padded"
+            U = U[:ws, :ws]
+            assert np.linalg.norm(U.T @ U - np.eye(ws)) <= 1e-13 * ws
+            H2[p:p + ws, p + ws:] = U.T @ H2[p:p + ws, p + ws:]
+            H2[:p, p:p + ws] = H2[:p, p:p + ws] @ U
+        H = H2
+    Hs = np.asfortranarray(H0.copy())
+    Qs = np.asfortranarray(np.eye(n))
+    for (s, t) in shifts:
+        oracle.francis_step_inplace(Hs, Qs, ktop, kbot, s, t)
+    assert np.abs(np.abs(H) - np.abs(Hs)).max() <= 1e-11 * np.linalg.norm(H0)
+    assert not np.tril(H, -2).any()
+
+
+def _aed(driver, tmp_path, H, ktop, kbot, nw):
+    n = H.shape[0]
+    raw = _call(driver, "aed", [np.array([n, ktop, kbot, nw], dtype=np.int32),
+                                np.asfortranarray(H).ravel(order="F")], tmp_path)
+    nd, nu = np.frombuffer(raw[:8], dtype=np.int32)
+    x = np.frombuffer(raw[8:], dtype=np.float64)
+    H2 = x[:n * n].reshape(n, n, order="F"); x = x[n * n:]
+    U = x[:UPAD * UPAD].reshape(UPAD, UPAD); x = x[UPAD * UPAD:]   # [i, j] = V(i, j)
+    sr, si = x[:96], x[96:192]; x = x[192:]
+    return int(nd), int(nu), H2, U, sr, si, x[:n], x[n:2 * n]
+
+
+def _block_eigs(T):
+    """Eigenvalues read from the diagonal blocks of a quasi-triangular T."""
+    m = T.shape[0]
+    out = np.zeros(m, dtype=complex)
+    k = 0
+    while k < m:
+        if k + 1 < m and T[k + 1, k] != 0.0:
+            out[k:k + 2] = np.linalg.eigvals(T[k:k + 2, k:k + 2])
+            k += 2
+        else:
+            out[k] = T[k, k]
+            k += 1
+    return out
+
+
+def _converging(n, seed, steps):
+    """A random Hessenberg matrix after a few double-shift steps (oracle),
+    so that its bottom is partly converged."""
+    H = np.asfortranarray(inputs.hessenberg_normal(n, seed))
+    Q = np.asfortranarray(np.eye(n))
+    for _ in range(steps):
+        a, b, c, d = H[n - 2, n - 2], H[n - 2, n - 1], H[n - 1, n - 2], H[n - 1, n - 1]
+        oracle.francis_step_inplace(H, Q, 0, n - 1, a + d, a * d - b * c)
+    return np.array(H)
+
+
+def _graded(n, seed, m, lo):
+    H = inputs.hessenberg_normal(n, seed)
+    sub = np.ones(n - 1)
+    sub[-m:] = np.logspace(-2, lo, m)
+    H[np.arange(1, n), np.arange(n - 1)] *= sub
+    return H
+
+
+@pytest.mark.parametrize("case", ["raw400", "conv256", "conv200", "graded", "all", "top"])
+def test_aed_window(driver, tmp_path, case):
+    if case == "raw400":
+        H, ktop, nw = inputs.hessenberg_normal(400, 5), 0, 48
+    elif case == "conv256":
+        H, ktop, nw = _converging(256, 1, 4), 0, 16
+    elif case == "conv200":
+        H, ktop, nw = _converging(200, 11, 6), 0, 24
+    elif case == "graded":
+        H, ktop, nw = _graded(300, 8, 120, -13), 0, 96
+    elif case == "all":
+        H, ktop, nw = _graded(160, 9, 100, -40), 0, 40
+    else:   # window reaching up to the active block top (no spike)
+        H, ktop, nw = _graded(120, 10, 50, -6), 40, 80
+        H[40, 39] = 0.0
+    n = H.shape[0]
+    kbot = n - 1
+    kw = kbot - nw + 1
+    nd, nu, H2, Vfull, sr, si, wr, wi = _aed(driver, tmp_path, H, ktop, kbot, nw)
+    assert nd + nu == nw and nd >= 0
+    W = H[kw:, kw:]
+    if nd == 0:
+        assert np.array_equal(H2, H), "nothing deflated: H must be unchanged"
+        return
+    assert not np.isnan(H2).any() and not np.isnan(Vfull).any()
+    assert not Vfull[nw:, :].any() and not Vfull[:, nw:].any()
+    V = Vfull[:nw, :nw]
+    T = H2[kw:, kw:]
+    assert np.linalg.norm(V.T @ V - np.eye(nw)) <= 1e-13 * nw
+    assert np.linalg.norm(V.T @ W @ V - T) <= 1e-14 * nw * np.linalg.norm(W)
+    assert not np.tril(T[:nu, :nu], -2).any()
+    assert not np.tril(T[nu:, nu:], -2).any()
+    assert not T[nu:, :nu].any()
+    # spike: V^T s e1 = (beta, 0, ...) on the undeflated part, negligible below
+    s = H[kw, kw - 1] if kw > ktop else 0.0
+    spike = s * V[0, :]
+    beta = H2[kw, kw - 1] if kw > ktop else 0.0
+    if nu:
+        assert abs(spike[0] - beta) <= 1e-13 * abs(s)
+        assert np.linalg.norm(spike[1:nu]) <= 1e-13 * abs(s)
+    teig = _block_eigs(T[nu:, nu:])
+    thr = np.maximum(ULP * np.abs(teig), 1e-290)
+    # each deflated block's spike entries are below ulp times its size
+    k = 0
+    Td = T[nu:, nu:]
+    while k < nd:
+        two = k + 1 < nd and Td[k + 1, k] != 0.0
+        size = 2 if two else 1
+        blk = Td[k:k + size, k:k + size]
+        foo = abs(blk[-1, -1]) + (np.sqrt(abs(blk[1, 0])) * np.sqrt(abs(blk[0, 1])) if two else 0)
+        assert np.abs(spike[nu + k:nu + k + size]).max() <= max(1e-290, ULP * (foo or abs(s))) * 1.0001
+        k += size
+    # reported eigenvalues: deflated part final (wr, wi), undeflated shifts (sr, si)
+    got_d = wr[kw + nu:] + 1j * wi[kw + nu:]
+    assert np.allclose(got_d, teig, rtol=1e-14, atol=1e-300)
+    # the window's spectrum is preserved
+    ev0 = np.linalg.eigvals(W)
+    ev1 = np.concatenate([np.linalg.eigvals(T[:nu, :nu]) if nu else [], teig])
+    from scipy.optimize import linear_sum_assignment
+    cost = np.abs(ev0[:, None] - ev1[None, :])
+    r, c = linear_sum_assignment(cost)
+    assert cost[r, c].max() <= 1e-9 * np.linalg.norm(W)
+    if case == "graded":
+        assert nd >= 40
+    if case in ("all", "top"):
+        assert nd == nw and H2[kw, kw - 1] == 0.0
