@@ -143,12 +143,13 @@ bool is_device_ptr(const void* p) {
 
 // ---- defaults and the tuning table -----------------------------------------
 struct TuneRow {
-  int nmax, ns, nb, step;
+  int nmax, ns, nb, step, nw;   // nw: early-deflation window (0: from ns, < 0: off)
 };
 // built-in table: plain double-shift sweeps for small orders, then more
-// shifts per sweep as the order grows
+// shifts per sweep as the order grows; early-deflation windows of 64 rows
+// for large orders (measured at n = 16384: 64 beat 48 and 96)
 const TuneRow kBuiltinTune[] = {
-    {299, 2, 1, 0}, {2999, 32, 16, 0}, {5999, 64, 16, 0}, {1 << 30, 128, 16, 0}};
+    {299, 2, 1, 0, 0}, {2999, 32, 16, 0, 0}, {5999, 64, 16, 0, 64}, {1 << 30, 128, 16, 0, 64}};
 std::mutex g_tune_mu;
 std::vector<TuneRow> g_tune(std::begin(kBuiltinTune), std::end(kBuiltinTune));
 
@@ -186,8 +187,9 @@ Params resolve(const schur_opts& o, int n) {
   p.max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30 * std::max(10, n) / std::max(2, p.ns) + 100;
   p.exc_period = o.exc_period > 0 ? o.exc_period : 6;
   p.time = (o.flags & SCHUR_FLAG_TIME_KERNELS) != 0;
-  if (o.aed_window < 0) p.nw = 0;
-  else if (o.aed_window > 0) p.nw = std::min(o.aed_window, SMALL_Z_MAX);
+  const int aw = o.aed_window != 0 ? o.aed_window : tr.nw;
+  if (aw < 0) p.nw = 0;
+  else if (aw > 0) p.nw = std::min(aw, SMALL_Z_MAX);
   else p.nw = std::min(SMALL_Z_MAX, std::max(16, p.ns + p.ns / 2));
   return p;
 }
@@ -444,7 +446,7 @@ struct Solver {
     t.Zt = h->U + (size_t)buf * MAXWIN * UPAD * UPAD;
     t.ldzt = UPAD;
     t.info = &h->ctrl->small_info;
-    t.itmax = 30;
+    t.itmax = 0;   // default budget
     hipEvent_t e0 = nullptr;
     if (P.time) h->timer.begin(s, e0);
     launch_small_z(t, nullptr, 1, m, s);
@@ -479,7 +481,7 @@ struct Solver {
     t.sr = h->ewr; t.si = h->ewi;
     t.wr = wr + (kbot - nw + 1); t.wi = wi + (kbot - nw + 1);
     t.ctrl = h->ctrl;
-    t.itmax = 30;
+    t.itmax = 0;   // default budget
     hipEvent_t e0 = nullptr;
     if (P.time) h->timer.begin(s, e0);
     launch_aed(t, s);
@@ -523,7 +525,7 @@ struct Solver {
       // a shift solve that does not converge only costs shifts: its own
       // status slot, read by the shift preparation
       t.info = &h->ctrl->nshift;
-      t.itmax = 30;
+      t.itmax = 0;   // default budget
       launch_small_eig(t, s);
     }
     launch_shift_prep(h->ewr, h->ewi, ns, &h->ctrl->nshift, exceptional ? 1 : 0, H, ldh, ktop,
@@ -889,7 +891,7 @@ struct BatchEngine {
         t.wr = m.wr + m.ktop;
         t.wi = m.wi + m.ktop;
         t.info = &ctrl_d[small[q]].small_info;
-        t.itmax = 30;
+        t.itmax = 0;   // default budget
         double* slot = Ubase + (size_t)q * UPAD * UPAD;
         if (whole) {
           t.Qacc = m.Q;
@@ -947,7 +949,7 @@ struct BatchEngine {
         t.sr = base; t.si = base + SMALL_EIG_MAX;
         t.wr = m.wr + (m.kbot - nw + 1); t.wi = m.wi + (m.kbot - nw + 1);
         t.ctrl = ctrl_d + big[q];
-        t.itmax = 30;
+        t.itmax = 0;   // default budget
         ah[who.size()] = t;
         who.push_back((int)q);
       }
@@ -1043,7 +1045,7 @@ struct BatchEngine {
             t.wr = base;
             t.wi = base + SMALL_EIG_MAX;
             t.info = &ctrl_d[big[q]].nshift;   // per-matrix scratch for the shift solve
-            t.itmax = 30;
+            t.itmax = 0;   // default budget
             th[ne++] = t;
             maxns = std::max(maxns, ns);
           }
@@ -1586,7 +1588,8 @@ int schur_server_get_stats(schur_server_t S, schur_server_stats* out) {
   return 0;
 }
 
-int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, const int* step) {
+int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, const int* step,
+                     const int* nw) {
   if (count < 0) return -1;
   std::vector<TuneRow> t;
   if (count == 0) {
@@ -1594,10 +1597,11 @@ int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, c
   } else {
     if (!nmax || !ns || !nb || !step) return -2;
     for (int i = 0; i < count; ++i) {
+      const int w = nw ? nw[i] : 0;
       if (ns[i] < 2 || ns[i] > SMALL_EIG_MAX || nb[i] < 1 || nb[i] > NBMAX || step[i] < 0 ||
-          (i > 0 && nmax[i] <= nmax[i - 1]))
+          w > SMALL_Z_MAX || (w > 0 && w < 4) || (i > 0 && nmax[i] <= nmax[i - 1]))
         return -2;
-      t.push_back(TuneRow{nmax[i], ns[i] & ~1, nb[i], step[i]});
+      t.push_back(TuneRow{nmax[i], ns[i] & ~1, nb[i], step[i], w});
     }
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -13,7 +13,7 @@ struct SmallTask {
   double* Zt; int ldzt;        // optional: Z^T written into a ldzt x ldzt slot, zero padded
   double* wr; double* wi;      // optional: eigenvalues of the block
   int* info;                   // optional: 0, or 1-based end of a non-converged block
-  int itmax;                   // Francis steps allowed per block end (<= 0: 30)
+  int itmax;                   // Francis steps per deflation (<= 0: 30 max(10, m))
   double* Qacc; int ldqacc;    // optional: Qacc(0:m, 0:m) <- Qacc(0:m, 0:m) Z
 };
 

@@ -32,7 +32,8 @@ __device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
   auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
 
   int i = m - 1, its = 0, info = 0;
-  const int itmax = T.itmax > 0 ? T.itmax : 30;
+  // steps allowed per deflation (the budget of the LAPACK-style iteration)
+  const int itmax = T.itmax > 0 ? T.itmax : 30 * (m > 10 ? m : 10);
   while (i >= 0) {
     // ---- deflation search: largest k in [1, i] with a negligible subdiagonal
     int l = 0;
@@ -103,9 +104,9 @@ __device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
 
     // ---- shifts: trailing 2x2 (Francis) or the ad-hoc exceptional pair
     double s, t;
-    if (its == 10 || its == 20) {
+    if (its % 10 == 0) {   // ad-hoc pair every 10 steps without deflation
       double w, e;
-      if (its == 10) {
+      if ((its / 10) % 2 == 1) {
         w = fabs(Sx(i, i - 1)) + fabs(Sx(i - 1, i - 2));
         e = Sx(i, i) + 0.75 * w;
       } else {
@@ -371,44 +372,12 @@ __device__ bool plan_swap(const double* S, int LD, int k, SwapPlan& pl) {
   return low <= thresh;   // false for NaN as well
 }
 
-// Rotate rows/columns i, i+1 of the m x m quasi-triangular S (and columns of
-// Z) so that the 2x2 block at i is in standard form.  Returns whether the
-// block stayed a complex pair.
-__device__ bool aed_std_block(double* S, double* Zs, int LD, int m, int i) {
-  const int lane = threadIdx.x;
-  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
-  auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
-  const Std2 o = standardize2(Sx(i, i), Sx(i, i + 1), Sx(i + 1, i), Sx(i + 1, i + 1));
-  __syncthreads();
-  if (!(o.cs == 1.0 && o.sn == 0.0)) {
-    for (int c = i + 2 + lane; c < m; c += 64) {
-      const double x = Sx(i, c), y = Sx(i + 1, c);
-      Sx(i, c) = o.cs * x + o.sn * y;
-      Sx(i + 1, c) = o.cs * y - o.sn * x;
-    }
-    for (int r = lane; r < i; r += 64) {
-      const double x = Sx(r, i), y = Sx(r, i + 1);
-      Sx(r, i) = o.cs * x + o.sn * y;
-      Sx(r, i + 1) = o.cs * y - o.sn * x;
-    }
-    for (int r = lane; r < m; r += 64) {
-      const double x = Zx(r, i), y = Zx(r, i + 1);
-      Zx(r, i) = o.cs * x + o.sn * y;
-      Zx(r, i + 1) = o.cs * y - o.sn * x;
-    }
-  }
-  if (lane == 0) {
-    Sx(i, i) = o.a; Sx(i, i + 1) = o.b;
-    Sx(i + 1, i) = o.c; Sx(i + 1, i + 1) = o.d;
-  }
-  __syncthreads();
-  return o.c != 0.0;
-}
-
 // Swap the adjacent diagonal blocks of orders p (at k) and r (at k + p) of
 // the m x m quasi-triangular S, updating the columns of Z.  Returns 0 when
-// done, 1 when the swap was rejected (nothing changed), 2 when the moved
-// block (now at k) split into two real eigenvalues.
+// done, 1 when the swap was rejected (nothing changed).  The 2x2 blocks are
+// left as the swap produces them (not standardised): the swaps do not need
+// standard form, and the blocks that end up deflated are standardised once
+// at the end.
 __device__ int aed_swap(double* S, double* Zs, int LD, int m, int k, int p, int r,
                         SwapPlan* plds) {
   const int lane = threadIdx.x;
@@ -448,7 +417,8 @@ __device__ int aed_swap(double* S, double* Zs, int LD, int m, int k, int p, int 
       if (i < N) Sx(k + i, c) = a[i];
   }
   __syncthreads();
-  // right: columns k .. k+N-1 of rows 0 .. k+N-1 of S and all rows of Z
+  // right: columns k .. k+N-1 of rows 0 .. k+N-1 of S and all rows of Z;
+  // the lane of row k+i also sets the new block structure of that row
   for (int q = lane; q < m + k + N; q += 64) {
     const bool inS = q < k + N;
     double* base = inS ? S : Zs;
@@ -464,22 +434,84 @@ __device__ int aed_swap(double* S, double* Zs, int LD, int m, int k, int p, int 
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] -= w * plds->v[h][i];
     }
+    if (inS && row >= k + r) {          // below the moved block: exact zeros
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        if (j < r) a[j] = 0.0;
+    }
+    if (inS && r == 1 && row == k) a[0] = dB;
+    if (inS && p == 1 && row == k + r) a[r] = dA;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       if (i < N) base[row + (k + i) * LD] = a[i];
   }
   __syncthreads();
-  if (lane == 0) {
-    for (int i = r; i < N; ++i)
-      for (int j = 0; j < r; ++j) Sx(k + i, k + j) = 0.0;
-    if (r == 1) Sx(k, k) = dB;
-    if (p == 1) Sx(k + r, k + r) = dA;
+  return 0;
+}
+
+// Standardise every 2x2 block of the quasi-triangular S whose first row is
+// in [lo, m), updating Z.  The rotations of different blocks commute (each
+// turns its own pair of rows and its own pair of columns), so all are
+// computed first and then applied together.  buf: 7 m doubles of LDS.
+__device__ void aed_std_all(double* S, double* Zs, int LD, int m, int lo, double* buf) {
+  const int lane = threadIdx.x;
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  double* cs_l = buf;
+  double* sn_l = buf + m;
+  double* isblk = buf + 2 * m;
+  double* blk = buf + 3 * m;   // the standard block, 4 entries per start row
+  for (int i = lo + lane; i < m; i += 64) {
+    cs_l[i] = 1.0;
+    sn_l[i] = 0.0;
+    isblk[i] = 0.0;
+    if (i + 1 < m && Sx(i + 1, i) != 0.0) {
+      isblk[i] = 1.0;
+      const Std2 o = standardize2(Sx(i, i), Sx(i, i + 1), Sx(i + 1, i), Sx(i + 1, i + 1));
+      cs_l[i] = o.cs;
+      sn_l[i] = o.sn;
+      blk[4 * (i - lo) + 0] = o.a;
+      blk[4 * (i - lo) + 1] = o.b;
+      blk[4 * (i - lo) + 2] = o.c;
+      blk[4 * (i - lo) + 3] = o.d;
+    }
   }
   __syncthreads();
-  int ret = 0;
-  if (r == 2 && !aed_std_block(S, Zs, LD, m, k)) ret = 2;
-  if (p == 2) (void)aed_std_block(S, Zs, LD, m, k + r);
-  return ret;
+  // row pairs: column c meets the blocks starting at i <= c
+  for (int c = lo + lane; c < m; c += 64) {
+    for (int i = lo; i + 1 < m && i <= c; ++i) {
+      const double cs = cs_l[i], sn = sn_l[i];
+      if (cs == 1.0 && sn == 0.0) continue;
+      const double x = Sx(i, c), y = Sx(i + 1, c);
+      Sx(i, c) = cs * x + sn * y;
+      Sx(i + 1, c) = cs * y - sn * x;
+    }
+  }
+  __syncthreads();
+  // column pairs: row r of S meets the blocks with i + 1 >= r; all rows of Z
+  for (int q = lane; q < 2 * m; q += 64) {
+    const bool inS = q < m;
+    const int r = inS ? q : q - m;
+    double* base = inS ? S : Zs;
+    for (int i = lo; i + 1 < m; ++i) {
+      if (inS && r > i + 1) continue;
+      const double cs = cs_l[i], sn = sn_l[i];
+      if (cs == 1.0 && sn == 0.0) continue;
+      const double x = base[r + i * LD], y = base[r + (i + 1) * LD];
+      base[r + i * LD] = cs * x + sn * y;
+      base[r + (i + 1) * LD] = cs * y - sn * x;
+    }
+  }
+  __syncthreads();
+  // the blocks exactly in standard form (a complex pair with equal diagonal,
+  // or two real eigenvalues with a zero subdiagonal)
+  for (int i = lo + lane; i + 1 < m; i += 64) {
+    if (isblk[i] == 0.0) continue;
+    Sx(i, i) = blk[4 * (i - lo) + 0];
+    Sx(i, i + 1) = blk[4 * (i - lo) + 1];
+    Sx(i + 1, i) = blk[4 * (i - lo) + 2];
+    Sx(i + 1, i + 1) = blk[4 * (i - lo) + 3];
+  }
+  __syncthreads();
 }
 
 // Householder reflector from a column held one entry per lane-slot:
@@ -522,8 +554,27 @@ __device__ void aed_reflector(double alpha, double* vv, int L, double& tau, doub
 
 // The whole early-deflation step on one window; S, Z (LD x MAXM each), vv
 // (MAXM) and plan live in LDS and belong to the calling wavefront.
+// 2x2 block [[a, b], [c, d]]: eigenvalues (re +- sqrt(disc)) or re +- i im,
+// without assuming standard form
+__device__ __forceinline__ void block_eigs(double a, double b, double c, double d, double& re,
+                                           double& im, double& r1, double& r2) {
+  const double h = 0.5 * (a - d);
+  const double disc = h * h + b * c;
+  re = 0.5 * (a + d);
+  if (disc < 0.0) {
+    im = sqrt(-disc);
+    r1 = r2 = re;
+  } else {
+    im = 0.0;
+    const double sq = sqrt(disc);
+    r1 = re + sq;
+    r2 = re - sq;
+  }
+}
+
 template <int MAXM>
-__device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, SwapPlan& plan) {
+__device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, SwapPlan& plan,
+                           double* stdbuf) {
   constexpr int LD = SmallSmem<MAXM>::LD;
   const int lane = threadIdx.x;
   const int nw = T.nw;
@@ -555,7 +606,11 @@ __device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, S
       foo = fabs(Sx(bot, bot));
       spk = fabs(s * Zx(0, bot));
     } else {
-      foo = fabs(Sx(bot, bot)) + sqrt(fabs(Sx(bot, bot - 1))) * sqrt(fabs(Sx(bot - 1, bot)));
+      // |Re| + |Im| of the pair (the blocks are not kept in standard form)
+      double re, im, r1, r2;
+      block_eigs(Sx(bot - 1, bot - 1), Sx(bot - 1, bot), Sx(bot, bot - 1), Sx(bot, bot), re, im,
+                 r1, r2);
+      foo = (im != 0.0) ? fabs(re) + im : fmax(fabs(r1), fabs(r2));
       spk = fmax(fabs(s * Zx(0, bot)), fabs(s * Zx(0, bot - 1)));
     }
     if (foo == 0.0) foo = fabs(s);
@@ -576,6 +631,8 @@ __device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, S
   }
   const int nu = bot + 1;
   const int nd = nw - nu;
+  // the deflated blocks are final: standard form now
+  if (nd > 0) aed_std_all(S, Z, LD, nw, nu, stdbuf);
 
   // ---- eigenvalues: undeflated blocks give the next shifts, deflated ones
   // are final (written when the caller asks for them)
@@ -583,8 +640,21 @@ __device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, S
     const bool first = (e + 1 < nw) && Sx(e + 1, e) != 0.0;
     const bool second = (e >= 1) && Sx(e, e - 1) != 0.0;
     double wr = Sx(e, e), wi = 0.0;
-    if (first) wi = sqrt(fabs(Sx(e, e + 1))) * sqrt(fabs(Sx(e + 1, e)));
-    if (second) wi = -sqrt(fabs(Sx(e - 1, e))) * sqrt(fabs(Sx(e, e - 1)));
+    if (first || second) {
+      const int b0 = first ? e : e - 1;
+      double re, im, r1, r2;
+      block_eigs(Sx(b0, b0), Sx(b0, b0 + 1), Sx(b0 + 1, b0), Sx(b0 + 1, b0 + 1), re, im, r1, r2);
+      if (e >= nu) {   // standard form: read off the block as the final S shows it
+        wr = Sx(e, e);
+        wi = sqrt(fabs(Sx(b0, b0 + 1))) * sqrt(fabs(Sx(b0 + 1, b0)));
+        if (second) wi = -wi;
+      } else if (im != 0.0) {
+        wr = re;
+        wi = first ? im : -im;
+      } else {
+        wr = first ? r1 : r2;
+      }
+    }
     if (e < nu) {
       T.sr[e] = wr;
       T.si[e] = wi;

@@ -122,9 +122,9 @@ int main(int argc, char** argv) {
         wr(n, NAN), wi(n, NAN);
     if (!rd(f, H.data(), H.size())) return 2;
     fclose(f);
-    static std::vector<double> S(LD * MAXM), Z(LD * MAXM), vv(MAXM);
+    static std::vector<double> S(LD * MAXM), Z(LD * MAXM), vv(MAXM), sb(7 * MAXM);
     static SwapPlan plan;
-    for (auto* v : {&S, &Z, &vv})
+    for (auto* v : {&S, &Z, &vv, &sb})
       for (double& x : *v) x = NAN;
     Ctrl ctrl{};
     ctrl.aed_nd = -99;
@@ -135,7 +135,9 @@ int main(int argc, char** argv) {
     const int kwtop = T.kbot - T.nw + 1;
     T.wr = wr.data() + kwtop; T.wi = wi.data() + kwtop;
     T.ctrl = &ctrl; T.itmax = 30;
-    run_workgroup(64, 0, [T] { aed_window<MAXM>(T, S.data(), Z.data(), vv.data(), plan); });
+    run_workgroup(64, 0, [T] {
+      aed_window<MAXM>(T, S.data(), Z.data(), vv.data(), plan, sb.data());
+    });
     FILE* g = fopen(argv[3], "wb");
     const int o[2] = {ctrl.aed_nd, ctrl.aed_nu};
     fwrite(o, sizeof(int), 2, g);

@@ -110,3 +110,22 @@ def test_batched_bad_member_reported(gpu_lib):
     S = Ss[0].cpu().numpy()
     assert checks.residual(good, Qs[0].cpu().numpy(), S) <= 1e-12
     h.close()
+
+
+def test_batched_slow_block_converges(gpu_lib):
+    """A 166 x 166 member (batch seed 40000 + 1342) whose last small block
+    needs more Francis steps per deflation than the old limit of 30; with
+    the LAPACK-sized budget it converges, alone in a batch and solo."""
+    import torch
+
+    print("case batched n=166 seed=41342", flush=True)
+    H = inputs.hessenberg_normal(166, inputs.SEED_BATCH_BASE + 1342)
+    h = gpu_lib.Handle(0)
+    Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(H)], handle=h)
+    torch.cuda.synchronize()
+    h.close()
+    assert rc == 0 and infos == [0], infos
+    S, Q, w = Ss[0].cpu().numpy(), Qs[0].cpu().numpy(), ws[0].cpu().numpy()
+    assert checks.structure_errors(S, w.real, w.imag) == []
+    assert checks.residual(H, Q, S) <= 1e-12
+    assert checks.orthogonality(Q) <= 1e-12
