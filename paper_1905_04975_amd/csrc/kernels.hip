@@ -23,56 +23,6 @@ namespace schur {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <bool WANTZ, int MAXM>
-__device__ void small_qr(const SmallTask& T, double* S, double* Zs) {
-  constexpr int LD = SmallSmem<MAXM>::LD;
-  const int m = T.m;
-  const int lane = threadIdx.x;
-  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
-  auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
-  small_load<WANTZ, MAXM>(T, S, Zs);
-  const int info = small_iter<WANTZ, MAXM>(T, S, Zs);
-  if (lane == 0 && T.info) *T.info = info;
-  if (WANTZ) {
-    // Schur form of the block back to global memory, Z^T into the U slot layout
-    for (int c = 0; c < m; ++c)
-      for (int r = lane; r < m; r += 64) T.A[r + (size_t)c * T.lda] = Sx(r, c);
-    if (T.Zt) {
-      for (int c = 0; c < T.ldzt; ++c)
-        for (int r = lane; r < T.ldzt; r += 64)
-          T.Zt[r + (size_t)c * T.ldzt] = (r < m && c < m) ? Zx(c, r) : 0.0;
-    }
-    if (T.Z) {
-      for (int c = 0; c < m; ++c)
-        for (int r = lane; r < m; r += 64) T.Z[r + (size_t)c * T.ldz] = Zx(r, c);
-    }
-    if (T.Qacc) {
-      // Qacc <- Qacc Z, rows by lanes, 16 columns at a time; the block's LDS
-      // copy (already written back) is the staging area
-      __syncthreads();
-      for (int r = lane; r < m; r += 64) {
-        for (int c0 = 0; c0 < m; c0 += 16) {
-          double acc[16];
-#pragma unroll
-          for (int j = 0; j < 16; ++j) acc[j] = 0.0;
-          for (int k = 0; k < m; ++k) {
-            const double q = T.Qacc[r + (size_t)k * T.ldqacc];
-#pragma unroll
-            for (int j = 0; j < 16; ++j)
-              if (c0 + j < m) acc[j] += q * Zx(k, c0 + j);
-          }
-#pragma unroll
-          for (int j = 0; j < 16; ++j)
-            if (c0 + j < m) Sx(r, c0 + j) = acc[j];
-        }
-      }
-      __syncthreads();
-      for (int c = 0; c < m; ++c)
-        for (int r = lane; r < m; r += 64) T.Qacc[r + (size_t)c * T.ldqacc] = Sx(r, c);
-    }
-  }
-}
-
 template <int MAXM>
 __global__ __launch_bounds__(64) void k_small_z(SmallTask t0, const SmallTask* tasks) {
   constexpr int LD = SmallSmem<MAXM>::LD;

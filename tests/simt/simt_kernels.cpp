@@ -1,11 +1,15 @@
 // Host driver that runs the device source of two LDS kernels on the CPU
-// (see hip/hip_runtime.h): the window chase of a sweep time step and the
-// early-deflation window step.  Test infrastructure.
+// (see hip/hip_runtime.h): the window chase of a sweep time step, the
+// small-block solver and the early-deflation window step.  Test
+// infrastructure.
 //
 //   simt_kernels chase in.bin out.bin
 //     in : int n, ktop, kbot, nst, nwin; double H[n*n] (column-major);
 //          double st[nst]; nwin x int (p, ws, tau0, tau1, nb, shift0)
 //     out: double H[n*n]; nwin x double Ut[128*128]
+//   simt_kernels small in.bin out.bin
+//     in : int m; double A[m*m] (upper Hessenberg, m <= 96)
+//     out: int info; double S[m*m]; double Z[m*m]; double wr[m], wi[m]
 //   simt_kernels aed in.bin out.bin
 //     in : int n, ktop, kbot, nw; double H[n*n]
 //     out: int nd, nu; double H[n*n]; double Ut[128*128]; double sr[96], si[96];
@@ -147,6 +151,32 @@ int main(int argc, char** argv) {
     fwrite(si.data(), sizeof(double), MAXM, g);
     fwrite(wr.data(), sizeof(double), n, g);
     fwrite(wi.data(), sizeof(double), n, g);
+    fclose(g);
+    return 0;
+  }
+  if (mode == "small") {
+    constexpr int MAXM = SMALL_Z_MAX;
+    constexpr int LD = SmallSmem<MAXM>::LD;
+    int hdr[1];
+    if (!rd(f, hdr, 1)) return 2;
+    const int m = hdr[0];
+    std::vector<double> A((size_t)m * m), Zo((size_t)m * m, NAN), wr(m, NAN), wi(m, NAN);
+    if (!rd(f, A.data(), A.size())) return 2;
+    fclose(f);
+    static std::vector<double> S(LD * MAXM), Z(LD * MAXM);
+    for (auto* v : {&S, &Z})
+      for (double& x : *v) x = NAN;
+    int info = -99;
+    SmallTask T{};
+    T.A = A.data(); T.lda = m; T.m = m; T.Z = Zo.data(); T.ldz = m;
+    T.wr = wr.data(); T.wi = wi.data(); T.info = &info; T.itmax = 0;
+    run_workgroup(64, 0, [T] { small_qr<true, MAXM>(T, S.data(), Z.data()); });
+    FILE* g = fopen(argv[3], "wb");
+    fwrite(&info, sizeof(int), 1, g);
+    fwrite(A.data(), sizeof(double), A.size(), g);
+    fwrite(Zo.data(), sizeof(double), Zo.size(), g);
+    fwrite(wr.data(), sizeof(double), m, g);
+    fwrite(wi.data(), sizeof(double), m, g);
     fclose(g);
     return 0;
   }

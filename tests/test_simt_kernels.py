@@ -222,3 +222,40 @@ def test_aed_window(driver, tmp_path, case):
         assert nd >= 40
     if case in ("all", "top"):
         assert nd == nw and H2[kw, kw - 1] == 0.0
+
+
+@pytest.mark.parametrize("m,seed,kind", [(5, 1, "normal"), (33, 2, "normal"), (64, 3, "normal"),
+                                         (96, 4, "normal"), (40, 5, "prescribed"),
+                                         (60, 6, "graded")])
+def test_small_block_solver(driver, tmp_path, m, seed, kind):
+    """The single-wavefront Francis solver with Z: a standardised real Schur
+    form, H = Z S Z^T, and the eigenvalues of the oracle."""
+    from tests import checks
+
+    if kind == "prescribed":
+        A, exact = inputs.prescribed(m, seed)
+    elif kind == "graded":
+        A = _graded(m, seed, m // 2, -10)
+    else:
+        A = inputs.hessenberg_normal(m, seed)
+    raw = _call(driver, "small", [np.array([m], dtype=np.int32),
+                                  np.asfortranarray(A).ravel(order="F")], tmp_path)
+    info = int(np.frombuffer(raw[:4], dtype=np.int32)[0])
+    x = np.frombuffer(raw[4:], dtype=np.float64)
+    S = x[:m * m].reshape(m, m, order="F"); x = x[m * m:]
+    Z = x[:m * m].reshape(m, m, order="F"); x = x[m * m:]
+    wr, wi = x[:m], x[m:2 * m]
+    assert info == 0
+    assert not np.isnan(S).any() and not np.isnan(Z).any()
+    assert checks.structure_errors(S, wr, wi) == []
+    assert checks.residual(A, Z, S) <= 1e-14 * m
+    assert checks.orthogonality(Z) <= 1e-14 * m
+    _, _, owr, owi, oinfo, _ = oracle.schur(A)
+    assert oinfo == 0
+    lam, lam_o = wr + 1j * wi, owr + 1j * owi
+    w, kappa = checks.eig_condition(np.triu(A, -1))
+    k = kappa[np.argmin(np.abs(lam_o[:, None] - w[None, :]), axis=1)]
+    from scipy.optimize import linear_sum_assignment
+    cost = np.abs(lam[:, None] - lam_o[None, :])
+    r, c = linear_sum_assignment(cost)
+    assert np.all(cost[r, c] <= checks.kappa_tolerance(A, lam_o[c], k[c], factor=200.0))
