@@ -37,6 +37,37 @@ __device__ __forceinline__ Refl make_reflector(int nr, double x, double y, doubl
   return h;
 }
 
+// 1 / d for a normal, finite d: the hardware reciprocal estimate refined by
+// two Newton steps (each doubles the correct bits), fewer dependent
+// instructions than the correctly rounded division sequence.
+__device__ __forceinline__ double fast_rcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+// make_reflector with a short critical path: when x^2 + y^2 + z^2 is far
+// from overflow and underflow (the normal case) no scaling is needed; the
+// scaled construction covers the rest.  Same reflector up to rounding.
+__device__ __forceinline__ Refl make_reflector_fast(int nr, double x, double y, double z) {
+  if (nr == 2) z = 0.0;
+  const double t2 = y * y + z * z;
+  const double s2 = x * x + t2;
+  if (!(t2 > 0x1p-900 && s2 < 0x1p+900)) return make_reflector(nr, x, y, z);
+  Refl h;
+  const double l = sqrt(s2);
+  const double b = (x < 0.0) ? l : -l;   // beta
+  const double d = x - b;                // x - beta
+  const double r = fast_rcp(b * d);
+  h.beta = b;
+  h.tau = -d * (d * r);                  // (beta - x) / beta
+  h.v2 = y * (b * r);                    // y / (x - beta)
+  h.v3 = z * (b * r);
+  return h;
+}
+
 // Shift pair as (sum, product) of the first column polynomial
 // (H - s1)(H - s2) e1 restricted to its three nonzeros.
 __device__ __forceinline__ void first_column(double h00, double h01, double h10, double h11,

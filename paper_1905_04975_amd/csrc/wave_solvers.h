@@ -130,48 +130,68 @@ __device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
     double x, y, z;
     first_column(Sx(l, l), Sx(l, l + 1), Sx(l + 1, l), Sx(l + 1, l + 1), Sx(l + 2, l + 1), s, t,
                  x, y, z);
+    __syncthreads();   // every lane has read the corner before the first left update
     for (int r = l; r <= i - 1; ++r) {
       const int nr = (r <= i - 2) ? 3 : 2;
+      // the third row / column of a 2-row reflector is replaced by a valid
+      // neighbour and the value selected away: every phase issues all its
+      // loads at once, without a branch, and never reads outside the block
+      const int r3 = (nr == 3) ? r + 2 : r + 1;
       if (r > l) {
         x = Sx(r, r - 1);
         y = Sx(r + 1, r - 1);
-        z = (nr == 3) ? Sx(r + 2, r - 1) : 0.0;
+        const double zz = Sx(r3, r - 1);
+        z = (nr == 3) ? zz : 0.0;
       }
-      const Refl h = make_reflector(nr, x, y, z);
-      __syncthreads();
-      if (h.tau == 0.0) continue;
+      const Refl h = make_reflector_fast(nr, x, y, z);
+      if (h.tau == 0.0) continue;   // uniform: every lane formed the same reflector
       const double tv2 = h.tau * h.v2, tv3 = h.tau * h.v3;
+      // left: rows r..r+2, columns r..cend (column r-1 is written after the
+      // barrier, as every lane has read it above)
       for (int c = r + lane; c <= cend; c += 64) {
-        const double a1 = Sx(r, c), a2 = Sx(r + 1, c);
-        const double a3 = (nr == 3) ? Sx(r + 2, c) : 0.0;
+        const double a1 = Sx(r, c), a2 = Sx(r + 1, c), t3 = Sx(r3, c);
+        const double a3 = (nr == 3) ? t3 : 0.0;
         const double w = a1 + h.v2 * a2 + h.v3 * a3;
         Sx(r, c) = a1 - h.tau * w;
         Sx(r + 1, c) = a2 - tv2 * w;
-        if (nr == 3) Sx(r + 2, c) = a3 - tv3 * w;
+        Sx(r3, c) = (nr == 3) ? a3 - tv3 * w : a2 - tv2 * w;   // r3 = r + 1 for two rows
       }
+      __syncthreads();
       if (r > l && lane == 0) {
         Sx(r, r - 1) = h.beta;
         Sx(r + 1, r - 1) = 0.0;
         if (nr == 3) Sx(r + 2, r - 1) = 0.0;
       }
-      __syncthreads();
+      // right: columns r..r+2 of rows rbeg..rlast, and of every row of Z,
+      // in one pass (one lane: one row of each)
       const int rlast = (r + 3 < i) ? r + 3 : i;
-      for (int q = rbeg + lane; q <= rlast; q += 64) {
-        const double a1 = Sx(q, r), a2 = Sx(q, r + 1);
-        const double a3 = (nr == 3) ? Sx(q, r + 2) : 0.0;
-        const double w = a1 + h.v2 * a2 + h.v3 * a3;
-        Sx(q, r) = a1 - h.tau * w;
-        Sx(q, r + 1) = a2 - tv2 * w;
-        if (nr == 3) Sx(q, r + 2) = a3 - tv3 * w;
-      }
-      if (WANTZ) {
-        for (int q = lane; q < m; q += 64) {
-          const double a1 = Zx(q, r), a2 = Zx(q, r + 1);
-          const double a3 = (nr == 3) ? Zx(q, r + 2) : 0.0;
-          const double w = a1 + h.v2 * a2 + h.v3 * a3;
-          Zx(q, r) = a1 - h.tau * w;
-          Zx(q, r + 1) = a2 - tv2 * w;
-          if (nr == 3) Zx(q, r + 2) = a3 - tv3 * w;
+      const int nzr = WANTZ ? m : 0;
+      const int nsr = rlast - rbeg + 1;
+      const int ntask = nsr > nzr ? nsr : nzr;
+      for (int q = lane; q < ntask; q += 64) {
+        // clamped rows: all loads are issued together, stores are predicated
+        const int qs = (rbeg + q <= rlast) ? rbeg + q : rlast;
+        const int qz = (q < m) ? q : m - 1;
+        const double s1 = Sx(qs, r), s2 = Sx(qs, r + 1), ts3 = Sx(qs, r3);
+        double z1 = 0.0, z2 = 0.0, tz3 = 0.0;
+        if (WANTZ) {
+          z1 = Zx(qz, r);
+          z2 = Zx(qz, r + 1);
+          tz3 = Zx(qz, r3);
+        }
+        const double s3 = (nr == 3) ? ts3 : 0.0;
+        const double z3 = (nr == 3) ? tz3 : 0.0;
+        const double ws = s1 + h.v2 * s2 + h.v3 * s3;
+        const double wz = z1 + h.v2 * z2 + h.v3 * z3;
+        if (q < nsr) {
+          Sx(qs, r) = s1 - h.tau * ws;
+          Sx(qs, r + 1) = s2 - tv2 * ws;
+          if (nr == 3) Sx(qs, r + 2) = s3 - tv3 * ws;
+        }
+        if (WANTZ && q < nzr) {
+          Zx(qz, r) = z1 - h.tau * wz;
+          Zx(qz, r + 1) = z2 - tv2 * wz;
+          if (nr == 3) Zx(qz, r + 2) = z3 - tv3 * wz;
         }
       }
       __syncthreads();
@@ -277,27 +297,46 @@ __device__ __forceinline__ double wave_max(double x) {
   return x;
 }
 
-// Solve M x = b (N <= 4) by Givens QR; a diagonal entry of R below smin in
-// magnitude is replaced by +-smin.  b is overwritten by x.
+// Solve M x = b (N <= 4) by Gaussian elimination with partial pivoting,
+// fully unrolled (row exchanges as selects, so everything stays in
+// registers); a pivot below smin in magnitude is replaced by +-smin.  b is
+// overwritten by x.  The swap that uses x is checked for backward stability
+// afterwards, so a poor solve only rejects the swap.
 template <int N>
 __device__ inline void tiny_solve(double (&M)[N][N], double (&b)[N], double smin) {
 #pragma unroll
   for (int j = 0; j < N; ++j) {
+    // pivot: largest |M[i][j]|, i >= j, swapped into row j
+    int piv = j;
+    double best = fabs(M[j][j]);
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
-      const double a = M[j][j], c = M[i][j];
-      const double r = hypot(a, c);
-      const double cs = (r == 0.0) ? 1.0 : a / r;
-      const double sn = (r == 0.0) ? 0.0 : c / r;
+      const double v = fabs(M[i][j]);
+      if (v > best) { best = v; piv = i; }
+    }
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      const bool sw = (piv == i);
 #pragma unroll
       for (int k = j; k < N; ++k) {
-        const double x = M[j][k], y = M[i][k];
-        M[j][k] = cs * x + sn * y;
-        M[i][k] = cs * y - sn * x;
+        const double t = M[j][k];
+        M[j][k] = sw ? M[i][k] : t;
+        M[i][k] = sw ? t : M[i][k];
       }
-      const double x = b[j], y = b[i];
-      b[j] = cs * x + sn * y;
-      b[i] = cs * y - sn * x;
+      const double t = b[j];
+      b[j] = sw ? b[i] : t;
+      b[i] = sw ? t : b[i];
+    }
+    double d = M[j][j];
+    if (fabs(d) < smin) d = (d < 0.0) ? -smin : smin;
+    M[j][j] = d;
+    const double rd = 1.0 / d;
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      const double f = M[i][j] * rd;
+#pragma unroll
+      for (int k = j + 1; k < N; ++k) M[i][k] -= f * M[j][k];
+      b[i] -= f * b[j];
     }
   }
 #pragma unroll
@@ -305,9 +344,7 @@ __device__ inline void tiny_solve(double (&M)[N][N], double (&b)[N], double smin
     double acc = b[j];
 #pragma unroll
     for (int k = j + 1; k < N; ++k) acc -= M[j][k] * b[k];
-    double d = M[j][j];
-    if (fabs(d) < smin) d = (d < 0.0) ? -smin : smin;
-    b[j] = acc / d;
+    b[j] = acc / M[j][j];
   }
 }
 
@@ -353,6 +390,12 @@ __device__ bool plan_swap(const double* S, int LD, int k, SwapPlan& pl) {
       x[i + P * j] = -T[i][P + j];
     }
   tiny_solve<M>(K, x, smin);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {   // every entry of the plan defined
+    pl.tau[h] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pl.v[h][i] = 0.0;
+  }
   // W = [X; I] (N x R), QR by R Householder reflectors
   double W[N][R];
 #pragma unroll
@@ -454,18 +497,28 @@ __device__ int aed_swap(double* S, double* Zs, int LD, int m, int k, int p, int 
   __syncthreads();
   if (!ok_lds) return 1;
   const int N = p + r;
+  // the plan in registers (the compiler cannot keep LDS values across the
+  // LDS stores of the loops below)
+  double pv[2][4], ptau[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    ptau[h] = (h < r) ? plds->tau[h] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pv[h][i] = (h < r) ? plds->v[h][i] : 0.0;
+  }
   // left: rows k .. k+N-1, columns k .. m-1
   for (int c = k + lane; c < m; c += 64) {
     double a[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) a[i] = (i < N) ? Sx(k + i, c) : 0.0;
-    for (int h = 0; h < r; ++h) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {   // tau = 0 beyond the r reflectors
       double w = 0.0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) w += plds->v[h][i] * a[i];
-      w *= plds->tau[h];
+      for (int i = 0; i < 4; ++i) w += pv[h][i] * a[i];
+      w *= ptau[h];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] -= plds->v[h][i] * w;
+      for (int i = 0; i < 4; ++i) a[i] -= pv[h][i] * w;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -481,13 +534,14 @@ __device__ int aed_swap(double* S, double* Zs, int LD, int m, int k, int p, int 
     double a[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) a[i] = (i < N) ? base[row + (k + i) * LD] : 0.0;
-    for (int h = 0; h < r; ++h) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
       double w = 0.0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) w += a[i] * plds->v[h][i];
-      w *= plds->tau[h];
+      for (int i = 0; i < 4; ++i) w += a[i] * pv[h][i];
+      w *= ptau[h];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] -= w * plds->v[h][i];
+      for (int i = 0; i < 4; ++i) a[i] -= w * pv[h][i];
     }
     if (inS && row >= k + r) {          // below the moved block: exact zeros
 #pragma unroll

@@ -35,3 +35,4 @@ unsigned long long __ballot(int p);
 void simt_wave_barrier();
 #define __builtin_amdgcn_wave_barrier() simt_wave_barrier()
 #define __builtin_amdgcn_fence(a, b) ((void)0)
+#define __builtin_amdgcn_rcp(x) (1.0 / (x))

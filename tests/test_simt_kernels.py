@@ -3,8 +3,8 @@
 ``tests/simt/`` compiles the HIP source of the window chase and of the
 early-deflation window step with g++ against a small stand-in for the
 device API: a workgroup is a set of host threads with real barriers, LDS is
-filled with NaN before every workgroup, and AddressSanitizer watches every
-access.  So a read of LDS the kernel never wrote, an out-of-range index or a
+filled with NaN before every workgroup, uninitialised locals are filled with
+a NaN pattern (clang), and AddressSanitizer watches every access.  So a read of LDS the kernel never wrote, an out-of-range index or a
 missing barrier shows up here, on the CPU.
 
 * window chase: whole sweeps (the sweep planner's windows, time step by time
@@ -34,12 +34,22 @@ UPAD = 128
 ULP = 2.0 ** -52
 
 
+def _host_compiler():
+    """ROCm's clang++ when present: it can fill every uninitialised local with
+    a NaN pattern (-ftrivial-auto-var-init=pattern), so a register the kernel
+    reads before writing shows up too; else g++."""
+    clang = "/opt/rocm/lib/llvm/bin/clang++"
+    if os.path.exists(clang):
+        return [clang, "-ftrivial-auto-var-init=pattern"]
+    if shutil.which("g++"):
+        return ["g++"]
+    pytest.skip("no host C++ compiler")
+
+
 @pytest.fixture(scope="module")
 def driver(tmp_path_factory):
-    if shutil.which("g++") is None:
-        pytest.skip("g++ not available")
     out = str(tmp_path_factory.mktemp("simt") / "simt_kernels")
-    cmd = ["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+    cmd = _host_compiler() + ["-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
            "-fno-sanitize-recover=undefined",
            "-I", os.path.join(HERE, "simt"), "-I", os.path.join(ROOT, "paper_1905_04975_amd", "csrc"),
            "-I", os.path.join(ROOT, "include"), os.path.join(HERE, "simt", "simt_kernels.cpp"),
