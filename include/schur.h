@@ -104,7 +104,8 @@ typedef struct schur_stats {
   double aed_ms;            /* summed duration of the early-deflation kernels   */
   int64_t aed_windows;      /* early-deflation windows processed               */
   int64_t aed_deflated;     /* eigenvalues deflated by them                    */
-  double reserved[1];
+  double aed_flops;         /* nominal work of those windows: 25 nw^3 (Schur   */
+                            /* form with vectors) + 10/3 nu^3 (reduction back) */
 } schur_stats;
 
 /* --------------------------------------------------------------------------

@@ -166,6 +166,13 @@ struct Params {
   bool time;
 };
 
+// nominal flops of one early-deflation window: the Schur form with vectors
+// (25 nw^3, the usual count of the double-shift QR with Schur vectors) and
+// the reduction of the undeflated part back to Hessenberg form with V
+double aed_work(int nw, int nu) {
+  return 25.0 * nw * (double)nw * nw + (10.0 / 3.0) * nu * (double)nu * nu;
+}
+
 // info code of a solve in which a non-finite value appeared (never for
 // finite input; reported instead of a Schur form)
 constexpr int kErrNonFinite = -105;
@@ -508,6 +515,7 @@ struct Solver {
     launch_q(aq, tq, buf);   // records the slot's events even when idle
     launch_gemms(a, tr, tc);
     h->stats.aed_deflated += nd;
+    h->stats.aed_flops += aed_work(nw, nd > 0 ? *nu : 0);
     return nd;
   }
 
@@ -969,6 +977,7 @@ struct BatchEngine {
           Mat& m = M[big[q]];
           const int nd = ctrl_h[big[q]].aed_nd;
           aed_nu[q] = ctrl_h[big[q]].aed_nu;
+          h->stats.aed_flops += aed_work(nwv[q], nd > 0 ? aed_nu[q] : 0);
           if (nd <= 0) continue;
           WinB& w = wh[nwin++];
           std::memset(&w, 0, sizeof(w));

@@ -49,9 +49,9 @@ __global__ __launch_bounds__(64) void k_aed(AedTask t0, const AedTask* tasks) {
   __shared__ double S[LD * MAXM];
   __shared__ double Z[LD * MAXM];
   __shared__ double vv[MAXM];
-  __shared__ SwapPlan plan;
+  __shared__ int ibuf[6 * MAXM];
   __shared__ double stdbuf[7 * MAXM];
-  aed_window<MAXM>(T, S, Z, vv, plan, stdbuf);
+  aed_window<MAXM>(T, S, Z, vv, ibuf, stdbuf);
 }
 
 // ============================================================================

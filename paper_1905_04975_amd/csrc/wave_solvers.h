@@ -470,94 +470,6 @@ __device__ bool plan_swap(const double* S, int LD, int k, SwapPlan& pl) {
   return low <= thresh;   // false for NaN as well
 }
 
-// Swap the adjacent diagonal blocks of orders p (at k) and r (at k + p) of
-// the m x m quasi-triangular S, updating the columns of Z.  Returns 0 when
-// done, 1 when the swap was rejected (nothing changed).  The 2x2 blocks are
-// left as the swap produces them (not standardised): the swaps do not need
-// standard form, and the blocks that end up deflated are standardised once
-// at the end.
-__device__ int aed_swap(double* S, double* Zs, int LD, int m, int k, int p, int r,
-                        SwapPlan* plds) {
-  const int lane = threadIdx.x;
-  auto Sx = [&](int rr, int c) -> double& { return S[rr + c * LD]; };
-  __shared__ int ok_lds;
-  __shared__ double dA, dB;
-  if (lane == 0) {
-    SwapPlan pl;
-    bool ok;
-    if (p == 1 && r == 1) ok = plan_swap<1, 1>(S, LD, k, pl);
-    else if (p == 1) ok = plan_swap<1, 2>(S, LD, k, pl);
-    else if (r == 1) ok = plan_swap<2, 1>(S, LD, k, pl);
-    else ok = plan_swap<2, 2>(S, LD, k, pl);
-    *plds = pl;
-    ok_lds = ok ? 1 : 0;
-    dA = Sx(k, k);           // the 1x1 eigenvalues are restored exactly
-    dB = Sx(k + p + r - 1, k + p + r - 1);
-  }
-  __syncthreads();
-  if (!ok_lds) return 1;
-  const int N = p + r;
-  // the plan in registers (the compiler cannot keep LDS values across the
-  // LDS stores of the loops below)
-  double pv[2][4], ptau[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    ptau[h] = (h < r) ? plds->tau[h] : 0.0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) pv[h][i] = (h < r) ? plds->v[h][i] : 0.0;
-  }
-  // left: rows k .. k+N-1, columns k .. m-1
-  for (int c = k + lane; c < m; c += 64) {
-    double a[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = (i < N) ? Sx(k + i, c) : 0.0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {   // tau = 0 beyond the r reflectors
-      double w = 0.0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) w += pv[h][i] * a[i];
-      w *= ptau[h];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] -= pv[h][i] * w;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (i < N) Sx(k + i, c) = a[i];
-  }
-  __syncthreads();
-  // right: columns k .. k+N-1 of rows 0 .. k+N-1 of S and all rows of Z;
-  // the lane of row k+i also sets the new block structure of that row
-  for (int q = lane; q < m + k + N; q += 64) {
-    const bool inS = q < k + N;
-    double* base = inS ? S : Zs;
-    const int row = inS ? q : q - (k + N);
-    double a[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = (i < N) ? base[row + (k + i) * LD] : 0.0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      double w = 0.0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) w += a[i] * pv[h][i];
-      w *= ptau[h];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] -= w * pv[h][i];
-    }
-    if (inS && row >= k + r) {          // below the moved block: exact zeros
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        if (j < r) a[j] = 0.0;
-    }
-    if (inS && r == 1 && row == k) a[0] = dB;
-    if (inS && p == 1 && row == k + r) a[r] = dA;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (i < N) base[row + (k + i) * LD] = a[i];
-  }
-  __syncthreads();
-  return 0;
-}
-
 // Standardise every 2x2 block of the quasi-triangular S whose first row is
 // in [lo, m), updating Z.  The rotations of different blocks commute (each
 // turns its own pair of rows and its own pair of columns), so all are
@@ -662,7 +574,8 @@ __device__ void aed_reflector(double alpha, double* vv, int L, double& tau, doub
 }
 
 // The whole early-deflation step on one window; S, Z (LD x MAXM each), vv
-// (MAXM) and plan live in LDS and belong to the calling wavefront.
+// (MAXM), ibuf (6 MAXM ints) and stdbuf (7 MAXM) live in LDS and belong to
+// the calling wavefront.
 // 2x2 block [[a, b], [c, d]]: eigenvalues (re +- sqrt(disc)) or re +- i im,
 // without assuming standard form
 __device__ __forceinline__ void block_eigs(double a, double b, double c, double d, double& re,
@@ -681,8 +594,243 @@ __device__ __forceinline__ void block_eigs(double a, double b, double c, double 
   }
 }
 
+// Pipelined reordering for early deflation.  The sequential rule (test the
+// bottom block; deflate it, or move it above every block not tested yet) is
+// kept, but the moves of several undeflatable blocks run concurrently: each
+// round, every moving block whose upper neighbour is untested swaps with it
+// (the windows of one round are disjoint, so all left updates precede all
+// right updates, as in a sweep), while the bottom block, which no swap of
+// the round touches, is tested.  Untested blocks thus flow down through the
+// moving ones to the bottom; every block meets the same swaps and the same
+// test as in the sequential order.  Returns nu: rows [0, nu) hold the
+// undeflated blocks, [nu, m) the deflated ones.  A rejected swap stops the
+// reordering with everything not yet deflated counted as undeflated.
+//   ibuf: 6 m ints of LDS; pbuf: 12 (m / 2 + 1) doubles of LDS.
+
+// One swap's left transform on column c (rows k..k+N-1) or right transform
+// on a row (columns k..k+N-1): a[] holds the N entries, v/tau the plan.
+__device__ __forceinline__ void swap_apply(double (&a)[4], const double* v, const double* tau,
+                                           int N) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    double w = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w += v[4 * h + i] * ((i < N) ? a[i] : 0.0);
+    w *= tau[h];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] -= v[4 * h + i] * w;
+  }
+}
+
+__device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* ibuf,
+                           double* pbuf) {
+  const int lane = threadIdx.x;
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
+  int* status = ibuf;            // per row: 0 untested, 1 undeflatable
+  int* mv_pos = ibuf + m;        // moving blocks, top to bottom
+  int* mv_sz = ibuf + 2 * m;
+  int* mv_tgt = ibuf + 3 * m;
+  int* sw_k = ibuf + 4 * m;      // this round's swaps (at most m / 2)
+  int* sw_p = sw_k + m / 2;
+  int* sw_j = ibuf + 5 * m;
+  int* sw_ok = sw_j + m / 2;
+  const int maxsw = m / 2 + 1;
+  double* pl_v = pbuf;               // 8 per swap
+  double* pl_t = pbuf + 8 * maxsw;   // 2 per swap
+  double* pl_d = pbuf + 10 * maxsw;  // 2 per swap (restored 1x1 diagonals)
+  __shared__ int sh_nmv, sh_bot, sh_left, sh_tgt;
+  for (int i = lane; i < m; i += 64) status[i] = 0;
+  if (lane == 0) {
+    sh_nmv = 0; sh_bot = m - 1; sh_left = m; sh_tgt = 0;
+  }
+  __syncthreads();
+  const double tiny = 2.2250738585072014e-308;
+  const double smlnum = tiny * ((double)m / kUlp);
+  int rounds = 0;
+  while (true) {
+    const int nmv = sh_nmv, bot = sh_bot, left = sh_left;
+    if (left == 0 || ++rounds > 4 * m + 16) break;   // the bound is never reached
+    // ---- this round's swaps: moving blocks with an untested upper neighbour
+    int nsw = 0;
+    for (int base = 0; base < nmv; base += 64) {
+      const int j = base + lane;
+      bool go = false;
+      int k = 0, as = 1;
+      if (j < nmv) {
+        const int pos = mv_pos[j];
+        if (pos > mv_tgt[j] && status[pos - 1] == 0) {
+          as = (pos - 2 >= 0 && status[pos - 2] == 0 && Sx(pos - 1, pos - 2) != 0.0) ? 2 : 1;
+          k = pos - as;
+          go = true;
+        }
+      }
+      const unsigned long long mask = __ballot(go);
+      if (go) {
+        const int idx = nsw + __builtin_popcountll(mask & ((1ull << lane) - 1ull));
+        sw_k[idx] = k;
+        sw_p[idx] = as;
+        sw_j[idx] = j;
+      }
+      nsw += __builtin_popcountll(mask);
+    }
+    // ---- bottom block test (it meets no swap window of this round)
+    const bool test = status[bot] == 0;
+    const int bs = (test && bot >= 1 && status[bot - 1] == 0 && Sx(bot, bot - 1) != 0.0) ? 2 : 1;
+    bool defl = false;
+    if (test) {
+      double foo, spk;
+      if (bs == 1) {
+        foo = fabs(Sx(bot, bot));
+        spk = fabs(s * Zx(0, bot));
+      } else {
+        double re, im, r1, r2;
+        block_eigs(Sx(bot - 1, bot - 1), Sx(bot - 1, bot), Sx(bot, bot - 1), Sx(bot, bot), re, im,
+                   r1, r2);
+        foo = (im != 0.0) ? fabs(re) + im : fmax(fabs(r1), fabs(r2));
+        spk = fmax(fabs(s * Zx(0, bot)), fabs(s * Zx(0, bot - 1)));
+      }
+      if (foo == 0.0) foo = fabs(s);
+      defl = spk <= fmax(smlnum, kUlp * foo);
+    }
+    __syncthreads();
+    // ---- plans, one lane per swap
+    if (lane < nsw) {
+      const int k = sw_k[lane], pp = sw_p[lane], rr = mv_sz[sw_j[lane]];
+      SwapPlan pl;
+      bool ok;
+      if (pp == 1 && rr == 1) ok = plan_swap<1, 1>(S, LD, k, pl);
+      else if (pp == 1) ok = plan_swap<1, 2>(S, LD, k, pl);
+      else if (rr == 1) ok = plan_swap<2, 1>(S, LD, k, pl);
+      else ok = plan_swap<2, 2>(S, LD, k, pl);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        pl_t[2 * lane + h] = (h < rr) ? pl.tau[h] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pl_v[8 * lane + 4 * h + i] = (h < rr) ? pl.v[h][i] : 0.0;
+      }
+      pl_d[2 * lane] = Sx(k, k);                                   // A's 1x1 eigenvalue
+      pl_d[2 * lane + 1] = Sx(k + pp + rr - 1, k + pp + rr - 1);   // B's
+      sw_ok[lane] = ok ? 1 : 0;
+    }
+    __syncthreads();
+    const bool bad = lane < nsw && sw_ok[lane] == 0;
+    if (__ballot(bad) != 0ull) break;   // uniform: nothing of this round is applied
+    if (nsw > 0) {
+      // lanes in groups of G per swap; a group walks its swap's columns
+      // (left) and rows (right) two at a time
+      const int G = 64 / nsw;
+      const int t = lane / G, sub = lane - t * G;
+      const bool mine = t < nsw;
+      int k = 0, pp = 1, rr = 1, N = 2;
+      double v[8], tau[2];
+      if (mine) {
+        k = sw_k[t]; pp = sw_p[t]; rr = mv_sz[sw_j[t]]; N = pp + rr;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = pl_v[8 * t + i];
+        tau[0] = pl_t[2 * t]; tau[1] = pl_t[2 * t + 1];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = 0.0;
+        tau[0] = tau[1] = 0.0;
+      }
+      // left: columns k..m-1, rows k..k+N-1
+      if (mine) {
+        for (int c = k + sub; c < m; c += 2 * G) {
+          const int c2 = c + G;
+          const bool two = c2 < m;
+          double a[4], b[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a[i] = Sx((i < N) ? k + i : k, c);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) b[i] = Sx((i < N) ? k + i : k, two ? c2 : c);
+          swap_apply(a, v, tau, N);
+          swap_apply(b, v, tau, N);
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (i < N) Sx(k + i, c) = a[i];
+          if (two) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (i < N) Sx(k + i, c2) = b[i];
+          }
+        }
+      }
+      __syncthreads();
+      // right: rows 0..k+N-1 of S, then rows 0..m-1 of Z (one index space)
+      if (mine) {
+        const int ns = k + N;
+        const int tot = ns + m;
+        const double dA = pl_d[2 * t], dB = pl_d[2 * t + 1];
+        for (int q = sub; q < tot; q += 2 * G) {
+          const int q2 = q + G;
+          const bool two = q2 < tot;
+          double* ba = (q < ns) ? S : Zs;
+          const int ra = (q < ns) ? q : q - ns;
+          double* bb = (two && q2 < ns) ? S : Zs;
+          const int rb = two ? ((q2 < ns) ? q2 : q2 - ns) : ra;
+          double* bbx = two ? bb : ba;
+          double a[4], b[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a[i] = ba[ra + ((i < N) ? k + i : k) * LD];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) b[i] = bbx[rb + ((i < N) ? k + i : k) * LD];
+          swap_apply(a, v, tau, N);
+          swap_apply(b, v, tau, N);
+          // rows of S inside the window: exact zeros below the moved block and
+          // the 1x1 eigenvalues restored
+          if (q < ns) {
+            if (ra >= k + rr) { a[0] = 0.0; if (rr == 2) a[1] = 0.0; }
+            if (rr == 1 && ra == k) a[0] = dB;
+            if (pp == 1 && ra == k + rr) a[rr] = dA;
+          }
+          if (two && q2 < ns) {
+            if (rb >= k + rr) { b[0] = 0.0; if (rr == 2) b[1] = 0.0; }
+            if (rr == 1 && rb == k) b[0] = dB;
+            if (pp == 1 && rb == k + rr) b[rr] = dA;
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (i < N) ba[ra + (k + i) * LD] = a[i];
+          if (two) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (i < N) bb[rb + (k + i) * LD] = b[i];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- bookkeeping: each swap's lane moves its block; the last lane
+    // records the bottom test (disjoint rows and entries)
+    if (lane < nsw) {
+      const int j = sw_j[lane], k = sw_k[lane], pp = sw_p[lane], rr = mv_sz[j];
+      mv_pos[j] = k;
+      for (int i = 0; i < rr; ++i) status[k + i] = 1;
+      for (int i = 0; i < pp; ++i) status[k + rr + i] = 0;
+    }
+    if (lane == 63 && test) {
+      if (defl) {
+        sh_bot = bot - bs;
+      } else {
+        const int j = nmv;
+        mv_pos[j] = bot - bs + 1;
+        mv_sz[j] = bs;
+        mv_tgt[j] = sh_tgt;
+        sh_tgt += bs;
+        for (int i = 0; i < bs; ++i) status[bot - bs + 1 + i] = 1;
+        sh_nmv = nmv + 1;
+      }
+      sh_left = left - bs;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  return sh_bot + 1;
+}
+
 template <int MAXM>
-__device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, SwapPlan& plan,
+__device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, int* ibuf,
                            double* stdbuf) {
   constexpr int LD = SmallSmem<MAXM>::LD;
   const int lane = threadIdx.x;
@@ -704,41 +852,7 @@ __device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, S
   }
 
   // ---- deflation checks from the bottom, undeflatable blocks moved up
-  const double tiny = 2.2250738585072014e-308;
-  const double smlnum = tiny * ((double)nw / kUlp);
-  int bot = nw - 1, ilst = 0;
-  bool stop = false;
-  while (!stop && ilst <= bot) {
-    const int bs = (bot > ilst && Sx(bot, bot - 1) != 0.0) ? 2 : 1;
-    double foo, spk;
-    if (bs == 1) {
-      foo = fabs(Sx(bot, bot));
-      spk = fabs(s * Zx(0, bot));
-    } else {
-      // |Re| + |Im| of the pair (the blocks are not kept in standard form)
-      double re, im, r1, r2;
-      block_eigs(Sx(bot - 1, bot - 1), Sx(bot - 1, bot), Sx(bot, bot - 1), Sx(bot, bot), re, im,
-                 r1, r2);
-      foo = (im != 0.0) ? fabs(re) + im : fmax(fabs(r1), fabs(r2));
-      spk = fmax(fabs(s * Zx(0, bot)), fabs(s * Zx(0, bot - 1)));
-    }
-    if (foo == 0.0) foo = fabs(s);
-    __syncthreads();
-    if (spk <= fmax(smlnum, kUlp * foo)) {
-      bot -= bs;
-      continue;
-    }
-    int pos = bot - bs + 1;
-    while (pos > ilst) {
-      const int above = (pos - 2 >= ilst && Sx(pos - 1, pos - 2) != 0.0) ? 2 : 1;
-      __syncthreads();
-      const int k = pos - above;
-      if (aed_swap(S, Z, LD, nw, k, above, bs, &plan) != 0) { stop = true; break; }
-      pos = k;
-    }
-    if (!stop) ilst += bs;
-  }
-  const int nu = bot + 1;
+  const int nu = aed_reorder(S, Z, LD, nw, s, ibuf, stdbuf);
   const int nd = nw - nu;
   // the deflated blocks are final: standard form now
   if (nd > 0) aed_std_all(S, Z, LD, nw, nu, stdbuf);

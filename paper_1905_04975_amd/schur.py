@@ -40,7 +40,7 @@ class SchurStats(ctypes.Structure):
                 ("colq_flops", ctypes.c_double), ("colq_ms", ctypes.c_double),
                 ("colq_launches", ctypes.c_int64),
                 ("aed_ms", ctypes.c_double), ("aed_windows", ctypes.c_int64),
-                ("aed_deflated", ctypes.c_int64), ("reserved", ctypes.c_double * 1)]
+                ("aed_deflated", ctypes.c_int64), ("aed_flops", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -127,9 +127,10 @@ int main(int argc, char** argv) {
     if (!rd(f, H.data(), H.size())) return 2;
     fclose(f);
     static std::vector<double> S(LD * MAXM), Z(LD * MAXM), vv(MAXM), sb(7 * MAXM);
-    static SwapPlan plan;
+    static std::vector<int> ib(6 * MAXM);
     for (auto* v : {&S, &Z, &vv, &sb})
       for (double& x : *v) x = NAN;
+    for (int& x : ib) x = -12345;
     Ctrl ctrl{};
     ctrl.aed_nd = -99;
     ctrl.aed_nu = -99;
@@ -140,7 +141,7 @@ int main(int argc, char** argv) {
     T.wr = wr.data() + kwtop; T.wi = wi.data() + kwtop;
     T.ctrl = &ctrl; T.itmax = 30;
     run_workgroup(64, 0, [T] {
-      aed_window<MAXM>(T, S.data(), Z.data(), vv.data(), plan, sb.data());
+      aed_window<MAXM>(T, S.data(), Z.data(), vv.data(), ib.data(), sb.data());
     });
     FILE* g = fopen(argv[3], "wb");
     const int o[2] = {ctrl.aed_nd, ctrl.aed_nu};
