@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--step-len", type=int, default=0)
     ap.add_argument("--aed-window", type=int, default=0,
                     help="early-deflation window (0: from ns, <0: off)")
+    ap.add_argument("--aed-nibble", type=int, default=0,
+                    help="percent of the window deflated above which no sweep follows")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle sample")
@@ -304,7 +306,7 @@ def main():
     wi = torch.empty(n, dtype=torch.float64, device=dev)
     gen_s = time.time() - t0
     hdl = schur.Handle(0, ns=args.ns, nb=args.nb, step=args.step_len, aed_window=args.aed_window,
-                       flags=schur.FLAG_TIME_KERNELS)
+                       aed_nibble=args.aed_nibble, flags=schur.FLAG_TIME_KERNELS)
     stream = torch.cuda.current_stream(dev)
 
     def one_step():

@@ -75,7 +75,10 @@ typedef struct schur_opts {
   int flags;       /* SCHUR_FLAG_*                                             */
   int aed_window;  /* early-deflation window order (<= 96); 0 = from ns,       */
                    /* < 0 = no early deflation (shifts from the trailing block) */
-  int reserved[4];
+  int aed_nibble;  /* a window that deflated more than this percentage of its  */
+                   /* rows is followed by another window instead of a sweep;   */
+                   /* 0 = by table, < 0 = always sweep                        */
+  int reserved[3];
 } schur_opts;
 
 #define SCHUR_FLAG_TIME_KERNELS 1   /* time each kernel family with HIP events */

@@ -163,6 +163,7 @@ TuneRow tune_for(int n) {
 struct Params {
   int ns, nb, step, nmin, max_sweeps, exc_period;
   int nw;      // early-deflation window order (0: none)
+  int nibble;  // skip the sweep after a window that deflated > nibble % of nw (-1: never)
   bool time;
 };
 
@@ -177,8 +178,8 @@ double aed_work(int nw, int nu) {
 // finite input; reported instead of a Schur form)
 constexpr int kErrNonFinite = -105;
 
-// early deflation: skip the next sweep when a window deflated more than
-// this percentage of its order (the remaining shifts are then stale)
+// early deflation: by default the next sweep is skipped when a window
+// deflated more than this percentage of its order
 constexpr int kAedSkipPct = 14;
 
 Params resolve(const schur_opts& o, int n) {
@@ -195,6 +196,7 @@ Params resolve(const schur_opts& o, int n) {
   p.exc_period = o.exc_period > 0 ? o.exc_period : 6;
   p.time = (o.flags & SCHUR_FLAG_TIME_KERNELS) != 0;
   const int aw = o.aed_window != 0 ? o.aed_window : tr.nw;
+  p.nibble = o.aed_nibble < 0 ? -1 : (o.aed_nibble > 0 ? o.aed_nibble : kAedSkipPct);
   if (aw < 0) p.nw = 0;
   else if (aw > 0) p.nw = std::min(aw, SMALL_Z_MAX);
   else p.nw = std::min(SMALL_Z_MAX, std::max(16, p.ns + p.ns / 2));
@@ -644,7 +646,7 @@ struct Solver {
           nodefl = 0;
           // many deflations: look again before spending a sweep; a block
           // that became small goes to the single-kernel solver
-          if (100 * nd > kAedSkipPct * nw || kbot - ktop + 1 <= P.nmin) continue;
+          if ((P.nibble >= 0 && 100 * nd > P.nibble * nw) || kbot - ktop + 1 <= P.nmin) continue;
         }
         const int m2 = kbot - ktop + 1;
         ns = std::max(2, std::min(P.ns, 2 * ((m2 - 2) / 6)));
@@ -989,7 +991,8 @@ struct BatchEngine {
           m.kbot -= nd;
           m.nodefl = 0;
           h->stats.aed_deflated += nd;
-          if (100 * nd > kAedSkipPct * nwv[q] || m.kbot - m.ktop + 1 <= m.P.nmin) sweep_it[q] = 0;
+          if ((m.P.nibble >= 0 && 100 * nd > m.P.nibble * nwv[q]) || m.kbot - m.ktop + 1 <= m.P.nmin)
+            sweep_it[q] = 0;
         }
         if (nwin > 0) {
           upload(h->b_aedw, sizeof(WinB) * nwin);

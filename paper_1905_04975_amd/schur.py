@@ -24,7 +24,8 @@ class SchurOpts(ctypes.Structure):
     _fields_ = [("ns", ctypes.c_int), ("nb", ctypes.c_int), ("step", ctypes.c_int),
                 ("nmin", ctypes.c_int), ("max_sweeps", ctypes.c_int),
                 ("exc_period", ctypes.c_int), ("flags", ctypes.c_int),
-                ("aed_window", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("aed_window", ctypes.c_int), ("aed_nibble", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
 
 
 class SchurStats(ctypes.Structure):
@@ -172,11 +173,13 @@ class Handle:
             pass
 
 
-def make_opts(ns=0, nb=0, step=0, nmin=0, max_sweeps=0, exc_period=0, flags=0, aed_window=0):
+def make_opts(ns=0, nb=0, step=0, nmin=0, max_sweeps=0, exc_period=0, flags=0, aed_window=0,
+              aed_nibble=0):
     o = SchurOpts()
     o.ns, o.nb, o.step, o.nmin = int(ns), int(nb), int(step), int(nmin)
     o.max_sweeps, o.exc_period, o.flags = int(max_sweeps), int(exc_period), int(flags)
     o.aed_window = int(aed_window)
+    o.aed_nibble = int(aed_nibble)
     return o
 
 
