@@ -948,13 +948,55 @@ __device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, i
     }
   }
 
-  // ---- write back: the window, its spike, and V^T into the panel slot
+  // ---- write back: the window and its spike
   for (int c = 0; c < nw; ++c)
     for (int r = lane; r <= c + 1 && r < nw; r += 64) Hw[r + (size_t)c * T.ldh] = Sx(r, c);
   if (lane == 0 && kwtop > T.ktop) T.H[kwtop + (size_t)(kwtop - 1) * T.ldh] = spike;
-  for (int c = 0; c < T.ldut; ++c)
-    for (int r = lane; r < T.ldut; r += 64)
-      T.Ut[r + (size_t)c * T.ldut] = (r < nw && c < nw) ? Zx(c, r) : 0.0;
+  __syncthreads();
+  // ---- V^T into the panel slot, after one first-order re-orthogonalisation
+  // V <- V (I - E / 2), E = V^T V - I: V's own rounding (it collected every
+  // rotation of the window) would otherwise reach Q; the window's S is free
+  // now and holds E
+  // (four independent sums per lane, rows unrolled, so loads run ahead)
+  for (int j = lane; j < nw; j += 64)
+    for (int i0 = 0; i0 < nw; i0 += 4) {
+      int ic[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ic[u] = (i0 + u < nw) ? i0 + u : nw - 1;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int r = 0; r < nw; ++r) {
+        const double zj = Zx(r, j);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += Zx(r, ic[u]) * zj;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u < nw) Sx(i0 + u, j) = acc[u] - ((i0 + u == j) ? 1.0 : 0.0);
+    }
+  __syncthreads();
+  for (int j = lane; j < T.ldut; j += 64) {
+    for (int r0 = 0; r0 < T.ldut; r0 += 4) {
+      double val[4] = {0.0, 0.0, 0.0, 0.0};
+      if (j < nw && r0 < nw) {
+        int rc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rc[u] = (r0 + u < nw) ? r0 + u : nw - 1;
+        double corr[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k = 0; k < nw; ++k) {
+          const double e = Sx(k, j);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) corr[u] += Zx(rc[u], k) * e;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          val[u] = (r0 + u < nw) ? Zx(rc[u], j) - 0.5 * corr[u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) T.Ut[j + (size_t)(r0 + u) * T.ldut] = val[u];   // Ut(j, r) = V(r, j)
+    }
+  }
 }
 
 

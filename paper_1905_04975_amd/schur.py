@@ -73,6 +73,12 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    try:
+        # the library binds to the HIP runtime already in the process (same
+        # soname); load torch's first, so that one runtime serves both
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("HIP library %s is missing: run `python -m paper_1905_04975_amd.build`"
                            % LIB_PATH)
