@@ -160,15 +160,16 @@ int schur_reduce_batched(schur_handle_t h, void* stream, int count, const int* n
  * Tuning table (written by the autotuner).  For a matrix (or active block)
  * of order n, the first entry with n <= nmax[i] supplies the shifts per
  * sweep, bulges per window chain, chain steps per window (0 = largest that
- * fits) and the early-deflation window (nw: 0 = from ns, < 0 = off, else
- * 4..96; nw may be NULL for all 0) whenever the handle's options leave them
- * 0.  Arrays of `count` entries, nmax strictly ascending; host memory, read
- * during the call.  Process-wide; count = 0 restores the built-in table.
- * Returns 0, -1 (count < 0) or -2 (an entry out of range).  Host-only, no
- * device work.
+ * fits), the early-deflation window (nw: 0 = from ns, < 0 = off, else
+ * 4..96) and its sweep-skip percentage (nibble: 0 = 14, < 0 = always sweep,
+ * else 1..100) whenever the handle's options leave them 0; nw and nibble may
+ * be NULL for all 0.  Arrays of `count` entries, nmax strictly ascending;
+ * host memory, read during the call.  Process-wide; count = 0 restores the
+ * built-in table.  Returns 0, -1 (count < 0) or -2 (an entry out of range).
+ * Host-only, no device work.
  * ------------------------------------------------------------------------ */
 int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, const int* step,
-                     const int* nw);
+                     const int* nw, const int* nibble);
 
 /* --------------------------------------------------------------------------
  * Sweep schedule (host-only diagnostic of the planner, no device work):

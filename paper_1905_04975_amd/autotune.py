@@ -1,12 +1,12 @@
 """Autotuner: picks shifts per sweep, bulges per window chain, chain steps per
-window and the early-deflation window for each matrix-order bucket, on the
-GPU it runs on.
+window, the early-deflation window and its sweep-skip percentage for each
+matrix-order bucket, on the GPU it runs on.
 
 For every bucket order n it times complete Schur reductions of a seeded
 random N(0,1) Hessenberg matrix for each candidate, keeps only candidates
 whose result passes the accuracy checks (info 0, backward-error and
 orthogonality probes, exact structure), and writes the fastest into a table
-``{"table": [{"nmax", "ns", "nb", "step", "nw"}, ...]}`` that the library applies
+``{"table": [{"nmax", "ns", "nb", "step", "nw", "nibble"}, ...]}`` that the library applies
 to every solve, batched solve and served request whose options leave these
 parameters unset.  The choice depends on n only, so a matrix gets the same
 parameters alone, in a batch or in a serving mix.
@@ -49,21 +49,29 @@ def candidates(n, quick):
     else:
         out = [c for c in out if c["nb"] in (1, 2, 4, 8, 16)]
     windows = [-1, 0, 32, 48, 64, 80, 96] if n >= 512 else [-1, 0, 16, 24, 32, 48]
+    nibbles = [0]
     if n >= 8192:
-        windows = [48, 64, 80]
+        windows = [56, 64, 72]
+        nibbles = [7, 14]
+    elif n >= 2048:
+        nibbles = [0, 7]
     full = []
     for c in out:
         for nw in windows:
             if nw > 0 and nw >= n // 2:
                 continue
-            full.append(dict(c, nw=nw))
+            for nib in nibbles:
+                if nw < 0 and nib != nibbles[0]:
+                    continue
+                full.append(dict(c, nw=nw, nibble=nib))
     return full
 
 
 def time_candidate(schur, torch, H0, c, reps):
     n = H0.shape[0]
     dev = H0.device
-    h = schur.Handle(0, ns=c["ns"], nb=c["nb"], step=c["step"], aed_window=c["nw"])
+    h = schur.Handle(0, ns=c["ns"], nb=c["nb"], step=c["step"], aed_window=c["nw"],
+                     aed_nibble=c["nibble"])
     best = math.inf
     ok = True
     for _ in range(reps):
@@ -113,16 +121,17 @@ def main():
         for c in candidates(n, args.quick):
             ok, t = time_candidate(schur, torch, H0, c, reps)
             results.append((c, ok, t))
-            print("n=%d ns=%d nb=%d nw=%d -> %s %.4f s" % (n, c["ns"], c["nb"], c["nw"],
-                                                           "ok" if ok else "FAIL", t), flush=True)
+            print("n=%d ns=%d nb=%d nw=%d nibble=%d -> %s %.4f s"
+                  % (n, c["ns"], c["nb"], c["nw"], c["nibble"], "ok" if ok else "FAIL", t),
+                  flush=True)
         good = [(t, c) for c, ok, t in results if ok]
         if not good:
             raise RuntimeError("no candidate passed at n=%d" % n)
         t, c = min(good, key=lambda z: z[0])
         nmax = (int(math.sqrt(n * buckets[i + 1])) if i + 1 < len(buckets) else (1 << 30))
-        rows.append({"nmax": nmax, "ns": c["ns"], "nb": c["nb"], "step": c["step"], "nw": c["nw"]})
-        meas[str(n)] = [{"ns": c2["ns"], "nb": c2["nb"], "nw": c2["nw"], "ok": ok, "seconds": t2}
-                        for c2, ok, t2 in results]
+        rows.append({"nmax": nmax, "ns": c["ns"], "nb": c["nb"], "step": c["step"], "nw": c["nw"],
+                     "nibble": c["nibble"]})
+        meas[str(n)] = [dict(c2, ok=ok, seconds=t2) for c2, ok, t2 in results]
     with open(args.out, "w") as f:
         json.dump({"table": rows, "measurements": meas,
                    "device": torch.cuda.get_device_name(0)}, f, indent=1)

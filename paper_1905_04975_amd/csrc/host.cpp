@@ -144,12 +144,17 @@ bool is_device_ptr(const void* p) {
 // ---- defaults and the tuning table -----------------------------------------
 struct TuneRow {
   int nmax, ns, nb, step, nw;   // nw: early-deflation window (0: from ns, < 0: off)
+  int nibble;                   // sweep-skip percentage after a window (0: default)
 };
 // built-in table: plain double-shift sweeps for small orders, then more
 // shifts per sweep as the order grows; early-deflation windows of 64 rows
-// for large orders (measured at n = 16384: 64 beat 48 and 96)
-const TuneRow kBuiltinTune[] = {
-    {299, 2, 1, 0, 0}, {2999, 32, 16, 0, 0}, {5999, 64, 16, 0, 64}, {1 << 30, 128, 16, 0, 64}};
+// for large orders, followed by another window rather than a sweep once it
+// deflates more than 7 % (measured at n = 16384: 64 rows beat 48 and 96;
+// 7 % needs no sweep, 14 % a few)
+const TuneRow kBuiltinTune[] = {{299, 2, 1, 0, 0, 0},
+                                {2999, 32, 16, 0, 0, 0},
+                                {5999, 64, 16, 0, 64, 7},
+                                {1 << 30, 128, 16, 0, 64, 7}};
 std::mutex g_tune_mu;
 std::vector<TuneRow> g_tune(std::begin(kBuiltinTune), std::end(kBuiltinTune));
 
@@ -196,7 +201,8 @@ Params resolve(const schur_opts& o, int n) {
   p.exc_period = o.exc_period > 0 ? o.exc_period : 6;
   p.time = (o.flags & SCHUR_FLAG_TIME_KERNELS) != 0;
   const int aw = o.aed_window != 0 ? o.aed_window : tr.nw;
-  p.nibble = o.aed_nibble < 0 ? -1 : (o.aed_nibble > 0 ? o.aed_nibble : kAedSkipPct);
+  const int nib = o.aed_nibble != 0 ? o.aed_nibble : tr.nibble;
+  p.nibble = nib < 0 ? -1 : (nib > 0 ? nib : kAedSkipPct);
   if (aw < 0) p.nw = 0;
   else if (aw > 0) p.nw = std::min(aw, SMALL_Z_MAX);
   else p.nw = std::min(SMALL_Z_MAX, std::max(16, p.ns + p.ns / 2));
@@ -1601,7 +1607,7 @@ int schur_server_get_stats(schur_server_t S, schur_server_stats* out) {
 }
 
 int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, const int* step,
-                     const int* nw) {
+                     const int* nw, const int* nibble) {
   if (count < 0) return -1;
   std::vector<TuneRow> t;
   if (count == 0) {
@@ -1610,10 +1616,11 @@ int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, c
     if (!nmax || !ns || !nb || !step) return -2;
     for (int i = 0; i < count; ++i) {
       const int w = nw ? nw[i] : 0;
+      const int nib = nibble ? nibble[i] : 0;
       if (ns[i] < 2 || ns[i] > SMALL_EIG_MAX || nb[i] < 1 || nb[i] > NBMAX || step[i] < 0 ||
-          w > SMALL_Z_MAX || (w > 0 && w < 4) || (i > 0 && nmax[i] <= nmax[i - 1]))
+          w > SMALL_Z_MAX || (w > 0 && w < 4) || nib > 100 || (i > 0 && nmax[i] <= nmax[i - 1]))
         return -2;
-      t.push_back(TuneRow{nmax[i], ns[i] & ~1, nb[i], step[i], w});
+      t.push_back(TuneRow{nmax[i], ns[i] & ~1, nb[i], step[i], w, nib});
     }
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -114,7 +114,7 @@ def load():
     lib.schur_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.schur_server_get_stats.restype = ctypes.c_int
     pi = ctypes.POINTER(ctypes.c_int)
-    lib.schur_set_tuning.argtypes = [ip, pi, pi, pi, pi, pi]
+    lib.schur_set_tuning.argtypes = [ip, pi, pi, pi, pi, pi, pi]
     lib.schur_set_tuning.restype = ctypes.c_int
     lib.schur_plan_sweep.argtypes = [ip, ip, ip, ip, ip, pi, ip]
     lib.schur_plan_sweep.restype = ctypes.c_int
@@ -335,14 +335,16 @@ class Server:
 
 
 def set_tuning(rows):
-    """Install a tuning table: rows of dicts with nmax, ns, nb, step and the
-    early-deflation window nw (ascending nmax)."""
+    """Install a tuning table: rows of dicts with nmax, ns, nb, step, the
+    early-deflation window nw and its sweep-skip percentage nibble
+    (ascending nmax)."""
     lib = load()
     k = len(rows)
     IA = ctypes.c_int * max(k, 1)
     rc = lib.schur_set_tuning(k, IA(*[r["nmax"] for r in rows]), IA(*[r["ns"] for r in rows]),
                               IA(*[r["nb"] for r in rows]), IA(*[r.get("step", 0) for r in rows]),
-                              IA(*[r.get("nw", 0) for r in rows]))
+                              IA(*[r.get("nw", 0) for r in rows]),
+                              IA(*[r.get("nibble", 0) for r in rows]))
     if rc != 0:
         raise ValueError("invalid tuning table (rc=%d)" % rc)
 

@@ -157,13 +157,14 @@ def test_planned_sweep_equals_sequential_double_shift_steps(n, ktop, kbot, npair
 
 
 def test_tuning_table_roundtrip():
-    rows = [{"nmax": 500, "ns": 8, "nb": 4, "step": 0, "nw": 24},
-            {"nmax": 1 << 30, "ns": 64, "nb": 16, "step": 0, "nw": -1}]
+    rows = [{"nmax": 500, "ns": 8, "nb": 4, "step": 0, "nw": 24, "nibble": 5},
+            {"nmax": 1 << 30, "ns": 64, "nb": 16, "step": 0, "nw": -1, "nibble": -1}]
     schur.set_tuning(rows)
     for bad in ({"nmax": 10, "ns": 1, "nb": 1, "step": 0},
                 {"nmax": 10, "ns": 4, "nb": 2, "step": 0, "nw": 2},
                 {"nmax": 10, "ns": 4, "nb": 2, "step": 0, "nw": 97},
-                {"nmax": 10, "ns": 4, "nb": 25, "step": 0}):
+                {"nmax": 10, "ns": 4, "nb": 25, "step": 0},
+                {"nmax": 10, "ns": 4, "nb": 2, "step": 0, "nibble": 101}):
         with pytest.raises(ValueError):
             schur.set_tuning([bad])
     with pytest.raises(ValueError):   # nmax must ascend
