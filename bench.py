@@ -50,7 +50,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle sample")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--workload", choices=["n16384", "batch", "serve"], default="n16384")
+    ap.add_argument("--sweep-ns", type=int, default=256,
+                    help="shifts per sweep of the forced-sweep measurement (0: skip it)")
+    ap.add_argument("--sweep-count", type=int, default=3,
+                    help="sweeps timed by the forced-sweep measurement")
+    ap.add_argument("--workload", choices=["n16384", "batch", "serve", "sweep"], default="n16384")
     ap.add_argument("--count", type=int, default=2000, help="batch: number of matrices")
     ap.add_argument("--plain-sample", type=int, default=60,
                     help="batch/serve: requests timed with per-matrix plain launches")
@@ -278,6 +282,85 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def table_row(n):
+    """The tuning-table row the library uses for order n (options left at 0)."""
+    from paper_1905_04975_amd import schur
+    try:
+        with open(schur.TUNING_PATH) as f:
+            rows = json.load(f)["table"]
+    except (OSError, ValueError, KeyError):
+        return {}
+    for r in sorted(rows, key=lambda r: r["nmax"]):
+        if n <= r["nmax"]:
+            return r
+    return {}
+
+
+def sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream):
+    """Forced multishift sweeps on the same matrix: `--sweep-ns` shifts per
+    sweep (the trailing block of that order gives them), a sweep after every
+    early-deflation window, stopped after `--sweep-count` sweeps.  Reports
+    the sweep kernels (window chase, row-panel and column-panel/Q products)
+    with HIP-event times; the partial reduction is still an orthogonal
+    similarity, which the probe checks."""
+    import torch
+    from paper_1905_04975_amd import schur
+
+    n = args.n
+    dev = H0.device
+    hs = schur.Handle(0, ns=args.sweep_ns, nb=args.nb, aed_nibble=-1,
+                      max_sweeps=args.sweep_count, flags=schur.FLAG_TIME_KERNELS)
+    H.copy_(H0)
+    Q.copy_(eye)
+    torch.cuda.synchronize(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    info = hs.reduce_async(stream.cuda_stream, n, H.data_ptr(), n, Q.data_ptr(), n,
+                           wr.data_ptr(), wi.data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize(dev)
+    st = hs.stats()
+    hs.close()
+    if info < 0:
+        raise RuntimeError("forced-sweep run failed: info=%d" % info)
+    nsw = max(1, st["sweeps"])
+
+    def gl(name, ms, launches, flops):
+        avg = ms / max(1, launches)
+        ach = flops / max(1, launches) / max(avg * 1e-3, 1e-30) / 1e12
+        return {"kernel": name, "bound": "mfma", "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS, "avg_launch_ms": avg,
+                "launches": launches, "flops_per_launch": flops / max(1, launches)}
+
+    gemm_ms = st["row_ms"] + st["colq_ms"]
+    res = None
+    if not args.no_check:
+        x = torch.randn(n, 2, dtype=torch.float64, device=dev,
+                        generator=torch.Generator(dev).manual_seed(1))
+        Hh = torch.triu(H0, -1)
+        res = (torch.linalg.norm(Hh @ x - Q @ (H @ (Q.t() @ x)))
+               / (torch.linalg.norm(Hh) * torch.linalg.norm(x))).item()
+    out = {
+        "shifts_per_sweep": args.sweep_ns, "sweeps": st["sweeps"],
+        "shifts_applied": st["shifts_applied"], "stop_info": info,
+        "seconds": e0.elapsed_time(e1) / 1e3,
+        "ms_per_sweep": {"chase": st["chase_ms"] / nsw, "row_panel": st["row_ms"] / nsw,
+                         "colq_panel": st["colq_ms"] / nsw, "shifts": st["shift_ms"] / nsw,
+                         "aed": st["aed_ms"] / nsw},
+        "gemm_tflops": st["gemm_flops"] / max(gemm_ms * 1e-3, 1e-30) / 1e12,
+        "gemm_frac_of_fp64_mfma_peak": st["gemm_flops"] / max(gemm_ms * 1e-3, 1e-30) / 1e12
+        / FP64_MFMA_PEAK_TFLOPS,
+        "k_panel_colq": gl("k_panel_colq", st["colq_ms"], st["colq_launches"], st["colq_flops"]),
+        "k_panel_row": gl("k_panel_row", st["row_ms"], st["row_launches"], st["row_flops"]),
+        "residual_probe": res,
+    }
+    print("sweep: %d sweeps of %d shifts, %.3f s, GEMM %.2f TFLOP/s" %
+          (st["sweeps"], args.sweep_ns, out["seconds"], out["gemm_tflops"]), file=sys.stderr,
+          flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.workload == "batch":
@@ -326,6 +409,15 @@ def main():
             raise RuntimeError("schur_reduce_async returned info=%d" % info)
         return e0.elapsed_time(e1) / 1e3, w1 - w0, hdl.stats()
 
+    if args.workload == "sweep":
+        # only the forced-sweep measurement (for profiling the sweep kernels)
+        sw = sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream)
+        print(json.dumps({"metric": "forced multishift sweeps at n=%d: update-GEMM FP64 TFLOP/s" % n,
+                          "value": sw["gemm_tflops"], "unit": "TFLOP/s", "n_gpus": 1,
+                          "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "schur_forced_sweeps_random_hessenberg", "n": n,
+                                     "seed": args.seed}, "sweep": sw}), flush=True)
+        return
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize(dev)
@@ -393,7 +485,10 @@ def main():
         check = {"residual_probe": r.item(), "orthogonality_probe": o.item(),
                  "max_below_subdiag": below,
                  "trace_err": abs(wr.sum().item() - torch.trace(H0).item()) / torch.linalg.norm(Hh).item()}
-    ns_used = args.ns if args.ns else 128
+    sweep = None
+    if args.sweep_ns > 0:
+        sweep = sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream)
+    row = table_row(n)
     out = {
         "metric": "Schur-reduction s & FP64 TFLOP/s at n=16384; batched solves/s; p99 latency",
         "value": value,
@@ -410,10 +505,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "schur_reduction_random_hessenberg", "n": n, "seed": args.seed,
                    "entries": "iid N(0,1) on and above the subdiagonal",
-                   "shifts_per_sweep": ns_used, "window": 128, "schur_vectors": True},
+                   "shifts_per_sweep": args.ns or row.get("ns"),
+                   "bulges_per_group": args.nb or row.get("nb"),
+                   "chase_window_rows": 128,
+                   "aed_window": args.aed_window or row.get("nw"),
+                   "sweep_skip_pct": args.aed_nibble or row.get("nibble") or 14,
+                   "sweeps_executed": st0["sweeps"], "schur_vectors": True},
         "roofline": roofline,
         "breakdown": breakdown,
-        "gemm_roofline": gemm_line,
+        "gemm_roofline_default": gemm_line,
+        "sweep": sweep,
         "check": check,
         "gen_seconds": gen_s,
     }

@@ -66,7 +66,9 @@ typedef struct schur_handle_s* schur_handle_t;
 
 /* Tuning options; zero fields take the built-in defaults (per-n table). */
 typedef struct schur_opts {
-  int ns;          /* shifts per sweep (even); 0 = by table                    */
+  int ns;          /* shifts per sweep (even, <= 256); 0 = by table. Above 128 */
+                   /* the trailing block that supplies them is reduced by a    */
+                   /* nested solve of this engine (no Schur vectors)           */
   int nb;          /* bulges per window chain (group), 1..24; 0 = by table     */
   int step;        /* chain steps per window; 0 = largest that fits 128 rows   */
   int nmin;        /* active blocks of order <= nmin are solved in one kernel  */

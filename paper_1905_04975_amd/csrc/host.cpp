@@ -40,6 +40,8 @@ using namespace schur;
 namespace {
 
 constexpr int NSMAX = 512;             // shifts buffer capacity
+constexpr int NS_MAX = 256;            // shifts per sweep; above SMALL_EIG_MAX the trailing
+                                       // block is reduced by a nested solve of this engine
 constexpr int REFL_STRIDE = WMAX * NBMAX * 3;
 
 struct HipErr {
@@ -124,6 +126,9 @@ struct schur_handle_s {
     size_t cap = 0;
   };
   Grow b_ctrl, b_defl, b_small, b_shift, b_win, b_u, b_sh, b_aedt, b_aedw;
+  // nested solve of a trailing block larger than SMALL_EIG_MAX (shifts only)
+  schur_handle_s* sub = nullptr;
+  double* shm = nullptr;         // NS_MAX x NS_MAX copy of the trailing block
 };
 
 namespace {
@@ -192,7 +197,7 @@ Params resolve(const schur_opts& o, int n) {
   const TuneRow tr = tune_for(n);
   p.ns = o.ns > 0 ? (o.ns & ~1) : tr.ns;
   if (p.ns < 2) p.ns = 2;
-  if (p.ns > SMALL_EIG_MAX) p.ns = SMALL_EIG_MAX;
+  if (p.ns > NS_MAX) p.ns = NS_MAX;
   p.nb = o.nb > 0 ? o.nb : (tr.nb > 0 ? tr.nb : 16);
   if (p.nb > NBMAX) p.nb = NBMAX;
   p.step = o.step > 0 ? o.step : tr.step;
@@ -332,6 +337,8 @@ void plan_sweep(int ktop, int kbot, int npair, int nbmax, int step_opt,
   }
 }
 
+int create_handle(schur_handle_s** out, int device, const schur_opts* opts);
+
 struct Solver {
   schur_handle_s* h;
   hipStream_t s;
@@ -343,22 +350,35 @@ struct Solver {
 
   int64_t tslot = 0;   // time steps issued so far (ring position of the U slots)
 
-  // Tile counts of the row panel and column panel (main stream) in `a`, and
+  // Workgroup counts of the row panel and column panel (main stream) in `a`, and
   // of the Q products (aux stream) in `aq`, a copy of `a`.
+  // Tiles per workgroup of one panel launch (one workgroup per CU at a
+  // time): the count that minimises rounds of workgroups x (tiles per
+  // workgroup + the fixed cost of a workgroup, about half a tile), so that
+  // the windows' ragged tile counts leave few CUs idle in the last round.
+  template <typename TilesOf>
+  static int tiles_per_block(int nwin, TilesOf tiles_of) {
+    constexpr int kCUs = 256;
+    int best = 1;
+    double best_cost = 1e300;
+    for (int tpb = 1; tpb <= PANEL_TPB; ++tpb) {
+      long blocks = 0;
+      for (int w = 0; w < nwin; ++w) blocks += panel_blocks(tiles_of(w), tpb);
+      if (blocks == 0) return 1;
+      const long rounds = (blocks + kCUs - 1) / kCUs;
+      const double cost = (double)rounds * (tpb + 0.5);
+      if (cost < best_cost - 1e-9) { best_cost = cost; best = tpb; }
+    }
+    return best;
+  }
+
   void fill_gemm(SweepArgs& a, SweepArgs& aq, int& tr, int& tc, int& tq) {
-    tr = 0;
-    tc = 0;
-    tq = 0;
     for (int w = 0; w < a.nwin; ++w) {
       Win& d = a.win[w];
       const int pe = d.p + d.ws - 1;
       d.tiles_r = std::max(0, (a.cend - pe - 1 + GEMM_T - 1) / GEMM_T);
       d.tiles_c = std::max(0, (d.p - a.rtop + GEMM_T - 1) / GEMM_T);
       d.tiles_q = 0;
-      d.base_r = tr;
-      d.base_cq = tc;
-      tr += d.tiles_r;
-      tc += d.tiles_c;
       const double ws = d.ws;
       const double fr = 2.0 * ws * ws * (double)std::max(0, a.cend - pe - 1);
       const double fc = 2.0 * ws * ws * ((double)(d.p - a.rtop) + (a.Q ? (double)n : 0.0));
@@ -366,14 +386,29 @@ struct Solver {
       h->stats.colq_flops += fc;
       h->stats.gemm_flops += fr + fc;
     }
+    a.tpb_r = tiles_per_block(a.nwin, [&](int w) { return a.win[w].tiles_r; });
+    a.tpb_cq = tiles_per_block(a.nwin, [&](int w) { return a.win[w].tiles_c; });
+    tr = 0;
+    tc = 0;
+    for (int w = 0; w < a.nwin; ++w) {
+      Win& d = a.win[w];
+      d.base_r = tr;
+      d.base_cq = tc;
+      tr += panel_blocks(d.tiles_r, a.tpb_r);
+      tc += panel_blocks(d.tiles_c, a.tpb_cq);
+    }
     aq = a;
+    const int tiles_q = a.Q ? (n + GEMM_T - 1) / GEMM_T : 0;
+    aq.tpb_r = 1;
+    aq.tpb_cq = tiles_per_block(aq.nwin, [&](int) { return tiles_q; });
+    tq = 0;
     for (int w = 0; w < aq.nwin; ++w) {
       Win& d = aq.win[w];
       d.tiles_r = 0;
       d.tiles_c = 0;
-      d.tiles_q = a.Q ? (n + GEMM_T - 1) / GEMM_T : 0;
+      d.tiles_q = tiles_q;
       d.base_cq = tq;
-      tq += d.tiles_q;
+      tq += panel_blocks(d.tiles_q, aq.tpb_cq);
     }
   }
 
@@ -527,9 +562,43 @@ struct Solver {
     return nd;
   }
 
+  // Eigenvalues of the trailing ns x ns block (H(kbot-ns+1:kbot, same)) by a
+  // nested solve of this engine on a copy, without Schur vectors; returns its
+  // info (0: ewr/ewi hold all ns eigenvalues).
+  int nested_shift_solve(int kbot, int ns) {
+    if (!h->sub) {
+      schur_handle_s* sub = nullptr;
+      if (create_handle(&sub, h->device, nullptr) != 0) throw HipErr{hipErrorOutOfMemory};
+      h->sub = sub;
+    }
+    if (!h->shm && hipMalloc(&h->shm, sizeof(double) * NS_MAX * NS_MAX) != hipSuccess)
+      throw HipErr{hipErrorOutOfMemory};
+    const int b0 = kbot - ns + 1;
+    HCHECK(hipMemcpy2DAsync(h->shm, sizeof(double) * ns, H + b0 + (size_t)b0 * ldh,
+                            sizeof(double) * ldh, sizeof(double) * ns, ns,
+                            hipMemcpyDeviceToDevice, s));
+    if (alloc_ws(h->sub, ns) != 0) throw HipErr{hipErrorOutOfMemory};
+    std::memset(&h->sub->stats, 0, sizeof(h->sub->stats));
+    schur_opts so{};
+    Solver sv{h->sub, s, resolve(so, ns), ns, h->shm, ns, nullptr, ns, h->ewr, h->ewi};
+    const int info = sv.run();
+    h->stats.launches += h->sub->stats.launches;
+    return info;
+  }
+
   void compute_shifts(int ktop, int kbot, int ns, bool exceptional) {
     hipEvent_t e0 = nullptr;
     if (P.time) h->timer.begin(s, e0);
+    if (!exceptional && ns > SMALL_EIG_MAX) {
+      // a failed nested solve (or a non-finite block) falls back to the ad-hoc pair
+      const int info = nested_shift_solve(kbot, ns);
+      launch_shift_prep(h->ewr, h->ewi, ns, nullptr, info != 0 ? 1 : 0, H, ldh, ktop, kbot, h->st,
+                        s);
+      HCHECK(hipGetLastError());
+      if (P.time) h->timer.end(s, e0, &h->stats.shift_ms);
+      h->stats.launches += 1;
+      return;
+    }
     if (!exceptional) {
       SmallTask t{};
       const int b0 = kbot - ns + 1;
@@ -879,7 +948,7 @@ struct BatchEngine {
     for (int i : big) {
       const Mat& m = M[i];
       const int len = m.kbot - m.ktop + 1;
-      const int ns = std::max(2, std::min(m.P.ns, 2 * ((len - 2) / 6)));
+      const int ns = std::max(2, std::min(std::min(m.P.ns, SMALL_EIG_MAX), 2 * ((len - 2) / 6)));
       gsum += (size_t)((ns / 2 + m.P.nb - 1) / m.P.nb);
     }
     const size_t nslots = std::max(std::max(gsum, small.size()), big.size());
@@ -1017,7 +1086,7 @@ struct BatchEngine {
       if (!sweep_it[q]) continue;
       Mat& m = M[big[q]];
       const int len = m.kbot - m.ktop + 1;
-      int ns = std::min(m.P.ns, 2 * ((len - 2) / 6));
+      int ns = std::min(std::min(m.P.ns, SMALL_EIG_MAX), 2 * ((len - 2) / 6));
       if (ns < 2) ns = 2;
       const bool exc = (m.nodefl > 0 && m.nodefl % m.P.exc_period == 0);
       if (!exc && aed_nu[q] >= 2 && 2 * aed_nu[q] >= ns) {
@@ -1154,8 +1223,8 @@ struct BatchEngine {
     w.tiles_q = w.c.Q ? (w.c.n + GEMM_T - 1) / GEMM_T : 0;
     w.base_r = tr;
     w.base_cq = tcq;
-    tr += w.tiles_r;
-    tcq += w.tiles_c + w.tiles_q;
+    tr += panel_blocks(w.tiles_r, PANEL_TPB_BATCH);
+    tcq += panel_blocks(w.tiles_c + w.tiles_q, PANEL_TPB_BATCH);
     const double ws = w.c.ws;
     const double fr = 2.0 * ws * ws * (double)std::max(0, w.c.cend - pe - 1);
     const double fc = 2.0 * ws * ws * ((double)(w.c.p - w.c.rtop) + (w.c.Q ? (double)w.c.n : 0.0));
@@ -1441,6 +1510,8 @@ int schur_destroy(schur_handle_t h) {
     if (h->ev_q[i]) (void)hipEventDestroy(h->ev_q[i]);
   }
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->sub) (void)schur_destroy(h->sub);
+  if (h->shm) (void)hipFree(h->shm);
   free_ws(h);
   delete h;
   return 0;
@@ -1617,7 +1688,7 @@ int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, c
     for (int i = 0; i < count; ++i) {
       const int w = nw ? nw[i] : 0;
       const int nib = nibble ? nibble[i] : 0;
-      if (ns[i] < 2 || ns[i] > SMALL_EIG_MAX || nb[i] < 1 || nb[i] > NBMAX || step[i] < 0 ||
+      if (ns[i] < 2 || ns[i] > NS_MAX || nb[i] < 1 || nb[i] > NBMAX || step[i] < 0 ||
           w > SMALL_Z_MAX || (w > 0 && w < 4) || nib > 100 || (i > 0 && nmax[i] <= nmax[i - 1]))
         return -2;
       t.push_back(TuneRow{nmax[i], ns[i] & ~1, nb[i], step[i], w, nib});

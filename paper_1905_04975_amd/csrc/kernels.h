@@ -53,8 +53,8 @@ void launch_shift_prep(const double* wr, const double* wi, int ns, const int* sm
                        int exceptional, const double* H, int ldh, int ktop, int kbot, double* st,
                        hipStream_t s);
 void launch_chase(const SweepArgs& a, hipStream_t s);
-void launch_panel_row(const SweepArgs& a, int tiles, hipStream_t s);
-void launch_panel_colq(const SweepArgs& a, int tiles, hipStream_t s);
+void launch_panel_row(const SweepArgs& a, int blocks, hipStream_t s);
+void launch_panel_colq(const SweepArgs& a, int blocks, hipStream_t s);
 void launch_check_finite(const double* H, int ldh, int n, Ctrl* ctrl, hipStream_t s);
 void launch_zero_lower(double* H, int ldh, int n, hipStream_t s);
 void launch_ctrl_reset(Ctrl* ctrl, hipStream_t s);
@@ -66,8 +66,8 @@ void launch_standardize(double* H, int ldh, double* Q, int ldq, int n, int kmin,
 // batched (descriptor arrays in device memory)
 void launch_small_tasks(const SmallTask* tasks, int count, int maxm, bool wantz, hipStream_t s);
 void launch_chase_b(const WinB* wins, int nwin, hipStream_t s);
-void launch_panel_row_b(const WinB* wins, int nwin, int tiles, hipStream_t s);
-void launch_panel_colq_b(const WinB* wins, int nwin, int tiles, hipStream_t s);
+void launch_panel_row_b(const WinB* wins, int nwin, int blocks, hipStream_t s);
+void launch_panel_colq_b(const WinB* wins, int nwin, int blocks, hipStream_t s);
 void launch_deflate_b(const DeflB* tasks, int count, hipStream_t s);
 void launch_shift_prep_b(const ShiftB* tasks, int count, hipStream_t s);
 

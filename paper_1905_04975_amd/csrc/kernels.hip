@@ -200,23 +200,37 @@ __device__ __forceinline__ int find_window_b(const WinB* wins, int nwin, int bid
   return lo;
 }
 
-// Y(ws x 64) = U^T X for one 64-column tile of a window's row panel, in place.
-__device__ void panel_row_tile(const WinCtx& d, int tile) {
-  __shared__ double Xs[WMAX * LDT];   // row-major tile: Xs[c + r*LDT]
+// Panel tiles are processed up to PANEL_TPB at a time by one workgroup of
+// four waves, one workgroup per CU (two 128 x 68 FP64 LDS buffers, 136 KiB):
+//  * the window's U (or U^T) is read into registers once;
+//  * while tile t is multiplied from LDS, the wave issues, one per k step,
+//    the global loads of tile t+1 (into registers) and the global stores of
+//    the results of tile t-1 (kept in a second set of accumulators), so that
+//    HBM traffic and the FP64 MFMA work overlap instead of alternating;
+//  * the operands of the next k step are read from LDS before the products
+//    of the current one are issued.
+// Each pass: tile t -> LDS, barrier, then the interleaved k loop.  One pass
+// more than there are tiles stores the last results.
+
+// Row panel: Y(ws x 64) = U^T X for 64-column tiles of H(p:p+ws-1, right of
+// the window).  Wave w owns rows 32w..32w+31 of U^T (A operand, registers)
+// and all 64 tile columns (B operand from LDS, row-major tile Xs[c + r*LDT]).
+// Element e of a thread's tile load: window row r = lane + 64 (e & 1), tile
+// column c = wave + 4 (e >> 1).  Element s of a thread's results: acc[s >> 4]
+// [(s >> 2) & 3][s & 3], row i0 + 16 (s >> 4) + lk + 4 (s & 3), column
+// 16 ((s >> 2) & 3) + li.
+__device__ void panel_row_tiles(const WinCtx& d, int t0, int t1) {
+  __shared__ double Xs[2][WMAX * LDT];
   const int p = d.p, ws = d.ws;
-  const int c0 = p + ws + tile * PT;
-  const int nc = min(PT, d.cend - c0);
   const int kpad = (ws + 3) & ~3;
   const double* Ut = d.U;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int i0 = wave * 32;
-  // this wave's A operands (rows i0..i0+31 of U^T, all k) go to registers
-  // before the tile load so that their latency hides behind it; the slot is
-  // zero padded to UPAD x UPAD, so the full K = UPAD is read
+  const bool active = i0 < ws;
   double ua[UPAD / 4][2];
-  if (i0 < ws) {
+  if (active) {
 #pragma unroll
     for (int ks = 0; ks < UPAD / 4; ++ks) {
       const int k = 4 * ks + lk;
@@ -224,65 +238,98 @@ __device__ void panel_row_tile(const WinCtx& d, int tile) {
       ua[ks][1] = Ut[(i0 + 16 + li) + (size_t)k * UPAD];
     }
   }
-
-  for (int idx = tid; idx < kpad * PT; idx += 256) {
-    const int c = idx / kpad, r = idx - c * kpad;
-    double v = 0.0;
-    if (r < ws && c < nc) v = d.H[(size_t)(p + r) + (size_t)(c0 + c) * d.ldh];
-    Xs[c + r * LDT] = v;
+  double* const H = d.H;
+  const size_t ldh = d.ldh;
+  // first column of tile t and its width
+  auto col0 = [&](int t) { return p + ws + t * PT; };
+  auto ncols = [&](int t) { return min(PT, d.cend - col0(t)); };
+  // rows past the window read row ws-1 and are zeroed on the way to LDS;
+  // columns past the panel are not read (uniform test per wave)
+  auto load_one = [&](double& dst, int c0, int nc, int e) {
+    const int r = lane + 64 * (e & 1), c = wave + 4 * (e >> 1);
+    dst = (c < nc) ? H[(size_t)(p + min(r, ws - 1)) + (size_t)(c0 + c) * ldh] : 0.0;
+  };
+  auto store_one = [&](const d4 (&res)[2][4], int c0, int nc, int s) {
+    const int ib = s >> 4, jb = (s >> 2) & 3, e = s & 3;
+    const int row = i0 + ib * 16 + lk + 4 * e, col = jb * 16 + li;
+    if (row < ws && col < nc) H[(size_t)(p + row) + (size_t)(c0 + col) * ldh] = res[ib][jb][e];
+  };
+  double pre[32];
+  {
+    const int c0 = col0(t0), nc = ncols(t0);
+#pragma unroll
+    for (int e = 0; e < 32; ++e) load_one(pre[e], c0, nc, e);
   }
-  __syncthreads();
-
-  if (i0 >= ws) return;
-  d4 acc[2][4];
-  for (int ib = 0; ib < 2; ++ib)
-    for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
+  __builtin_amdgcn_s_waitcnt(0);   // U and the first tile are in registers
+  d4 acc[2][4], accp[2][4];
+  for (int t = t0; t <= t1; ++t) {
+    const bool cur = t < t1, prev = t > t0 && active, next = t + 1 < t1;
+    double* X = Xs[(t - t0) & 1];
+    if (cur) {
 #pragma unroll
-  for (int ks = 0; ks < UPAD / 4; ++ks) {
-    if (4 * ks >= kpad) break;
-    const int k = 4 * ks + lk;
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-      const double b = Xs[(jb * 16 + li) + k * LDT];
-      acc[0][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][0], b, acc[0][jb], 0, 0, 0);
-      acc[1][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][1], b, acc[1][jb], 0, 0, 0);
+      for (int e = 0; e < 32; ++e) {
+        const int r = lane + 64 * (e & 1), c = wave + 4 * (e >> 1);
+        X[c + r * LDT] = r < ws ? pre[e] : 0.0;   // r < 128, c < 64: inside the buffer
+      }
+      __syncthreads();
     }
-  }
-  for (int ib = 0; ib < 2; ++ib)
-    for (int jb = 0; jb < 4; ++jb) {
-      const int col = jb * 16 + li;
-      if (col >= nc) continue;
-      for (int e = 0; e < 4; ++e) {
-        const int row = i0 + ib * 16 + lk + 4 * e;
-        if (row < ws) d.H[(size_t)(p + row) + (size_t)(c0 + col) * d.ldh] = acc[ib][jb][e];
+    const int cn0 = col0(t + 1), nnc = ncols(t + 1);
+    const int cp0 = col0(t - 1), npc = ncols(t - 1);
+    const bool mm = active && cur;
+    if (mm) {
+      for (int ib = 0; ib < 2; ++ib)
+        for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+    double bn[4];
+    if (mm) {
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) bn[jb] = X[(jb * 16 + li) + lk * LDT];
+    }
+#pragma unroll
+    for (int ks = 0; ks < UPAD / 4; ++ks) {
+      if (next) load_one(pre[ks], cn0, nnc, ks);
+      if (prev) store_one(accp, cp0, npc, ks);
+      if (mm && 4 * ks < kpad) {
+        double b[4];
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) b[jb] = bn[jb];
+        const int kn = min(4 * ks + 4, kpad - 4) + lk;   // the last step re-reads a valid row
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) bn[jb] = X[(jb * 16 + li) + kn * LDT];
+        __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the products below
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+          acc[0][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][0], b[jb], acc[0][jb], 0, 0, 0);
+          acc[1][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][1], b[jb], acc[1][jb], 0, 0, 0);
+        }
       }
     }
+    if (mm) {
+      for (int ib = 0; ib < 2; ++ib)
+        for (int jb = 0; jb < 4; ++jb) accp[ib][jb] = acc[ib][jb];
+    }
+  }
 }
 
-// Y(64 x ws) = X U for one 64-row tile of a window's column panel (tile <
-// tiles_c) or of Q (the remaining tiles).
-__device__ void panel_colq_tile(const WinCtx& d, int tile, int tiles_c) {
-  __shared__ double Xs[WMAX * LDT];   // column-major tile: Xs[r + c*LDT]
+// Column panel and Q: Y(64 x ws) = X U for 64-row tiles; tile < tiles_c is
+// a tile of H(rtop:p-1, p:p+ws-1), the others are tiles of Q(:, p:p+ws-1).
+// Wave w owns columns 32w..32w+31 of U (B operand, registers) and all 64
+// tile rows (A operand from LDS, column-major tile Xs[r + c*LDT]).  Element
+// e of a thread's tile load: tile row lane, window column wave + 4 e.
+// Element s of a thread's results: acc[s >> 3][(s >> 2) & 1][s & 3], row
+// 16 (s >> 3) + lk + 4 (s & 3), column j0 + 16 ((s >> 2) & 1) + li.
+__device__ void panel_colq_tiles(const WinCtx& d, int t0, int t1, int tiles_c) {
+  __shared__ double Xs[2][WMAX * LDT];
   const int p = d.p, ws = d.ws;
-  double* M;
-  int ld, r0, rend;
-  if (tile < tiles_c) {
-    M = d.H; ld = d.ldh; r0 = d.rtop + tile * PT; rend = p;
-  } else {
-    tile -= tiles_c;
-    M = d.Q; ld = d.ldq; r0 = tile * PT; rend = d.n;
-  }
-  const int nr = min(PT, rend - r0);
   const int kpad = (ws + 3) & ~3;
   const double* Ut = d.U;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int j0 = wave * 32;
-  // this wave's B operands (columns j0..j0+31 of U, all k) go to registers
-  // before the tile load (zero-padded slot, full K = UPAD)
+  const bool active = j0 < ws;
   double ub[UPAD / 4][2];
-  if (j0 < ws) {
+  if (active) {
 #pragma unroll
     for (int ks = 0; ks < UPAD / 4; ++ks) {
       const int k = 4 * ks + lk;
@@ -290,59 +337,120 @@ __device__ void panel_colq_tile(const WinCtx& d, int tile, int tiles_c) {
       ub[ks][1] = Ut[(j0 + 16 + li) + (size_t)k * UPAD];
     }
   }
-
-  for (int idx = tid; idx < kpad * PT; idx += 256) {
-    const int c = idx / PT, r = idx - c * PT;
-    double v = 0.0;
-    if (r < nr && c < ws) v = M[(size_t)(r0 + r) + (size_t)(p + c) * ld];
-    Xs[r + c * LDT] = v;
-  }
-  __syncthreads();
-
-  if (j0 >= ws) return;
-  d4 acc[4][2];
-  for (int ib = 0; ib < 4; ++ib)
-    for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int ks = 0; ks < UPAD / 4; ++ks) {
-    if (4 * ks >= kpad) break;
-    const int k = 4 * ks + lk;
-#pragma unroll
-    for (int ib = 0; ib < 4; ++ib) {
-      const double av = Xs[(ib * 16 + li) + k * LDT];
-      acc[ib][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ub[ks][0], acc[ib][0], 0, 0, 0);
-      acc[ib][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ub[ks][1], acc[ib][1], 0, 0, 0);
+  // tile t: first element (row r0, column p) and number of rows
+  struct Tile { double* base; size_t ld; int nr; };
+  auto tile = [&](int t) {
+    Tile T;
+    if (t < tiles_c) {
+      const int r0 = d.rtop + t * PT;
+      T.base = d.H + (size_t)r0 + (size_t)p * d.ldh; T.ld = d.ldh; T.nr = min(PT, p - r0);
+    } else {
+      const int r0 = (t - tiles_c) * PT;
+      T.base = d.Q + (size_t)r0 + (size_t)p * d.ldq; T.ld = d.ldq; T.nr = min(PT, d.n - r0);
     }
+    return T;
+  };
+  // rows past the tile read its last row and are zeroed on the way to LDS;
+  // columns past the window are not read (uniform test per wave)
+  auto load_one = [&](double& dst, const Tile& T, int e) {
+    const int c = wave + 4 * e;
+    dst = (c < ws) ? T.base[(size_t)min(lane, T.nr - 1) + (size_t)c * T.ld] : 0.0;
+  };
+  auto store_one = [&](const d4 (&res)[4][2], const Tile& T, int s) {
+    const int ib = s >> 3, jb = (s >> 2) & 1, e = s & 3;
+    const int row = ib * 16 + lk + 4 * e, col = j0 + jb * 16 + li;
+    if (row < T.nr && col < ws) T.base[(size_t)row + (size_t)col * T.ld] = res[ib][jb][e];
+  };
+  double pre[32];
+  {
+    const Tile T = tile(t0);
+#pragma unroll
+    for (int e = 0; e < 32; ++e) load_one(pre[e], T, e);
   }
-  for (int ib = 0; ib < 4; ++ib)
-    for (int jb = 0; jb < 2; ++jb) {
-      const int col = j0 + jb * 16 + li;
-      if (col >= ws) continue;
-      for (int e = 0; e < 4; ++e) {
-        const int row = ib * 16 + lk + 4 * e;
-        if (row < nr) M[(size_t)(r0 + row) + (size_t)(p + col) * ld] = acc[ib][jb][e];
+  __builtin_amdgcn_s_waitcnt(0);   // U and the first tile are in registers
+  d4 acc[4][2], accp[4][2];
+  for (int t = t0; t <= t1; ++t) {
+    const bool cur = t < t1, prev = t > t0 && active, next = t + 1 < t1;
+    double* X = Xs[(t - t0) & 1];
+    if (cur) {
+      const int nr_t = tile(t).nr;
+#pragma unroll
+      for (int e = 0; e < 32; ++e)   // inside the buffer
+        X[lane + (wave + 4 * e) * LDT] = lane < nr_t ? pre[e] : 0.0;
+      __syncthreads();
+    }
+    const Tile TN = tile(next ? t + 1 : t0), TP = tile(prev ? t - 1 : t0);
+    const bool mm = active && cur;
+    if (mm) {
+      for (int ib = 0; ib < 4; ++ib)
+        for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+    double an[4];
+    if (mm) {
+#pragma unroll
+      for (int ib = 0; ib < 4; ++ib) an[ib] = X[(ib * 16 + li) + lk * LDT];
+    }
+#pragma unroll
+    for (int ks = 0; ks < UPAD / 4; ++ks) {
+      if (next) load_one(pre[ks], TN, ks);
+      if (prev) store_one(accp, TP, ks);
+      if (mm && 4 * ks < kpad) {
+        double av[4];
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) av[ib] = an[ib];
+        const int kn = min(4 * ks + 4, kpad - 4) + lk;   // the last step re-reads a valid row
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) an[ib] = X[(ib * 16 + li) + kn * LDT];
+        __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the products below
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+          acc[ib][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ib], ub[ks][0], acc[ib][0], 0, 0, 0);
+          acc[ib][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ib], ub[ks][1], acc[ib][1], 0, 0, 0);
+        }
       }
     }
+    if (mm) {
+      for (int ib = 0; ib < 4; ++ib)
+        for (int jb = 0; jb < 2; ++jb) accp[ib][jb] = acc[ib][jb];
+    }
+  }
 }
 
-__global__ __launch_bounds__(256, 2) void k_panel_row(SweepArgs a) {
+// tiles [t0, t1) of the window whose workgroup prefix is `base`
+__device__ __forceinline__ void block_tiles(int bid, int base, int tiles, int tpb, int& t0,
+                                            int& t1) {
+  t0 = (bid - base) * tpb;
+  t1 = min(tiles, t0 + tpb);
+}
+
+__global__ __launch_bounds__(256, 1) void k_panel_row(SweepArgs a) {
   const int w = find_window(a, blockIdx.x, true);
-  panel_row_tile(ctx_of(a, a.win[w]), blockIdx.x - a.win[w].base_r);
+  int t0, t1;
+  block_tiles(blockIdx.x, a.win[w].base_r, a.win[w].tiles_r, a.tpb_r, t0, t1);
+  panel_row_tiles(ctx_of(a, a.win[w]), t0, t1);
 }
 
-__global__ __launch_bounds__(256, 2) void k_panel_colq(SweepArgs a) {
+__global__ __launch_bounds__(256, 1) void k_panel_colq(SweepArgs a) {
   const int w = find_window(a, blockIdx.x, false);
-  panel_colq_tile(ctx_of(a, a.win[w]), blockIdx.x - a.win[w].base_cq, a.win[w].tiles_c);
+  int t0, t1;
+  block_tiles(blockIdx.x, a.win[w].base_cq, a.win[w].tiles_c + a.win[w].tiles_q, a.tpb_cq, t0,
+              t1);
+  panel_colq_tiles(ctx_of(a, a.win[w]), t0, t1, a.win[w].tiles_c);
 }
 
-__global__ __launch_bounds__(256, 2) void k_panel_row_b(const WinB* wins, int nwin) {
+__global__ __launch_bounds__(256, 1) void k_panel_row_b(const WinB* wins, int nwin) {
   const int w = find_window_b(wins, nwin, blockIdx.x, true);
-  panel_row_tile(wins[w].c, blockIdx.x - wins[w].base_r);
+  int t0, t1;
+  block_tiles(blockIdx.x, wins[w].base_r, wins[w].tiles_r, PANEL_TPB_BATCH, t0, t1);
+  panel_row_tiles(wins[w].c, t0, t1);
 }
 
-__global__ __launch_bounds__(256, 2) void k_panel_colq_b(const WinB* wins, int nwin) {
+__global__ __launch_bounds__(256, 1) void k_panel_colq_b(const WinB* wins, int nwin) {
   const int w = find_window_b(wins, nwin, blockIdx.x, false);
-  panel_colq_tile(wins[w].c, blockIdx.x - wins[w].base_cq, wins[w].tiles_c);
+  int t0, t1;
+  block_tiles(blockIdx.x, wins[w].base_cq, wins[w].tiles_c + wins[w].tiles_q, PANEL_TPB_BATCH,
+              t0, t1);
+  panel_colq_tiles(wins[w].c, t0, t1, wins[w].tiles_c);
 }
 
 // ============================================================================
@@ -695,12 +803,12 @@ void launch_chase(const SweepArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_chase, dim3(a.nwin), dim3(CHASE_THREADS), 0, s, a);
 }
 
-void launch_panel_row(const SweepArgs& a, int tiles, hipStream_t s) {
-  if (tiles > 0) hipLaunchKernelGGL(k_panel_row, dim3(tiles), dim3(256), 0, s, a);
+void launch_panel_row(const SweepArgs& a, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_panel_row, dim3(blocks), dim3(256), 0, s, a);
 }
 
-void launch_panel_colq(const SweepArgs& a, int tiles, hipStream_t s) {
-  if (tiles > 0) hipLaunchKernelGGL(k_panel_colq, dim3(tiles), dim3(256), 0, s, a);
+void launch_panel_colq(const SweepArgs& a, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_panel_colq, dim3(blocks), dim3(256), 0, s, a);
 }
 
 void launch_small_tasks(const SmallTask* tasks, int count, int maxm, bool wantz, hipStream_t s) {
@@ -721,12 +829,12 @@ void launch_chase_b(const WinB* wins, int nwin, hipStream_t s) {
   if (nwin > 0) hipLaunchKernelGGL(k_chase_b, dim3(nwin), dim3(CHASE_THREADS), 0, s, wins);
 }
 
-void launch_panel_row_b(const WinB* wins, int nwin, int tiles, hipStream_t s) {
-  if (tiles > 0) hipLaunchKernelGGL(k_panel_row_b, dim3(tiles), dim3(256), 0, s, wins, nwin);
+void launch_panel_row_b(const WinB* wins, int nwin, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_panel_row_b, dim3(blocks), dim3(256), 0, s, wins, nwin);
 }
 
-void launch_panel_colq_b(const WinB* wins, int nwin, int tiles, hipStream_t s) {
-  if (tiles > 0) hipLaunchKernelGGL(k_panel_colq_b, dim3(tiles), dim3(256), 0, s, wins, nwin);
+void launch_panel_colq_b(const WinB* wins, int nwin, int blocks, hipStream_t s) {
+  if (blocks > 0) hipLaunchKernelGGL(k_panel_colq_b, dim3(blocks), dim3(256), 0, s, wins, nwin);
 }
 
 void launch_deflate_b(const DeflB* tasks, int count, hipStream_t s) {

@@ -25,6 +25,8 @@ constexpr int UPAD = WMAX;         // leading dimension of the U slots
 constexpr int SMALL_Z_MAX = 96;    // block order solved in LDS with its Z
 constexpr int SMALL_EIG_MAX = 128; // block order solved in LDS, eigenvalues only
 constexpr int GEMM_T = 64;         // panel tile edge (rows or columns)
+constexpr int PANEL_TPB = 8;       // most panel tiles per workgroup (one load of U)
+constexpr int PANEL_TPB_BATCH = 4; // panel tiles per workgroup of the batched launches
 constexpr int REFL_LDS = 1280;     // reflectors (chain step x bulge) logged in LDS per window
 
 // ---- one diagonal window of a sweep (a "window task") -----------------------
@@ -37,8 +39,8 @@ struct Win {
   int tiles_r;        // row-panel tiles  (columns pe+1 .. ncol-1)
   int tiles_c;        // column-panel tiles (rows rtop .. p-1)
   int tiles_q;        // Q tiles (rows 0 .. n-1)
-  int base_r;         // prefix of tiles_r over the windows
-  int base_cq;        // prefix of tiles_c + tiles_q over the windows
+  int base_r;         // prefix of panel_blocks(tiles_r, tpb_r) over the windows
+  int base_cq;        // prefix of panel_blocks(tiles_c + tiles_q, tpb_cq) over the windows
 };
 
 struct SweepArgs {
@@ -53,6 +55,7 @@ struct SweepArgs {
   double* refl;             // reflector slots (v2, v3, tau) per chain step & bulge
   int refl_stride;          // doubles per reflector slot
   int nwin;
+  int tpb_r, tpb_cq;        // panel tiles per workgroup of the row and column/Q launches
   Win win[MAXWIN];
 };
 
@@ -72,9 +75,15 @@ struct WinCtx {
 struct WinB {
   WinCtx c;
   int tiles_r, tiles_c, tiles_q;
-  int base_r, base_cq;      // prefixes over the launch's windows (ascending)
+  int base_r, base_cq;      // workgroup prefixes over the launch's windows (ascending)
   int pad;
 };
+
+// workgroups of a panel launch that cover `tiles` tiles of one window, tpb
+// tiles per workgroup
+__host__ __device__ inline int panel_blocks(int tiles, int tpb) {
+  return (tiles + tpb - 1) / tpb;
+}
 
 // ---- small control block kept in device memory ----------------------------
 struct Ctrl {
