@@ -48,6 +48,29 @@ __device__ __forceinline__ double fast_rcp(double d) {
   return fma(r, e, r);
 }
 
+// Orders the LDS accesses of the lanes of one wavefront before and after it
+// (they execute in order on the hardware; the fences keep the compiler from
+// moving them across, and the wave barrier makes the CPU emulation of the
+// lanes, which run freely, wait for each other).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Value of v held by lane src of the wavefront (src uniform, 0..63): two
+// v_readlane_b32 into scalar registers, no LDS round trip.
+__device__ __forceinline__ double lane_read(double v, int src) {
+  unsigned long long b;
+  __builtin_memcpy(&b, &v, sizeof(b));
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  const unsigned long long r = ((unsigned long long)hi << 32) | lo;
+  double d;
+  __builtin_memcpy(&d, &r, sizeof(d));
+  return d;
+}
+
 // make_reflector with a short critical path: when x^2 + y^2 + z^2 is far
 // from overflow and underflow (the normal case) no scaling is needed; the
 // scaled construction covers the rest.  Same reflector up to rounding.

@@ -20,6 +20,104 @@ struct SmallSmem {
   static constexpr int LD = MAXM | 1;
 };
 
+// One double-shift bulge chase over rows/cols l..i of the m x m block in
+// LDS with Schur vectors (whole-block updates: left to column m-1, right from
+// row 0, all rows of Z), for m <= 64.  Lane q owns column q in the left
+// updates and row q (of S and of Z) in the right updates.  Per position r
+// the wavefront waits for LDS once instead of three times:
+//  * the bulge column S(r..r+2, r-1) was just computed by the right update
+//    of position r-1 in row lanes r..r+2 and is taken from their registers
+//    (lane_read);
+//  * the left update's operands S(r..r+2, q) were loaded at the end of
+//    position r-1, right after its stores, so the load overlaps the
+//    reflector of position r;
+//  * the right update's operands S(q, r..r+2) are loaded after the left
+//    stores of this position (the one wait); Z's columns r, r+1 come from
+//    this lane's previous Z update and column r+2, untouched so far in this
+//    step, was loaded a position ahead.
+// Every updated value is stored to LDS at once, so the block in LDS is exact
+// after every position (the lanes of a wavefront access LDS in order;
+// wave_sync orders the accesses that read another lane's stores).
+// x, y, z: first column of the shift polynomial (position l).
+template <int MAXM>
+__device__ void chase_reg(double* S, double* Zs, int m_in, int l_in, int i_in, double x,
+                          double y, double z) {
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  // the bounds are the same in every lane: in scalar registers, the position
+  // loop and the lane numbers of lane_read are scalar too
+  const int m = __builtin_amdgcn_readfirstlane(m_in);
+  const int l = __builtin_amdgcn_readfirstlane(l_in);
+  const int i = __builtin_amdgcn_readfirstlane(i_in);
+  const int q = threadIdx.x;
+  const bool inm = q < m;
+  const int qc = inm ? q : m - 1;   // clamped: every lane issues valid loads
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
+  // left operands S(r..r+2, q) and Z(q, r..r+2) of the first position
+  double cA = Sx(l, qc), cB = Sx(l + 1, qc), cC = Sx(l + 2, qc);
+  double zA = Zx(qc, l), zB = Zx(qc, l + 1), zC = Zx(qc, l + 2);
+  double o1 = 0.0;   // S(q, r-1) from this row's last right update
+  wave_sync();       // every lane has read its operands before any lane stores
+  for (int r = l; r <= i - 1; ++r) {
+    const bool three = r <= i - 2;
+    const int r2 = three ? r + 2 : r + 1;   // the third row / column, or a valid stand-in
+    if (r > l) {
+      x = lane_read(o1, r);
+      y = lane_read(o1, r + 1);
+      z = three ? lane_read(o1, r + 2) : 0.0;
+    }
+    const Refl h = make_reflector_fast(three ? 3 : 2, x, y, z);
+    const double tv2 = h.tau * h.v2, tv3 = h.tau * h.v3;
+
+    // ---- left update: rows r..r+2, columns r..m-1 (column lane q)
+    const double a3 = three ? cC : 0.0;
+    const double wl = cA + h.v2 * cB + h.v3 * a3;
+    if (inm && q >= r) {
+      Sx(r, q) = cA - h.tau * wl;
+      Sx(r + 1, q) = cB - tv2 * wl;
+      if (three) Sx(r + 2, q) = a3 - tv3 * wl;
+    }
+    if (r > l && q == 0) {   // the bulge column: beta above two zeros
+      Sx(r, r - 1) = h.beta;
+      Sx(r + 1, r - 1) = 0.0;
+      if (three) Sx(r + 2, r - 1) = 0.0;
+    }
+    wave_sync();   // the left stores precede the right update's loads
+
+    // ---- right update: columns r..r+2 of rows 0..min(r+3, i), all rows of Z
+    const int rlast = (r + 3 < i) ? r + 3 : i;
+    const double s1 = Sx(qc, r), s2 = Sx(qc, r + 1), t3 = Sx(qc, r2);
+    const double s3 = three ? t3 : 0.0;
+    const double z3 = three ? zC : 0.0;
+    const double wr = s1 + h.v2 * s2 + h.v3 * s3;
+    const double wz = zA + h.v2 * zB + h.v3 * z3;
+    const double e1 = s1 - h.tau * wr;
+    if (q <= rlast) {
+      Sx(q, r) = e1;
+      Sx(q, r + 1) = s2 - tv2 * wr;
+      if (three) Sx(q, r + 2) = s3 - tv3 * wr;
+    }
+    o1 = e1;
+    const double f2 = zB - tv2 * wz, f3 = z3 - tv3 * wz;
+    if (inm) {
+      Zx(q, r) = zA - h.tau * wz;
+      Zx(q, r + 1) = f2;
+      if (three) Zx(q, r + 2) = f3;
+    }
+    zA = f2;
+    zB = f3;
+    wave_sync();   // this position's stores precede the loads below
+    // operands of position r+1: S(r+1..r+3, q) as just stored, Z(q, r+3)
+    // untouched so far (indices clamped to the block)
+    const int r3 = (r + 3 < m - 1) ? r + 3 : m - 1;
+    cA = Sx(r + 1, qc);
+    cB = Sx((r + 2 < m - 1) ? r + 2 : m - 1, qc);
+    cC = Sx(r3, qc);
+    zC = Zx(qc, r3);
+  }
+  __syncthreads();
+}
+
 // Francis double-shift iteration on the m x m block already in LDS (S, and Z
 // when WANTZ), one wavefront.  Writes T.wr / T.wi of converged blocks when
 // given; returns 0 or the 1-based end of a block that did not converge.
@@ -131,6 +229,10 @@ __device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
     first_column(Sx(l, l), Sx(l, l + 1), Sx(l + 1, l), Sx(l + 1, l + 1), Sx(l + 2, l + 1), s, t,
                  x, y, z);
     __syncthreads();   // every lane has read the corner before the first left update
+    if (WANTZ && m <= 64) {
+      chase_reg<MAXM>(S, Zs, m, l, i, x, y, z);
+      continue;
+    }
     for (int r = l; r <= i - 1; ++r) {
       const int nr = (r <= i - 2) ? 3 : 2;
       // the third row / column of a 2-row reflector is replaced by a valid

@@ -29,12 +29,6 @@ namespace schur {
 // ============================================================================
 constexpr int CHASE_THREADS = 1024;
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __device__ void chase_window(const WinCtx& d) {
   __shared__ double W[LDW * WMAX];
   __shared__ double R[REFL_LDS * 3];

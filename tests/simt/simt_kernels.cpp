@@ -18,7 +18,7 @@
 #include "wave_solvers.h"
 #include "window_chase.h"
 
-#include <pthread.h>
+#include <atomic>
 
 #include <cstdio>
 #include <string>
@@ -30,14 +30,38 @@ thread_local simt_dim3 blockIdx;
 simt_dim3 blockDim{64, 1, 1};
 
 namespace {
-pthread_barrier_t g_all, g_wave[16];
+// Barrier of n threads: arrival count plus a generation number; waiters spin
+// briefly, then yield (the lanes outnumber the host cores, and the kernels
+// cross a barrier every few instructions, where a sleeping barrier would
+// spend most of the time in the kernel's scheduler).
+struct SpinBarrier {
+  std::atomic<int> count{0};
+  std::atomic<unsigned> gen{0};
+  int n = 0;
+  void init(int threads) {
+    n = threads;
+    count.store(0);
+  }
+  void wait() {
+    const unsigned g = gen.load(std::memory_order_acquire);
+    if (count.fetch_add(1, std::memory_order_acq_rel) == n - 1) {
+      count.store(0, std::memory_order_relaxed);
+      gen.fetch_add(1, std::memory_order_acq_rel);
+      return;
+    }
+    int spins = 0;
+    while (gen.load(std::memory_order_acquire) == g)
+      if (++spins > 32) std::this_thread::yield();
+  }
+};
+SpinBarrier g_all, g_wave[16];
 int g_threads = 64;
 double g_shfl[1024];
 int g_ball[1024];
 }  // namespace
 
-void __syncthreads() { pthread_barrier_wait(&g_all); }
-void simt_wave_barrier() { pthread_barrier_wait(&g_wave[threadIdx.x >> 6]); }
+void __syncthreads() { g_all.wait(); }
+void simt_wave_barrier() { g_wave[threadIdx.x >> 6].wait(); }
 
 // only used by one-wavefront kernels (workgroup = one wavefront)
 double __shfl_xor(double x, int o, int) {
@@ -47,6 +71,19 @@ double __shfl_xor(double x, int o, int) {
   const double r = g_shfl[l ^ o];
   __syncthreads();
   return r;
+}
+
+// readlane: two slot sets used alternately, so one barrier per call is
+// enough (a lane can write call k+2's slot only after every lane has passed
+// call k+1's barrier, i.e. has read call k's value)
+int g_rdl[2][1024];
+thread_local unsigned g_rdl_calls = 0;
+int simt_readlane(int v, int src) {
+  const int l = threadIdx.x;
+  const unsigned k = g_rdl_calls++ & 1u;
+  g_rdl[k][l] = v;
+  __syncthreads();
+  return g_rdl[k][src];
 }
 
 unsigned long long __ballot(int p) {
@@ -67,8 +104,8 @@ void run_workgroup(int threads, int block, F f) {
   memset(__start_simt_lds, 0xff, (size_t)(__stop_simt_lds - __start_simt_lds));   // NaN
   g_threads = threads;
   blockDim = simt_dim3{(unsigned)threads, 1, 1};
-  pthread_barrier_init(&g_all, nullptr, threads);
-  for (int w = 0; w < threads / 64; ++w) pthread_barrier_init(&g_wave[w], nullptr, 64);
+  g_all.init(threads);
+  for (int w = 0; w < threads / 64; ++w) g_wave[w].init(64);
   std::vector<std::thread> th;
   for (int l = 0; l < threads; ++l)
     th.emplace_back([=] {
@@ -77,8 +114,6 @@ void run_workgroup(int threads, int block, F f) {
       f();
     });
   for (auto& t : th) t.join();
-  pthread_barrier_destroy(&g_all);
-  for (int w = 0; w < threads / 64; ++w) pthread_barrier_destroy(&g_wave[w]);
 }
 
 template <class T>
