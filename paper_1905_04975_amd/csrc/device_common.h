@@ -48,14 +48,15 @@ __device__ __forceinline__ double fast_rcp(double d) {
   return fma(r, e, r);
 }
 
-// Orders the LDS accesses of the lanes of one wavefront before and after it
-// (they execute in order on the hardware; the fences keep the compiler from
-// moving them across, and the wave barrier makes the CPU emulation of the
-// lanes, which run freely, wait for each other).
+// Orders the LDS accesses of the lanes of one wavefront before and after it.
+// The hardware executes a wavefront's LDS instructions in order, so only the
+// compiler must be kept from moving memory accesses across (a signal fence:
+// no instruction, and no wait for outstanding LDS operations); the wave
+// barrier makes the CPU emulation of the lanes, which run freely, wait for
+// each other.
 __device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // Value of v held by lane src of the wavefront (src uniform, 0..63): two

@@ -72,10 +72,11 @@ __device__ void chase_reg(double* S, double* Zs, int m_in, int l_in, int i_in, d
     // ---- left update: rows r..r+2, columns r..m-1 (column lane q)
     const double a3 = three ? cC : 0.0;
     const double wl = cA + h.v2 * cB + h.v3 * a3;
+    const double n2 = cB - tv2 * wl, n3 = a3 - tv3 * wl;
     if (inm && q >= r) {
       Sx(r, q) = cA - h.tau * wl;
-      Sx(r + 1, q) = cB - tv2 * wl;
-      if (three) Sx(r + 2, q) = a3 - tv3 * wl;
+      Sx(r + 1, q) = n2;
+      if (three) Sx(r + 2, q) = n3;
     }
     if (r > l && q == 0) {   // the bulge column: beta above two zeros
       Sx(r, r - 1) = h.beta;
@@ -110,10 +111,15 @@ __device__ void chase_reg(double* S, double* Zs, int m_in, int l_in, int i_in, d
     // operands of position r+1: S(r+1..r+3, q) as just stored, Z(q, r+3)
     // untouched so far (indices clamped to the block)
     const int r3 = (r + 3 < m - 1) ? r + 3 : m - 1;
-    cA = Sx(r + 1, qc);
-    cB = Sx((r + 2 < m - 1) ? r + 2 : m - 1, qc);
+    const double lA = Sx(r + 1, qc), lB = Sx((r + 2 < m - 1) ? r + 2 : m - 1, qc);
     cC = Sx(r3, qc);
     zC = Zx(qc, r3);
+    // columns right of the next bulge were changed by this left update only:
+    // its results (equal to the loaded values) stay in the registers that
+    // were stored from, which the compiler then does not reuse early
+    const bool far = q >= r + 3;
+    cA = far ? n2 : lA;
+    cB = far ? n3 : lB;
   }
   __syncthreads();
 }
