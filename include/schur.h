@@ -80,7 +80,12 @@ typedef struct schur_opts {
   int aed_nibble;  /* a window that deflated more than this percentage of its  */
                    /* rows is followed by another window instead of a sweep;   */
                    /* 0 = by table, < 0 = always sweep                        */
-  int reserved[3];
+  int split_window; /* parallel early deflation: window order (<= 96) of the   */
+                    /* passes that deflate on windows tiling every unreduced   */
+                    /* block at once before the sweeps; 0 = 96, < 0 = off      */
+  int split_min_n;  /* smallest order that starts with those passes;          */
+                    /* 0 = 2048                                                */
+  int reserved[1];
 } schur_opts;
 
 #define SCHUR_FLAG_TIME_KERNELS 1   /* time each kernel family with HIP events */
@@ -111,6 +116,12 @@ typedef struct schur_stats {
   int64_t aed_deflated;     /* eigenvalues deflated by them                    */
   double aed_flops;         /* nominal work of those windows: 25 nw^3 (Schur   */
                             /* form with vectors) + 10/3 nu^3 (reduction back) */
+  int64_t split_passes;     /* parallel early-deflation passes                  */
+  int64_t split_windows;    /* windows of those passes                          */
+  int64_t split_accepted;   /* windows that split their block (V applied)       */
+  int64_t split_converged;  /* rows in converged 1x1 / 2x2 blocks after them    */
+  double split_ms;          /* summed duration of their window kernels (TIME)  */
+  double split_flops;       /* nominal work of their windows (as aed_flops)    */
 } schur_stats;
 
 /* --------------------------------------------------------------------------

@@ -126,6 +126,9 @@ struct schur_handle_s {
     size_t cap = 0;
   };
   Grow b_ctrl, b_defl, b_small, b_shift, b_win, b_u, b_sh, b_aedt, b_aedw;
+  // parallel early-deflation passes: tasks, outcomes, V^T slots, block
+  // starts, panel descriptors
+  Grow b_splt, b_splr, b_splu, b_splz, b_splw;
   // nested solve of a trailing block larger than SMALL_EIG_MAX (shifts only)
   schur_handle_s* sub = nullptr;
   double* shm = nullptr;         // NS_MAX x NS_MAX copy of the trailing block
@@ -174,6 +177,8 @@ struct Params {
   int ns, nb, step, nmin, max_sweeps, exc_period;
   int nw;      // early-deflation window order (0: none)
   int nibble;  // skip the sweep after a window that deflated > nibble % of nw (-1: never)
+  int split_nw;     // window order of the parallel early-deflation passes (0: none)
+  int split_min_n;  // smallest order that runs them
   bool time;
 };
 
@@ -192,6 +197,10 @@ constexpr int kErrNonFinite = -105;
 // deflated more than this percentage of its order
 constexpr int kAedSkipPct = 14;
 
+// parallel early deflation: default smallest order, and the most passes
+constexpr int kSplitMinN = 2048;
+constexpr int kSplitMaxPasses = 64;
+
 Params resolve(const schur_opts& o, int n) {
   Params p;
   const TuneRow tr = tune_for(n);
@@ -208,6 +217,10 @@ Params resolve(const schur_opts& o, int n) {
   const int aw = o.aed_window != 0 ? o.aed_window : tr.nw;
   const int nib = o.aed_nibble != 0 ? o.aed_nibble : tr.nibble;
   p.nibble = nib < 0 ? -1 : (nib > 0 ? nib : kAedSkipPct);
+  p.split_nw = o.split_window < 0 ? 0 : (o.split_window > 0 ? std::min(o.split_window, SMALL_Z_MAX)
+                                                              : SMALL_Z_MAX);
+  if (p.split_nw < 3) p.split_nw = 0;
+  p.split_min_n = o.split_min_n > 0 ? o.split_min_n : kSplitMinN;
   if (aw < 0) p.nw = 0;
   else if (aw > 0) p.nw = std::min(aw, SMALL_Z_MAX);
   else p.nw = std::min(SMALL_Z_MAX, std::max(16, p.ns + p.ns / 2));
@@ -266,6 +279,8 @@ void free_ws(schur_handle_s* h) {
   free_grow(h->b_ctrl); free_grow(h->b_defl); free_grow(h->b_small);
   free_grow(h->b_shift); free_grow(h->b_win); free_grow(h->b_u); free_grow(h->b_sh);
   free_grow(h->b_aedt); free_grow(h->b_aedw);
+  free_grow(h->b_splt); free_grow(h->b_splr); free_grow(h->b_splu); free_grow(h->b_splz);
+  free_grow(h->b_splw);
   if (h->U) (void)hipFree(h->U);
   if (h->refl) (void)hipFree(h->refl);
   if (h->st) (void)hipFree(h->st);
@@ -278,6 +293,25 @@ void free_ws(schur_handle_s* h) {
   h->U = h->refl = h->st = h->ewr = h->ewi = nullptr;
   h->ctrl = nullptr; h->ctrl_h = nullptr; h->blist = nullptr; h->bcount = nullptr;
   h->blist_cap = 0;
+}
+
+// Panel tiles of one window of a batched panel launch (PANEL_TPB_BATCH tiles
+// per workgroup), appended after the workgroups counted so far.
+void fill_tiles_b(WinB& w, int& tr, int& tcq, schur_stats& st) {
+  const int pe = w.c.p + w.c.ws - 1;
+  w.tiles_r = std::max(0, (w.c.cend - pe - 1 + GEMM_T - 1) / GEMM_T);
+  w.tiles_c = std::max(0, (w.c.p - w.c.rtop + GEMM_T - 1) / GEMM_T);
+  w.tiles_q = w.c.Q ? (w.c.n + GEMM_T - 1) / GEMM_T : 0;
+  w.base_r = tr;
+  w.base_cq = tcq;
+  tr += panel_blocks(w.tiles_r, PANEL_TPB_BATCH);
+  tcq += panel_blocks(w.tiles_c + w.tiles_q, PANEL_TPB_BATCH);
+  const double ws = w.c.ws;
+  const double fr = 2.0 * ws * ws * (double)std::max(0, w.c.cend - pe - 1);
+  const double fc = 2.0 * ws * ws * ((double)(w.c.p - w.c.rtop) + (w.c.Q ? (double)w.c.n : 0.0));
+  st.row_flops += fr;
+  st.colq_flops += fc;
+  st.gemm_flops += fr + fc;
 }
 
 // ---- sweep schedule ---------------------------------------------------------
@@ -662,6 +696,158 @@ struct Solver {
     }
   }
 
+  // Parallel early deflation (split_window): passes of windows that tile
+  // every unreduced block at once.  A pass scans the subdiagonal for the
+  // unreduced blocks, solves and tests all windows in one launch, scales
+  // the coupling entries, and applies the V of every window that split its
+  // block to the row panels (one launch) and to the column panels and Q
+  // (one launch; the windows are disjoint, so each launch updates disjoint
+  // rows or columns).  The passes stop once one neither shrinks the largest
+  // unreduced block by a tenth nor reduces the unreduced rows by 1 %; the
+  // sweeps and bottom windows then finish what is left.
+  void split_phase() {
+    const int nw = P.split_nw;
+    grow(h->b_splz, (size_t)n, true);
+    unsigned char* zd = (unsigned char*)h->b_splz.dev;
+    unsigned char* zh = (unsigned char*)h->b_splz.host;
+    struct Wn { int a, nw, above, below; };
+    std::vector<Wn> wins;
+    std::vector<std::pair<int, int>> regs, ws;
+    int64_t prev_active = -1;
+    int prev_max = -1;
+    for (int pass = 0; pass < kSplitMaxPasses; ++pass) {
+      launch_split_scan(H, ldh, n, zd, s);
+      HCHECK(hipGetLastError());
+      h->stats.launches += 1;
+      HCHECK(hipMemcpyAsync(zh, zd, (size_t)n, hipMemcpyDeviceToHost, s));
+      HCHECK(hipStreamSynchronize(s));
+      regs.clear();
+      int64_t active = 0;
+      int mx = 0;
+      for (int k = 0; k < n;) {
+        int e = k + 1;
+        while (e < n && !zh[e]) ++e;
+        const int m = e - k;
+        if (m >= 3) {
+          regs.push_back({k, e - 1});
+          active += m;
+          mx = std::max(mx, m);
+        }
+        k = e;
+      }
+      h->stats.split_converged = n - active;
+      if (active == 0) break;
+      if (prev_active >= 0 && 100 * (prev_active - active) < prev_active &&
+          10 * (int64_t)mx > 9 * (int64_t)prev_max)
+        break;
+      prev_active = active;
+      prev_max = mx;
+      // windows of each block, listed top to bottom; every other pass moves
+      // the boundaries by half a window
+      wins.clear();
+      for (const auto& r : regs) {
+        const int lo = r.first, hi = r.second;
+        const int first = ((pass & 1) && hi - lo + 1 > nw) ? nw / 2 : nw;
+        ws.clear();   // (start, order), bottom to top
+        for (int b = hi + 1; b > lo;) {
+          const int a = std::max(lo, b - (ws.empty() ? first : nw));
+          ws.push_back({a, b - a});
+          b = a;
+        }
+        if (ws.size() >= 2 && ws.back().second < 16) {
+          // a short top window and the one below it become two halves
+          const int tot = ws.back().second + ws[ws.size() - 2].second;
+          const int top = ws.back().first;
+          ws.pop_back();
+          ws.pop_back();
+          ws.push_back({top + tot / 2, tot - tot / 2});
+          ws.push_back({top, tot / 2});
+        }
+        for (int j = (int)ws.size() - 1; j >= 0; --j) {
+          Wn w;
+          w.a = ws[j].first;
+          w.nw = ws[j].second;
+          w.above = (j == (int)ws.size() - 1) ? -1 : (int)wins.size() - 1;
+          w.below = j > 0 ? 1 : 0;
+          if (w.nw < 1 || w.nw > SMALL_Z_MAX) throw HipErr{hipErrorInvalidValue};
+          wins.push_back(w);
+        }
+      }
+      const int cnt = (int)wins.size();
+      grow(h->b_splt, sizeof(SplitTask) * cnt, true);
+      grow(h->b_splr, sizeof(SplitRes) * cnt, true);
+      grow(h->b_splu, sizeof(double) * (size_t)UPAD * UPAD * cnt, false);
+      SplitTask* th = (SplitTask*)h->b_splt.host;
+      SplitRes* rd = (SplitRes*)h->b_splr.dev;
+      double* ud = (double*)h->b_splu.dev;
+      for (int i = 0; i < cnt; ++i) {
+        SplitTask& t = th[i];
+        std::memset(&t, 0, sizeof(t));
+        t.H = H; t.ldh = ldh;
+        t.a = wins[i].a; t.nw = wins[i].nw;
+        t.above = wins[i].above; t.below = wins[i].below;
+        t.itmax = 0;   // default budget
+        t.Ut = ud + (size_t)i * UPAD * UPAD; t.ldut = UPAD;
+        t.res = rd + i;
+      }
+      SplitTask* td = (SplitTask*)h->b_splt.dev;
+      HCHECK(hipMemcpyAsync(td, th, sizeof(SplitTask) * cnt, hipMemcpyHostToDevice, s));
+      hipEvent_t e0 = nullptr;
+      if (P.time) h->timer.begin(s, e0);
+      launch_split(td, cnt, s);
+      HCHECK(hipGetLastError());
+      if (P.time) h->timer.end(s, e0, &h->stats.split_ms);
+      launch_split_fix(td, cnt, s);
+      HCHECK(hipGetLastError());
+      h->stats.launches += 2;
+      h->stats.split_passes += 1;
+      h->stats.split_windows += cnt;
+      SplitRes* rh = (SplitRes*)h->b_splr.host;
+      HCHECK(hipMemcpyAsync(rh, rd, sizeof(SplitRes) * cnt, hipMemcpyDeviceToHost, s));
+      HCHECK(hipStreamSynchronize(s));
+      if (P.time) h->timer.harvest();
+      grow(h->b_splw, sizeof(WinB) * cnt, true);
+      WinB* wh = (WinB*)h->b_splw.host;
+      int nwin = 0, tr = 0, tcq = 0;
+      for (int i = 0; i < cnt; ++i) {
+        const SplitRes& r = rh[i];
+        h->stats.split_flops +=
+            aed_work(wins[i].nw, r.split ? r.nu : 0) + (10.0 / 3.0) * r.nb * (double)r.nb * r.nb;
+        if (!r.split) continue;
+        h->stats.split_accepted += 1;
+        WinB& w = wh[nwin++];
+        std::memset(&w, 0, sizeof(w));
+        w.c.H = H; w.c.Q = Q; w.c.U = ud + (size_t)i * UPAD * UPAD; w.c.st = nullptr;
+        w.c.ldh = ldh; w.c.ldq = ldq; w.c.n = n;
+        w.c.ktop = 0; w.c.kbot = n - 1; w.c.rtop = 0; w.c.cend = n;
+        w.c.p = wins[i].a; w.c.ws = wins[i].nw;
+        fill_tiles_b(w, tr, tcq, h->stats);
+      }
+      if (nwin > 0) {
+        WinB* wd = (WinB*)h->b_splw.dev;
+        HCHECK(hipMemcpyAsync(wd, wh, sizeof(WinB) * nwin, hipMemcpyHostToDevice, s));
+        if (tr > 0) {
+          if (P.time) h->timer.begin(s, e0);
+          launch_panel_row_b(wd, nwin, tr, s);
+          HCHECK(hipGetLastError());
+          if (P.time) h->timer.end(s, e0, &h->stats.row_ms);
+          h->stats.row_launches += 1;
+          h->stats.gemm_launches += 1;
+          h->stats.launches += 1;
+        }
+        if (tcq > 0) {
+          if (P.time) h->timer.begin(s, e0);
+          launch_panel_colq_b(wd, nwin, tcq, s);
+          HCHECK(hipGetLastError());
+          if (P.time) h->timer.end(s, e0, &h->stats.colq_ms);
+          h->stats.colq_launches += 1;
+          h->stats.gemm_launches += 1;
+          h->stats.launches += 1;
+        }
+      }
+    }
+  }
+
   int run() {
     // the aux stream starts after the work already queued on the solve stream
     HCHECK(hipEventRecord(h->ev_join, s));
@@ -671,6 +857,7 @@ struct Solver {
     sync_ctrl();
     if (h->ctrl_h->bad) return -2;
     launch_zero_lower(H, ldh, n, s);
+    if (P.split_nw > 0 && n >= P.split_min_n) split_phase();
     int info = 0;
     int kbot = n - 1;
     int nodefl = 0;
@@ -1216,22 +1403,7 @@ struct BatchEngine {
     }
   }
 
-  void fill_tiles(WinB& w, int& tr, int& tcq) {
-    const int pe = w.c.p + w.c.ws - 1;
-    w.tiles_r = std::max(0, (w.c.cend - pe - 1 + GEMM_T - 1) / GEMM_T);
-    w.tiles_c = std::max(0, (w.c.p - w.c.rtop + GEMM_T - 1) / GEMM_T);
-    w.tiles_q = w.c.Q ? (w.c.n + GEMM_T - 1) / GEMM_T : 0;
-    w.base_r = tr;
-    w.base_cq = tcq;
-    tr += panel_blocks(w.tiles_r, PANEL_TPB_BATCH);
-    tcq += panel_blocks(w.tiles_c + w.tiles_q, PANEL_TPB_BATCH);
-    const double ws = w.c.ws;
-    const double fr = 2.0 * ws * ws * (double)std::max(0, w.c.cend - pe - 1);
-    const double fc = 2.0 * ws * ws * ((double)(w.c.p - w.c.rtop) + (w.c.Q ? (double)w.c.n : 0.0));
-    h->stats.row_flops += fr;
-    h->stats.colq_flops += fc;
-    h->stats.gemm_flops += fr + fc;
-  }
+  void fill_tiles(WinB& w, int& tr, int& tcq) { fill_tiles_b(w, tr, tcq, h->stats); }
 };
 
 int solve_batched(schur_handle_s* h, hipStream_t s, int count, const int* n, double* const* H,

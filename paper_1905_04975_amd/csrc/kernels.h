@@ -29,6 +29,27 @@ struct AedTask {
   int itmax;
 };
 
+// Outcome of one window of a parallel early-deflation pass.
+struct SplitRes {
+  int split;                   // 1: the window was transformed (V^T in its slot)
+  int nu, nf, nb;              // rows coupled upward, free (deflated), coupled downward
+  double ftop, fbot;           // factors of the new coupling entries above / below
+};
+
+// One window H(a:a+nw, a:a+nw) of a parallel early-deflation pass over the
+// unreduced blocks of H; nw <= SMALL_Z_MAX.  Windows of one pass tile the
+// unreduced blocks without overlap.
+struct SplitTask {
+  double* H; int ldh;
+  int a, nw;
+  int above;                   // task index of the window ending at row a (-1: block top)
+  int below;                   // 1: the block continues below the window
+  int itmax;
+  int pad;
+  double* Ut; int ldut;        // V^T of the window, zero padded to ldut x ldut
+  SplitRes* res;               // this window's outcome
+};
+
 // One matrix of a batched deflation scan.
 struct DeflB {
   double* H; double* Q; double* wr; double* wi;
@@ -49,6 +70,9 @@ void launch_small_z(const SmallTask& t, const SmallTask* tasks, int count, int m
 void launch_small_eig(const SmallTask& t, hipStream_t s);
 void launch_aed(const AedTask& t, hipStream_t s);
 void launch_aed_b(const AedTask* tasks, int count, hipStream_t s);
+void launch_split(const SplitTask* tasks, int count, hipStream_t s);
+void launch_split_fix(const SplitTask* tasks, int count, hipStream_t s);
+void launch_split_scan(double* H, int ldh, int n, unsigned char* zero, hipStream_t s);
 void launch_shift_prep(const double* wr, const double* wi, int ns, const int* small_info,
                        int exceptional, const double* H, int ldh, int ktop, int kbot, double* st,
                        hipStream_t s);

@@ -54,6 +54,56 @@ __global__ __launch_bounds__(64) void k_aed(AedTask t0, const AedTask* tasks) {
   aed_window<MAXM>(T, S, Z, vv, ibuf, stdbuf);
 }
 
+// One window of a parallel early-deflation pass per workgroup (one wavefront,
+// window and Schur vectors in LDS).
+template <int MAXM>
+__global__ __launch_bounds__(64) void k_split(const SplitTask* tasks) {
+  const SplitTask T = tasks[blockIdx.x];
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  __shared__ double S[LD * MAXM];
+  __shared__ double Z[LD * MAXM];
+  __shared__ double vv[MAXM];
+  __shared__ int ibuf[6 * MAXM];
+  __shared__ double pbuf[7 * MAXM];
+  split_window<MAXM>(T, S, Z, vv, ibuf, pbuf);
+}
+
+// After a pass: the subdiagonal entry coupling each window to the one above
+// it takes the factors of both (1 for a window left untouched).  Separate
+// launch: every window reads its couplings before any is rewritten.
+__global__ void k_split_fix(const SplitTask* tasks, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const SplitTask t = tasks[i];
+  if (t.above < 0) return;
+  const SplitRes r = *t.res;
+  const SplitRes u = *tasks[t.above].res;
+  const double f = (r.split ? r.ftop : 1.0) * (u.split ? u.fbot : 1.0);
+  t.H[t.a + (size_t)(t.a - 1) * t.ldh] *= f;
+}
+
+// Negligible subdiagonal entries (same test as the deflation scan) set to
+// zero over the whole matrix; zero[k] = 1 where row k starts a block.
+__global__ void k_split_scan(double* H, int ldh, int n, unsigned char* zero) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    if (k == 0) {
+      zero[0] = 1;
+      continue;
+    }
+    double* hp = H + k + (size_t)(k - 1) * ldh;
+    const double sub = fabs(*hp);
+    double tst = fabs(H[(k - 1) + (size_t)(k - 1) * ldh]) + fabs(H[k + (size_t)k * ldh]);
+    if (tst == 0.0) {
+      tst = fabs(H[(k - 1) + (size_t)k * ldh]);
+      if (k >= 2) tst += fabs(H[(k - 1) + (size_t)(k - 2) * ldh]);
+      if (k + 1 < n) tst += fabs(H[(k + 1) + (size_t)k * ldh]);
+    }
+    const bool z = sub <= kUlp * tst;
+    if (z && sub != 0.0) *hp = 0.0;
+    zero[k] = z ? 1 : 0;
+  }
+}
+
 // ============================================================================
 // Shift preparation: sort the trailing-block eigenvalues by decreasing
 // modulus (conjugate pairs stay together), pair the real ones, and emit one
@@ -790,6 +840,23 @@ void launch_aed(const AedTask& t, hipStream_t s) {
 void launch_aed_b(const AedTask* tasks, int count, hipStream_t s) {
   if (count > 0)
     hipLaunchKernelGGL((k_aed<SMALL_Z_MAX>), dim3(count), dim3(64), 0, s, AedTask{}, tasks);
+}
+
+void launch_split(const SplitTask* tasks, int count, hipStream_t s) {
+  if (count > 0)
+    hipLaunchKernelGGL((k_split<SMALL_Z_MAX>), dim3(count), dim3(64), 0, s, tasks);
+}
+
+void launch_split_fix(const SplitTask* tasks, int count, hipStream_t s) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_split_fix, dim3((count + 255) / 256), dim3(256), 0, s, tasks, count);
+}
+
+void launch_split_scan(double* H, int ldh, int n, unsigned char* zero, hipStream_t s) {
+  if (n > 0) {
+    const int blocks = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
+    hipLaunchKernelGGL(k_split_scan, dim3(blocks), dim3(256), 0, s, H, ldh, n, zero);
+  }
 }
 
 void launch_shift_prep(const double* wr, const double* wi, int ns, const int* small_info,

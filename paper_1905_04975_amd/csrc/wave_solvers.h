@@ -730,8 +730,12 @@ __device__ __forceinline__ void swap_apply(double (&a)[4], const double* v, cons
   }
 }
 
+//   xr: rows above the block (rows -xr..-1 of S, same columns) that take the
+//   right transforms too; zrows: rows of Zs that take them; srow: the row of
+//   Zs whose entries, times s, form the spike (0 for a bottom window).
 __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* ibuf,
-                           double* pbuf) {
+                           double* pbuf, int xr = 0, int zrows = -1, int srow = 0) {
+  if (zrows < 0) zrows = m;
   const int lane = threadIdx.x;
   auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
   auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
@@ -790,13 +794,13 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
       double foo, spk;
       if (bs == 1) {
         foo = fabs(Sx(bot, bot));
-        spk = fabs(s * Zx(0, bot));
+        spk = fabs(s * Zx(srow, bot));
       } else {
         double re, im, r1, r2;
         block_eigs(Sx(bot - 1, bot - 1), Sx(bot - 1, bot), Sx(bot, bot - 1), Sx(bot, bot), re, im,
                    r1, r2);
         foo = (im != 0.0) ? fabs(re) + im : fmax(fabs(r1), fabs(r2));
-        spk = fmax(fabs(s * Zx(0, bot)), fabs(s * Zx(0, bot - 1)));
+        spk = fmax(fabs(s * Zx(srow, bot)), fabs(s * Zx(srow, bot - 1)));
       }
       if (foo == 0.0) foo = fabs(s);
       defl = spk <= fmax(smlnum, kUlp * foo);
@@ -865,18 +869,19 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
         }
       }
       __syncthreads();
-      // right: rows 0..k+N-1 of S, then rows 0..m-1 of Z (one index space)
+      // right: rows -xr..k+N-1 of S, then rows 0..zrows-1 of Z (one index
+      // space; ra below is the S row relative to the block)
       if (mine) {
-        const int ns = k + N;
-        const int tot = ns + m;
+        const int ns = xr + k + N;
+        const int tot = ns + zrows;
         const double dA = pl_d[2 * t], dB = pl_d[2 * t + 1];
         for (int q = sub; q < tot; q += 2 * G) {
           const int q2 = q + G;
           const bool two = q2 < tot;
           double* ba = (q < ns) ? S : Zs;
-          const int ra = (q < ns) ? q : q - ns;
+          const int ra = (q < ns) ? q - xr : q - ns;
           double* bb = (two && q2 < ns) ? S : Zs;
-          const int rb = two ? ((q2 < ns) ? q2 : q2 - ns) : ra;
+          const int rb = two ? ((q2 < ns) ? q2 - xr : q2 - ns) : ra;
           double* bbx = two ? bb : ba;
           double a[4], b[4];
 #pragma unroll
@@ -935,6 +940,56 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
   }
   __syncthreads();
   return sh_bot + 1;
+}
+
+// V^T of a window into its panel slot (ldut x ldut, zero padded), after one
+// first-order re-orthogonalisation V <- V (I - E / 2), E = V^T V - I: V's
+// own rounding (it collected every rotation of the window) would otherwise
+// reach Q.  S (free once the window is written back) holds E.
+// (four independent sums per lane, rows unrolled, so loads run ahead)
+__device__ void aed_write_vt(double* S, const double* Z, int LD, int nw, double* Ut, int ldut) {
+  const int lane = threadIdx.x;
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  auto Zx = [&](int r, int c) -> double { return Z[r + c * LD]; };
+  for (int j = lane; j < nw; j += 64)
+    for (int i0 = 0; i0 < nw; i0 += 4) {
+      int ic[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ic[u] = (i0 + u < nw) ? i0 + u : nw - 1;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int r = 0; r < nw; ++r) {
+        const double zj = Zx(r, j);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += Zx(r, ic[u]) * zj;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u < nw) Sx(i0 + u, j) = acc[u] - ((i0 + u == j) ? 1.0 : 0.0);
+    }
+  __syncthreads();
+  for (int j = lane; j < ldut; j += 64) {
+    for (int r0 = 0; r0 < ldut; r0 += 4) {
+      double val[4] = {0.0, 0.0, 0.0, 0.0};
+      if (j < nw && r0 < nw) {
+        int rc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rc[u] = (r0 + u < nw) ? r0 + u : nw - 1;
+        double corr[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k = 0; k < nw; ++k) {
+          const double e = Sx(k, j);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) corr[u] += Zx(rc[u], k) * e;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          val[u] = (r0 + u < nw) ? Zx(rc[u], j) - 0.5 * corr[u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) Ut[j + (size_t)(r0 + u) * ldut] = val[u];   // Ut(j, r) = V(r, j)
+    }
+  }
 }
 
 template <int MAXM>
@@ -1061,51 +1116,203 @@ __device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, i
     for (int r = lane; r <= c + 1 && r < nw; r += 64) Hw[r + (size_t)c * T.ldh] = Sx(r, c);
   if (lane == 0 && kwtop > T.ktop) T.H[kwtop + (size_t)(kwtop - 1) * T.ldh] = spike;
   __syncthreads();
-  // ---- V^T into the panel slot, after one first-order re-orthogonalisation
-  // V <- V (I - E / 2), E = V^T V - I: V's own rounding (it collected every
-  // rotation of the window) would otherwise reach Q; the window's S is free
-  // now and holds E
-  // (four independent sums per lane, rows unrolled, so loads run ahead)
-  for (int j = lane; j < nw; j += 64)
-    for (int i0 = 0; i0 < nw; i0 += 4) {
-      int ic[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) ic[u] = (i0 + u < nw) ? i0 + u : nw - 1;
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-      for (int r = 0; r < nw; ++r) {
-        const double zj = Zx(r, j);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] += Zx(r, ic[u]) * zj;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (i0 + u < nw) Sx(i0 + u, j) = acc[u] - ((i0 + u == j) ? 1.0 : 0.0);
-    }
-  __syncthreads();
-  for (int j = lane; j < T.ldut; j += 64) {
-    for (int r0 = 0; r0 < T.ldut; r0 += 4) {
-      double val[4] = {0.0, 0.0, 0.0, 0.0};
-      if (j < nw && r0 < nw) {
-        int rc[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) rc[u] = (r0 + u < nw) ? r0 + u : nw - 1;
-        double corr[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int k = 0; k < nw; ++k) {
-          const double e = Sx(k, j);
-#pragma unroll
-          for (int u = 0; u < 4; ++u) corr[u] += Zx(rc[u], k) * e;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          val[u] = (r0 + u < nw) ? Zx(rc[u], j) - 0.5 * corr[u] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) T.Ut[j + (size_t)(r0 + u) * T.ldut] = val[u];   // Ut(j, r) = V(r, j)
-    }
-  }
+  aed_write_vt(S, Z, LD, nw, T.Ut, T.ldut);
 }
 
+
+// ============================================================================
+// Early deflation on many windows at once.  Windows tile the unreduced
+// blocks of H; each window W (order nw <= SMALL_Z_MAX) is coupled to the
+// rest of its block by one subdiagonal entry above it (st, row 0 of W) and
+// one below it (sb, last column of W).  With W = V T V^T in real Schur form
+// the couplings become st V(0, .) on the left and sb V(nw-1, .) below.
+//   1. blocks whose entries of st V(0, .) are not negligible move to the top
+//      of T (the bottom-window reordering, rows [0, nu));
+//   2. if every one of them has negligible entries in sb V(nw-1, .), the
+//      window splits its block: among the remaining blocks, those with
+//      negligible sb V(nw-1, .) entries stay on top (free: deflated), the
+//      others move to the bottom (rows [bs, nw)); this is the same
+//      reordering on the flipped block J T^T J, whose spike is the last row
+//      of V;
+//   3. each coupled part is brought back to Hessenberg form with its
+//      coupling reflected onto one entry (the upper part as after a bottom
+//      window, the lower one flipped), so that H stays Hessenberg with zero
+//      subdiagonal entries around the free part;
+//   4. the window and V^T go out; the caller applies V to the panels and to
+//      Q and scales the coupling entries by the reflected first entries.
+// A window that does not split is left untouched (V = I).  Every dropped
+// entry is below the early-deflation threshold, so each pass is a backward
+// stable orthogonal similarity, as a bottom window is (paper Sec. 3.2, AED).
+// ============================================================================
+
+// Anti-transpose of the trailing block T = S(lo:nw, lo:nw) in place
+// (T(r, c) <-> T(d-1-c, d-1-r), d = nw - lo), with the columns lo..nw-1 of
+// the rows above it (S(0:lo, .)) and of Z (all nw rows) put in reverse
+// order.  J T^T J is quasi-triangular when T is; a similarity by Y of the
+// flipped block is a similarity by J Y J of T, and the reversed columns take
+// it as their right transform.  The map is its own inverse.
+__device__ void flip_tail(double* S, double* Z, int LD, int nw, int lo) {
+  const int lane = threadIdx.x;
+  const int d = nw - lo;
+  __syncthreads();
+  if (d <= 1) return;
+  for (int idx = lane; idx < d * d; idx += 64) {
+    const int r = idx % d, c = idx / d;
+    if (r + c < d - 1) {
+      double* p = S + (lo + r) + (lo + c) * LD;
+      double* q = S + (lo + d - 1 - c) + (lo + d - 1 - r) * LD;
+      const double t = *p;
+      *p = *q;
+      *q = t;
+    }
+  }
+  const int rows = lo + nw;
+  const int half = d / 2;
+  for (int idx = lane; idx < rows * half; idx += 64) {
+    const int q = idx % rows, j = idx / rows;
+    double* base = (q < lo) ? S + q : Z + (q - lo);
+    double* p1 = base + (lo + j) * LD;
+    double* p2 = base + (nw - 1 - j) * LD;
+    const double t = *p1;
+    *p1 = *p2;
+    *p2 = t;
+  }
+  __syncthreads();
+}
+
+// Reflector I - tau vv vv^T (vv[0] = 1, L entries) applied to rows
+// r0..r0+L-1 of S over columns c0..ncols-1 (left), then to columns
+// r0..r0+L-1 over rows -xr..rend-1 of S and rows 0..zrows-1 of Z (right).
+__device__ void refl_apply(double* S, double* Z, int LD, const double* vv, double tau, int r0,
+                           int L, int c0, int ncols, int xr, int rend, int zrows) {
+  const int lane = threadIdx.x;
+  for (int c = c0 + lane; c < ncols; c += 64) {
+    double w = 0.0;
+    for (int i = 0; i < L; ++i) w += vv[i] * S[(r0 + i) + c * LD];
+    w *= tau;
+    for (int i = 0; i < L; ++i) S[(r0 + i) + c * LD] -= vv[i] * w;
+  }
+  __syncthreads();
+  const int ns = xr + rend;
+  for (int q = lane; q < ns + zrows; q += 64) {
+    double* base = (q < ns) ? S + (q - xr) : Z + (q - ns);
+    double w = 0.0;
+    for (int j = 0; j < L; ++j) w += base[(r0 + j) * LD] * vv[j];
+    w *= tau;
+    for (int j = 0; j < L; ++j) base[(r0 + j) * LD] -= w * vv[j];
+  }
+  __syncthreads();
+}
+
+// The m x m quasi-triangular block B = S(0:m, 0:m) is coupled to the rest of
+// the matrix through the row Z(srow, 0:m) (times a scalar): reflect that row
+// onto its first entry, then bring B back to Hessenberg form with reflectors
+// that leave row and column 0 alone.  Left transforms run over columns
+// 0..ncols-1, right transforms over rows -xr..m-1 of S and rows 0..zrows-1
+// of Z.  Returns the first entry of the reflected row.
+__device__ double spike_reduce(double* S, double* Z, int LD, int m, int ncols, int xr, int zrows,
+                               int srow, double* vv) {
+  const int lane = threadIdx.x;
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  __syncthreads();
+  if (m <= 0) return 0.0;
+  if (m == 1) return Z[srow];
+  for (int i = lane; i < m; i += 64) vv[i] = Z[srow + i * LD];
+  __syncthreads();
+  const double alpha = vv[0];
+  double tau, beta;
+  aed_reflector(alpha, vv, m, tau, beta);
+  if (tau != 0.0) refl_apply(S, Z, LD, vv, tau, 0, m, 0, ncols, xr, m, zrows);
+  for (int j = 0; j + 2 < m; ++j) {
+    const int L = m - j - 1;   // rows j+1 .. m-1
+    const double a0 = Sx(j + 1, j);
+    for (int i = 1 + lane; i < L; i += 64) vv[i] = Sx(j + 1 + i, j);
+    __syncthreads();
+    double tj, bj;
+    aed_reflector(a0, vv, L, tj, bj);
+    if (tj == 0.0) continue;
+    if (lane == 0) Sx(j + 1, j) = bj;
+    for (int i = 2 + lane; i <= L; i += 64) Sx(j + i, j) = 0.0;
+    refl_apply(S, Z, LD, vv, tj, j + 1, L, j + 1, ncols, xr, m, zrows);
+  }
+  __syncthreads();
+  return beta;
+}
+
+template <int MAXM>
+__device__ void split_window(const SplitTask& T, double* S, double* Z, double* vv, int* ibuf,
+                             double* pbuf) {
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  const int lane = threadIdx.x;
+  const int nw = T.nw, a = T.a;
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  auto Zx = [&](int r, int c) -> double& { return Z[r + c * LD]; };
+  SplitRes out;
+  out.split = 0; out.nu = nw; out.nf = 0; out.nb = 0; out.ftop = 1.0; out.fbot = 1.0;
+  do {   // every exit below is uniform over the wavefront
+    if (nw < 1 || nw > MAXM) break;
+    double* Hw = T.H + a + (size_t)a * T.ldh;
+    const double st = (T.above >= 0) ? T.H[a + (size_t)(a - 1) * T.ldh] : 0.0;
+    const double sb = T.below ? T.H[(a + nw) + (size_t)(a + nw - 1) * T.ldh] : 0.0;
+    SmallTask t{};
+    t.A = Hw; t.lda = T.ldh; t.m = nw; t.itmax = T.itmax;
+    small_load<true, MAXM>(t, S, Z);
+    if (small_iter<true, MAXM>(t, S, Z) != 0) break;
+    // ---- 1. blocks coupled upward to the top
+    const int nu = (st != 0.0) ? aed_reorder(S, Z, LD, nw, st, ibuf, pbuf) : 0;
+    // ---- 2. they must not reach the coupling below
+    if (nu > 0 && sb != 0.0) {
+      const double smlnum = 2.2250738585072014e-308 * ((double)nw / kUlp);
+      bool bad = false;
+      for (int e = lane; e < nu; e += 64) {
+        if (e >= 1 && Sx(e, e - 1) != 0.0) continue;   // second row of a 2x2 block
+        const bool two = e + 1 < nu && Sx(e + 1, e) != 0.0;
+        double foo, spk;
+        if (!two) {
+          foo = fabs(Sx(e, e));
+          spk = fabs(sb * Zx(nw - 1, e));
+        } else {
+          double re, im, r1, r2;
+          block_eigs(Sx(e, e), Sx(e, e + 1), Sx(e + 1, e), Sx(e + 1, e + 1), re, im, r1, r2);
+          foo = (im != 0.0) ? fabs(re) + im : fmax(fabs(r1), fabs(r2));
+          spk = fmax(fabs(sb * Zx(nw - 1, e)), fabs(sb * Zx(nw - 1, e + 1)));
+        }
+        if (foo == 0.0) foo = fabs(sb);
+        if (!(spk <= fmax(smlnum, kUlp * foo))) bad = true;
+      }
+      if (__ballot(bad) != 0ull) break;
+    }
+    // ---- the rest against the coupling below: free blocks stay on top,
+    // coupled ones go to the bottom (a bottom-window reordering of the
+    // flipped block, whose spike row is the last row of Z)
+    int nb = 0;
+    if (sb != 0.0 && nu < nw) {
+      flip_tail(S, Z, LD, nw, nu);
+      nb = aed_reorder(S + nu + nu * LD, Z + nu * LD, LD, nw - nu, sb, ibuf, pbuf, nu, nw, nw - 1);
+      flip_tail(S, Z, LD, nw, nu);
+    }
+    const int bs = nw - nb;
+    // ---- 3. coupled parts back to Hessenberg form
+    double ftop = 0.0, fbot = 0.0;
+    if (nu > 0) ftop = spike_reduce(S, Z, LD, nu, nw, 0, nw, 0, vv);
+    if (nb > 0) {
+      flip_tail(S, Z, LD, nw, bs);
+      fbot = spike_reduce(S + bs + bs * LD, Z + bs * LD, LD, nb, nb, bs, nw, nw - 1, vv);
+      flip_tail(S, Z, LD, nw, bs);
+    }
+    // ---- 4. the window back into H, V^T into its slot
+    for (int c = 0; c < nw; ++c)
+      for (int r = lane; r <= c + 1 && r < nw; r += 64) Hw[r + (size_t)c * T.ldh] = Sx(r, c);
+    __syncthreads();
+    aed_write_vt(S, Z, LD, nw, T.Ut, T.ldut);
+    out.split = 1;
+    out.nu = nu;
+    out.nb = nb;
+    out.nf = nw - nu - nb;
+    out.ftop = ftop;
+    out.fbot = fbot;
+  } while (false);
+  if (lane == 0) *T.res = out;
+}
 
 }  // namespace schur

@@ -25,7 +25,8 @@ class SchurOpts(ctypes.Structure):
                 ("nmin", ctypes.c_int), ("max_sweeps", ctypes.c_int),
                 ("exc_period", ctypes.c_int), ("flags", ctypes.c_int),
                 ("aed_window", ctypes.c_int), ("aed_nibble", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("split_window", ctypes.c_int), ("split_min_n", ctypes.c_int),
+                ("reserved", ctypes.c_int * 1)]
 
 
 class SchurStats(ctypes.Structure):
@@ -41,7 +42,10 @@ class SchurStats(ctypes.Structure):
                 ("colq_flops", ctypes.c_double), ("colq_ms", ctypes.c_double),
                 ("colq_launches", ctypes.c_int64),
                 ("aed_ms", ctypes.c_double), ("aed_windows", ctypes.c_int64),
-                ("aed_deflated", ctypes.c_int64), ("aed_flops", ctypes.c_double)]
+                ("aed_deflated", ctypes.c_int64), ("aed_flops", ctypes.c_double),
+                ("split_passes", ctypes.c_int64), ("split_windows", ctypes.c_int64),
+                ("split_accepted", ctypes.c_int64), ("split_converged", ctypes.c_int64),
+                ("split_ms", ctypes.c_double), ("split_flops", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -180,12 +184,14 @@ class Handle:
 
 
 def make_opts(ns=0, nb=0, step=0, nmin=0, max_sweeps=0, exc_period=0, flags=0, aed_window=0,
-              aed_nibble=0):
+              aed_nibble=0, split_window=0, split_min_n=0):
     o = SchurOpts()
     o.ns, o.nb, o.step, o.nmin = int(ns), int(nb), int(step), int(nmin)
     o.max_sweeps, o.exc_period, o.flags = int(max_sweeps), int(exc_period), int(flags)
     o.aed_window = int(aed_window)
     o.aed_nibble = int(aed_nibble)
+    o.split_window = int(split_window)
+    o.split_min_n = int(split_min_n)
     return o
 
 

@@ -10,6 +10,10 @@
 //   simt_kernels small in.bin out.bin
 //     in : int m; double A[m*m] (upper Hessenberg, m <= 96)
 //     out: int info; double S[m*m]; double Z[m*m]; double wr[m], wi[m]
+//   simt_kernels split in.bin out.bin
+//     in : int n, a, nw, above, below; double H[n*n]
+//     out: int split, nu, nf, nb; double ftop, fbot; double H[n*n];
+//          double Ut[128*128]
 //   simt_kernels aed in.bin out.bin
 //     in : int n, ktop, kbot, nw; double H[n*n]
 //     out: int nd, nu; double H[n*n]; double Ut[128*128]; double sr[96], si[96];
@@ -187,6 +191,38 @@ int main(int argc, char** argv) {
     fwrite(si.data(), sizeof(double), MAXM, g);
     fwrite(wr.data(), sizeof(double), n, g);
     fwrite(wi.data(), sizeof(double), n, g);
+    fclose(g);
+    return 0;
+  }
+  if (mode == "split") {
+    constexpr int MAXM = SMALL_Z_MAX;
+    constexpr int LD = SmallSmem<MAXM>::LD;
+    int hdr[5];
+    if (!rd(f, hdr, 5)) return 2;
+    const int n = hdr[0];
+    std::vector<double> H((size_t)n * n), Ut(UPAD * UPAD, NAN);
+    if (!rd(f, H.data(), H.size())) return 2;
+    fclose(f);
+    static std::vector<double> S(LD * MAXM), Z(LD * MAXM), vv(MAXM), pb(7 * MAXM);
+    static std::vector<int> ib(6 * MAXM);
+    for (auto* v : {&S, &Z, &vv, &pb})
+      for (double& x : *v) x = NAN;
+    for (int& x : ib) x = -12345;
+    SplitRes res{-9, -9, -9, -9, NAN, NAN};
+    SplitTask T{};
+    T.H = H.data(); T.ldh = n; T.a = hdr[1]; T.nw = hdr[2];
+    T.above = hdr[3] ? 0 : -1; T.below = hdr[4]; T.itmax = 0;
+    T.Ut = Ut.data(); T.ldut = UPAD; T.res = &res;
+    run_workgroup(64, 0, [T] {
+      split_window<MAXM>(T, S.data(), Z.data(), vv.data(), ib.data(), pb.data());
+    });
+    FILE* g = fopen(argv[3], "wb");
+    const int o[4] = {res.split, res.nu, res.nf, res.nb};
+    fwrite(o, sizeof(int), 4, g);
+    fwrite(&res.ftop, sizeof(double), 1, g);
+    fwrite(&res.fbot, sizeof(double), 1, g);
+    fwrite(H.data(), sizeof(double), H.size(), g);
+    fwrite(Ut.data(), sizeof(double), Ut.size(), g);
     fclose(g);
     return 0;
   }

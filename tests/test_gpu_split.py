@@ -1,0 +1,77 @@
+"""GPU parity of the parallel early-deflation passes (windows tiling every
+unreduced block at once, each an early-deflation step against the couplings
+above and below it; paper Sec. 3.2, AED) against the oracle's spectrum.
+
+The passes run by default from n = 2048; here they are forced on smaller
+matrices so that the oracle and LAPACK condition numbers stay affordable.
+Checked as for every Schur form: backward error and orthogonality <= 1e-12,
+exact structure, eigenvalues (condition weighted on random matrices, 1e-9
+relative on a prescribed normal spectrum), and the same result as with the
+passes off on what is unique (the spectrum)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_04975_amd import inputs
+from tests import checks
+from tests.test_gpu_parity import _check_schur, _kappa_match, _run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,seed,nw", [(1500, 61, 0), (700, 62, 64), (1201, 63, 96)])
+def test_split_passes_random(gpu_lib, n, seed, nw):
+    print("case split passes n=%d seed=%d nw=%d" % (n, seed, nw), flush=True)
+    H = inputs.hessenberg_normal(n, seed)
+    S, Q, w, info, st = _run(gpu_lib, H, split_min_n=64, split_window=nw)
+    _check_schur(H, S, Q, w, info)
+    assert st["split_passes"] > 0 and st["split_windows"] > 0
+    assert st["split_accepted"] > 0 and st["split_converged"] > 0
+    _kappa_match(H, w)
+    S0, Q0, w0, info0, st0 = _run(gpu_lib, H, split_window=-1)
+    _check_schur(H, S0, Q0, w0, info0)
+    assert st0["split_passes"] == 0
+    # GPU against the oracle: both matched one to one to LAPACK's eigenvalues,
+    # then compared through them (condition-weighted bound on each side)
+    wo, oinfo = oracle.eigenvalues(H)
+    assert oinfo == 0
+    from scipy.optimize import linear_sum_assignment
+
+    wref, kappa = checks.eig_condition(H)
+
+    def to_ref(x):
+        r, c = linear_sum_assignment(np.abs(x[:, None] - wref[None, :]))
+        perm = np.empty(n, dtype=int)
+        perm[c] = r
+        return perm
+
+    tol = checks.kappa_tolerance(H, wref, kappa, factor=100.0)
+    assert (np.abs(w[to_ref(w)] - wo[to_ref(wo)]) <= 2 * tol).all()
+
+
+def test_split_passes_prescribed_vs_truth(gpu_lib):
+    """A normal spectrum (no localisation): the first pass splits little and
+    the sweeps take over; eigenvalues to 1e-9 relative of the exact ones."""
+    print("case split passes prescribed n=1024", flush=True)
+    H, exact = inputs.prescribed(1024, inputs.SEED_N1024)
+    S, Q, w, info, st = _run(gpu_lib, H, split_min_n=64)
+    _check_schur(H, S, Q, w, info)
+    assert st["split_passes"] >= 1
+    from scipy.optimize import linear_sum_assignment
+
+    cost = np.abs(w[:, None] - exact[None, :])
+    r, c = linear_sum_assignment(cost)
+    scale = np.maximum(np.abs(exact[c]), np.linalg.norm(H) / np.sqrt(1024))
+    assert (cost[r, c] <= 1e-9 * scale).all()
+
+
+def test_split_passes_without_q(gpu_lib):
+    """No Schur vectors: the same spectrum and the same S as with them
+    (the Q products do not feed back into H)."""
+    print("case split passes no Q n=900", flush=True)
+    H = inputs.hessenberg_normal(900, 64)
+    S, Q, w, info, st = _run(gpu_lib, H, split_min_n=64)
+    _check_schur(H, S, Q, w, info)
+    S1, _, w1, info1, st1 = _run(gpu_lib, H, want_q=False, split_min_n=64)
+    assert info1 == 0 and st1["split_accepted"] == st["split_accepted"]
+    assert np.array_equal(S1, S) and np.array_equal(w1, w)

@@ -269,3 +269,105 @@ def test_small_block_solver(driver, tmp_path, m, seed, kind):
     cost = np.abs(lam[:, None] - lam_o[None, :])
     r, c = linear_sum_assignment(cost)
     assert np.all(cost[r, c] <= checks.kappa_tolerance(A, lam_o[c], k[c], factor=200.0))
+
+
+def _split(driver, tmp_path, H, a, nw, above, below):
+    n = H.shape[0]
+    raw = _call(driver, "split", [np.array([n, a, nw, int(above), int(below)], dtype=np.int32),
+                                  np.asfortranarray(H).ravel(order="F")], tmp_path)
+    split, nu, nf, nb = (int(v) for v in np.frombuffer(raw[:16], dtype=np.int32))
+    ftop, fbot = np.frombuffer(raw[16:32], dtype=np.float64)
+    x = np.frombuffer(raw[32:], dtype=np.float64)
+    H2 = x[:n * n].reshape(n, n, order="F")
+    U = x[n * n:n * n + UPAD * UPAD].reshape(UPAD, UPAD)   # [i, j] = V(i, j)
+    return split, nu, nf, nb, float(ftop), float(fbot), H2, U
+
+
+@pytest.mark.parametrize("case", ["mid_split", "mid_nosplit", "bottom", "top", "whole"])
+def test_split_window(driver, tmp_path, case):
+    """One window of a parallel early-deflation pass (paper Sec. 3.2, AED
+    applied to windows inside the matrix): when it splits, V is orthogonal,
+    V^T W V is the returned window with zero subdiagonal entries around the
+    free part, the couplings above and below are reflected onto one entry
+    each, every dropped coupling entry is below the deflation threshold, and
+    the window's spectrum is preserved; otherwise H is untouched."""
+    above = below = True
+    if case == "mid_split":
+        H, a, nw = inputs.hessenberg_normal(700, 3), 124, 96
+    elif case == "mid_nosplit":
+        H, a, nw = inputs.hessenberg_normal(700, 3), 100, 96
+    elif case == "bottom":
+        H, a, nw, below = inputs.hessenberg_normal(300, 4), 204, 96, False
+    elif case == "top":
+        H, a, nw, above = inputs.hessenberg_normal(300, 5), 0, 96, False
+    else:
+        H, a, nw, above, below = inputs.hessenberg_normal(80, 6), 0, 80, False, False
+    n = H.shape[0]
+    split, nu, nf, nb, ftop, fbot, H2, Vfull = _split(driver, tmp_path, H, a, nw, above, below)
+    if case == "mid_nosplit":
+        assert split == 0
+    else:
+        assert split == 1
+    if not split:
+        assert np.array_equal(H2, H), "a window that does not split leaves H unchanged"
+        return
+    assert nu + nf + nb == nw and min(nu, nf, nb) >= 0
+    if not above:
+        assert nu == 0
+    if not below:
+        assert nb == 0
+    if case == "whole":
+        assert nf == nw
+    bs = nw - nb
+    outside = np.ones((n, n), dtype=bool)
+    outside[a:a + nw, a:a + nw] = False
+    assert np.array_equal(H2[outside], H[outside]), "only the window itself is written"
+    assert not np.isnan(Vfull).any()
+    assert not Vfull[nw:, :].any() and not Vfull[:, nw:].any()
+    V = Vfull[:nw, :nw]
+    W = H[a:a + nw, a:a + nw]
+    T = np.triu(H2[a:a + nw, a:a + nw], -1)
+    assert np.linalg.norm(V.T @ V - np.eye(nw)) <= 1e-13 * nw
+    assert np.linalg.norm(V.T @ W @ V - T) <= 1e-14 * nw * np.linalg.norm(W)
+    # zero subdiagonal entries around the free part, free part quasi-triangular
+    if nu and nu < nw:
+        assert T[nu, nu - 1] == 0.0
+    if nb and bs > 0:
+        assert T[bs, bs - 1] == 0.0
+    sub = np.diag(T, -1)[nu:bs - 1] if bs - nu >= 2 else np.zeros(0)
+    assert not (np.logical_and(sub[:-1] != 0, sub[1:] != 0)).any()
+    # couplings: reflected onto one entry, the dropped ones below the threshold
+    st = H[a, a - 1] if above else 0.0
+    sb = H[a + nw, a + nw - 1] if below else 0.0
+
+    def blocks(lo, hi):
+        k = lo
+        while k < hi:
+            two = k + 1 < hi and T[k + 1, k] != 0.0
+            yield k, 2 if two else 1
+            k += 2 if two else 1
+
+    def dropped_ok(vrow, s, lo, hi):
+        for k, size in blocks(lo, hi):
+            blk = T[k:k + size, k:k + size]
+            foo = (abs(np.linalg.eigvals(blk)).max() if size == 2 else abs(blk[0, 0])) or abs(s)
+            assert np.abs(s * vrow[k:k + size]).max() <= max(1e-290, ULP * foo) * 4 + 1e-15 * abs(s) * 0
+
+    if nu:
+        assert abs(V[0, 0] - ftop) <= 1e-13
+        assert np.linalg.norm(V[0, 1:nu]) <= 1e-13
+    if above:
+        dropped_ok(V[0, :], st, nu, nw)
+    if nb:
+        assert abs(V[nw - 1, nw - 1] - fbot) <= 1e-13
+        assert np.linalg.norm(V[nw - 1, bs:nw - 1]) <= 1e-13
+    if below:
+        dropped_ok(V[nw - 1, :], sb, 0, bs)
+    # the upward- and downward-coupled parts are Hessenberg (stored that way)
+    # and the window's spectrum is preserved
+    ev0 = np.linalg.eigvals(W)
+    ev1 = np.linalg.eigvals(T)
+    from scipy.optimize import linear_sum_assignment
+    cost = np.abs(ev0[:, None] - ev1[None, :])
+    r, c = linear_sum_assignment(cost)
+    assert cost[r, c].max() <= 1e-8 * np.linalg.norm(W)
