@@ -3,9 +3,11 @@
 
 One step = one complete Schur reduction (paper Sec. 2, Eq. (4)) of a random
 N(0,1) upper Hessenberg matrix of order 16384 (seed 3) with Schur vectors:
-every iteration (deflation scan, early deflation on a bottom window, shifts,
-bulge-chain windows, panel products), the final small blocks and the 2x2
-standardisation run inside the timed region.  H and Q are resident in HBM
+the parallel early-deflation passes (windows tiling every unreduced block),
+the batched finish of the small blocks they leave, every further iteration
+(deflation scan, early deflation on a bottom window, shifts, bulge-chain
+windows, panel products) and the 2x2 standardisation run inside the timed
+region.  H and Q are resident in HBM
 before timing starts; between steps they are reset from device copies
 outside the timed region.
 
@@ -46,6 +48,8 @@ def parse():
                     help="early-deflation window (0: from ns, <0: off)")
     ap.add_argument("--aed-nibble", type=int, default=0,
                     help="percent of the window deflated above which no sweep follows")
+    ap.add_argument("--split-window", type=int, default=0,
+                    help="window of the parallel early-deflation passes (0: 96, <0: off)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the oracle sample")
@@ -389,7 +393,8 @@ def main():
     wi = torch.empty(n, dtype=torch.float64, device=dev)
     gen_s = time.time() - t0
     hdl = schur.Handle(0, ns=args.ns, nb=args.nb, step=args.step_len, aed_window=args.aed_window,
-                       aed_nibble=args.aed_nibble, flags=schur.FLAG_TIME_KERNELS)
+                       aed_nibble=args.aed_nibble, split_window=args.split_window,
+                       flags=schur.FLAG_TIME_KERNELS)
     stream = torch.cuda.current_stream(dev)
 
     def one_step():
@@ -441,6 +446,8 @@ def main():
         "k_panel_colq": (agg("colq_ms"), agg("colq_launches"), agg("colq_flops")),
         "k_panel_row": (agg("row_ms"), agg("row_launches"), agg("row_flops")),
         "k_aed": (agg("aed_ms"), agg("aed_windows"), agg("aed_flops")),
+        # one launch per pass, one window per workgroup
+        "k_split": (agg("split_ms"), agg("split_passes"), agg("split_flops")),
     }
 
     def line(name, bound, peak):
@@ -452,17 +459,24 @@ def main():
                 "avg_launch_ms": avg_ms, "launches": launches,
                 "flops_per_launch": flops / max(1, launches)}
 
-    # the dominant kernel by time: the early-deflation window (one workgroup,
-    # a chain of dependent small steps) once it does most of the work, else
-    # the panel products (FP64 MFMA)
+    # the dominant kernel by time: the parallel early-deflation windows or the
+    # bottom early-deflation window (one wavefront per window, chains of
+    # dependent small steps: FP64 vector ALU against the chip's vector peak),
+    # else the panel products (FP64 MFMA)
     gemm_name = max(("k_panel_colq", "k_panel_row"), key=lambda k: kern[k][0])
     gemm_line = line(gemm_name, "mfma", FP64_MFMA_PEAK_TFLOPS)
-    if kern["k_aed"][0] > kern[gemm_name][0] + agg("chase_ms"):
-        roofline = line("k_aed", "alu", FP64_VECTOR_PEAK_TFLOPS)
-        # one workgroup by construction: the ceiling it could reach is one
-        # compute unit's share of the FP64 vector peak
-        roofline["peak_one_cu"] = FP64_VECTOR_PEAK_TFLOPS / 256
-        roofline["frac_one_cu"] = roofline["achieved"] / roofline["peak_one_cu"]
+    lds_name = max(("k_split", "k_aed"), key=lambda k: kern[k][0])
+    if kern[lds_name][0] > kern[gemm_name][0] + agg("chase_ms"):
+        roofline = line(lds_name, "alu", FP64_VECTOR_PEAK_TFLOPS)
+        # one wavefront (one CU, whose LDS it fills) per window: the ceiling
+        # within reach is the share of the FP64 vector peak of the CUs the
+        # launch occupies
+        cus = 1.0
+        if lds_name == "k_split":
+            cus = min(256.0, agg("split_windows") / max(1, agg("split_passes")))
+        roofline["cus_per_launch"] = cus
+        roofline["peak_used_cus"] = FP64_VECTOR_PEAK_TFLOPS * cus / 256
+        roofline["frac_used_cus"] = roofline["achieved"] / roofline["peak_used_cus"]
     else:
         roofline = gemm_line
     st0 = stats[-1]
@@ -472,6 +486,9 @@ def main():
         "aed_windows": st0["aed_windows"], "aed_deflated": st0["aed_deflated"],
         "sweeps": st0["sweeps"], "windows": st0["windows"], "launches": st0["launches"],
         "shifts_applied": st0["shifts_applied"],
+        "split_ms": st0["split_ms"], "split_passes": st0["split_passes"],
+        "split_windows": st0["split_windows"], "split_accepted": st0["split_accepted"],
+        "split_converged": st0["split_converged"], "small_solves": st0["small_solves"],
         "executed_gemm_tflops": st0["gemm_flops"] / (1e3 * total / len(walls)) / 1e9,
     }
     check = None
@@ -510,6 +527,8 @@ def main():
                    "chase_window_rows": 128,
                    "aed_window": args.aed_window or row.get("nw"),
                    "sweep_skip_pct": args.aed_nibble or row.get("nibble") or 14,
+                   "split_window": args.split_window or 96,
+                   "split_passes": st0["split_passes"],
                    "sweeps_executed": st0["sweeps"], "schur_vectors": True},
         "roofline": roofline,
         "breakdown": breakdown,

@@ -129,6 +129,7 @@ struct schur_handle_s {
   // parallel early-deflation passes: tasks, outcomes, V^T slots, block
   // starts, panel descriptors
   Grow b_splt, b_splr, b_splu, b_splz, b_splw;
+  Grow b_splq, b_splb;   // batched finish: per-block Z slots, block orders
   // nested solve of a trailing block larger than SMALL_EIG_MAX (shifts only)
   schur_handle_s* sub = nullptr;
   double* shm = nullptr;         // NS_MAX x NS_MAX copy of the trailing block
@@ -280,7 +281,7 @@ void free_ws(schur_handle_s* h) {
   free_grow(h->b_shift); free_grow(h->b_win); free_grow(h->b_u); free_grow(h->b_sh);
   free_grow(h->b_aedt); free_grow(h->b_aedw);
   free_grow(h->b_splt); free_grow(h->b_splr); free_grow(h->b_splu); free_grow(h->b_splz);
-  free_grow(h->b_splw);
+  free_grow(h->b_splw); free_grow(h->b_splq); free_grow(h->b_splb);
   if (h->U) (void)hipFree(h->U);
   if (h->refl) (void)hipFree(h->refl);
   if (h->st) (void)hipFree(h->st);
@@ -372,6 +373,9 @@ void plan_sweep(int ktop, int kbot, int npair, int nbmax, int step_opt,
 }
 
 int create_handle(schur_handle_s** out, int device, const schur_opts* opts);
+void batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<int, int>>& blocks,
+                  int n, double* H, int ldh, double* Q, int ldq, double* wr, double* wi,
+                  bool time);
 
 struct Solver {
   schur_handle_s* h;
@@ -696,23 +700,32 @@ struct Solver {
     }
   }
 
-  // Parallel early deflation (split_window): passes of windows that tile
-  // every unreduced block at once.  A pass scans the subdiagonal for the
-  // unreduced blocks, solves and tests all windows in one launch, scales
-  // the coupling entries, and applies the V of every window that split its
-  // block to the row panels (one launch) and to the column panels and Q
-  // (one launch; the windows are disjoint, so each launch updates disjoint
-  // rows or columns).  The passes stop once one neither shrinks the largest
-  // unreduced block by a tenth nor reduces the unreduced rows by 1 %; the
-  // sweeps and bottom windows then finish what is left.
+  // Parallel early deflation (split_window): passes of windows over every
+  // unreduced block at once.  A pass scans the subdiagonal for the
+  // unreduced blocks and lays two tilings of windows over each of them, the
+  // second with its boundaries half a window further up (as long as the
+  // launch fits the CUs).  One launch solves and tests every window, each
+  // writing its result to its own slot.  Per block, the host keeps the set of
+  // disjoint windows that split with the most rows deflated (weighted
+  // interval scheduling); one launch writes those into H and scales their
+  // coupling entries, and their V go to the row panels (one launch) and to
+  // the column panels and Q (one launch; disjoint windows, so each launch
+  // updates disjoint rows or columns).  Once the unreduced blocks all have
+  // order <= UPAD, or a pass neither shrinks the largest block by a tenth
+  // nor reduces the unreduced rows by 1 %, the blocks of order <= UPAD are
+  // finished together by the batched engine; sweeps and bottom windows
+  // finish what is left.
   void split_phase() {
+    constexpr int kCUs = 256;
     const int nw = P.split_nw;
     grow(h->b_splz, (size_t)n, true);
     unsigned char* zd = (unsigned char*)h->b_splz.dev;
     unsigned char* zh = (unsigned char*)h->b_splz.host;
-    struct Wn { int a, nw, above, below; };
+    struct Wn { int a, nw, top, below; };
     std::vector<Wn> wins;
     std::vector<std::pair<int, int>> regs, ws;
+    std::vector<int> order, best_prev, pick;
+    std::vector<double> best;
     int64_t prev_active = -1;
     int prev_max = -1;
     for (int pass = 0; pass < kSplitMaxPasses; ++pass) {
@@ -737,17 +750,21 @@ struct Solver {
       }
       h->stats.split_converged = n - active;
       if (active == 0) break;
-      if (prev_active >= 0 && 100 * (prev_active - active) < prev_active &&
-          10 * (int64_t)mx > 9 * (int64_t)prev_max)
+      const bool stuck = prev_active >= 0 && 100 * (prev_active - active) < prev_active &&
+                         10 * (int64_t)mx > 9 * (int64_t)prev_max;
+      if (stuck || mx <= UPAD) {
+        std::vector<std::pair<int, int>> fin;
+        for (const auto& r : regs)
+          if (r.second - r.first + 1 <= UPAD) fin.push_back(r);
+        batch_blocks(h, s, fin, n, H, ldh, Q, ldq, wr, wi, P.time);
         break;
+      }
       prev_active = active;
       prev_max = mx;
-      // windows of each block, listed top to bottom; every other pass moves
-      // the boundaries by half a window
-      wins.clear();
-      for (const auto& r : regs) {
-        const int lo = r.first, hi = r.second;
-        const int first = ((pass & 1) && hi - lo + 1 > nw) ? nw / 2 : nw;
+      // ---- candidate windows: per block, tiling 0 (bottom window of nw or
+      // nw / 2 rows, alternating between passes) for every block, tiling 1
+      // (the other offset) for the largest blocks while the launch fits
+      auto tile = [&](int lo, int hi, int first) {
         ws.clear();   // (start, order), bottom to top
         for (int b = hi + 1; b > lo;) {
           const int a = std::max(lo, b - (ws.empty() ? first : nw));
@@ -763,32 +780,64 @@ struct Solver {
           ws.push_back({top + tot / 2, tot - tot / 2});
           ws.push_back({top, tot / 2});
         }
-        for (int j = (int)ws.size() - 1; j >= 0; --j) {
-          Wn w;
-          w.a = ws[j].first;
-          w.nw = ws[j].second;
-          w.above = (j == (int)ws.size() - 1) ? -1 : (int)wins.size() - 1;
-          w.below = j > 0 ? 1 : 0;
-          if (w.nw < 1 || w.nw > SMALL_Z_MAX) throw HipErr{hipErrorInvalidValue};
-          wins.push_back(w);
+      };
+      const int f0 = (pass & 1) ? nw / 2 : nw, f1 = (pass & 1) ? nw : nw / 2;
+      std::vector<int> tilings(regs.size(), 1);
+      int total = 0;
+      for (const auto& r : regs) total += (r.second - r.first + 1 + nw - 1) / nw + 1;
+      order.resize(regs.size());
+      for (size_t i = 0; i < regs.size(); ++i) order[i] = (int)i;
+      std::sort(order.begin(), order.end(), [&](int x, int y) {
+        return regs[x].second - regs[x].first > regs[y].second - regs[y].first;
+      });
+      for (int i : order) {
+        const int m = regs[i].second - regs[i].first + 1;
+        const int extra = (m + nw - 1) / nw + 1;
+        if (m > nw && total + extra <= kCUs) {
+          tilings[i] = 2;
+          total += extra;
         }
       }
+      wins.clear();
+      std::vector<std::pair<int, int>> span(regs.size());   // candidate range per block
+      for (size_t i = 0; i < regs.size(); ++i) {
+        const int lo = regs[i].first, hi = regs[i].second;
+        span[i].first = (int)wins.size();
+        for (int t = 0; t < tilings[i]; ++t) {
+          tile(lo, hi, (hi - lo + 1 > nw) ? (t == 0 ? f0 : f1) : nw);
+          for (int j = (int)ws.size() - 1; j >= 0; --j) {
+            Wn w;
+            w.a = ws[j].first;
+            w.nw = ws[j].second;
+            w.top = w.a > lo ? 1 : 0;
+            w.below = (w.a + w.nw <= hi) ? 1 : 0;
+            if (w.nw < 1 || w.nw > SMALL_Z_MAX) throw HipErr{hipErrorInvalidValue};
+            wins.push_back(w);
+          }
+        }
+        span[i].second = (int)wins.size();
+      }
       const int cnt = (int)wins.size();
+      const size_t wslot = (size_t)SMALL_Z_MAX * SMALL_Z_MAX;
       grow(h->b_splt, sizeof(SplitTask) * cnt, true);
       grow(h->b_splr, sizeof(SplitRes) * cnt, true);
       grow(h->b_splu, sizeof(double) * (size_t)UPAD * UPAD * cnt, false);
+      grow(h->b_splq, sizeof(double) * wslot * cnt, false);
       SplitTask* th = (SplitTask*)h->b_splt.host;
       SplitRes* rd = (SplitRes*)h->b_splr.dev;
       double* ud = (double*)h->b_splu.dev;
+      double* wo = (double*)h->b_splq.dev;
       for (int i = 0; i < cnt; ++i) {
         SplitTask& t = th[i];
         std::memset(&t, 0, sizeof(t));
         t.H = H; t.ldh = ldh;
         t.a = wins[i].a; t.nw = wins[i].nw;
-        t.above = wins[i].above; t.below = wins[i].below;
+        t.above = wins[i].top ? 0 : -1;   // read as a flag by the window kernel
+        t.below = wins[i].below;
         t.itmax = 0;   // default budget
         t.Ut = ud + (size_t)i * UPAD * UPAD; t.ldut = UPAD;
         t.res = rd + i;
+        t.Wo = wo + (size_t)i * wslot; t.ldwo = SMALL_Z_MAX;
       }
       SplitTask* td = (SplitTask*)h->b_splt.dev;
       HCHECK(hipMemcpyAsync(td, th, sizeof(SplitTask) * cnt, hipMemcpyHostToDevice, s));
@@ -797,25 +846,78 @@ struct Solver {
       launch_split(td, cnt, s);
       HCHECK(hipGetLastError());
       if (P.time) h->timer.end(s, e0, &h->stats.split_ms);
-      launch_split_fix(td, cnt, s);
-      HCHECK(hipGetLastError());
-      h->stats.launches += 2;
+      h->stats.launches += 1;
       h->stats.split_passes += 1;
       h->stats.split_windows += cnt;
       SplitRes* rh = (SplitRes*)h->b_splr.host;
       HCHECK(hipMemcpyAsync(rh, rd, sizeof(SplitRes) * cnt, hipMemcpyDeviceToHost, s));
       HCHECK(hipStreamSynchronize(s));
       if (P.time) h->timer.harvest();
-      grow(h->b_splw, sizeof(WinB) * cnt, true);
+      // ---- per block: disjoint splitting windows of most weight (1 + rows
+      // deflated), by weighted interval scheduling over the window ends
+      pick.clear();
+      for (size_t i = 0; i < regs.size(); ++i) {
+        const int c0 = span[i].first, c1 = span[i].second;
+        order.clear();
+        for (int c = c0; c < c1; ++c) {
+          h->stats.split_flops += aed_work(wins[c].nw, rh[c].split ? rh[c].nu : 0) +
+                                  (10.0 / 3.0) * rh[c].nb * (double)rh[c].nb * rh[c].nb;
+          if (rh[c].split) order.push_back(c);
+        }
+        std::sort(order.begin(), order.end(), [&](int x, int y) {
+          return wins[x].a + wins[x].nw < wins[y].a + wins[y].nw;
+        });
+        const int k = (int)order.size();
+        best.assign(k + 1, 0.0);
+        best_prev.assign(k + 1, 0);
+        for (int j = 1; j <= k; ++j) {
+          const Wn& w = wins[order[j - 1]];
+          int p = j - 1;   // windows ending at or above this one's start
+          while (p > 0 && wins[order[p - 1]].a + wins[order[p - 1]].nw > w.a) --p;
+          const double take = best[p] + 1.0 + rh[order[j - 1]].nf;
+          if (take > best[j - 1]) {
+            best[j] = take;
+            best_prev[j] = p;
+          } else {
+            best[j] = best[j - 1];
+            best_prev[j] = -1;   // not taken
+          }
+        }
+        for (int j = k; j > 0;) {
+          if (best_prev[j] >= 0) {
+            pick.push_back(order[j - 1]);
+            j = best_prev[j];
+          } else {
+            --j;
+          }
+        }
+      }
+      std::sort(pick.begin(), pick.end(), [&](int x, int y) { return wins[x].a < wins[y].a; });
+      const int ncm = (int)pick.size();
+      if (ncm == 0) continue;
+      grow(h->b_splb, sizeof(SplitCommit) * ncm, true);
+      SplitCommit* ch = (SplitCommit*)h->b_splb.host;
+      for (int j = 0; j < ncm; ++j) {
+        const Wn& w = wins[pick[j]];
+        SplitCommit& c = ch[j];
+        c.task = pick[j];
+        c.above = (j > 0 && wins[pick[j - 1]].a + wins[pick[j - 1]].nw == w.a) ? pick[j - 1] : -1;
+        c.fix_top = w.top;
+        const bool next_adj = j + 1 < ncm && wins[pick[j + 1]].a == w.a + w.nw;
+        c.fix_below = (w.below && !next_adj) ? 1 : 0;
+      }
+      SplitCommit* cd = (SplitCommit*)h->b_splb.dev;
+      HCHECK(hipMemcpyAsync(cd, ch, sizeof(SplitCommit) * ncm, hipMemcpyHostToDevice, s));
+      launch_split_commit(cd, ncm, td, s);
+      HCHECK(hipGetLastError());
+      h->stats.launches += 1;
+      h->stats.split_accepted += ncm;
+      grow(h->b_splw, sizeof(WinB) * ncm, true);
       WinB* wh = (WinB*)h->b_splw.host;
-      int nwin = 0, tr = 0, tcq = 0;
-      for (int i = 0; i < cnt; ++i) {
-        const SplitRes& r = rh[i];
-        h->stats.split_flops +=
-            aed_work(wins[i].nw, r.split ? r.nu : 0) + (10.0 / 3.0) * r.nb * (double)r.nb * r.nb;
-        if (!r.split) continue;
-        h->stats.split_accepted += 1;
-        WinB& w = wh[nwin++];
+      int tr = 0, tcq = 0;
+      for (int j = 0; j < ncm; ++j) {
+        const int i = pick[j];
+        WinB& w = wh[j];
         std::memset(&w, 0, sizeof(w));
         w.c.H = H; w.c.Q = Q; w.c.U = ud + (size_t)i * UPAD * UPAD; w.c.st = nullptr;
         w.c.ldh = ldh; w.c.ldq = ldq; w.c.n = n;
@@ -823,27 +925,25 @@ struct Solver {
         w.c.p = wins[i].a; w.c.ws = wins[i].nw;
         fill_tiles_b(w, tr, tcq, h->stats);
       }
-      if (nwin > 0) {
-        WinB* wd = (WinB*)h->b_splw.dev;
-        HCHECK(hipMemcpyAsync(wd, wh, sizeof(WinB) * nwin, hipMemcpyHostToDevice, s));
-        if (tr > 0) {
-          if (P.time) h->timer.begin(s, e0);
-          launch_panel_row_b(wd, nwin, tr, s);
-          HCHECK(hipGetLastError());
-          if (P.time) h->timer.end(s, e0, &h->stats.row_ms);
-          h->stats.row_launches += 1;
-          h->stats.gemm_launches += 1;
-          h->stats.launches += 1;
-        }
-        if (tcq > 0) {
-          if (P.time) h->timer.begin(s, e0);
-          launch_panel_colq_b(wd, nwin, tcq, s);
-          HCHECK(hipGetLastError());
-          if (P.time) h->timer.end(s, e0, &h->stats.colq_ms);
-          h->stats.colq_launches += 1;
-          h->stats.gemm_launches += 1;
-          h->stats.launches += 1;
-        }
+      WinB* wd = (WinB*)h->b_splw.dev;
+      HCHECK(hipMemcpyAsync(wd, wh, sizeof(WinB) * ncm, hipMemcpyHostToDevice, s));
+      if (tr > 0) {
+        if (P.time) h->timer.begin(s, e0);
+        launch_panel_row_b(wd, ncm, tr, s);
+        HCHECK(hipGetLastError());
+        if (P.time) h->timer.end(s, e0, &h->stats.row_ms);
+        h->stats.row_launches += 1;
+        h->stats.gemm_launches += 1;
+        h->stats.launches += 1;
+      }
+      if (tcq > 0) {
+        if (P.time) h->timer.begin(s, e0);
+        launch_panel_colq_b(wd, ncm, tcq, s);
+        HCHECK(hipGetLastError());
+        if (P.time) h->timer.end(s, e0, &h->stats.colq_ms);
+        h->stats.colq_launches += 1;
+        h->stats.gemm_launches += 1;
+        h->stats.launches += 1;
       }
     }
   }
@@ -1405,6 +1505,79 @@ struct BatchEngine {
 
   void fill_tiles(WinB& w, int& tr, int& tcq) { fill_tiles_b(w, tr, tcq, h->stats); }
 };
+
+// Independent unreduced blocks [lo, hi] of one matrix (order <= UPAD each)
+// solved together by the batched engine, in place in H, each with its own Z
+// accumulated in a slot; then Z^T X for the rows right of each block, X Z for
+// the rows above it and for Q, in one row-panel and one column-panel launch.
+void batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<int, int>>& blocks,
+                  int n, double* H, int ldh, double* Q, int ldq, double* wr, double* wi,
+                  bool time) {
+  const int cnt = (int)blocks.size();
+  if (cnt == 0) return;
+  const size_t slot = (size_t)UPAD * UPAD;
+  grow(h->b_splq, sizeof(double) * slot * cnt, false);
+  grow(h->b_splu, sizeof(double) * slot * cnt, false);
+  grow(h->b_splb, sizeof(int) * cnt, true);
+  double* zq = (double*)h->b_splq.dev;
+  double* ut = (double*)h->b_splu.dev;
+  int* sz = (int*)h->b_splb.host;
+  for (int i = 0; i < cnt; ++i) {
+    sz[i] = blocks[i].second - blocks[i].first + 1;
+    if (sz[i] < 1 || sz[i] > UPAD) throw HipErr{hipErrorInvalidValue};
+  }
+  HCHECK(hipMemcpyAsync(h->b_splb.dev, sz, sizeof(int) * cnt, hipMemcpyHostToDevice, s));
+  launch_slot_ident(zq, (const int*)h->b_splb.dev, cnt, s);
+  HCHECK(hipGetLastError());
+  BatchEngine b;
+  b.init(h, s, cnt);
+  for (int i = 0; i < cnt; ++i) {
+    const int lo = blocks[i].first;
+    b.add(i, sz[i], H + lo + (size_t)lo * ldh, ldh, zq + (size_t)i * slot, UPAD, wr + lo, wi + lo,
+          (uint64_t)i);
+  }
+  int64_t guard = 0;
+  while (b.any_active()) {
+    b.round();
+    if (++guard > (int64_t)4 * 1000 * 1000) throw HipErr{hipErrorUnknown};
+  }
+  b.settle();
+  launch_slot_transpose(zq, ut, cnt, s);
+  HCHECK(hipGetLastError());
+  grow(h->b_splw, sizeof(WinB) * cnt, true);
+  WinB* wh = (WinB*)h->b_splw.host;
+  int tr = 0, tcq = 0;
+  for (int i = 0; i < cnt; ++i) {
+    WinB& w = wh[i];
+    std::memset(&w, 0, sizeof(w));
+    w.c.H = H; w.c.Q = Q; w.c.U = ut + (size_t)i * slot; w.c.st = nullptr;
+    w.c.ldh = ldh; w.c.ldq = ldq; w.c.n = n;
+    w.c.ktop = 0; w.c.kbot = n - 1; w.c.rtop = 0; w.c.cend = n;
+    w.c.p = blocks[i].first; w.c.ws = sz[i];
+    fill_tiles_b(w, tr, tcq, h->stats);
+  }
+  WinB* wd = (WinB*)h->b_splw.dev;
+  HCHECK(hipMemcpyAsync(wd, wh, sizeof(WinB) * cnt, hipMemcpyHostToDevice, s));
+  hipEvent_t e0 = nullptr;
+  if (tr > 0) {
+    if (time) h->timer.begin(s, e0);
+    launch_panel_row_b(wd, cnt, tr, s);
+    HCHECK(hipGetLastError());
+    if (time) h->timer.end(s, e0, &h->stats.row_ms);
+    h->stats.row_launches += 1;
+  }
+  if (tcq > 0) {
+    if (time) h->timer.begin(s, e0);
+    launch_panel_colq_b(wd, cnt, tcq, s);
+    HCHECK(hipGetLastError());
+    if (time) h->timer.end(s, e0, &h->stats.colq_ms);
+    h->stats.colq_launches += 1;
+  }
+  h->stats.gemm_launches += (tr > 0) + (tcq > 0);
+  h->stats.launches += 2 + (tr > 0) + (tcq > 0);
+  // the staging buffers are rewritten by the next call: wait for the copies
+  HCHECK(hipStreamSynchronize(s));
+}
 
 int solve_batched(schur_handle_s* h, hipStream_t s, int count, const int* n, double* const* H,
                   const int* ldh, double* const* Q, const int* ldq, double* const* wr,

@@ -42,12 +42,23 @@ struct SplitRes {
 struct SplitTask {
   double* H; int ldh;
   int a, nw;
-  int above;                   // task index of the window ending at row a (-1: block top)
+  int above;                   // >= 0: the block continues above the window (coupling H(a, a-1))
   int below;                   // 1: the block continues below the window
   int itmax;
   int pad;
   double* Ut; int ldut;        // V^T of the window, zero padded to ldut x ldut
   SplitRes* res;               // this window's outcome
+  double* Wo; int ldwo;        // optional: the new window goes here instead of into H
+  int pad2;
+};
+
+// A window of a pass whose result is written into H (windows of one commit
+// launch are disjoint).
+struct SplitCommit {
+  int task;                    // index into the pass's SplitTask array
+  int above;                   // committed window ending at row a-1 (-1: none)
+  int fix_top;                 // 1: scale H(a, a-1) (coupling above the window)
+  int fix_below;               // 1: scale H(a+nw, a+nw-1) (no committed window below)
 };
 
 // One matrix of a batched deflation scan.
@@ -71,8 +82,10 @@ void launch_small_eig(const SmallTask& t, hipStream_t s);
 void launch_aed(const AedTask& t, hipStream_t s);
 void launch_aed_b(const AedTask* tasks, int count, hipStream_t s);
 void launch_split(const SplitTask* tasks, int count, hipStream_t s);
-void launch_split_fix(const SplitTask* tasks, int count, hipStream_t s);
+void launch_split_commit(const SplitCommit* cm, int count, const SplitTask* tasks, hipStream_t s);
 void launch_split_scan(double* H, int ldh, int n, unsigned char* zero, hipStream_t s);
+void launch_slot_ident(double* U, const int* sizes, int count, hipStream_t s);
+void launch_slot_transpose(const double* src, double* dst, int count, hipStream_t s);
 void launch_shift_prep(const double* wr, const double* wi, int ns, const int* small_info,
                        int exceptional, const double* H, int ldh, int ktop, int kbot, double* st,
                        hipStream_t s);

@@ -68,18 +68,27 @@ __global__ __launch_bounds__(64) void k_split(const SplitTask* tasks) {
   split_window<MAXM>(T, S, Z, vv, ibuf, pbuf);
 }
 
-// After a pass: the subdiagonal entry coupling each window to the one above
-// it takes the factors of both (1 for a window left untouched).  Separate
-// launch: every window reads its couplings before any is rewritten.
-__global__ void k_split_fix(const SplitTask* tasks, int count) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const SplitTask t = tasks[i];
-  if (t.above < 0) return;
-  const SplitRes r = *t.res;
-  const SplitRes u = *tasks[t.above].res;
-  const double f = (r.split ? r.ftop : 1.0) * (u.split ? u.fbot : 1.0);
-  t.H[t.a + (size_t)(t.a - 1) * t.ldh] *= f;
+// Chosen windows of a pass (disjoint) written from their output slots into
+// H (the Hessenberg part), and the coupling entries at their ends scaled:
+// above by this window's and the committed neighbour's factors, below by
+// this window's alone when no committed window starts there.  One
+// workgroup per window.
+__global__ void k_split_commit(const SplitCommit* cm, const SplitTask* tasks) {
+  const SplitCommit c = cm[blockIdx.x];
+  const SplitTask t = tasks[c.task];
+  const int nw = t.nw;
+  for (int idx = threadIdx.x; idx < nw * nw; idx += blockDim.x) {
+    const int r = idx % nw, col = idx / nw;
+    if (r <= col + 1) t.H[(t.a + r) + (size_t)(t.a + col) * t.ldh] = t.Wo[r + (size_t)col * t.ldwo];
+  }
+  if (threadIdx.x == 0) {
+    const SplitRes r = *t.res;
+    if (c.fix_top) {
+      const double f = r.ftop * (c.above >= 0 ? tasks[c.above].res->fbot : 1.0);
+      t.H[t.a + (size_t)(t.a - 1) * t.ldh] *= f;
+    }
+    if (c.fix_below) t.H[(t.a + nw) + (size_t)(t.a + nw - 1) * t.ldh] *= r.fbot;
+  }
 }
 
 // Negligible subdiagonal entries (same test as the deflation scan) set to
@@ -101,6 +110,29 @@ __global__ void k_split_scan(double* H, int ldh, int n, unsigned char* zero) {
     const bool z = sub <= kUlp * tst;
     if (z && sub != 0.0) *hp = 0.0;
     zero[k] = z ? 1 : 0;
+  }
+}
+
+// Identity of order sizes[b] in the leading corner of UPAD x UPAD slot b,
+// zero elsewhere (grid.y = slots).
+__global__ void k_slot_ident(double* U, const int* sizes) {
+  const int b = blockIdx.y;
+  const int m = sizes[b];
+  double* u = U + (size_t)b * UPAD * UPAD;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < UPAD * UPAD;
+       idx += gridDim.x * blockDim.x) {
+    const int r = idx % UPAD, c = idx / UPAD;
+    u[idx] = (r == c && r < m) ? 1.0 : 0.0;
+  }
+}
+
+// Slot b of dst = transpose of slot b of src (grid.y = slots).
+__global__ void k_slot_transpose(const double* src, double* dst) {
+  const size_t off = (size_t)blockIdx.y * UPAD * UPAD;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < UPAD * UPAD;
+       idx += gridDim.x * blockDim.x) {
+    const int r = idx % UPAD, c = idx / UPAD;
+    dst[off + c + (size_t)r * UPAD] = src[off + idx];
   }
 }
 
@@ -847,9 +879,8 @@ void launch_split(const SplitTask* tasks, int count, hipStream_t s) {
     hipLaunchKernelGGL((k_split<SMALL_Z_MAX>), dim3(count), dim3(64), 0, s, tasks);
 }
 
-void launch_split_fix(const SplitTask* tasks, int count, hipStream_t s) {
-  if (count > 0)
-    hipLaunchKernelGGL(k_split_fix, dim3((count + 255) / 256), dim3(256), 0, s, tasks, count);
+void launch_split_commit(const SplitCommit* cm, int count, const SplitTask* tasks, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_split_commit, dim3(count), dim3(256), 0, s, cm, tasks);
 }
 
 void launch_split_scan(double* H, int ldh, int n, unsigned char* zero, hipStream_t s) {
@@ -857,6 +888,14 @@ void launch_split_scan(double* H, int ldh, int n, unsigned char* zero, hipStream
     const int blocks = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
     hipLaunchKernelGGL(k_split_scan, dim3(blocks), dim3(256), 0, s, H, ldh, n, zero);
   }
+}
+
+void launch_slot_ident(double* U, const int* sizes, int count, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_slot_ident, dim3(16, count), dim3(256), 0, s, U, sizes);
+}
+
+void launch_slot_transpose(const double* src, double* dst, int count, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_slot_transpose, dim3(16, count), dim3(256), 0, s, src, dst);
 }
 
 void launch_shift_prep(const double* wr, const double* wi, int ns, const int* small_info,

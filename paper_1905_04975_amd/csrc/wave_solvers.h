@@ -1300,9 +1300,11 @@ __device__ void split_window(const SplitTask& T, double* S, double* Z, double* v
       fbot = spike_reduce(S + bs + bs * LD, Z + bs * LD, LD, nb, nb, bs, nw, nw - 1, vv);
       flip_tail(S, Z, LD, nw, bs);
     }
-    // ---- 4. the window back into H, V^T into its slot
+    // ---- 4. the window back into H (or its output slot), V^T into its slot
+    double* Wd = T.Wo ? T.Wo : Hw;
+    const int ldw = T.Wo ? T.ldwo : T.ldh;
     for (int c = 0; c < nw; ++c)
-      for (int r = lane; r <= c + 1 && r < nw; r += 64) Hw[r + (size_t)c * T.ldh] = Sx(r, c);
+      for (int r = lane; r <= c + 1 && r < nw; r += 64) Wd[r + (size_t)c * ldw] = Sx(r, c);
     __syncthreads();
     aed_write_vt(S, Z, LD, nw, T.Ut, T.ldut);
     out.split = 1;
