@@ -312,7 +312,7 @@ def sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream):
 
     n = args.n
     dev = H0.device
-    hs = schur.Handle(0, ns=args.sweep_ns, nb=args.nb, aed_nibble=-1,
+    hs = schur.Handle(0, ns=args.sweep_ns, nb=args.nb, aed_nibble=-1, split_window=-1,
                       max_sweeps=args.sweep_count, flags=schur.FLAG_TIME_KERNELS)
     H.copy_(H0)
     Q.copy_(eye)

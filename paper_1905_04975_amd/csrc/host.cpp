@@ -373,7 +373,7 @@ void plan_sweep(int ktop, int kbot, int npair, int nbmax, int step_opt,
 }
 
 int create_handle(schur_handle_s** out, int device, const schur_opts* opts);
-void batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<int, int>>& blocks,
+bool batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<int, int>>& blocks,
                   int n, double* H, int ldh, double* Q, int ldq, double* wr, double* wi,
                   bool time);
 
@@ -715,7 +715,7 @@ struct Solver {
   // nor reduces the unreduced rows by 1 %, the blocks of order <= UPAD are
   // finished together by the batched engine; sweeps and bottom windows
   // finish what is left.
-  void split_phase() {
+  bool split_phase() {
     constexpr int kCUs = 256;
     const int nw = P.split_nw;
     grow(h->b_splz, (size_t)n, true);
@@ -749,15 +749,16 @@ struct Solver {
         k = e;
       }
       h->stats.split_converged = n - active;
-      if (active == 0) break;
+      if (active == 0) return true;
       const bool stuck = prev_active >= 0 && 100 * (prev_active - active) < prev_active &&
                          10 * (int64_t)mx > 9 * (int64_t)prev_max;
       if (stuck || mx <= UPAD) {
         std::vector<std::pair<int, int>> fin;
         for (const auto& r : regs)
           if (r.second - r.first + 1 <= UPAD) fin.push_back(r);
-        batch_blocks(h, s, fin, n, H, ldh, Q, ldq, wr, wi, P.time);
-        break;
+        const bool ok = batch_blocks(h, s, fin, n, H, ldh, Q, ldq, wr, wi, P.time);
+        if (ok && fin.size() == regs.size()) h->stats.split_converged = n;
+        return ok && fin.size() == regs.size();
       }
       prev_active = active;
       prev_max = mx;
@@ -946,6 +947,7 @@ struct Solver {
         h->stats.launches += 1;
       }
     }
+    return false;
   }
 
   int run() {
@@ -957,12 +959,13 @@ struct Solver {
     sync_ctrl();
     if (h->ctrl_h->bad) return -2;
     launch_zero_lower(H, ldh, n, s);
-    if (P.split_nw > 0 && n >= P.split_min_n) split_phase();
+    // nothing left after the parallel passes: straight to the standardisation
+    const bool done = P.split_nw > 0 && n >= P.split_min_n && split_phase();
     int info = 0;
     int kbot = n - 1;
     int nodefl = 0;
     int64_t sweeps = 0;
-    while (true) {
+    while (!done) {
       hipEvent_t e0 = nullptr;
       if (P.time) h->timer.begin(s, e0);
       launch_deflate(H, ldh, kbot, 0, h->ctrl, s);
@@ -1109,6 +1112,10 @@ struct BatchEngine {
   Ctrl* ctrl_h = nullptr;
   double* shbuf = nullptr;
   int64_t rounds = 0;
+  // hold small active blocks back while any matrix still sweeps, so that
+  // they are solved by one launch (for blocks of one matrix that must all
+  // finish before anything else runs)
+  bool defer_small = false;
 
   template <class T>
   T* dev_of(schur_handle_s::Grow& g) { return (T*)g.dev; }
@@ -1228,6 +1235,7 @@ struct BatchEngine {
       else if (++m.sweeps > m.P.max_sweeps) { m.info = m.kbot + 1; m.active = false; }
       else big.push_back(i);
     }
+    if (defer_small && !big.empty()) small.clear();
     if (small.empty() && big.empty()) return;
     // U slots: one per small block, per early-deflation window, and per
     // window of the widest sweep time step (at most one per bulge group)
@@ -1510,11 +1518,12 @@ struct BatchEngine {
 // solved together by the batched engine, in place in H, each with its own Z
 // accumulated in a slot; then Z^T X for the rows right of each block, X Z for
 // the rows above it and for Q, in one row-panel and one column-panel launch.
-void batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<int, int>>& blocks,
+// Returns true when every block reached Schur form.
+bool batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<int, int>>& blocks,
                   int n, double* H, int ldh, double* Q, int ldq, double* wr, double* wi,
                   bool time) {
   const int cnt = (int)blocks.size();
-  if (cnt == 0) return;
+  if (cnt == 0) return true;
   const size_t slot = (size_t)UPAD * UPAD;
   grow(h->b_splq, sizeof(double) * slot * cnt, false);
   grow(h->b_splu, sizeof(double) * slot * cnt, false);
@@ -1531,6 +1540,7 @@ void batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<
   HCHECK(hipGetLastError());
   BatchEngine b;
   b.init(h, s, cnt);
+  b.defer_small = true;
   for (int i = 0; i < cnt; ++i) {
     const int lo = blocks[i].first;
     b.add(i, sz[i], H + lo + (size_t)lo * ldh, ldh, zq + (size_t)i * slot, UPAD, wr + lo, wi + lo,
@@ -1542,6 +1552,8 @@ void batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<
     if (++guard > (int64_t)4 * 1000 * 1000) throw HipErr{hipErrorUnknown};
   }
   b.settle();
+  bool ok = true;
+  for (int i = 0; i < cnt; ++i) ok = ok && b.M[i].info == 0;
   launch_slot_transpose(zq, ut, cnt, s);
   HCHECK(hipGetLastError());
   grow(h->b_splw, sizeof(WinB) * cnt, true);
@@ -1577,6 +1589,7 @@ void batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<
   h->stats.launches += 2 + (tr > 0) + (tcq > 0);
   // the staging buffers are rewritten by the next call: wait for the copies
   HCHECK(hipStreamSynchronize(s));
+  return ok;
 }
 
 int solve_batched(schur_handle_s* h, hipStream_t s, int count, const int* n, double* const* H,
