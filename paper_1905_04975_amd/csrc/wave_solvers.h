@@ -124,6 +124,124 @@ __device__ void chase_reg(double* S, double* Zs, int m_in, int l_in, int i_in, d
   __syncthreads();
 }
 
+// The same chase for 64 < m <= 128: lane q owns columns q and q + 64 in the
+// left updates and rows q and q + 64 (of S and of Z) in the right updates;
+// the bulge column comes from the slot of the lanes that computed it.
+template <int MAXM>
+__device__ void chase_reg2(double* S, double* Zs, int m_in, int l_in, int i_in, double x,
+                           double y, double z) {
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  const int m = __builtin_amdgcn_readfirstlane(m_in);
+  const int l = __builtin_amdgcn_readfirstlane(l_in);
+  const int i = __builtin_amdgcn_readfirstlane(i_in);
+  const int q = threadIdx.x;        // slot 0: q < 64 < m
+  const int qb = q + 64;            // slot 1
+  const bool inb = qb < m;
+  const int qbc = inb ? qb : m - 1;   // clamped: every lane issues valid loads
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
+  // value of row `row` of the last right update, from the lane that owns it
+  auto bulge = [&](double o0, double o1, int row) -> double {
+    return (row < 64) ? lane_read(o0, row) : lane_read(o1, row - 64);
+  };
+  double cA0 = Sx(l, q), cB0 = Sx(l + 1, q), cC0 = Sx(l + 2, q);
+  double cA1 = Sx(l, qbc), cB1 = Sx(l + 1, qbc), cC1 = Sx(l + 2, qbc);
+  double zA0 = Zx(q, l), zB0 = Zx(q, l + 1), zC0 = Zx(q, l + 2);
+  double zA1 = Zx(qbc, l), zB1 = Zx(qbc, l + 1), zC1 = Zx(qbc, l + 2);
+  double o0 = 0.0, o1 = 0.0;   // S(q, r-1), S(q+64, r-1) from the last right update
+  wave_sync();
+  for (int r = l; r <= i - 1; ++r) {
+    const bool three = r <= i - 2;
+    const int r2 = three ? r + 2 : r + 1;
+    if (r > l) {
+      x = bulge(o0, o1, r);
+      y = bulge(o0, o1, r + 1);
+      z = three ? bulge(o0, o1, r + 2) : 0.0;
+    }
+    const Refl h = make_reflector_fast(three ? 3 : 2, x, y, z);
+    const double tv2 = h.tau * h.v2, tv3 = h.tau * h.v3;
+
+    // ---- left update: rows r..r+2, columns q and q+64 (from r on)
+    const double a30 = three ? cC0 : 0.0, a31 = three ? cC1 : 0.0;
+    const double wl0 = cA0 + h.v2 * cB0 + h.v3 * a30;
+    const double wl1 = cA1 + h.v2 * cB1 + h.v3 * a31;
+    const double n20 = cB0 - tv2 * wl0, n30 = a30 - tv3 * wl0;
+    const double n21 = cB1 - tv2 * wl1, n31 = a31 - tv3 * wl1;
+    if (q >= r) {
+      Sx(r, q) = cA0 - h.tau * wl0;
+      Sx(r + 1, q) = n20;
+      if (three) Sx(r + 2, q) = n30;
+    }
+    if (inb && qb >= r) {
+      Sx(r, qb) = cA1 - h.tau * wl1;
+      Sx(r + 1, qb) = n21;
+      if (three) Sx(r + 2, qb) = n31;
+    }
+    if (r > l && q == 0) {   // the bulge column: beta above two zeros
+      Sx(r, r - 1) = h.beta;
+      Sx(r + 1, r - 1) = 0.0;
+      if (three) Sx(r + 2, r - 1) = 0.0;
+    }
+    wave_sync();   // the left stores precede the right update's loads
+
+    // ---- right update: columns r..r+2 of rows q, q+64 (up to min(r+3, i)),
+    // and of rows q, q+64 of Z
+    const int rlast = (r + 3 < i) ? r + 3 : i;
+    const double s10 = Sx(q, r), s20 = Sx(q, r + 1), t30 = Sx(q, r2);
+    const double s11 = Sx(qbc, r), s21 = Sx(qbc, r + 1), t31 = Sx(qbc, r2);
+    const double s30 = three ? t30 : 0.0, s31 = three ? t31 : 0.0;
+    const double z30 = three ? zC0 : 0.0, z31 = three ? zC1 : 0.0;
+    const double wr0 = s10 + h.v2 * s20 + h.v3 * s30;
+    const double wr1 = s11 + h.v2 * s21 + h.v3 * s31;
+    const double wz0 = zA0 + h.v2 * zB0 + h.v3 * z30;
+    const double wz1 = zA1 + h.v2 * zB1 + h.v3 * z31;
+    const double e10 = s10 - h.tau * wr0, e11 = s11 - h.tau * wr1;
+    if (q <= rlast) {
+      Sx(q, r) = e10;
+      Sx(q, r + 1) = s20 - tv2 * wr0;
+      if (three) Sx(q, r + 2) = s30 - tv3 * wr0;
+    }
+    if (inb && qb <= rlast) {
+      Sx(qb, r) = e11;
+      Sx(qb, r + 1) = s21 - tv2 * wr1;
+      if (three) Sx(qb, r + 2) = s31 - tv3 * wr1;
+    }
+    o0 = e10;
+    o1 = e11;
+    const double f20 = zB0 - tv2 * wz0, f30 = z30 - tv3 * wz0;
+    const double f21 = zB1 - tv2 * wz1, f31 = z31 - tv3 * wz1;
+    Zx(q, r) = zA0 - h.tau * wz0;
+    Zx(q, r + 1) = f20;
+    if (three) Zx(q, r + 2) = f30;
+    if (inb) {
+      Zx(qb, r) = zA1 - h.tau * wz1;
+      Zx(qb, r + 1) = f21;
+      if (three) Zx(qb, r + 2) = f31;
+    }
+    zA0 = f20;
+    zB0 = f30;
+    zA1 = f21;
+    zB1 = f31;
+    wave_sync();   // this position's stores precede the loads below
+    // operands of position r+1 (indices clamped to the block); columns right
+    // of the next bulge keep this left update's results from the registers
+    const int r3 = (r + 3 < m - 1) ? r + 3 : m - 1;
+    const int rb = (r + 2 < m - 1) ? r + 2 : m - 1;
+    const double lA0 = Sx(r + 1, q), lB0 = Sx(rb, q);
+    const double lA1 = Sx(r + 1, qbc), lB1 = Sx(rb, qbc);
+    cC0 = Sx(r3, q);
+    cC1 = Sx(r3, qbc);
+    zC0 = Zx(q, r3);
+    zC1 = Zx(qbc, r3);
+    const bool far0 = q >= r + 3, far1 = qb >= r + 3;
+    cA0 = far0 ? n20 : lA0;
+    cB0 = far0 ? n30 : lB0;
+    cA1 = far1 ? n21 : lA1;
+    cB1 = far1 ? n31 : lB1;
+  }
+  __syncthreads();
+}
+
 // Francis double-shift iteration on the m x m block already in LDS (S, and Z
 // when WANTZ), one wavefront.  Writes T.wr / T.wi of converged blocks when
 // given; returns 0 or the 1-based end of a block that did not converge.
@@ -237,6 +355,10 @@ __device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
     __syncthreads();   // every lane has read the corner before the first left update
     if (WANTZ && m <= 64) {
       chase_reg<MAXM>(S, Zs, m, l, i, x, y, z);
+      continue;
+    }
+    if (WANTZ && MAXM > 64 && m <= 128) {
+      chase_reg2<MAXM>(S, Zs, m, l, i, x, y, z);
       continue;
     }
     for (int r = l; r <= i - 1; ++r) {

@@ -236,7 +236,8 @@ def test_aed_window(driver, tmp_path, case):
 
 @pytest.mark.parametrize("m,seed,kind", [(5, 1, "normal"), (33, 2, "normal"), (64, 3, "normal"),
                                          (96, 4, "normal"), (40, 5, "prescribed"),
-                                         (60, 6, "graded")])
+                                         (60, 6, "graded"), (65, 7, "normal"),
+                                         (80, 8, "prescribed"), (90, 9, "graded")])
 def test_small_block_solver(driver, tmp_path, m, seed, kind):
     """The single-wavefront Francis solver with Z: a standardised real Schur
     form, H = Z S Z^T, and the eigenvalues of the oracle."""
