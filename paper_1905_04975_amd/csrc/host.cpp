@@ -132,6 +132,9 @@ struct schur_handle_s {
   Grow b_splq, b_splb;   // batched finish: per-block Z slots, block orders
   // nested solve of a trailing block larger than SMALL_EIG_MAX (shifts only)
   schur_handle_s* sub = nullptr;
+  // buffers of the parallel early-deflation passes that the batched engine
+  // runs on its large matrices (kept apart from the engine's own)
+  schur_handle_s* side = nullptr;
   double* shm = nullptr;         // NS_MAX x NS_MAX copy of the trailing block
 };
 
@@ -728,6 +731,7 @@ struct Solver {
     std::vector<double> best;
     int64_t prev_active = -1;
     int prev_max = -1;
+    int interior = 0;   // committed windows with blocks both above and below
     for (int pass = 0; pass < kSplitMaxPasses; ++pass) {
       launch_split_scan(H, ldh, n, zd, s);
       HCHECK(hipGetLastError());
@@ -895,7 +899,15 @@ struct Solver {
       }
       std::sort(pick.begin(), pick.end(), [&](int x, int y) { return wins[x].a < wins[y].a; });
       const int ncm = (int)pick.size();
-      if (ncm == 0) continue;
+      for (int j : pick) interior += (wins[j].top && wins[j].below) ? 1 : 0;
+      // no window split inside a block in the first two passes (both
+      // offsets): the eigenvectors are not localised, the sweeps are the
+      // better tool (windows at the block ends are still committed)
+      const bool give_up = pass == 1 && interior == 0;
+      if (ncm == 0) {
+        if (give_up) return false;
+        continue;
+      }
       grow(h->b_splb, sizeof(SplitCommit) * ncm, true);
       SplitCommit* ch = (SplitCommit*)h->b_splb.host;
       for (int j = 0; j < ncm; ++j) {
@@ -946,6 +958,7 @@ struct Solver {
         h->stats.gemm_launches += 1;
         h->stats.launches += 1;
       }
+      if (give_up) return false;
     }
     return false;
   }
@@ -1116,6 +1129,9 @@ struct BatchEngine {
   // they are solved by one launch (for blocks of one matrix that must all
   // finish before anything else runs)
   bool defer_small = false;
+  // run the parallel early-deflation passes on large matrices (off for the
+  // engine that finishes the blocks those passes leave)
+  bool allow_split = true;
 
   template <class T>
   T* dev_of(schur_handle_s::Grow& g) { return (T*)g.dev; }
@@ -1188,7 +1204,25 @@ struct BatchEngine {
       m.checked = true;
       if (ctrl_h[i].bad) { m.info = -2; m.active = false; continue; }
       launch_zero_lower(m.H, m.ldh, m.n, s);
+      if (allow_split && m.P.split_nw > 0 && m.n >= m.P.split_min_n) split_passes(m);
     }
+  }
+
+  // the parallel early-deflation passes of a single solve on one large
+  // matrix (on a side handle's buffers), before its rounds start
+  void split_passes(Mat& m) {
+    if (!h->side) {
+      schur_handle_s* side = nullptr;
+      if (create_handle(&side, h->device, &h->opts) != 0) throw HipErr{hipErrorOutOfMemory};
+      h->side = side;
+    }
+    Solver sv{h->side, s, m.P, m.n, m.H, m.ldh, m.Q, m.ldq, m.wr, m.wi};
+    sv.P.time = false;
+    sv.split_phase();
+    h->stats.split_passes += h->side->stats.split_passes;
+    h->stats.split_windows += h->side->stats.split_windows;
+    h->stats.split_accepted += h->side->stats.split_accepted;
+    std::memset(&h->side->stats, 0, sizeof(h->side->stats));
   }
 
   // One round.  Afterwards, matrices with used && !active are finished
@@ -1541,6 +1575,7 @@ bool batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<
   BatchEngine b;
   b.init(h, s, cnt);
   b.defer_small = true;
+  b.allow_split = false;
   for (int i = 0; i < cnt; ++i) {
     const int lo = blocks[i].first;
     b.add(i, sz[i], H + lo + (size_t)lo * ldh, ldh, zq + (size_t)i * slot, UPAD, wr + lo, wi + lo,
@@ -1869,6 +1904,7 @@ int schur_destroy(schur_handle_t h) {
   }
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->sub) (void)schur_destroy(h->sub);
+  if (h->side) (void)schur_destroy(h->side);
   if (h->shm) (void)hipFree(h->shm);
   free_ws(h);
   delete h;

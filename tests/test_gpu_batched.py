@@ -129,3 +129,33 @@ def test_batched_slow_block_converges(gpu_lib):
     assert checks.structure_errors(S, w.real, w.imag) == []
     assert checks.residual(H, Q, S) <= 1e-12
     assert checks.orthogonality(Q) <= 1e-12
+
+
+def test_batched_large_members_use_passes(gpu_lib):
+    """Members from order 256 on (forced; 2048 by default) start with the
+    parallel early-deflation passes on a side handle, then join the rounds;
+    every member meets the bar and its spectrum matches its solo solve."""
+    import torch
+
+    sizes = [300, 40, 520, 97, 700, 260]
+    mats = [inputs.hessenberg_normal(n, 42000 + i) for i, n in enumerate(sizes)]
+    mats[5] = inputs.prescribed(260, 42005)[0]
+    print("case batched with passes, orders %s" % sizes, flush=True)
+    h = gpu_lib.Handle(0, split_min_n=256)
+    Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(H) for H in mats], handle=h)
+    torch.cuda.synchronize()
+    st = h.stats()
+    assert rc == 0 and all(i == 0 for i in infos), infos
+    assert st["split_passes"] > 0 and st["split_accepted"] > 0
+    h.close()
+    for H, S, Q, w in zip(mats, Ss, Qs, ws):
+        S, Q, w = S.cpu().numpy(), Q.cpu().numpy(), w.cpu().numpy()
+        n = H.shape[0]
+        assert checks.structure_errors(S, w.real, w.imag) == [], n
+        assert checks.residual(H, Q, S) <= 1e-12, n
+        assert checks.orthogonality(Q) <= 1e-12, n
+        wref, kappa = checks.eig_condition(H)
+        from scipy.optimize import linear_sum_assignment
+        cost = np.abs(w[:, None] - wref[None, :])
+        r, c = linear_sum_assignment(cost)
+        assert np.all(cost[r, c] <= checks.kappa_tolerance(H, wref[c], kappa[c], factor=100.0)), n

@@ -89,3 +89,27 @@ def test_budget_forces_queueing(gpu_lib):
         S, Q, w, info, lat = res[t]
         _check(H, S, Q, w, info)
     assert res[tbig[0]][3] == -101
+
+
+def test_served_large_requests_use_passes(gpu_lib):
+    """Large requests (here from order 400 on) start with the parallel
+    early-deflation passes inside the engine; a random and a prescribed one
+    among small ones: every result meets the bar and equals the one alone."""
+    sizes = [(700, "normal"), (90, "normal"), (600, "prescribed"), (150, "prescribed"),
+             (520, "normal")]
+    mats = [inputs.hessenberg_normal(n, 51000 + i) if kind == "normal"
+            else inputs.prescribed(n, 51000 + i)[0] for i, (n, kind) in enumerate(sizes)]
+    print("case served large requests with passes", flush=True)
+    srv = gpu_lib.Server(0, split_min_n=400)
+    tickets = [srv.submit(H) for H in mats]
+    res = _wait(srv, tickets)
+    mixed = [res[t] for t, _ in tickets]
+    alone = []
+    for H in mats:
+        t = srv.submit(H)
+        alone.append(_wait(srv, [t])[t[0]])
+    srv.close()
+    for H, (S, Q, w, info, lat), (S1, Q1, w1, info1, lat1) in zip(mats, mixed, alone):
+        _check(H, S, Q, w, info)
+        _check(H, S1, Q1, w1, info1)
+        assert checks.match_eigs(w, w1).max() <= 1e-10 * np.linalg.norm(H)
