@@ -1966,6 +1966,9 @@ int schur_server_create(schur_server_t* out, int device, size_t hbm_budget_bytes
     HCHECK(hipSetDevice(device));
     if (alloc_ws(S->h, 2) != 0) throw HipErr{hipErrorOutOfMemory};
     S->eng.init(S->h, S->h->stream, S->slots);
+    // the passes run on the host thread that drives the rounds: they would
+    // stall every other resident request for their duration
+    S->eng.allow_split = false;
     S->resident.assign(S->slots, nullptr);
     HCHECK(hipStreamSynchronize(S->h->stream));
   } catch (const HipErr&) {

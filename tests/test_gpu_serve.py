@@ -91,15 +91,16 @@ def test_budget_forces_queueing(gpu_lib):
     assert res[tbig[0]][3] == -101
 
 
-def test_served_large_requests_use_passes(gpu_lib):
-    """Large requests (here from order 400 on) start with the parallel
-    early-deflation passes inside the engine; a random and a prescribed one
-    among small ones: every result meets the bar and equals the one alone."""
+def test_served_large_requests_equal_alone(gpu_lib):
+    """Larger requests, random and prescribed, among small ones (with the
+    parallel-pass threshold lowered: the server still runs no passes, so the
+    option must not change its results): every result meets the bar and
+    equals the one alone."""
     sizes = [(700, "normal"), (90, "normal"), (600, "prescribed"), (150, "prescribed"),
              (520, "normal")]
     mats = [inputs.hessenberg_normal(n, 51000 + i) if kind == "normal"
             else inputs.prescribed(n, 51000 + i)[0] for i, (n, kind) in enumerate(sizes)]
-    print("case served large requests with passes", flush=True)
+    print("case served larger requests", flush=True)
     srv = gpu_lib.Server(0, split_min_n=400)
     tickets = [srv.submit(H) for H in mats]
     res = _wait(srv, tickets)
