@@ -78,3 +78,35 @@ def test_split_passes_without_q(gpu_lib):
     S1, _, w1, info1, st1 = _run(gpu_lib, H, want_q=False, split_min_n=64)
     assert info1 == 0 and st1["split_accepted"] == st["split_accepted"]
     assert np.array_equal(S1, S) and np.array_equal(w1, w)
+
+
+def test_split_passes_edge_blocks(gpu_lib):
+    """Blocks of orders 1, 2, 3, 15, 17, 96, 97, 128, 129, 200 and 700
+    (zero subdiagonal entries between them) with the passes forced: short top
+    windows merged, blocks finished whole by one window, blocks of order
+    <= 128 finished in batch, the rest by passes; the result meets the bar."""
+    print("case split passes edge blocks", flush=True)
+    orders = [1, 2, 3, 15, 17, 96, 97, 128, 129, 200, 700]
+    n = sum(orders)
+    H = inputs.hessenberg_normal(n, 65)
+    cut = np.cumsum(orders)[:-1]
+    H[cut, cut - 1] = 0.0
+    S, Q, w, info, st = _run(gpu_lib, H, split_min_n=64)
+    _check_schur(H, S, Q, w, info)
+    assert st["split_passes"] >= 1
+    _kappa_match(H, w)
+
+
+def test_split_passes_triangular_and_tiny(gpu_lib):
+    """Upper triangular input (every block of order 1) and a matrix of
+    order 3 with the passes forced: nothing to split, S = H, Q = I."""
+    print("case split passes triangular", flush=True)
+    n = 300
+    H = np.triu(inputs.hessenberg_normal(n, 66))
+    S, Q, w, info, st = _run(gpu_lib, H, split_min_n=2)
+    assert info == 0
+    assert np.array_equal(S, H) and np.array_equal(Q, np.eye(n))
+    assert np.array_equal(w.real, np.diag(H)) and not w.imag.any()
+    H3 = inputs.hessenberg_normal(3, 67)
+    S3, Q3, w3, info3, st3 = _run(gpu_lib, H3, split_min_n=2)
+    _check_schur(H3, S3, Q3, w3, info3)
