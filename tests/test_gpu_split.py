@@ -19,14 +19,15 @@ from tests.test_gpu_parity import _check_schur, _kappa_match, _run
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("n,seed,nw", [(1500, 61, 0), (700, 62, 80), (1201, 63, 96)])
+@pytest.mark.parametrize("n,seed,nw", [(1500, 61, 0), (700, 62, 80), (1201, 63, 96),
+                                       (800, 68, 50), (500, 69, 33)])
 def test_split_passes_random(gpu_lib, n, seed, nw):
     print("case split passes n=%d seed=%d nw=%d" % (n, seed, nw), flush=True)
     H = inputs.hessenberg_normal(n, seed)
     S, Q, w, info, st = _run(gpu_lib, H, split_min_n=64, split_window=nw)
     _check_schur(H, S, Q, w, info)
     assert st["split_passes"] > 0 and st["split_windows"] > 0
-    if nw != 80:   # 80-row windows may find no split here, then the sweeps finish
+    if nw in (0, 96):   # smaller windows may find no split here, then the sweeps finish
         assert st["split_accepted"] > 0 and st["split_converged"] > 0
     _kappa_match(H, w)
     S0, Q0, w0, info0, st0 = _run(gpu_lib, H, split_window=-1)
