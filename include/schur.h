@@ -196,6 +196,28 @@ int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, c
 int schur_plan_sweep(int ktop, int kbot, int npair, int nb, int step, int* out, int cap);
 
 /* --------------------------------------------------------------------------
+ * Window tiling of the parallel early-deflation passes (host-only
+ * diagnostic of the solver's own code, no device work; the passes apply the
+ * early-deflation step of paper Sec. 3.2 to windows inside the matrix): the
+ * windows laid over the unreduced block [lo, hi] (0-based) with a bottom
+ * window of `first` rows (1 <= first <= nw) and the others of nw rows; a top
+ * window shorter than 16 rows and the one below it become two halves.
+ * Writes up to `cap` (start, order) pairs, top to bottom, to `out`; returns
+ * the number of windows (which may exceed cap) or -1 on bad arguments.
+ * ------------------------------------------------------------------------ */
+int schur_plan_split(int lo, int hi, int nw, int first, int* out, int cap);
+
+/* --------------------------------------------------------------------------
+ * Window selection of a pass (host-only diagnostic of the solver's own
+ * code): among `count` candidate windows of one block (start a[i], order
+ * w[i] >= 1, weight wt[i] > 0; host arrays) the disjoint set of largest total
+ * weight.  Writes the chosen indices in increasing start order to `picked`
+ * (room for `count` entries); returns how many were chosen, or -1 on bad
+ * arguments.
+ * ------------------------------------------------------------------------ */
+int schur_select_windows(int count, const int* a, const int* w, const double* wt, int* picked);
+
+/* --------------------------------------------------------------------------
  * Serving loop (continuous batching).  A server owns a device handle and a
  * background thread.  Requests (HOST matrices) queue FIFO; between rounds of
  * the batched engine (one sweep per resident matrix per round) the thread

@@ -375,6 +375,61 @@ void plan_sweep(int ktop, int kbot, int npair, int nbmax, int step_opt,
   }
 }
 
+// ---- parallel early deflation: window tiling and selection (host) ---------
+// Windows over the unreduced block [lo, hi], bottom-aligned: the bottom one
+// has `first` rows (at most nw), the others nw, the top one what is left; a
+// top window shorter than 16 rows and the one below it become two halves.
+// Writes (start, order) pairs bottom to top.
+void split_tile(int lo, int hi, int first, int nw, std::vector<std::pair<int, int>>& ws) {
+  ws.clear();
+  for (int b = hi + 1; b > lo;) {
+    const int a = std::max(lo, b - (ws.empty() ? first : nw));
+    ws.push_back({a, b - a});
+    b = a;
+  }
+  if (ws.size() >= 2 && ws.back().second < 16) {
+    const int tot = ws.back().second + ws[ws.size() - 2].second;
+    const int top = ws.back().first;
+    ws.pop_back();
+    ws.pop_back();
+    ws.push_back({top + tot / 2, tot - tot / 2});
+    ws.push_back({top, tot / 2});
+  }
+}
+
+// Among candidate windows (start a[c], order w[c], weight wt[c]) of one
+// block, the disjoint set of largest total weight (weighted interval
+// scheduling over the window ends).  Appends the chosen indices of `cand`.
+void split_select(const std::vector<int>& cand, const int* a, const int* w, const double* wt,
+                  std::vector<int>& pick) {
+  std::vector<int> order(cand);
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return a[x] + w[x] < a[y] + w[y]; });
+  const int k = (int)order.size();
+  std::vector<double> best(k + 1, 0.0);
+  std::vector<int> prev(k + 1, -1);
+  for (int j = 1; j <= k; ++j) {
+    const int c = order[j - 1];
+    int p = j - 1;   // windows ending at or above this one's start
+    while (p > 0 && a[order[p - 1]] + w[order[p - 1]] > a[c]) --p;
+    const double take = best[p] + wt[c];
+    if (take > best[j - 1]) {
+      best[j] = take;
+      prev[j] = p;
+    } else {
+      best[j] = best[j - 1];
+      prev[j] = -1;   // not taken
+    }
+  }
+  for (int j = k; j > 0;) {
+    if (prev[j] >= 0) {
+      pick.push_back(order[j - 1]);
+      j = prev[j];
+    } else {
+      --j;
+    }
+  }
+}
+
 int create_handle(schur_handle_s** out, int device, const schur_opts* opts);
 bool batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<int, int>>& blocks,
                   int n, double* H, int ldh, double* Q, int ldq, double* wr, double* wi,
@@ -727,8 +782,7 @@ struct Solver {
     struct Wn { int a, nw, top, below; };
     std::vector<Wn> wins;
     std::vector<std::pair<int, int>> regs, ws;
-    std::vector<int> order, best_prev, pick;
-    std::vector<double> best;
+    std::vector<int> order, pick;
     int64_t prev_active = -1;
     int prev_max = -1;
     int interior = 0;   // committed windows with blocks both above and below
@@ -769,23 +823,7 @@ struct Solver {
       // ---- candidate windows: per block, tiling 0 (bottom window of nw or
       // nw / 2 rows, alternating between passes) for every block, tiling 1
       // (the other offset) for the largest blocks while the launch fits
-      auto tile = [&](int lo, int hi, int first) {
-        ws.clear();   // (start, order), bottom to top
-        for (int b = hi + 1; b > lo;) {
-          const int a = std::max(lo, b - (ws.empty() ? first : nw));
-          ws.push_back({a, b - a});
-          b = a;
-        }
-        if (ws.size() >= 2 && ws.back().second < 16) {
-          // a short top window and the one below it become two halves
-          const int tot = ws.back().second + ws[ws.size() - 2].second;
-          const int top = ws.back().first;
-          ws.pop_back();
-          ws.pop_back();
-          ws.push_back({top + tot / 2, tot - tot / 2});
-          ws.push_back({top, tot / 2});
-        }
-      };
+      auto tile = [&](int lo, int hi, int first) { split_tile(lo, hi, first, nw, ws); };
       const int f0 = (pass & 1) ? nw / 2 : nw, f1 = (pass & 1) ? nw : nw / 2;
       std::vector<int> tilings(regs.size(), 1);
       int total = 0;
@@ -861,41 +899,20 @@ struct Solver {
       // ---- per block: disjoint splitting windows of most weight (1 + rows
       // deflated), by weighted interval scheduling over the window ends
       pick.clear();
+      std::vector<int> ca(cnt), cw(cnt);
+      std::vector<double> cwt(cnt);
+      for (int c = 0; c < cnt; ++c) {
+        ca[c] = wins[c].a;
+        cw[c] = wins[c].nw;
+        cwt[c] = 1.0 + rh[c].nf;
+        h->stats.split_flops += aed_work(wins[c].nw, rh[c].split ? rh[c].nu : 0) +
+                                (10.0 / 3.0) * rh[c].nb * (double)rh[c].nb * rh[c].nb;
+      }
       for (size_t i = 0; i < regs.size(); ++i) {
-        const int c0 = span[i].first, c1 = span[i].second;
         order.clear();
-        for (int c = c0; c < c1; ++c) {
-          h->stats.split_flops += aed_work(wins[c].nw, rh[c].split ? rh[c].nu : 0) +
-                                  (10.0 / 3.0) * rh[c].nb * (double)rh[c].nb * rh[c].nb;
+        for (int c = span[i].first; c < span[i].second; ++c)
           if (rh[c].split) order.push_back(c);
-        }
-        std::sort(order.begin(), order.end(), [&](int x, int y) {
-          return wins[x].a + wins[x].nw < wins[y].a + wins[y].nw;
-        });
-        const int k = (int)order.size();
-        best.assign(k + 1, 0.0);
-        best_prev.assign(k + 1, 0);
-        for (int j = 1; j <= k; ++j) {
-          const Wn& w = wins[order[j - 1]];
-          int p = j - 1;   // windows ending at or above this one's start
-          while (p > 0 && wins[order[p - 1]].a + wins[order[p - 1]].nw > w.a) --p;
-          const double take = best[p] + 1.0 + rh[order[j - 1]].nf;
-          if (take > best[j - 1]) {
-            best[j] = take;
-            best_prev[j] = p;
-          } else {
-            best[j] = best[j - 1];
-            best_prev[j] = -1;   // not taken
-          }
-        }
-        for (int j = k; j > 0;) {
-          if (best_prev[j] >= 0) {
-            pick.push_back(order[j - 1]);
-            j = best_prev[j];
-          } else {
-            --j;
-          }
-        }
+        split_select(order, ca.data(), cw.data(), cwt.data(), pick);
       }
       std::sort(pick.begin(), pick.end(), [&](int x, int y) { return wins[x].a < wins[y].a; });
       const int ncm = (int)pick.size();
@@ -2094,6 +2111,32 @@ int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, c
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.swap(t);
   return 0;
+}
+
+int schur_plan_split(int lo, int hi, int nw, int first, int* out, int cap) {
+  if (lo < 0 || hi < lo || nw < 1 || nw > SMALL_Z_MAX || first < 1 || first > nw || cap < 0 ||
+      (cap > 0 && !out))
+    return -1;
+  std::vector<std::pair<int, int>> ws;
+  split_tile(lo, hi, first, nw, ws);
+  const int k = (int)ws.size();
+  for (int j = 0; j < k && j < cap; ++j) {   // top to bottom
+    out[2 * j] = ws[k - 1 - j].first;
+    out[2 * j + 1] = ws[k - 1 - j].second;
+  }
+  return k;
+}
+
+int schur_select_windows(int count, const int* a, const int* w, const double* wt, int* picked) {
+  if (count < 0 || (count > 0 && (!a || !w || !wt || !picked))) return -1;
+  for (int i = 0; i < count; ++i)
+    if (a[i] < 0 || w[i] < 1 || !(wt[i] > 0.0)) return -1;
+  std::vector<int> cand(count), pick;
+  for (int i = 0; i < count; ++i) cand[i] = i;
+  split_select(cand, a, w, wt, pick);
+  std::sort(pick.begin(), pick.end(), [&](int x, int y) { return a[x] < a[y]; });
+  for (size_t j = 0; j < pick.size(); ++j) picked[j] = pick[j];
+  return (int)pick.size();
 }
 
 int schur_plan_sweep(int ktop, int kbot, int npair, int nb, int step, int* out, int cap) {

@@ -56,7 +56,8 @@ FLAG_TIME_KERNELS = 1
 EXPORTS = ("schur_reduce", "schur_create", "schur_destroy", "schur_set_opts",
            "schur_get_stats", "schur_reduce_async", "schur_reduce_batched",
            "schur_server_create", "schur_server_destroy", "schur_submit", "schur_poll",
-           "schur_server_get_stats", "schur_set_tuning", "schur_plan_sweep")
+           "schur_server_get_stats", "schur_set_tuning", "schur_plan_sweep",
+           "schur_plan_split", "schur_select_windows")
 
 TUNING_PATH = os.path.join(HERE, "tuning.json")
 
@@ -122,6 +123,10 @@ def load():
     lib.schur_set_tuning.restype = ctypes.c_int
     lib.schur_plan_sweep.argtypes = [ip, ip, ip, ip, ip, pi, ip]
     lib.schur_plan_sweep.restype = ctypes.c_int
+    lib.schur_plan_split.argtypes = [ip, ip, ip, ip, pi, ip]
+    lib.schur_plan_split.restype = ctypes.c_int
+    lib.schur_select_windows.argtypes = [ip, pi, pi, ctypes.POINTER(ctypes.c_double), pi]
+    lib.schur_select_windows.restype = ctypes.c_int
     _lib = lib
     path = os.environ.get("SCHUR_TUNE_TABLE", TUNING_PATH)
     if os.path.exists(path):
@@ -374,3 +379,29 @@ def plan_sweep(ktop, kbot, npair, nb, step=0):
     buf = (ctypes.c_int * (7 * max(k, 1)))()
     lib.schur_plan_sweep(int(ktop), int(kbot), int(npair), int(nb), int(step), buf, k)
     return [tuple(buf[7 * i:7 * i + 7]) for i in range(k)]
+
+
+def plan_split(lo, hi, nw, first):
+    """Host-only window tiling of a parallel early-deflation pass over the
+    block [lo, hi]: list of (start, order), top to bottom."""
+    lib = load()
+    k = lib.schur_plan_split(int(lo), int(hi), int(nw), int(first), None, 0)
+    if k < 0:
+        raise ValueError("bad tiling arguments")
+    buf = (ctypes.c_int * (2 * max(k, 1)))()
+    lib.schur_plan_split(int(lo), int(hi), int(nw), int(first), buf, k)
+    return [(buf[2 * i], buf[2 * i + 1]) for i in range(k)]
+
+
+def select_windows(starts, orders, weights):
+    """Host-only window selection of a pass: indices of the disjoint
+    candidate windows of largest total weight, in increasing start order."""
+    lib = load()
+    c = len(starts)
+    IA = ctypes.c_int * max(c, 1)
+    DA = ctypes.c_double * max(c, 1)
+    out = IA()
+    k = lib.schur_select_windows(c, IA(*starts), IA(*orders), DA(*weights), out)
+    if k < 0:
+        raise ValueError("bad selection arguments")
+    return [out[i] for i in range(k)]

@@ -170,3 +170,67 @@ def test_tuning_table_roundtrip():
     with pytest.raises(ValueError):   # nmax must ascend
         schur.set_tuning(rows[::-1])
     schur.set_tuning([])   # built-in table back
+
+
+# ---- parallel early deflation: window tiling and selection (host code the
+# solver uses, exported as diagnostics) ----
+
+@pytest.mark.parametrize("lo,hi,nw,first", [
+    (0, 299, 96, 96), (0, 299, 96, 48), (10, 120, 96, 48), (5, 5, 96, 96), (0, 2, 96, 48),
+    (3, 98, 96, 96), (0, 96, 96, 96), (0, 111, 96, 96), (7, 16000, 96, 48), (0, 700, 80, 40),
+    (0, 333, 33, 16), (0, 1000, 3, 1), (100, 100 + 96 + 15, 96, 96), (0, 127, 96, 48)])
+def test_split_tiling(lo, hi, nw, first):
+    ws = schur.plan_split(lo, hi, nw, first)
+    m = hi - lo + 1
+    assert ws[0][0] == lo and ws[-1][0] + ws[-1][1] == hi + 1
+    for (a0, w0), (a1, w1) in zip(ws, ws[1:]):
+        assert a0 + w0 == a1                      # contiguous, top to bottom
+    assert all(1 <= w <= nw for _, w in ws)
+    if m <= first:
+        assert ws == [(lo, m)]                    # one window: the whole block
+    elif len(ws) >= 3:
+        assert ws[-1][1] == first                 # bottom window as asked
+        assert all(w == nw for _, w in ws[2:-1])  # full windows in between
+    if len(ws) >= 2:
+        assert ws[0][1] >= min(16, (ws[0][1] + ws[1][1]) // 2)   # no short top window
+
+
+def test_split_tiling_bad_arguments():
+    for args in [(-1, 10, 96, 96), (10, 5, 96, 96), (0, 10, 0, 1), (0, 10, 97, 96),
+                 (0, 10, 96, 0), (0, 10, 48, 96)]:
+        with pytest.raises(ValueError):
+            schur.plan_split(*args)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_split_selection_is_optimal(seed):
+    """Against brute force over every subset: the chosen windows are
+    disjoint and of largest total weight."""
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(1, 11))
+    a = rng.integers(0, 300, size=k).tolist()
+    w = rng.integers(1, 97, size=k).tolist()
+    wt = (1 + rng.integers(0, 40, size=k)).astype(float).tolist()
+    pick = schur.select_windows(a, w, wt)
+    assert pick == sorted(pick, key=lambda i: a[i]) and len(set(pick)) == len(pick)
+    for x, y in zip(pick, pick[1:]):
+        assert a[x] + w[x] <= a[y]
+    best = 0.0
+    for mask in range(1 << k):
+        idx = [i for i in range(k) if mask >> i & 1]
+        idx.sort(key=lambda i: a[i])
+        if all(a[x] + w[x] <= a[y] for x, y in zip(idx, idx[1:])):
+            best = max(best, sum(wt[i] for i in idx))
+    assert sum(wt[i] for i in pick) == best
+
+
+def test_split_selection_edge_cases():
+    assert schur.select_windows([], [], []) == []
+    assert schur.select_windows([5], [10], [1.0]) == [0]
+    # equal windows: one of them; touching windows: both
+    assert len(schur.select_windows([0, 0], [10, 10], [1.0, 1.0])) == 1
+    assert schur.select_windows([0, 10], [10, 10], [1.0, 1.0]) == [0, 1]
+    with pytest.raises(ValueError):
+        schur.select_windows([0], [0], [1.0])
+    with pytest.raises(ValueError):
+        schur.select_windows([0], [5], [0.0])
