@@ -159,3 +159,23 @@ def test_batched_large_members_use_passes(gpu_lib):
         cost = np.abs(w[:, None] - wref[None, :])
         r, c = linear_sum_assignment(cost)
         assert np.all(cost[r, c] <= checks.kappa_tolerance(H, wref[c], kappa[c], factor=100.0)), n
+
+
+def test_batched_passes_without_q(gpu_lib):
+    """Members with the passes and no Schur vectors: the same S and spectrum
+    as with them (the Q products never feed back into H)."""
+    import torch
+
+    print("case batched with passes, no Q", flush=True)
+    mats = [inputs.hessenberg_normal(n, 43000 + i) for i, n in enumerate((300, 520, 64))]
+    h = gpu_lib.Handle(0, split_min_n=256)
+    Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(H) for H in mats], handle=h)
+    S0, Q0, w0, infos0, rc0 = gpu_lib.reduce_batched([_to_dev(H) for H in mats], want_q=False,
+                                                     handle=h)
+    torch.cuda.synchronize()
+    h.close()
+    assert rc == 0 and rc0 == 0 and Q0 is None
+    for H, S, Q, w, Sn, wn in zip(mats, Ss, Qs, ws, S0, w0):
+        S, Q, w = S.cpu().numpy(), Q.cpu().numpy(), w.cpu().numpy()
+        assert checks.residual(H, Q, S) <= 1e-12 and checks.orthogonality(Q) <= 1e-12
+        assert np.array_equal(Sn.cpu().numpy(), S) and np.array_equal(wn.cpu().numpy(), w)
