@@ -82,7 +82,10 @@ typedef struct schur_opts {
                    /* 0 = by table, < 0 = always sweep                        */
   int split_window; /* parallel early deflation: window order (<= 96) of the   */
                     /* passes that deflate on windows tiling every unreduced   */
-                    /* block at once before the sweeps; 0 = 96, < 0 = off      */
+                    /* block at once before the sweeps (the early-deflation    */
+                    /* step of paper Sec. 3.2 applied to interior windows);    */
+                    /* 0 = 96, < 0 = off.  Single solves and members of        */
+                    /* batched calls use them; the server does not             */
   int split_min_n;  /* smallest order that starts with those passes;          */
                     /* 0 = 2048                                                */
   int reserved[1];
