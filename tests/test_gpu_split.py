@@ -111,3 +111,41 @@ def test_split_passes_triangular_and_tiny(gpu_lib):
     H3 = inputs.hessenberg_normal(3, 67)
     S3, Q3, w3, info3, st3 = _run(gpu_lib, H3, split_min_n=2)
     _check_schur(H3, S3, Q3, w3, info3)
+
+
+def test_split_passes_padded_leading_dimensions(gpu_lib):
+    """H and Q inside larger column-major buffers (ldh = n + 7, ldq = n + 3)
+    with the passes forced: the padding is never touched and the result is
+    the one the unpadded call gives."""
+    import torch
+
+    print("case split passes padded ld", flush=True)
+    n, ph, pq = 900, 7, 3
+    H = inputs.hessenberg_normal(n, 70)
+    dev = torch.device("cuda:0")
+    hb = torch.full((n + ph, n), 7.5, dtype=torch.float64)
+    hb[:n, :] = torch.from_numpy(H)
+    qb = torch.full((n + pq, n), -3.25, dtype=torch.float64)
+    qb[:n, :] = torch.eye(n, dtype=torch.float64)
+    # column-major storage: the (ld x n) buffer is the transpose of a row-major (n x ld) one
+    Hd = hb.t().contiguous().to(dev)
+    Qd = qb.t().contiguous().to(dev)
+    wr = torch.empty(n, dtype=torch.float64, device=dev)
+    wi = torch.empty_like(wr)
+    h = gpu_lib.Handle(0, split_min_n=64)
+    stream = torch.cuda.current_stream(dev)
+    info = h.reduce_async(stream.cuda_stream, n, Hd.data_ptr(), n + ph, Qd.data_ptr(), n + pq,
+                          wr.data_ptr(), wi.data_ptr())
+    torch.cuda.synchronize()
+    st = h.stats()
+    h.close()
+    assert info == 0 and st["split_passes"] > 0
+    hb2 = Hd.cpu().t()
+    qb2 = Qd.cpu().t()
+    assert torch.all(hb2[n:, :] == 7.5) and torch.all(qb2[n:, :] == -3.25)
+    S, Q = hb2[:n, :].numpy(), qb2[:n, :].numpy()
+    w = wr.cpu().numpy() + 1j * wi.cpu().numpy()
+    _check_schur(H, S, Q, w, 0)
+    S1, Q1, w1, info1, st1 = _run(gpu_lib, H, split_min_n=64)
+    assert info1 == 0
+    assert np.array_equal(S1, S) and np.array_equal(Q1, Q) and np.array_equal(w1, w)
