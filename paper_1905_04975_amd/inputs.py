@@ -17,6 +17,16 @@ Recipes (all numpy ``Generator(PCG64(seed))``):
   (``scipy.linalg.hessenberg``).  The ground-truth eigenvalues are returned.
 * ``paper_like(n, seed)`` -- dense entries U(-1, 1) reduced to Hessenberg
   form, the test-matrix recipe of the paper's experiments (Sec. 5).
+* ``paper_like_law(n, seed)`` -- a draw from the distribution of the
+  Householder Hessenberg form of a dense matrix with iid N(0, 1/3) entries
+  (1/3 is the variance of U(-1, 1)), sampled directly in O(n^2): entries on
+  and above the diagonal iid N(0, 1/3), subdiagonal entry (k+1, k) equal to
+  sqrt(chi^2_{n-1-k} / 3).  The law is exact for Gaussian entries (each
+  Householder step maps the column below the diagonal to its norm and
+  leaves the rest iid Gaussian, by orthogonal invariance); for U(-1, 1)
+  entries it matches the first two moments of every entry of the reduced
+  form.  It stands in for ``paper_like`` at orders where the dense CPU
+  reduction takes minutes (n = 16384).
 * ``batch_sizes(count, lo, hi, seed)`` -- matrix orders for batched runs.
 
 All matrices are returned column-major (Fortran order), float64.
@@ -86,6 +96,16 @@ def paper_like(n: int, seed: int) -> np.ndarray:
     return np.asfortranarray(np.triu(sla.hessenberg(a), -1))
 
 
+def paper_like_law(n: int, seed: int) -> np.ndarray:
+    rng = _rng(seed)
+    sd = 1.0 / np.sqrt(3.0)
+    h = np.triu(rng.standard_normal((n, n)), 0) * sd
+    if n > 1:
+        df = np.arange(n - 1, 0, -1, dtype=np.float64)   # n-1, ..., 1
+        h[np.arange(1, n), np.arange(n - 1)] = np.sqrt(rng.chisquare(df) / 3.0)
+    return np.asfortranarray(h)
+
+
 def batch_sizes(count: int, lo: int, hi: int, seed: int) -> np.ndarray:
     rng = _rng(seed)
     return rng.integers(lo, hi + 1, size=count)
@@ -95,6 +115,7 @@ def batch_sizes(count: int, lo: int, hi: int, seed: int) -> np.ndarray:
 SEED_N256 = 1          # N(0,1) Hessenberg, n = 256
 SEED_N1024 = 2         # prescribed spectrum, n = 1024
 SEED_N16384 = 3        # N(0,1) Hessenberg, n = 16384
+SEED_PAPER_LIKE = 6    # dense-derived recipe (paper Sec. 5), n = 16384
 SEED_BATCH_SIZES = 4   # batch of 2000, orders U{32..512}
 SEED_BATCH_BASE = 40000
 SEED_SERVE = 5

@@ -186,6 +186,60 @@ def test_cyclic_permutation_needs_exceptional_shifts():
     assert checks.match_eigs(wr + 1j * wi, exact).max() <= 1e-13
 
 
+def _cyclic(m):
+    C = np.zeros((m, m))
+    C[0, m - 1] = 1.0
+    C[np.arange(1, m), np.arange(m - 1)] = 1.0
+    return C
+
+
+def second_adhoc_step_error(C, lib=None):
+    """Implicit-Q check of the 20th non-deflating step of a block end (the
+    second ad-hoc shift, reading R7: the 2x2 [[e, w], [-0.4375 w, e]] with
+    w = |h(l+1,l)| + |h(l+2,l+1)| and e = h(l,l) + 0.75 w, taken from the
+    top of the unreduced block l..i).  The oracle stopped with an iteration
+    cap of 19 holds the state just before that step, with a cap of 20 the
+    state just after it (same block end).  A Francis step with shift sum s
+    and product t is the orthogonal similarity whose first column on the
+    block is parallel to (B^2 - s B + t I) e_1 (implicit-Q theorem); that
+    column is formed here with numpy.  Returns (| |q . x| - 1 |, block)."""
+    S19, Q19, _, _, i19, _ = oracle.schur(C, itmax=19, lib=lib)
+    S20, Q20, _, _, i20, _ = oracle.schur(C, itmax=20, lib=lib)
+    assert i19 > 0, "the block end converged before its 20th step"
+    if i20 != i19:
+        return np.inf, None
+    i = i19 - 1
+    l = max([k for k in range(1, i + 1) if S19[k, k - 1] == 0.0] + [0])
+    w = abs(S19[l + 1, l]) + abs(S19[l + 2, l + 1])
+    e = S19[l, l] + 0.75 * w
+    s, t = 2.0 * e, e * e + 0.4375 * w * w
+    B = S19[l:i + 1, l:i + 1]
+    x = (B @ B - s * B + t * np.eye(i - l + 1))[:, 0]
+    x /= np.linalg.norm(x)
+    q = (Q19.T @ Q20)[l:i + 1, l]
+    return abs(abs(q @ x) - 1.0), (l, i)
+
+
+@pytest.mark.parametrize("m", [19, 31])
+def test_cyclic_permutation_second_adhoc_shift(m):
+    """Cyclic shifts of order 19 and 31 stagnate past the first ad-hoc shift:
+    a block end reaches its 20th step (the run capped at 19 steps fails), the
+    uncapped run still converges to the m-th roots of unity, and the 20th
+    step is the Francis step of the top-of-block ad-hoc pair."""
+    C = _cyclic(m)
+    _, _, _, _, info19, _ = oracle.schur(C, itmax=19)
+    assert info19 > 0
+    S, Q, wr, wi, info, iters = oracle.schur(C)
+    assert info == 0 and iters >= 20
+    assert checks.structure_errors(S, wr, wi) == []
+    assert checks.residual(C, Q, S) <= 100 * m * U
+    assert checks.orthogonality(Q) <= 100 * m * U
+    exact = np.exp(2j * np.pi * np.arange(m) / m)
+    assert checks.match_eigs(wr + 1j * wi, exact).max() <= 1e-13
+    err, blk = second_adhoc_step_error(C)
+    assert err <= 100 * m * U, (err, blk)
+
+
 def test_upper_triangular_is_fixed_point():
     n = 20
     rng = np.random.default_rng(3)

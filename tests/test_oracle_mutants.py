@@ -14,6 +14,7 @@ import pytest
 import oracle
 from paper_1905_04975_amd import inputs
 from tests import checks
+from tests.test_oracle import _cyclic, second_adhoc_step_error
 
 U = 2.0 ** -53
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle_schur.c")
@@ -31,6 +32,14 @@ MUTANTS = {
     "q_skips_last_reflector": ("if (Q) orc_right(Q, ldq, r, nr, 0, n - 1", "if (Q && nr == 3) orc_right(Q, ldq, r, nr, 0, n - 1"),
     "complex_wi": ("double wi = sqrt(fabs(nb)) * sqrt(fabs(nc));", "double wi = sqrt(fabs(nb)) * sqrt(fabs(nb));"),
     "householder_v3": ("*v3 = z / d;", "*v3 = z / b;"),
+    # the second ad-hoc shift (top of the block, reading R7)
+    "adhoc2_row_index": ("w = fabs(HX(l + 1, l)) + fabs(HX(l + 2, l + 1));",
+                         "w = fabs(HX(l + 1, l)) + fabs(HX(l + 2, l));"),
+    "adhoc2_dropped_term": ("w = fabs(HX(l + 1, l)) + fabs(HX(l + 2, l + 1));",
+                            "w = fabs(HX(l + 1, l));"),
+    "adhoc2_e_sign": ("e = HX(l, l) + 0.75 * w;", "e = HX(l, l) - 0.75 * w;"),
+    "adhoc2_e_diag": ("e = HX(l, l) + 0.75 * w;", "e = HX(l + 1, l + 1) + 0.75 * w;"),
+    "adhoc2_skipped": ("if (its == 10 || its == 20) {", "if (its == 10) {"),
 }
 
 
@@ -78,6 +87,10 @@ def _pins_pass(lib):
             w = np.linalg.eigvals(H)
             if checks.match_eigs(wr + 1j * wi, w).max() > 1e-9 * np.linalg.norm(H):
                 return False
+        # the second ad-hoc shift: implicit-Q check of the 20th step
+        err, _ = second_adhoc_step_error(_cyclic(19), lib=lib)
+        if not err <= 100 * 19 * U:
+            return False
         return True
     except Exception:
         return False
