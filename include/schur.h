@@ -221,6 +221,17 @@ int schur_plan_split(int lo, int hi, int nw, int first, int* out, int cap);
 int schur_select_windows(int count, const int* a, const int* w, const double* wt, int* picked);
 
 /* --------------------------------------------------------------------------
+ * Candidate weight of a window of a pass (host-only diagnostic of the
+ * solver's own code): split = the window passed its tests, nf = rows it
+ * deflated, top / below = 1 when its block continues above / below it.
+ * Returns 1 + nf, or 0 when the window is no candidate: it failed its tests,
+ * or it sits at an end of its block and deflated nothing (it would neither
+ * deflate nor split).  An interior window that deflated nothing still splits
+ * its block (weight 1).
+ * ------------------------------------------------------------------------ */
+double schur_split_weight(int split, int nf, int top, int below);
+
+/* --------------------------------------------------------------------------
  * Serving loop (continuous batching).  A server owns a device handle and a
  * background thread.  Requests (HOST matrices) queue FIFO; between rounds of
  * the batched engine (one sweep per resident matrix per round) the thread

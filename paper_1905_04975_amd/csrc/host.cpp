@@ -430,6 +430,19 @@ void split_select(const std::vector<int>& cand, const int* a, const int* w, cons
   }
 }
 
+// Weight of a window of a pass as a candidate for the selection: 1 + rows
+// deflated for a window that passed its tests, 0 (not a candidate) when it
+// failed them, or when it sits at an end of its block (no coupling above or
+// none below, so its one-sided test cannot fail) and deflated nothing: such
+// a window neither deflates nor splits, and committing it would only cost
+// panel products and rounding.  An interior window that deflated nothing
+// still splits its block between its up- and down-coupled parts.
+double split_weight(int split, int nf, int top, int below) {
+  if (!split) return 0.0;
+  if (nf <= 0 && !(top && below)) return 0.0;
+  return 1.0 + (double)std::max(0, nf);
+}
+
 int create_handle(schur_handle_s** out, int device, const schur_opts* opts);
 bool batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<int, int>>& blocks,
                   int n, double* H, int ldh, double* Q, int ldq, double* wr, double* wi,
@@ -904,14 +917,14 @@ struct Solver {
       for (int c = 0; c < cnt; ++c) {
         ca[c] = wins[c].a;
         cw[c] = wins[c].nw;
-        cwt[c] = 1.0 + rh[c].nf;
+        cwt[c] = split_weight(rh[c].split, rh[c].nf, wins[c].top, wins[c].below);
         h->stats.split_flops += aed_work(wins[c].nw, rh[c].split ? rh[c].nu : 0) +
                                 (10.0 / 3.0) * rh[c].nb * (double)rh[c].nb * rh[c].nb;
       }
       for (size_t i = 0; i < regs.size(); ++i) {
         order.clear();
         for (int c = span[i].first; c < span[i].second; ++c)
-          if (rh[c].split) order.push_back(c);
+          if (cwt[c] > 0.0) order.push_back(c);
         split_select(order, ca.data(), cw.data(), cwt.data(), pick);
       }
       std::sort(pick.begin(), pick.end(), [&](int x, int y) { return wins[x].a < wins[y].a; });
@@ -2137,6 +2150,10 @@ int schur_select_windows(int count, const int* a, const int* w, const double* wt
   std::sort(pick.begin(), pick.end(), [&](int x, int y) { return a[x] < a[y]; });
   for (size_t j = 0; j < pick.size(); ++j) picked[j] = pick[j];
   return (int)pick.size();
+}
+
+double schur_split_weight(int split, int nf, int top, int below) {
+  return split_weight(split, nf, top, below);
 }
 
 int schur_plan_sweep(int ktop, int kbot, int npair, int nb, int step, int* out, int cap) {

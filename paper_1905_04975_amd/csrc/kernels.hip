@@ -91,26 +91,30 @@ __global__ void k_split_commit(const SplitCommit* cm, const SplitTask* tasks) {
   }
 }
 
-// Negligible subdiagonal entries (same test as the deflation scan) set to
-// zero over the whole matrix; zero[k] = 1 where row k starts a block.
-__global__ void k_split_scan(double* H, int ldh, int n, unsigned char* zero) {
+// Negligible subdiagonal entries (same test as the deflation scan) over the
+// whole matrix: zero[k] = 1 where row k starts a block.  Read-only on H, so
+// every test sees the original neighbours; k_split_zero writes the zeros.
+__global__ void k_split_scan(const double* H, int ldh, int n, unsigned char* zero) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     if (k == 0) {
       zero[0] = 1;
       continue;
     }
-    double* hp = H + k + (size_t)(k - 1) * ldh;
-    const double sub = fabs(*hp);
+    const double sub = fabs(H[k + (size_t)(k - 1) * ldh]);
     double tst = fabs(H[(k - 1) + (size_t)(k - 1) * ldh]) + fabs(H[k + (size_t)k * ldh]);
     if (tst == 0.0) {
       tst = fabs(H[(k - 1) + (size_t)k * ldh]);
       if (k >= 2) tst += fabs(H[(k - 1) + (size_t)(k - 2) * ldh]);
       if (k + 1 < n) tst += fabs(H[(k + 1) + (size_t)k * ldh]);
     }
-    const bool z = sub <= kUlp * tst;
-    if (z && sub != 0.0) *hp = 0.0;
-    zero[k] = z ? 1 : 0;
+    zero[k] = (sub <= kUlp * tst) ? 1 : 0;
   }
+}
+
+// The entries flagged by k_split_scan set to exactly zero.
+__global__ void k_split_zero(double* H, int ldh, int n, const unsigned char* zero) {
+  for (int k = 1 + blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+    if (zero[k]) H[k + (size_t)(k - 1) * ldh] = 0.0;
 }
 
 // Identity of order sizes[b] in the leading corner of UPAD x UPAD slot b,
@@ -603,12 +607,12 @@ __global__ __launch_bounds__(DEFL_THREADS) void k_deflate(double* H, int ldh, in
       if (k + 1 <= kbot) tst += fabs(H[(k + 1) + (size_t)k * ldh]);
     }
     if (!isfinite(sub) || !isfinite(tst)) atomicOr(&ctrl->bad, 1);
-    if (sub <= kUlp * tst) {
-      if (sub != 0.0) H[k + (size_t)(k - 1) * ldh] = 0.0;
-      atomicOr(&bits[k >> 5], 1u << (k & 31));
-    }
+    if (sub <= kUlp * tst) atomicOr(&bits[k >> 5], 1u << (k & 31));
   }
   __syncthreads();
+  // zeros written only after every test has read the original neighbours
+  for (int k = klo + 1 + tid; k <= kbot; k += DEFL_THREADS)
+    if (bits[k >> 5] & (1u << (k & 31))) H[k + (size_t)(k - 1) * ldh] = 0.0;
   if (tid < 64) {
     const int lane = tid;
     int kb = kbot, kt = 0, peeled = 0;
@@ -683,11 +687,12 @@ __global__ __launch_bounds__(256) void k_deflate_b(const DeflB* tasks) {
       if (k + 1 <= kbot) tst += fabs(H[(k + 1) + (size_t)k * ldh]);
     }
     if (!isfinite(sub) || !isfinite(tst)) atomicOr(&T.out->bad, 1);
-    if (sub <= kUlp * tst) {
-      if (sub != 0.0) H[k + (size_t)(k - 1) * ldh] = 0.0;
-      atomicOr(&bits[k >> 5], 1u << (k & 31));
-    }
+    if (sub <= kUlp * tst) atomicOr(&bits[k >> 5], 1u << (k & 31));
   }
+  __syncthreads();
+  // zeros written only after every test has read the original neighbours
+  for (int k = 1 + tid; k <= kbot; k += 256)
+    if (bits[k >> 5] & (1u << (k & 31))) H[k + (size_t)(k - 1) * ldh] = 0.0;
   __syncthreads();
   int kt = 0;
   while (kbot >= 0) {
@@ -886,7 +891,10 @@ void launch_split_commit(const SplitCommit* cm, int count, const SplitTask* task
 void launch_split_scan(double* H, int ldh, int n, unsigned char* zero, hipStream_t s) {
   if (n > 0) {
     const int blocks = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
-    hipLaunchKernelGGL(k_split_scan, dim3(blocks), dim3(256), 0, s, H, ldh, n, zero);
+    hipLaunchKernelGGL(k_split_scan, dim3(blocks), dim3(256), 0, s, (const double*)H, ldh, n,
+                       zero);
+    hipLaunchKernelGGL(k_split_zero, dim3(blocks), dim3(256), 0, s, H, ldh, n,
+                       (const unsigned char*)zero);
   }
 }
 

@@ -57,7 +57,7 @@ EXPORTS = ("schur_reduce", "schur_create", "schur_destroy", "schur_set_opts",
            "schur_get_stats", "schur_reduce_async", "schur_reduce_batched",
            "schur_server_create", "schur_server_destroy", "schur_submit", "schur_poll",
            "schur_server_get_stats", "schur_set_tuning", "schur_plan_sweep",
-           "schur_plan_split", "schur_select_windows")
+           "schur_plan_split", "schur_select_windows", "schur_split_weight")
 
 TUNING_PATH = os.path.join(HERE, "tuning.json")
 
@@ -127,6 +127,8 @@ def load():
     lib.schur_plan_split.restype = ctypes.c_int
     lib.schur_select_windows.argtypes = [ip, pi, pi, ctypes.POINTER(ctypes.c_double), pi]
     lib.schur_select_windows.restype = ctypes.c_int
+    lib.schur_split_weight.argtypes = [ip, ip, ip, ip]
+    lib.schur_split_weight.restype = ctypes.c_double
     _lib = lib
     path = os.environ.get("SCHUR_TUNE_TABLE", TUNING_PATH)
     if os.path.exists(path):
@@ -405,3 +407,8 @@ def select_windows(starts, orders, weights):
     if k < 0:
         raise ValueError("bad selection arguments")
     return [out[i] for i in range(k)]
+
+
+def split_weight(split, nf, top, below):
+    """Host-only candidate weight of a window of a pass (0: not a candidate)."""
+    return load().schur_split_weight(int(split), int(nf), int(top), int(below))

@@ -234,3 +234,16 @@ def test_split_selection_edge_cases():
         schur.select_windows([0], [0], [1.0])
     with pytest.raises(ValueError):
         schur.select_windows([0], [5], [0.0])
+
+
+def test_split_candidate_weight():
+    """A window that failed its tests is no candidate; one at an end of its
+    block that deflated nothing neither deflates nor splits, so it is none
+    either; an interior window that deflated nothing still splits its block
+    (weight 1); otherwise the weight is 1 + rows deflated."""
+    assert schur.split_weight(0, 5, 1, 1) == 0.0
+    for top, below in ((0, 1), (1, 0), (0, 0)):
+        assert schur.split_weight(1, 0, top, below) == 0.0
+        assert schur.split_weight(1, 7, top, below) == 8.0
+    assert schur.split_weight(1, 0, 1, 1) == 1.0
+    assert schur.split_weight(1, 3, 1, 1) == 4.0
