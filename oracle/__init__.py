@@ -4,11 +4,16 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
 the CPU-baseline leg of ``bench.py`` may import this package.  The product
 library never calls it, links it or shares code with it.
 
-The arithmetic lives in ``oracle_schur.c`` (plain C, binary64, no BLAS):
-the practical Francis double-shift QR iteration that the paper points to for
-the theory of the Schur reduction (Sec. 2, Eq. (4); Golub & Van Loan,
-Sec. 7.5).  This module only builds that file with ``gcc`` and marshals
-numpy arrays (column-major, Fortran order) through ``ctypes``.
+The arithmetic lives in plain C files (binary64, no BLAS):
+
+* ``oracle_schur.c`` -- the practical Francis double-shift QR iteration that
+  the paper points to for the theory of the Schur reduction (Sec. 2,
+  Eq. (4); Golub & Van Loan, Sec. 7.5);
+* ``oracle_hess.c`` -- the Householder reduction to Hessenberg form (Sec. 2,
+  Eq. (3); Golub & Van Loan, Sec. 7.4.3).
+
+This module only builds those files with ``gcc`` and marshals numpy arrays
+(column-major, Fortran order) through ``ctypes``.
 """
 from __future__ import annotations
 
@@ -19,17 +24,19 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle_schur.c")
+_SRCS = [os.path.join(_HERE, f) for f in ("oracle_schur.c", "oracle_hess.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile ``oracle_schur.c`` into ``liboracle.so`` (gcc -O2, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the oracle sources into ``liboracle.so`` (gcc -O2, no fast-math)."""
+    stale = not os.path.exists(_LIB) or any(
+        os.path.getmtime(_LIB) < os.path.getmtime(src) for src in _SRCS)
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off",
-                               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+                               "-shared", "-fPIC", "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -48,6 +55,8 @@ def _bind(path):
                                         ctypes.c_int, ctypes.c_int,
                                         ctypes.c_double, ctypes.c_double]
     lib.oracle_francis_step.restype = None
+    lib.oracle_hessenberg.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int]
+    lib.oracle_hessenberg.restype = ctypes.c_int
     return lib
 
 
@@ -122,3 +131,23 @@ def francis_step_inplace(H, Q, l, i, s, t, lib=None):
         assert Q.flags.f_contiguous and Q.dtype == np.float64
     lib.oracle_francis_step(n, _dptr(H), n, _dptr(Q) if Q is not None else None, n,
                             int(l), int(i), float(s), float(t))
+
+
+def hessenberg(A, Q=None, want_q=True, lib=None):
+    """Householder reduction of the dense matrix ``A`` to upper Hessenberg
+    form (paper Sec. 2, Eq. (3)).  Returns ``(H, Q)`` with ``A = Q H Q^T``
+    (``Q`` is ``Q_in @ Q1``; ``Q_in`` defaults to the identity)."""
+    lib = lib or _load()
+    H = np.array(A, dtype=np.float64, order="F", copy=True)
+    n = H.shape[0]
+    assert H.shape == (n, n)
+    if want_q:
+        Qm = np.eye(n, order="F") if Q is None else np.array(Q, dtype=np.float64, order="F",
+                                                               copy=True)
+        qptr = _dptr(Qm)
+    else:
+        Qm, qptr = None, None
+    rc = lib.oracle_hessenberg(n, _dptr(H) if n else None, max(1, n), qptr, max(1, n))
+    if rc != 0:
+        raise MemoryError("oracle_hessenberg: workspace")
+    return H, Qm

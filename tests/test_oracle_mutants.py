@@ -17,7 +17,9 @@ from tests import checks
 from tests.test_oracle import _cyclic, second_adhoc_step_error
 
 U = 2.0 ** -53
-SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle_schur.c")
+ODIR = os.path.dirname(oracle.__file__)
+SRC = os.path.join(ODIR, "oracle_schur.c")
+SOURCES = [os.path.join(ODIR, f) for f in ("oracle_schur.c", "oracle_hess.c")]
 
 MUTANTS = {
     "shift_product_sign": ("- s * h00 + t;", "- s * h00 - t;"),
@@ -43,15 +45,22 @@ MUTANTS = {
 }
 
 
-def _build_mutant(tmp_path, name):
-    old, new = MUTANTS[name]
-    src = open(SRC).read()
+def build_mutant(tmp_path, name, old, new, target=SRC):
+    """The oracle library with one replacement planted in a private copy of
+    the source `target` (the other sources unchanged)."""
+    src = open(target).read()
     assert src.count(old) == 1, name
     path = tmp_path / ("m_%s.c" % name)
     path.write_text(src.replace(old, new))
+    srcs = [str(path) if f == target else f for f in SOURCES]
     so = tmp_path / ("m_%s.so" % name)
-    subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", "-o", str(so), str(path), "-lm"])
+    subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", "-o", str(so), *srcs, "-lm"])
     return oracle._bind(str(so))
+
+
+def _build_mutant(tmp_path, name):
+    old, new = MUTANTS[name]
+    return build_mutant(tmp_path, name, old, new)
 
 
 def _pins_pass(lib):
