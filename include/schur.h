@@ -125,6 +125,17 @@ typedef struct schur_stats {
   int64_t split_converged;  /* rows in converged 1x1 / 2x2 blocks after them    */
   double split_ms;          /* summed duration of their window kernels (TIME)  */
   double split_flops;       /* nominal work of their windows (as aed_flops)    */
+  double small_ms;          /* summed duration of the small-block solves (TIME) */
+  double small_flops;       /* their nominal work: 25 m^3 per block of order m  */
+                            /* with Schur vectors, 10 m^3 for eigenvalues only  */
+                            /* (shift solves)                                   */
+  double chase_flops;       /* counted work of the window chases: 10 flops per  */
+                            /* touched row or column and reflector, for the    */
+                            /* left and right updates in the window and the    */
+                            /* accumulation of U                                */
+  int64_t small_launches;   /* launches of the small-block solver (each may     */
+                            /* carry many blocks)                               */
+  int64_t aed_launches;     /* launches of the early-deflation kernels          */
 } schur_stats;
 
 /* --------------------------------------------------------------------------

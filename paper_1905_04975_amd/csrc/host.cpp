@@ -193,6 +193,11 @@ double aed_work(int nw, int nu) {
   return 25.0 * nw * (double)nw * nw + (10.0 / 3.0) * nu * (double)nu * nu;
 }
 
+// counted flops of one window chase: per chain step and bulge, 10 flops for
+// each row or column of the window its reflector touches in the left and
+// right updates together (about ws of them), and 10 per row of U
+double chase_work(int ws, int nb, int steps) { return 20.0 * ws * (double)nb * steps; }
+
 // info code of a solve in which a non-finite value appeared (never for
 // finite input; reported instead of a Schur form)
 constexpr int kErrNonFinite = -105;
@@ -610,8 +615,10 @@ struct Solver {
     if (P.time) h->timer.begin(s, e0);
     launch_small_z(t, nullptr, 1, m, s);
     HCHECK(hipGetLastError());
-    if (P.time) h->timer.end(s, e0, &h->stats.other_ms);
+    if (P.time) h->timer.end(s, e0, &h->stats.small_ms);
     h->stats.small_solves += 1;
+    h->stats.small_launches += 1;
+    h->stats.small_flops += 25.0 * m * (double)m * m;
     h->stats.launches += 1;
     SweepArgs a, aq;
     base_args(a, ktop, kbot);
@@ -648,6 +655,7 @@ struct Solver {
     if (P.time) h->timer.end(s, e0, &h->stats.aed_ms);
     h->stats.launches += 1;
     h->stats.aed_windows += 1;
+    h->stats.aed_launches += 1;
     sync_ctrl();
     const int nd = h->ctrl_h->aed_nd;
     *nu = h->ctrl_h->aed_nu;
@@ -692,6 +700,9 @@ struct Solver {
     Solver sv{h->sub, s, resolve(so, ns), ns, h->shm, ns, nullptr, ns, h->ewr, h->ewi};
     const int info = sv.run();
     h->stats.launches += h->sub->stats.launches;
+    const schur_stats& ss = h->sub->stats;
+    h->stats.small_flops += ss.gemm_flops + ss.chase_flops + ss.small_flops + ss.aed_flops +
+                            ss.split_flops;
     return info;
   }
 
@@ -721,6 +732,7 @@ struct Solver {
       t.info = &h->ctrl->nshift;
       t.itmax = 0;   // default budget
       launch_small_eig(t, s);
+      h->stats.small_flops += 10.0 * ns * (double)ns * ns;
     }
     launch_shift_prep(h->ewr, h->ewi, ns, &h->ctrl->nshift, exceptional ? 1 : 0, H, ldh, ktop,
                       kbot, h->st, s);
@@ -756,6 +768,7 @@ struct Solver {
         d.nb = pl.nb; d.shift0 = pl.shift0; d.slot = buf * MAXWIN + w;
         h->stats.windows += 1;
         h->stats.chain_steps += pl.tau1 - pl.tau0;
+        h->stats.chase_flops += chase_work(pl.ws, pl.nb, pl.tau1 - pl.tau0);
       }
       hipEvent_t e0 = nullptr;
       if (P.time) h->timer.begin(s, e0);
@@ -1162,6 +1175,15 @@ struct BatchEngine {
   // run the parallel early-deflation passes on large matrices (off for the
   // engine that finishes the blocks those passes leave)
   bool allow_split = true;
+  // time the kernel families with HIP events into the handle's counters
+  bool time = false;
+  hipEvent_t e0 = nullptr;
+  void tbeg() { if (time) h->timer.begin(s, e0); }
+  void tend(double* acc) { if (time) h->timer.end(s, e0, acc); }
+  void sync() {
+    HCHECK(hipStreamSynchronize(s));
+    if (time) h->timer.harvest();
+  }
 
   template <class T>
   T* dev_of(schur_handle_s::Grow& g) { return (T*)g.dev; }
@@ -1270,11 +1292,13 @@ struct BatchEngine {
       dh[q] = DeflB{m.H, m.Q, m.wr, m.wi, m.ldh, m.ldq, m.n, m.kbot, ctrl_d + idx[q]};
     }
     upload(h->b_defl, sizeof(DeflB) * idx.size());
+    tbeg();
     launch_deflate_b(dev_of<DeflB>(h->b_defl), (int)idx.size(), s);
     HCHECK(hipGetLastError());
+    tend(&h->stats.other_ms);
     h->stats.launches += 1;
     HCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl) * cap, hipMemcpyDeviceToHost, s));
-    HCHECK(hipStreamSynchronize(s));
+    sync();
     // ---- classify
     std::vector<int> small, big;
     for (int i : idx) {
@@ -1355,19 +1379,20 @@ struct BatchEngine {
         m.kbot = m.ktop - 1;     // the block is finished by this round's launches
         if (m.kbot < 0) m.active = false;   // a failure is read from its ctrl later
         h->stats.small_solves += 1;
+        h->stats.small_flops += 25.0 * len * (double)len * len;
       }
       upload(h->b_small, sizeof(SmallTask) * small.size());
+      tbeg();
       launch_small_tasks(dev_of<SmallTask>(h->b_small), (int)small.size(), maxm, true, s);
       HCHECK(hipGetLastError());
+      tend(&h->stats.small_ms);
       h->stats.launches += 1;
+      h->stats.small_launches += 1;
       if (nwin > 0) {
         upload(h->b_win, sizeof(WinB) * nwin);
-        launch_panel_row_b(dev_of<WinB>(h->b_win), nwin, tr, s);
-        launch_panel_colq_b(dev_of<WinB>(h->b_win), nwin, tcq, s);
-        HCHECK(hipGetLastError());
-        h->stats.launches += (tr > 0) + (tcq > 0);
+        panels(dev_of<WinB>(h->b_win), nwin, tr, tcq);
       }
-      if (!big.empty()) HCHECK(hipStreamSynchronize(s));   // slots and staging reused below
+      if (!big.empty()) sync();   // slots and staging reused below
     }
     if (big.empty()) return;
     // ---- early deflation: one workgroup per matrix, then V applied to the
@@ -1399,12 +1424,15 @@ struct BatchEngine {
       }
       if (!who.empty()) {
         upload(h->b_aedt, sizeof(AedTask) * who.size());
+        tbeg();
         launch_aed_b(dev_of<AedTask>(h->b_aedt), (int)who.size(), s);
         HCHECK(hipGetLastError());
+        tend(&h->stats.aed_ms);
         h->stats.launches += 1;
+        h->stats.aed_launches += 1;
         h->stats.aed_windows += (int64_t)who.size();
         HCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl) * cap, hipMemcpyDeviceToHost, s));
-        HCHECK(hipStreamSynchronize(s));
+        sync();
         grow(h->b_aedw, sizeof(WinB) * who.size(), true);
         WinB* wh = host_of<WinB>(h->b_aedw);
         int nwin = 0, tr = 0, tcq = 0;
@@ -1430,10 +1458,7 @@ struct BatchEngine {
         }
         if (nwin > 0) {
           upload(h->b_aedw, sizeof(WinB) * nwin);
-          launch_panel_row_b(dev_of<WinB>(h->b_aedw), nwin, tr, s);
-          launch_panel_colq_b(dev_of<WinB>(h->b_aedw), nwin, tcq, s);
-          HCHECK(hipGetLastError());
-          h->stats.launches += (tr > 0) + (tcq > 0);
+          panels(dev_of<WinB>(h->b_aedw), nwin, tr, tcq);
         }
       }
     }
@@ -1494,6 +1519,7 @@ struct BatchEngine {
             t.itmax = 0;   // default budget
             th[ne++] = t;
             maxns = std::max(maxns, ns);
+            h->stats.small_flops += 10.0 * ns * (double)ns * ns;
           }
           sh[nsh++] = ShiftB{base, base + SMALL_EIG_MAX, exc ? nullptr : &ctrl_d[big[q]].nshift,
                              m.H, base + 2 * SMALL_EIG_MAX, ns, exc ? 1 : 0, m.ldh, m.ktop, m.kbot,
@@ -1505,9 +1531,11 @@ struct BatchEngine {
       }
       upload(h->b_small, sizeof(SmallTask) * ne);
       upload(h->b_shift, sizeof(ShiftB) * nsh);
+      tbeg();
       if (ne > 0) launch_small_tasks(dev_of<SmallTask>(h->b_small), ne, maxns, false, s);
       launch_shift_prep_b(dev_of<ShiftB>(h->b_shift), nsh, s);
       HCHECK(hipGetLastError());
+      tend(&h->stats.shift_ms);
       h->stats.launches += 1 + (ne > 0);
     }
     // ---- merged sweeps: time step t carries the windows of every matrix
@@ -1543,6 +1571,7 @@ struct BatchEngine {
             ++k;
             h->stats.windows += 1;
             h->stats.chain_steps += pl.tau1 - pl.tau0;
+            h->stats.chase_flops += chase_work(pl.ws, pl.nb, pl.tau1 - pl.tau0);
           }
         }
         tr_t[t] = tr;
@@ -1553,12 +1582,13 @@ struct BatchEngine {
       for (size_t t = 0; t < tmax; ++t) {
         const int nw = (int)per_t[t];
         if (nw == 0) continue;
+        tbeg();
         launch_chase_b(wd + off[t], nw, s);
-        launch_panel_row_b(wd + off[t], nw, tr_t[t], s);
-        launch_panel_colq_b(wd + off[t], nw, tcq_t[t], s);
         HCHECK(hipGetLastError());
+        tend(&h->stats.chase_ms);
         h->stats.chase_launches += 1;
-        h->stats.launches += 1 + (tr_t[t] > 0) + (tcq_t[t] > 0);
+        h->stats.launches += 1;
+        panels(wd + off[t], nw, tr_t[t], tcq_t[t]);
       }
     }
   }
@@ -1567,7 +1597,7 @@ struct BatchEngine {
   // finished inside the last launches.
   void settle() {
     HCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl) * cap, hipMemcpyDeviceToHost, s));
-    HCHECK(hipStreamSynchronize(s));
+    sync();
     for (int i = 0; i < cap; ++i) {
       Mat& m = M[i];
       if (m.used && !m.active && m.info == 0 && m.last_small_top >= 0 && ctrl_h[i].small_info != 0)
@@ -1576,6 +1606,27 @@ struct BatchEngine {
   }
 
   void fill_tiles(WinB& w, int& tr, int& tcq) { fill_tiles_b(w, tr, tcq, h->stats); }
+
+  // row-panel and column-panel/Q products of `nwin` windows (descriptors on
+  // the device)
+  void panels(const WinB* wd, int nwin, int tr, int tcq) {
+    if (tr > 0) {
+      tbeg();
+      launch_panel_row_b(wd, nwin, tr, s);
+      HCHECK(hipGetLastError());
+      tend(&h->stats.row_ms);
+      h->stats.row_launches += 1;
+    }
+    if (tcq > 0) {
+      tbeg();
+      launch_panel_colq_b(wd, nwin, tcq, s);
+      HCHECK(hipGetLastError());
+      tend(&h->stats.colq_ms);
+      h->stats.colq_launches += 1;
+    }
+    h->stats.gemm_launches += (tr > 0) + (tcq > 0);
+    h->stats.launches += (tr > 0) + (tcq > 0);
+  }
 };
 
 // Independent unreduced blocks [lo, hi] of one matrix (order <= UPAD each)
@@ -1606,6 +1657,7 @@ bool batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<
   b.init(h, s, cnt);
   b.defer_small = true;
   b.allow_split = false;
+  b.time = time;
   for (int i = 0; i < cnt; ++i) {
     const int lo = blocks[i].first;
     b.add(i, sz[i], H + lo + (size_t)lo * ldh, ldh, zq + (size_t)i * slot, UPAD, wr + lo, wi + lo,
@@ -1667,6 +1719,7 @@ int solve_batched(schur_handle_s* h, hipStream_t s, int count, const int* n, dou
     std::memset(&h->stats, 0, sizeof(h->stats));
     BatchEngine b;
     b.init(h, s ? s : h->stream, count);
+    b.time = (h->opts.flags & SCHUR_FLAG_TIME_KERNELS) != 0;
     std::vector<int> pre(count, 0);
     for (int i = 0; i < count; ++i) {
       double* qi = Q ? Q[i] : nullptr;

@@ -576,11 +576,7 @@ __global__ void k_set_identity(double* Q, int ldq, int n) {
 }
 
 __global__ void k_ctrl_reset(Ctrl* ctrl) {
-  if (threadIdx.x == 0) {
-    ctrl->bad = 0;
-    ctrl->small_info = 0;
-    ctrl->ndefl = 0;
-  }
+  if (threadIdx.x == 0) *ctrl = Ctrl{};   // every field of a solve starts at zero
 }
 
 // ============================================================================

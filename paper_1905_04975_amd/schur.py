@@ -45,7 +45,10 @@ class SchurStats(ctypes.Structure):
                 ("aed_deflated", ctypes.c_int64), ("aed_flops", ctypes.c_double),
                 ("split_passes", ctypes.c_int64), ("split_windows", ctypes.c_int64),
                 ("split_accepted", ctypes.c_int64), ("split_converged", ctypes.c_int64),
-                ("split_ms", ctypes.c_double), ("split_flops", ctypes.c_double)]
+                ("split_ms", ctypes.c_double), ("split_flops", ctypes.c_double),
+                ("small_ms", ctypes.c_double), ("small_flops", ctypes.c_double),
+                ("chase_flops", ctypes.c_double), ("small_launches", ctypes.c_int64),
+                ("aed_launches", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
