@@ -10,7 +10,10 @@ The arithmetic lives in plain C files (binary64, no BLAS):
   the paper points to for the theory of the Schur reduction (Sec. 2,
   Eq. (4); Golub & Van Loan, Sec. 7.5);
 * ``oracle_hess.c`` -- the Householder reduction to Hessenberg form (Sec. 2,
-  Eq. (3); Golub & Van Loan, Sec. 7.4.3).
+  Eq. (3); Golub & Van Loan, Sec. 7.4.3);
+* ``oracle_evec.c`` -- eigenvectors of a real Schur form by back
+  substitution with overflow protection, and their backtransform (Sec. 2,
+  Eqs. (5) and (6)).
 
 This module only builds those files with ``gcc`` and marshals numpy arrays
 (column-major, Fortran order) through ``ctypes``.
@@ -24,7 +27,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, f) for f in ("oracle_schur.c", "oracle_hess.c")]
+_SRCS = [os.path.join(_HERE, f) for f in ("oracle_schur.c", "oracle_hess.c",
+                                                 "oracle_evec.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -57,6 +61,9 @@ def _bind(path):
     lib.oracle_francis_step.restype = None
     lib.oracle_hessenberg.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int]
     lib.oracle_hessenberg.restype = ctypes.c_int
+    lib.oracle_eigenvectors.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int, dp,
+                                        ctypes.c_int]
+    lib.oracle_eigenvectors.restype = ctypes.c_int
     return lib
 
 
@@ -151,3 +158,43 @@ def hessenberg(A, Q=None, want_q=True, lib=None):
     if rc != 0:
         raise MemoryError("oracle_hessenberg: workspace")
     return H, Qm
+
+
+def eigenvectors(S, Q=None, lib=None):
+    """Eigenvectors of the real Schur form ``S`` (paper Sec. 2, Eq. (5)) in
+    LAPACK's real layout (a complex pair's real and imaginary parts in two
+    adjacent columns), backtransformed with ``Q`` when given (Eq. (6)), each
+    scaled to largest |Re| + |Im| = 1."""
+    lib = lib or _load()
+    S = np.array(S, dtype=np.float64, order="F", copy=True)
+    n = S.shape[0]
+    X = np.zeros((n, n), order="F")
+    qptr = None
+    if Q is not None:
+        Qm = np.array(Q, dtype=np.float64, order="F", copy=True)
+        qptr = _dptr(Qm)
+    rc = lib.oracle_eigenvectors(n, _dptr(S) if n else None, max(1, n), qptr, max(1, n),
+                                 _dptr(X) if n else None, max(1, n))
+    if rc != 0:
+        raise MemoryError("oracle_eigenvectors: workspace")
+    return X
+
+
+def complex_vectors(S, X):
+    """Columns of LAPACK's real layout as complex vectors, with eigenvalues."""
+    n = S.shape[0]
+    lam = np.zeros(n, dtype=complex)
+    V = np.zeros((X.shape[0], n), dtype=complex)
+    k = 0
+    while k < n:
+        if k + 1 < n and S[k + 1, k] != 0.0:
+            wi = np.sqrt(abs(S[k, k + 1])) * np.sqrt(abs(S[k + 1, k]))
+            lam[k], lam[k + 1] = S[k, k] + 1j * wi, S[k, k] - 1j * wi
+            V[:, k] = X[:, k] + 1j * X[:, k + 1]
+            V[:, k + 1] = X[:, k] - 1j * X[:, k + 1]
+            k += 2
+        else:
+            lam[k] = S[k, k]
+            V[:, k] = X[:, k]
+            k += 1
+    return lam, V
