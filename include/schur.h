@@ -136,6 +136,13 @@ typedef struct schur_stats {
   int64_t small_launches;   /* launches of the small-block solver (each may     */
                             /* carry many blocks)                               */
   int64_t aed_launches;     /* launches of the early-deflation kernels          */
+  /* schur_hessenberg */
+  double hess_panel_ms;     /* summed duration of the panels' column kernels    */
+                            /* (TIME)                                           */
+  double hess_gemv_bytes;   /* bytes of the trailing matrix streamed by the     */
+                            /* matrix-vector products (8 per entry and column)  */
+  double hess_gemm_ms;      /* summed duration of the panels' products (TIME)   */
+  double hess_gemm_flops;   /* flops of those products                          */
 } schur_stats;
 
 /* --------------------------------------------------------------------------
@@ -168,6 +175,28 @@ int schur_get_stats(schur_handle_t h, schur_stats* out);
  * ------------------------------------------------------------------------ */
 int schur_reduce_async(schur_handle_t h, void* stream, int n, double* H, int ldh, double* Q,
                        int ldq, double* wr, double* wi, int* info_out);
+
+/* --------------------------------------------------------------------------
+ * schur_hessenberg -- Hessenberg reduction A = Q1 H Q1^T (paper Sec. 2,
+ * Eq. (3)), the step before the Schur reduction: H = schur_hessenberg(A),
+ * then schur_reduce(H, Q) with the same Q gives A = (Q1 Q2) S (Q1 Q2)^T.
+ *   h        handle (its workspace; stream NULL = the handle's stream)
+ *   n        order, n >= 0
+ *   A        device, lda x n; in: dense A; out: H (upper Hessenberg, exact
+ *            zeros below the first subdiagonal)
+ *   lda      >= max(1, n)
+ *   Q        device, ldq x n or NULL; in: Q_in; out: Q_in Q1 (pass the
+ *            identity to get Q1; Q1 e_1 = e_1)
+ *   ldq      >= max(1, n) when Q != NULL
+ * Blocked Householder reflectors, panels of 32 columns; the new subdiagonal
+ * entry of a column is -sign(x_1) ||x|| (the LAPACK convention).  All work is
+ * enqueued on the stream in order and the call returns without waiting for
+ * it (workspace growth aside); results are final when the stream reaches
+ * them.  Returns 0, -1 (n), -2 (A), -3 (lda), -5 (ldq), -101 (device
+ * memory), -102 (HIP error), -103 (not device memory), -104 (handle).
+ * ------------------------------------------------------------------------ */
+int schur_hessenberg(schur_handle_t h, void* stream, int n, double* A, int lda, double* Q,
+                     int ldq);
 
 /* --------------------------------------------------------------------------
  * schur_reduce_batched -- many independent Hessenberg matrices of uneven

@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "../../include/schur.h"
+#include "hess.h"
 #include "kernels.h"
 #include "schur_internal.h"
 
@@ -130,6 +131,9 @@ struct schur_handle_s {
   // starts, panel descriptors
   Grow b_splt, b_splr, b_splu, b_splz, b_splw;
   Grow b_splq, b_splb;   // batched finish: per-block Z slots, block orders
+  // Hessenberg reduction: V and Y of a panel, T / tau / pivot, per-workgroup
+  // partials, partial matrix-vector products, product scratch
+  Grow b_hvy, b_ht, b_hp, b_hy, b_hw;
   // nested solve of a trailing block larger than SMALL_EIG_MAX (shifts only)
   schur_handle_s* sub = nullptr;
   // buffers of the parallel early-deflation passes that the batched engine
@@ -290,6 +294,8 @@ void free_ws(schur_handle_s* h) {
   free_grow(h->b_aedt); free_grow(h->b_aedw);
   free_grow(h->b_splt); free_grow(h->b_splr); free_grow(h->b_splu); free_grow(h->b_splz);
   free_grow(h->b_splw); free_grow(h->b_splq); free_grow(h->b_splb);
+  free_grow(h->b_hvy); free_grow(h->b_ht); free_grow(h->b_hp); free_grow(h->b_hy);
+  free_grow(h->b_hw);
   if (h->U) (void)hipFree(h->U);
   if (h->refl) (void)hipFree(h->refl);
   if (h->st) (void)hipFree(h->st);
@@ -1133,6 +1139,110 @@ int solve(schur_handle_s* h, hipStream_t s, int n, double* H, int ldh, double* Q
     std::memset(&h->stats, 0, sizeof(h->stats));
     Solver sv{h, s ? s : h->stream, resolve(h->opts, n), n, H, ldh, Q, ldq, wr, wi};
     return sv.run();
+  } catch (const HipErr& e) {
+    (void)hipGetLastError();
+    return e.e == hipErrorOutOfMemory ? -101 : -102;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Hessenberg reduction A = Q1 H Q1^T (paper Sec. 2, Eq. (3)): blocked
+// Householder reduction in panels of NBH columns.  Per column of a panel five
+// launches (update of the column by the panel's earlier reflectors, its
+// reflector, one matrix-vector product with the trailing matrix, the new
+// column of Y = A V T and of T); per panel the top rows of Y, the right
+// update of the trailing columns, the top rows of the panel's columns, the
+// left update of the trailing block and Q <- Q (I - V T V^T) as FP64 MFMA
+// products.  No host synchronisation: every launch is stream-ordered.
+// ---------------------------------------------------------------------------
+int hess_reduce(schur_handle_s* h, hipStream_t s, int n, double* A, int lda, double* Q, int ldq) {
+  if (n < 0 || n > 524288) return -1;
+  if (n == 0) return 0;
+  if (!A) return -2;
+  if (lda < std::max(1, n)) return -3;
+  if (Q && ldq < std::max(1, n)) return -5;
+  if (!is_device_ptr(A) || (Q && !is_device_ptr(Q))) return -103;
+  try {
+    HCHECK(hipSetDevice(h->device));
+    std::memset(&h->stats, 0, sizeof(h->stats));
+    if (n <= 2) return 0;
+    const int rows_max = n - 1;
+    const int nwg_max = (rows_max + HROWS - 1) / HROWS;
+    constexpr int kSplitMax = 64;
+    double* vy = (double*)grow(h->b_hvy, sizeof(double) * 2 * (size_t)n * NBH, false);
+    double* tt = (double*)grow(h->b_ht, sizeof(double) * (NBH * NBH + NBH + 8), false);
+    double* pp = (double*)grow(h->b_hp, sizeof(double) * (size_t)nwg_max * (2 * HPART + 2), false);
+    double* yp = (double*)grow(h->b_hy, sizeof(double) * (size_t)n * kSplitMax, false);
+    double* ww = (double*)grow(h->b_hw, sizeof(double) * 2 * (size_t)n * NBH, false);
+    HessArgs g{};
+    g.A = A; g.lda = lda; g.n = n;
+    g.V = vy; g.Y = vy + (size_t)n * NBH;
+    g.T = tt; g.tau = tt + NBH * NBH; g.sc = tt + NBH * NBH + NBH;
+    g.part = pp; g.part3 = pp + (size_t)nwg_max * HPART; g.part2 = pp + (size_t)nwg_max * 2 * HPART;
+    g.ypart = yp;
+    double* W = ww;
+    double* W2 = ww + (size_t)n * NBH;
+    const bool time = (h->opts.flags & SCHUR_FLAG_TIME_KERNELS) != 0;
+    hipEvent_t e0 = nullptr;
+    for (int K = 0; K < n - 2; K += NBH) {
+      const int ib = std::min(NBH, n - 2 - K);
+      const int m1 = n - K - 1;
+      const int nwg = (m1 + HROWS - 1) / HROWS;
+      launch_hess_zero(g.V, (size_t)n * NBH, s);
+      launch_hess_zero(g.T, (size_t)NBH * NBH, s);
+      if (time) h->timer.begin(s, e0);
+      for (int i = 0; i < ib; ++i) {
+        // column splits of the matrix-vector product: about 1024 workgroups,
+        // at least 32 columns each
+        const int cols = n - (K + i + 1);
+        int cs = std::max(1, 1024 / nwg);
+        cs = std::min(std::min(cs, kSplitMax), std::max(1, cols / 32));
+        launch_hess_column(g, K, i, cs, s);
+        HCHECK(hipGetLastError());
+        h->stats.launches += (i > 0) + 4;
+        h->stats.hess_gemv_bytes += 8.0 * (double)m1 * cols;
+      }
+      if (time) h->timer.end(s, e0, &h->stats.hess_panel_ms);
+      if (time) h->timer.begin(s, e0);
+      const int nt = n - K - ib;   // trailing columns K+ib .. n-1
+      // top rows of Y: Y(0:K+1, :) = A(0:K+1, K+1:n) V(K+1:n, :) T
+      launch_gemm(false, false, K + 1, ib, m1, 1.0, A + (size_t)(K + 1) * lda, lda, g.V + (K + 1), n,
+                  0.0, W, n, s);
+      launch_gemm(false, false, K + 1, ib, ib, 1.0, W, n, g.T, NBH, 0.0, g.Y, n, s);
+      // right update of the trailing columns, all rows: A -= Y V(K+ib:n, :)^T
+      launch_gemm(false, true, n, nt, ib, -1.0, g.Y, n, g.V + (K + ib), n, 1.0,
+                  A + (size_t)(K + ib) * lda, lda, s);
+      // top rows of the panel's columns K+1 .. K+ib-1
+      launch_gemm(false, true, K + 1, ib - 1, ib, -1.0, g.Y, n, g.V + (K + 1), n, 1.0,
+                  A + (size_t)(K + 1) * lda, lda, s);
+      // left update of the trailing block: A -= V (A^T V T)^T
+      double* At = A + (K + 1) + (size_t)(K + ib) * lda;
+      launch_gemm(true, false, nt, ib, m1, 1.0, At, lda, g.V + (K + 1), n, 0.0, W, n, s);
+      launch_gemm(false, false, nt, ib, ib, 1.0, W, n, g.T, NBH, 0.0, W2, n, s);
+      launch_gemm(false, true, m1, nt, ib, -1.0, g.V + (K + 1), n, W2, n, 1.0, At, lda, s);
+      double fl = 2.0 * (K + 1) * (double)ib * (m1 + ib) + 2.0 * n * (double)nt * ib +
+                  2.0 * (K + 1) * (double)(ib - 1) * ib + 2.0 * nt * (double)ib * (m1 + ib) +
+                  2.0 * m1 * (double)nt * ib;
+      int launches = 7;
+      if (Q) {   // Q(:, K+1:n) <- Q (I - V T V^T)
+        launch_gemm(false, false, n, ib, m1, 1.0, Q + (size_t)(K + 1) * ldq, ldq, g.V + (K + 1), n,
+                    0.0, W, n, s);
+        launch_gemm(false, false, n, ib, ib, 1.0, W, n, g.T, NBH, 0.0, W2, n, s);
+        launch_gemm(false, true, n, m1, ib, -1.0, W2, n, g.V + (K + 1), n, 1.0,
+                    Q + (size_t)(K + 1) * ldq, ldq, s);
+        fl += 2.0 * n * (double)ib * (m1 + ib) + 2.0 * n * (double)m1 * ib;
+        launches += 3;
+      }
+      HCHECK(hipGetLastError());
+      if (time) h->timer.end(s, e0, &h->stats.hess_gemm_ms);
+      h->stats.hess_gemm_flops += fl;
+      h->stats.launches += launches + 2;
+    }
+    if (time) {
+      HCHECK(hipStreamSynchronize(s));
+      h->timer.harvest();
+    }
+    return 0;
   } catch (const HipErr& e) {
     (void)hipGetLastError();
     return e.e == hipErrorOutOfMemory ? -101 : -102;
@@ -2019,6 +2129,12 @@ int schur_reduce(int n, double* H, int ldh, double* Q, int ldq, double* wr, doub
   }
   std::lock_guard<std::mutex> lk(g_mu);
   return solve(h, h->stream, n, H, ldh, Q, ldq, wr, wi);
+}
+
+int schur_hessenberg(schur_handle_t h, void* stream, int n, double* A, int lda, double* Q,
+                     int ldq) {
+  if (!h) return -104;
+  return hess_reduce(h, stream ? (hipStream_t)stream : h->stream, n, A, lda, Q, ldq);
 }
 
 int schur_reduce_async(schur_handle_t h, void* stream, int n, double* H, int ldh, double* Q,

@@ -48,7 +48,9 @@ class SchurStats(ctypes.Structure):
                 ("split_ms", ctypes.c_double), ("split_flops", ctypes.c_double),
                 ("small_ms", ctypes.c_double), ("small_flops", ctypes.c_double),
                 ("chase_flops", ctypes.c_double), ("small_launches", ctypes.c_int64),
-                ("aed_launches", ctypes.c_int64)]
+                ("aed_launches", ctypes.c_int64),
+                ("hess_panel_ms", ctypes.c_double), ("hess_gemv_bytes", ctypes.c_double),
+                ("hess_gemm_ms", ctypes.c_double), ("hess_gemm_flops", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -60,7 +62,8 @@ EXPORTS = ("schur_reduce", "schur_create", "schur_destroy", "schur_set_opts",
            "schur_get_stats", "schur_reduce_async", "schur_reduce_batched",
            "schur_server_create", "schur_server_destroy", "schur_submit", "schur_poll",
            "schur_server_get_stats", "schur_set_tuning", "schur_plan_sweep",
-           "schur_plan_split", "schur_select_windows", "schur_split_weight")
+           "schur_plan_split", "schur_select_windows", "schur_split_weight",
+           "schur_hessenberg")
 
 TUNING_PATH = os.path.join(HERE, "tuning.json")
 
@@ -104,6 +107,8 @@ def load():
     lib.schur_get_stats.restype = ctypes.c_int
     lib.schur_reduce_async.argtypes = [vp, vp, ip, dp, ip, dp, ip, dp, dp, ctypes.POINTER(ip)]
     lib.schur_reduce_async.restype = ctypes.c_int
+    lib.schur_hessenberg.argtypes = [vp, vp, ip, dp, ip, dp, ip]
+    lib.schur_hessenberg.restype = ctypes.c_int
     pint = ctypes.POINTER(ctypes.c_int)
     pptr = ctypes.POINTER(ctypes.c_void_p)
     lib.schur_reduce_batched.argtypes = [vp, vp, ip, pint, pptr, pint, pptr, pint, pptr, pptr, pint]
@@ -169,6 +174,10 @@ class Handle:
         rc = load().schur_reduce_async(self._h, stream, int(n), H, int(ldh), Q, int(ldq), wr, wi,
                                        ctypes.byref(info))
         return rc
+
+    def hessenberg_async(self, stream, n, A, lda, Q, ldq):
+        """C ``schur_hessenberg`` with raw device pointers; returns its code."""
+        return load().schur_hessenberg(self._h, stream, int(n), A, int(lda), Q, int(ldq))
 
     def reduce_batched(self, stream, ns, Hs, ldhs, Qs, ldqs, wrs, wis):
         count = len(ns)
@@ -250,6 +259,34 @@ def reduce(H, Q=None, want_q=True, handle=None, stream=None):
                                    wi.data_ptr())
     w = torch.complex(wr[:n], wi[:n])
     return S, Qm, w, info
+
+
+def hessenberg(A, Q=None, want_q=True, handle=None, stream=None):
+    """Hessenberg form of the dense CUDA/HIP float64 tensor ``A`` (paper
+    Sec. 2, Eq. (3)).  Returns ``(H, Q, rc)``; ``A`` is overwritten when it
+    is already column-major, ``Q`` (default the identity) accumulates
+    ``Q_in Q1``."""
+    import torch
+
+    n = A.shape[0]
+    H, lda = _colmajor(A)
+    dev = H.device
+    if want_q:
+        Qm = torch.eye(n, dtype=torch.float64, device=dev).t() if Q is None else Q
+        Qm, ldq = _colmajor(Qm)
+        qptr = Qm.data_ptr()
+    else:
+        Qm, ldq, qptr = None, 1, None
+    own = handle is None
+    if own:
+        handle = Handle(dev.index or 0)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = handle.hessenberg_async(stream, n, H.data_ptr(), lda, qptr, ldq)
+    if own:
+        torch.cuda.synchronize(dev)
+        handle.close()
+    return H, Qm, rc
 
 
 def reduce_batched(Hs, want_q=True, handle=None, stream=None):
