@@ -40,7 +40,8 @@
  *       <=-100   runtime failure: -101 out of device memory, -102 HIP error,
  *                -103 pointer is not device memory, -104 bad handle,
  *                -105 a non-finite value appeared during the iteration
- *                (an internal failure; H and Q are then unspecified).
+ *                (an internal failure; H and Q are then unspecified),
+ *                -106 n above the maximum of schur_reduce_noalloc.
  *   - entries of H below the first subdiagonal are ignored on input and are
  *     exactly zero on output; S's 2x2 blocks are standardised (equal diagonal
  *     entries, off-diagonal entries of opposite sign, i.e. a complex pair);
@@ -197,6 +198,35 @@ int schur_reduce_async(schur_handle_t h, void* stream, int n, double* H, int ldh
  * ------------------------------------------------------------------------ */
 int schur_hessenberg(schur_handle_t h, void* stream, int n, double* A, int lda, double* Q,
                      int ldq);
+
+/* --------------------------------------------------------------------------
+ * schur_reduce_noalloc -- the Schur reduction of schur_reduce for callers
+ * that cannot allocate memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  It calls no hipMalloc, hipFree,
+ * hipHostMalloc or other allocating device routine, creates no stream or
+ * event, and takes its workspace from a static device array of
+ * SCHUR_NOALLOC_SCRATCH_BYTES (about 6.6 MB) that each GPU it runs on holds
+ * until the process ends.  Host-side planning uses ordinary C++ containers.
+ *   stream   hipStream_t as void* (NULL = the null stream); all device work
+ *            runs on it, in order
+ *   n        0 <= n <= SCHUR_NOALLOC_MAX_N; larger orders return -106
+ *            (the workspace holds the block list of at most that order)
+ *   H, ldh, Q, ldq, wr, wi   as in schur_reduce (device pointers of the
+ *            current device; the caller passes inputs and outputs)
+ * Differences from schur_reduce: no parallel early-deflation passes (their
+ * per-window workspace is not in the array), at most 128 shifts per sweep
+ * (no nested shift solve), one stream (the Q products are not overlapped
+ * with the window chase).  Returns like schur_reduce; the results are final
+ * when it returns.  Every call on a device shares that device's array, which
+ * keeps the last call's contents (the control block is cleared at the start
+ * of each call); calls from several host threads on one device are
+ * serialised by the library, calls from several processes use separate
+ * arrays.
+ * ------------------------------------------------------------------------ */
+#define SCHUR_NOALLOC_MAX_N 32768
+#define SCHUR_NOALLOC_SCRATCH_BYTES 6632192
+int schur_reduce_noalloc(void* stream, int n, double* H, int ldh, double* Q, int ldq,
+                         double* wr, double* wi);
 
 /* --------------------------------------------------------------------------
  * schur_reduce_batched -- many independent Hessenberg matrices of uneven

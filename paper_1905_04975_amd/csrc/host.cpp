@@ -469,6 +469,9 @@ struct Solver {
   double* wr; double* wi;
 
   int64_t tslot = 0;   // time steps issued so far (ring position of the U slots)
+  // everything on stream s, one U-slot buffer, no events (the handle has no
+  // aux stream): the entry point that allocates nothing
+  bool one_stream = false;
 
   // Workgroup counts of the row panel and column panel (main stream) in `a`, and
   // of the Q products (aux stream) in `aq`, a copy of `a`.
@@ -535,6 +538,10 @@ struct Solver {
   // ring buffer of U slots for the next time step: wait until the Q products
   // that last read this buffer are done
   int acquire_buffer() {
+    if (one_stream) {   // stream order: the last time step's readers are done
+      ++tslot;
+      return 0;
+    }
     const int buf = (int)(tslot % NBUF);
     if (tslot >= NBUF) HCHECK(hipStreamWaitEvent(s, h->ev_q[buf], 0));
     ++tslot;
@@ -543,6 +550,16 @@ struct Solver {
 
   // Q products of one time step on the aux stream, after the U slots are ready
   void launch_q(const SweepArgs& aq, int tq, int buf) {
+    if (one_stream) {
+      if (tq > 0) {
+        launch_panel_colq(aq, tq, s);
+        HCHECK(hipGetLastError());
+        h->stats.colq_launches += 1;
+        h->stats.gemm_launches += 1;
+        h->stats.launches += 1;
+      }
+      return;
+    }
     HCHECK(hipEventRecord(h->ev_u[buf], s));
     if (tq > 0) {
       HCHECK(hipStreamWaitEvent(h->aux, h->ev_u[buf], 0));
@@ -560,6 +577,7 @@ struct Solver {
 
   // main stream waits for everything issued on the aux stream
   void join_aux() {
+    if (one_stream) return;
     HCHECK(hipEventRecord(h->ev_join, h->aux));
     HCHECK(hipStreamWaitEvent(s, h->ev_join, 0));
   }
@@ -1014,8 +1032,10 @@ struct Solver {
 
   int run() {
     // the aux stream starts after the work already queued on the solve stream
-    HCHECK(hipEventRecord(h->ev_join, s));
-    HCHECK(hipStreamWaitEvent(h->aux, h->ev_join, 0));
+    if (!one_stream) {
+      HCHECK(hipEventRecord(h->ev_join, s));
+      HCHECK(hipStreamWaitEvent(h->aux, h->ev_join, 0));
+    }
     launch_ctrl_reset(h->ctrl, s);
     launch_check_finite(H, ldh, n, h->ctrl, s);
     sync_ctrl();
@@ -1246,6 +1266,92 @@ int hess_reduce(schur_handle_s* h, hipStream_t s, int n, double* A, int lda, dou
   } catch (const HipErr& e) {
     (void)hipGetLastError();
     return e.e == hipErrorOutOfMemory ? -101 : -102;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Entry point that allocates nothing (schur_reduce_noalloc).  Its workspace
+// lives in one static device array per GPU, carved as below: U slots of one
+// time step (a single stream needs no ring of buffers), the reflector log,
+// shift and eigenvalue buffers, the control block and the block list of the
+// standardisation for orders up to SCHUR_NOALLOC_MAX_N.  The array's name is
+// a host-side stand-in in host code: kernels get the address
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kNaU = align256(sizeof(double) * (size_t)MAXWIN * UPAD * UPAD);
+constexpr size_t kNaRefl = align256(sizeof(double) * (size_t)MAXWIN * REFL_STRIDE);
+constexpr size_t kNaVec = align256(sizeof(double) * NSMAX);
+constexpr size_t kNaCtrl = align256(sizeof(Ctrl));
+constexpr size_t kNaCount = 256;
+constexpr int kNaBlist = SCHUR_NOALLOC_MAX_N / 2 + 2;
+constexpr size_t kNaBytes =
+    kNaU + kNaRefl + 3 * kNaVec + kNaCtrl + kNaCount + align256(sizeof(int) * (size_t)kNaBlist);
+
+static_assert(kNaBytes == SCHUR_NOALLOC_SCRATCH_BYTES, "workspace size stated in schur.h");
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+struct NoAllocDev {
+  schur_handle_s* h = nullptr;   // host-side state; its buffers point into scratch
+  Ctrl ctrl_host{};              // host mirror of the control block
+  std::mutex mu;                 // calls on one device run one at a time
+};
+NoAllocDev g_na[64];
+std::mutex g_na_setup;
+
+// once per device, with that device current: the device address of its copy
+// of the array, carved into the handle's buffers
+int noalloc_setup(int dev) {
+  std::lock_guard<std::mutex> lk(g_na_setup);
+  NoAllocDev& d = g_na[dev];
+  if (d.h) return 0;
+  void* base = nullptr;
+  if (hipGetSymbolAddress(&base, HIP_SYMBOL(scratch)) != hipSuccess || !base) {
+    (void)hipGetLastError();
+    return -102;
+  }
+  unsigned char* b = (unsigned char*)base;
+  schur_handle_s* h = new schur_handle_s();
+  h->device = dev;
+  h->U = (double*)b;      b += kNaU;
+  h->refl = (double*)b;   b += kNaRefl;
+  h->st = (double*)b;     b += kNaVec;
+  h->ewr = (double*)b;    b += kNaVec;
+  h->ewi = (double*)b;    b += kNaVec;
+  h->ctrl = (Ctrl*)b;     b += kNaCtrl;
+  h->bcount = (int*)b;    b += kNaCount;
+  h->blist = (int*)b;
+  h->blist_cap = kNaBlist;
+  h->ctrl_h = &d.ctrl_host;
+  d.h = h;
+  return 0;
+}
+
+int solve_noalloc(hipStream_t s, int n, double* H, int ldh, double* Q, int ldq, double* wr,
+                  double* wi) {
+  int rc = check_args(n, H, ldh, Q, ldq, wr, wi);
+  if (rc != 0) return rc;
+  if (n > SCHUR_NOALLOC_MAX_N) return -106;
+  if (n == 0) return 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -102;
+  rc = noalloc_setup(dev);
+  if (rc) return rc;
+  NoAllocDev& d = g_na[dev];
+  std::lock_guard<std::mutex> lk(d.mu);
+  schur_handle_s* h = d.h;
+  try {
+    std::memset(&h->stats, 0, sizeof(h->stats));
+    Params P = resolve(schur_opts{}, n);
+    P.split_nw = 0;                        // the passes need per-window workspace
+    P.ns = std::min(P.ns, SMALL_EIG_MAX);  // shifts without a nested solve
+    P.time = false;                        // timing needs events
+    Solver sv{h, s, P, n, H, ldh, Q, ldq, wr, wi};
+    sv.one_stream = true;
+    return sv.run();
+  } catch (const HipErr& e) {
+    (void)hipGetLastError();
+    return -102;
   }
 }
 
@@ -2129,6 +2235,11 @@ int schur_reduce(int n, double* H, int ldh, double* Q, int ldq, double* wr, doub
   }
   std::lock_guard<std::mutex> lk(g_mu);
   return solve(h, h->stream, n, H, ldh, Q, ldq, wr, wi);
+}
+
+int schur_reduce_noalloc(void* stream, int n, double* H, int ldh, double* Q, int ldq,
+                         double* wr, double* wi) {
+  return solve_noalloc((hipStream_t)stream, n, H, ldh, Q, ldq, wr, wi);
 }
 
 int schur_hessenberg(schur_handle_t h, void* stream, int n, double* A, int lda, double* Q,

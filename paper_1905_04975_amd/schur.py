@@ -63,7 +63,7 @@ EXPORTS = ("schur_reduce", "schur_create", "schur_destroy", "schur_set_opts",
            "schur_server_create", "schur_server_destroy", "schur_submit", "schur_poll",
            "schur_server_get_stats", "schur_set_tuning", "schur_plan_sweep",
            "schur_plan_split", "schur_select_windows", "schur_split_weight",
-           "schur_hessenberg")
+           "schur_reduce_noalloc", "schur_hessenberg")
 
 TUNING_PATH = os.path.join(HERE, "tuning.json")
 
@@ -109,6 +109,8 @@ def load():
     lib.schur_reduce_async.restype = ctypes.c_int
     lib.schur_hessenberg.argtypes = [vp, vp, ip, dp, ip, dp, ip]
     lib.schur_hessenberg.restype = ctypes.c_int
+    lib.schur_reduce_noalloc.argtypes = [vp, ip, dp, ip, dp, ip, dp, dp]
+    lib.schur_reduce_noalloc.restype = ctypes.c_int
     pint = ctypes.POINTER(ctypes.c_int)
     pptr = ctypes.POINTER(ctypes.c_void_p)
     lib.schur_reduce_batched.argtypes = [vp, vp, ip, pint, pptr, pint, pptr, pint, pptr, pptr, pint]
@@ -147,6 +149,13 @@ def load():
 def schur_reduce(n, H, ldh, Q, ldq, wr, wi):
     """C ``schur_reduce`` with raw device pointers (ints); returns info."""
     return load().schur_reduce(int(n), H, int(ldh), Q, int(ldq), wr, wi)
+
+
+def schur_reduce_noalloc(stream, n, H, ldh, Q, ldq, wr, wi):
+    """C ``schur_reduce_noalloc`` (workspace in a static device array, no
+    allocation) with raw device pointers (ints) and a hipStream_t (int or
+    None); returns info."""
+    return load().schur_reduce_noalloc(stream, int(n), H, int(ldh), Q, int(ldq), wr, wi)
 
 
 class Handle:
