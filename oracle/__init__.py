@@ -13,7 +13,9 @@ The arithmetic lives in plain C files (binary64, no BLAS):
   Eq. (3); Golub & Van Loan, Sec. 7.4.3);
 * ``oracle_evec.c`` -- eigenvectors of a real Schur form by back
   substitution with overflow protection, and their backtransform (Sec. 2,
-  Eqs. (5) and (6)).
+  Eqs. (5) and (6));
+* ``oracle_reorder.c`` -- reordering of a real Schur form so that selected
+  eigenvalues lead, by swaps of adjacent diagonal blocks (Sec. 2, Eq. (7)).
 
 This module only builds those files with ``gcc`` and marshals numpy arrays
 (column-major, Fortran order) through ``ctypes``.
@@ -28,7 +30,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, f) for f in ("oracle_schur.c", "oracle_hess.c",
-                                                 "oracle_evec.c")]
+                                                 "oracle_evec.c", "oracle_reorder.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -64,6 +66,9 @@ def _bind(path):
     lib.oracle_eigenvectors.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int, dp,
                                         ctypes.c_int]
     lib.oracle_eigenvectors.restype = ctypes.c_int
+    lib.oracle_reorder.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int, ip, dp, dp,
+                                   ip]
+    lib.oracle_reorder.restype = ctypes.c_int
     return lib
 
 
@@ -198,3 +203,27 @@ def complex_vectors(S, X):
             V[:, k] = X[:, k]
             k += 1
     return lam, V
+
+
+def reorder(S, select, Q=None, want_q=True, lib=None):
+    """Reorder the real Schur form ``S`` so that the selected eigenvalues
+    lead (paper Sec. 2, Eq. (7)).  Returns ``(S', Q, wr, wi, m, info)``
+    with ``S = Q3 S' Q3^T`` (``Q`` is ``Q_in @ Q3``), ``m`` the number of
+    selected eigenvalues, ``info`` 1 when a swap was rejected."""
+    lib = lib or _load()
+    S = np.array(S, dtype=np.float64, order="F", copy=True)
+    n = S.shape[0]
+    sel = np.ascontiguousarray(np.asarray(select, dtype=np.int32).reshape(n))
+    if want_q:
+        Qm = np.eye(n, order="F") if Q is None else np.array(Q, dtype=np.float64, order="F",
+                                                               copy=True)
+        qptr = _dptr(Qm)
+    else:
+        Qm, qptr = None, None
+    wr = np.zeros(n)
+    wi = np.zeros(n)
+    m = ctypes.c_int(0)
+    info = lib.oracle_reorder(n, _dptr(S) if n else None, max(1, n), qptr, max(1, n),
+                              sel.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dptr(wr),
+                              _dptr(wi), ctypes.byref(m))
+    return S, Qm, wr, wi, int(m.value), int(info)

@@ -19,7 +19,8 @@ from tests.test_oracle import _cyclic, second_adhoc_step_error
 U = 2.0 ** -53
 ODIR = os.path.dirname(oracle.__file__)
 SRC = os.path.join(ODIR, "oracle_schur.c")
-SOURCES = [os.path.join(ODIR, f) for f in ("oracle_schur.c", "oracle_hess.c", "oracle_evec.c")]
+SOURCES = [os.path.join(ODIR, f) for f in ("oracle_schur.c", "oracle_hess.c", "oracle_evec.c",
+                                                  "oracle_reorder.c")]
 
 MUTANTS = {
     "shift_product_sign": ("- s * h00 + t;", "- s * h00 - t;"),
