@@ -144,6 +144,16 @@ typedef struct schur_stats {
                             /* matrix-vector products (8 per entry and column)  */
   double hess_gemm_ms;      /* summed duration of the panels' products (TIME)   */
   double hess_gemm_flops;   /* flops of those products                          */
+  /* schur_eigenvectors */
+  double ev_solve_ms;       /* summed duration of the tile solves (TIME)        */
+  double ev_gemm_ms;        /* summed duration of the tile-row updates (TIME)   */
+  double ev_gemm_flops;     /* flops of those updates                           */
+  double ev_back_ms;        /* duration of the backtransform product (TIME)     */
+  double ev_back_flops;     /* its flops (2 n^3)                                */
+  /* schur_reorder */
+  double reorder_ms;        /* summed duration of the window tasks (TIME)       */
+  int64_t reorder_windows;  /* windows processed                                */
+  int64_t reorder_steps;    /* time steps (launches of window tasks)            */
 } schur_stats;
 
 /* --------------------------------------------------------------------------
@@ -198,6 +208,82 @@ int schur_reduce_async(schur_handle_t h, void* stream, int n, double* H, int ldh
  * ------------------------------------------------------------------------ */
 int schur_hessenberg(schur_handle_t h, void* stream, int n, double* A, int lda, double* Q,
                      int ldq);
+
+/* --------------------------------------------------------------------------
+ * schur_eigenvectors -- eigenvectors of a real Schur form and their
+ * backtransform (paper Sec. 2, Eqs. (5) and (6)), the step after the Schur
+ * reduction: with S and Q = Q1 Q2 from schur_hessenberg and schur_reduce,
+ * X holds the eigenvectors of A.
+ *   h        handle (its workspace; stream NULL = the handle's stream)
+ *   n        order, n >= 0
+ *   S        device, lds x n, read only: a standardised real Schur form (as
+ *            schur_reduce returns it: 2x2 blocks with equal diagonal and
+ *            off-diagonal entries of opposite sign, exact zeros elsewhere
+ *            below the diagonal)
+ *   lds      >= max(1, n)
+ *   Q        device, ldq x n or NULL, read only: X = Q Y (NULL: X = Y, the
+ *            eigenvectors of S)
+ *   ldq      >= max(1, n) when Q != NULL
+ *   X        device, ldx x n, output (must not overlap S or Q): LAPACK's
+ *            real layout -- column k a real eigenvector, columns k and k+1
+ *            the real and imaginary parts of the eigenvector of the
+ *            eigenvalue with positive imaginary part of the 2x2 block at
+ *            rows k, k+1; each eigenvector scaled to largest |Re| + |Im| = 1
+ *   ldx      >= max(1, n)
+ * Conventions (LAPACK's): y(p) = 1 at the row p of a real eigenvalue,
+ * zeros below; for a pair (y(p), y(p+1)) = (1, i wi / S(p,p+1)) when
+ * |S(p,p+1)| >= |S(p+1,p)|, else (-wi / S(p+1,p), i); pivots smaller than
+ * max(ulp |lambda|, tiny) are raised to that.  Overflow protection: every
+ * vector is scaled down before a division or update could pass ~2^960.
+ * Work is enqueued on the stream after one read of S's subdiagonal (a
+ * synchronisation) that places the tiles; results are final when the stream
+ * reaches them.  With Q the handle keeps an n x n workspace.  Returns 0,
+ * -1 (n), -2 (S), -3 (lds), -5 (ldq), -6 (X), -7 (ldx), -101, -102, -103,
+ * -104.
+ * ------------------------------------------------------------------------ */
+int schur_eigenvectors(schur_handle_t h, void* stream, int n, const double* S, int lds,
+                       const double* Q, int ldq, double* X, int ldx);
+
+/* --------------------------------------------------------------------------
+ * schur_reorder -- eigenvalue reordering (paper Sec. 2, Eq. (7)): an
+ * orthogonal Q3 with S = Q3 S' Q3^T, S' a standardised real Schur form whose
+ * leading m x m block carries exactly the selected eigenvalues, keeping
+ * their diagonal order; Q <- Q Q3.  With S and Q = Q1 Q2 from the previous
+ * steps, the first m columns of Q span the invariant subspace of A for the
+ * selected eigenvalues.
+ *   h        handle (its workspace; stream NULL = the handle's stream)
+ *   n        order, n >= 0
+ *   S        device, lds x n; in: a standardised real Schur form (as
+ *            schur_reduce returns it); out: S'
+ *   lds      >= max(1, n)
+ *   Q        device, ldq x n or NULL; in: Q_in; out: Q_in Q3
+ *   ldq      >= max(1, n) when Q != NULL
+ *   select   HOST, n ints: select[k] != 0 selects eigenvalue k (either row
+ *            of a 2x2 block selects the pair)
+ *   wr, wi   device, n doubles each: the eigenvalues of S' (diagonal order)
+ *   m        HOST int or NULL: the number of selected eigenvalues
+ * Method (Sec. 3.2): chunks of at most 32 selected rows travel to the top
+ * through chains of diagonal windows (at most 96 rows, in LDS) in which
+ * adjacent blocks are swapped (2x2 and 3x3 / 4x4 Householder reflectors from
+ * the Sylvester equation of the two blocks), each window's factor applied
+ * to the rest of S and to Q as FP64 MFMA products; chains of later chunks
+ * follow a few time steps behind.  Returns 0; 1 when a swap was rejected as
+ * unstable (eigenvalues too close to separate, LAPACK's convention: S and Q
+ * are then a valid but only partly reordered pair); -1 (n), -2 (S),
+ * -3 (lds), -5 (ldq), -6 (select), -7 (wr), -8 (wi), -101, -102, -103, -104.
+ * Synchronises at the start (S's subdiagonal, for the plan) and at the end.
+ * ------------------------------------------------------------------------ */
+int schur_reorder(schur_handle_t h, void* stream, int n, double* S, int lds, double* Q, int ldq,
+                  const int* select, double* wr, double* wi, int* m);
+
+/* --------------------------------------------------------------------------
+ * Reordering schedule (host-only diagnostic of the library's planner, no
+ * device work): for blocks of orders bsize[i] (1 or 2, summing to n) with
+ * selection flags bsel[i], the window chains of schur_reorder.  Writes up
+ * to `cap` records of 4 ints (chain, time step, first row, order) to `out`;
+ * returns the number of windows (which may exceed cap) or -1.
+ * ------------------------------------------------------------------------ */
+int schur_plan_reorder(int n, const int* bsize, const int* bsel, int nblocks, int* out, int cap);
 
 /* --------------------------------------------------------------------------
  * schur_reduce_noalloc -- the Schur reduction of schur_reduce for callers

@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "../../include/schur.h"
+#include "evec.h"
 #include "hess.h"
 #include "kernels.h"
 #include "schur_internal.h"
@@ -134,6 +135,10 @@ struct schur_handle_s {
   // Hessenberg reduction: V and Y of a panel, T / tau / pivot, per-workgroup
   // partials, partial matrix-vector products, product scratch
   Grow b_hvy, b_ht, b_hp, b_hy, b_hw;
+  // eigenvectors: Y when they are backtransformed, per-column bounds
+  Grow b_evy, b_evb;
+  // reordering: row flags + info, window tasks, panel descriptors, U slots
+  Grow b_rsel, b_rtask, b_rwin, b_ru;
   // nested solve of a trailing block larger than SMALL_EIG_MAX (shifts only)
   schur_handle_s* sub = nullptr;
   // buffers of the parallel early-deflation passes that the batched engine
@@ -295,7 +300,8 @@ void free_ws(schur_handle_s* h) {
   free_grow(h->b_splt); free_grow(h->b_splr); free_grow(h->b_splu); free_grow(h->b_splz);
   free_grow(h->b_splw); free_grow(h->b_splq); free_grow(h->b_splb);
   free_grow(h->b_hvy); free_grow(h->b_ht); free_grow(h->b_hp); free_grow(h->b_hy);
-  free_grow(h->b_hw);
+  free_grow(h->b_hw); free_grow(h->b_evy); free_grow(h->b_evb);
+  free_grow(h->b_rsel); free_grow(h->b_rtask); free_grow(h->b_rwin); free_grow(h->b_ru);
   if (h->U) (void)hipFree(h->U);
   if (h->refl) (void)hipFree(h->refl);
   if (h->st) (void)hipFree(h->st);
@@ -1263,6 +1269,333 @@ int hess_reduce(schur_handle_s* h, hipStream_t s, int n, double* A, int lda, dou
       h->timer.harvest();
     }
     return 0;
+  } catch (const HipErr& e) {
+    (void)hipGetLastError();
+    return e.e == hipErrorOutOfMemory ? -101 : -102;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Eigenvectors of a real Schur form (paper Sec. 2, Eqs. (5) and (6)): tile
+// rows of about 64 (never splitting a 2x2 block) from the bottom; per tile
+// row one launch solves the tile's rows of every eigenvector with entries
+// there (overflow-protected back substitution, one thread per eigenvalue)
+// and one FP64 MFMA product updates every row above; then the backtransform
+// X = Q Y as one product and the normalisation.  The only host
+// synchronisation is the read of S's subdiagonal that places the tiles.
+// ---------------------------------------------------------------------------
+int evec_compute(schur_handle_s* h, hipStream_t s, int n, const double* S, int lds,
+                 const double* Q, int ldq, double* X, int ldx) {
+  if (n < 0 || n > 524288) return -1;
+  if (n == 0) return 0;
+  if (!S) return -2;
+  if (lds < std::max(1, n)) return -3;
+  if (Q && ldq < std::max(1, n)) return -5;
+  if (!X) return -6;
+  if (ldx < std::max(1, n)) return -7;
+  if (!is_device_ptr(S) || (Q && !is_device_ptr(Q)) || !is_device_ptr(X)) return -103;
+  try {
+    HCHECK(hipSetDevice(h->device));
+    std::memset(&h->stats, 0, sizeof(h->stats));
+    // tile rows: about 64 rows, extended by one where a 2x2 block would be split
+    std::vector<double> sub(std::max(1, n - 1), 0.0);
+    if (n > 1) {
+      HCHECK(hipMemcpy2DAsync(sub.data(), sizeof(double), S + 1, sizeof(double) * (lds + 1),
+                              sizeof(double), n - 1, hipMemcpyDeviceToHost, s));
+      HCHECK(hipStreamSynchronize(s));
+    }
+    std::vector<int> bnd{0};
+    while (bnd.back() < n) {
+      int e = std::min(n, bnd.back() + 64);
+      if (e < n && sub[e - 1] != 0.0) ++e;   // S(e, e-1) != 0: rows e-1, e form a block
+      if (e - bnd.back() > EVTMAX) throw HipErr{hipErrorInvalidValue};
+      bnd.push_back(e);
+    }
+    double* Y = X;
+    int ldy = ldx;
+    if (Q) {
+      Y = (double*)grow(h->b_evy, sizeof(double) * (size_t)n * n, false);
+      ldy = n;
+    }
+    double* wb = (double*)grow(h->b_evb, sizeof(double) * 2 * (size_t)n, false);
+    EvArgs g{S, lds, Y, ldy, n, wb, wb + n};
+    const bool time = (h->opts.flags & SCHUR_FLAG_TIME_KERNELS) != 0;
+    hipEvent_t e0 = nullptr;
+    launch_ev_prep(g, s);
+    HCHECK(hipGetLastError());
+    for (int t = (int)bnd.size() - 2; t >= 0; --t) {
+      const int r0 = bnd[t], r1 = bnd[t + 1];
+      if (time) h->timer.begin(s, e0);
+      launch_ev_diag(g, r0, r1, s);
+      HCHECK(hipGetLastError());
+      if (time) h->timer.end(s, e0, &h->stats.ev_solve_ms);
+      if (r0 > 0) {
+        if (time) h->timer.begin(s, e0);
+        launch_gemm(false, false, r0, n - r0, r1 - r0, -1.0, S + (size_t)r0 * lds, lds,
+                    Y + r0 + (size_t)r0 * ldy, ldy, 1.0, Y + (size_t)r0 * ldy, ldy, s);
+        HCHECK(hipGetLastError());
+        if (time) h->timer.end(s, e0, &h->stats.ev_gemm_ms);
+        h->stats.ev_gemm_flops += 2.0 * r0 * (double)(n - r0) * (r1 - r0);
+      }
+      h->stats.launches += 1 + (r0 > 0);
+    }
+    if (Q) {
+      if (time) h->timer.begin(s, e0);
+      launch_gemm(false, false, n, n, n, 1.0, Q, ldq, Y, ldy, 0.0, X, ldx, s);
+      HCHECK(hipGetLastError());
+      if (time) h->timer.end(s, e0, &h->stats.ev_back_ms);
+      h->stats.ev_back_flops += 2.0 * n * (double)n * n;
+      h->stats.launches += 1;
+    }
+    launch_ev_normalise(X, ldx, S, lds, n, s);
+    HCHECK(hipGetLastError());
+    h->stats.launches += 3;
+    if (time) {
+      HCHECK(hipStreamSynchronize(s));
+      h->timer.harvest();
+    }
+    return 0;
+  } catch (const HipErr& e) {
+    (void)hipGetLastError();
+    return e.e == hipErrorOutOfMemory ? -101 : -102;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Eigenvalue reordering (paper Sec. 2, Eq. (7); Sec. 3.2): the selected
+// blocks move to the top in chunks of at most kReorderChunk rows, in
+// diagonal order.  A chunk travels up through a chain of diagonal windows
+// of at most SMALL_Z_MAX rows: each window holds the chunk's blocks gathered
+// so far at its bottom (plus any further blocks of the chunk it covers) and
+// moves them to its top; the window's orthogonal factor goes to the row
+// panel right of it, the column panel above it and Q.  Chains of later
+// chunks follow in lock-step a few time steps behind, each window strictly
+// below the windows of earlier chunks at the same time step, so every time
+// step is one launch of window tasks and one launch each of left and right
+// updates, in a sequentially consistent order (the window / right / left
+// update task structure of Sec. 3.2).  The whole schedule is planned on the
+// host from the block structure and the selection before anything runs.
+// ---------------------------------------------------------------------------
+constexpr int kReorderChunk = 32;
+
+struct RWin { int a, w; };
+
+// Plan: per chain (chunk) its windows, per chain its start time step.
+// blocks: sizes in diagonal order; sel: selected flags per block.
+void plan_reorder(int n, std::vector<int> bsz, std::vector<char> bsel, int W,
+                  std::vector<std::vector<RWin>>& chains, std::vector<int>& start) {
+  chains.clear();
+  start.clear();
+  const int nb = (int)bsz.size();
+  // row of each block start in the current (simulated) layout
+  int ilst = 0, i = 0;
+  while (i < nb && bsel[i]) ilst += bsz[i++];   // already leading
+  while (true) {
+    // the next chunk: selected blocks in order, at most kReorderChunk rows
+    // (a block larger than that still forms a chunk of its own)
+    int pos = ilst, j = i, kc = 0, last_end = -1, jl = -1;
+    std::vector<int> pick;
+    for (; j < nb; ++j) {
+      if (bsel[j]) {
+        if (kc > 0 && kc + bsz[j] > kReorderChunk) break;
+        kc += bsz[j];
+        last_end = pos + bsz[j];
+        jl = j;
+        pick.push_back(j);
+      }
+      pos += bsz[j];
+    }
+    if (kc == 0) break;
+    // blocks i .. jl cover rows [ilst, last_end): simulate the chain on them
+    std::vector<int> lsz(bsz.begin() + i, bsz.begin() + jl + 1);
+    std::vector<char> lsel(bsel.begin() + i, bsel.begin() + jl + 1);
+    std::vector<RWin> chain;
+    int bot = last_end;
+    while (true) {
+      int top = std::max(ilst, bot - W);
+      // align top to a block start (never split a 2x2 block)
+      int r = ilst;
+      size_t b = 0;
+      while (b < lsz.size() && r + lsz[b] <= top) r += lsz[b++];
+      if (r < top) { r += lsz[b]; ++b; }
+      top = r;
+      const size_t b0 = b;
+      size_t b1 = b0;
+      int rr = top;
+      while (b1 < lsz.size() && rr < bot) rr += lsz[b1++];
+      // stable partition of the window's blocks: the chunk's first
+      std::vector<int> s1, s2;
+      std::vector<char> f1, f2;
+      int kin = 0;
+      for (size_t q = b0; q < b1; ++q) {
+        if (lsel[q]) { s1.push_back(lsz[q]); f1.push_back(1); kin += lsz[q]; }
+        else { s2.push_back(lsz[q]); f2.push_back(0); }
+      }
+      size_t q = b0;
+      for (size_t u = 0; u < s1.size(); ++u, ++q) { lsz[q] = s1[u]; lsel[q] = 1; }
+      for (size_t u = 0; u < s2.size(); ++u, ++q) { lsz[q] = s2[u]; lsel[q] = 0; }
+      chain.push_back({top, bot - top});
+      if (top <= ilst) break;
+      bot = top + kin;
+    }
+    chains.push_back(chain);
+    // the global layout after the chunk: its blocks first, the rest in order
+    for (size_t q = 0; q < lsz.size(); ++q) { bsz[i + q] = lsz[q]; bsel[i + q] = lsel[q]; }
+    // blocks moved to the top are done; mark them unselected for later chunks
+    int moved = 0;
+    while (moved < kc) { moved += bsz[i]; bsel[i] = 0; ++i; }
+    ilst += kc;
+  }
+  // start times: each chain a time step after the previous one at least, and
+  // at every time step strictly below the windows of all earlier chains
+  for (size_t c = 0; c < chains.size(); ++c) {
+    int s0 = c == 0 ? 0 : start[c - 1] + 1;
+    for (;; ++s0) {
+      bool ok = true;
+      for (size_t d = 0; d < c && ok; ++d) {
+        for (size_t t = 0; t < chains[c].size() && ok; ++t) {
+          const int tt = s0 + (int)t - start[d];
+          if (tt < 0 || tt >= (int)chains[d].size()) continue;
+          const RWin& x = chains[c][t];
+          const RWin& y = chains[d][tt];
+          if (x.a < y.a + y.w) ok = false;
+        }
+      }
+      if (ok) break;
+    }
+    start.push_back(s0);
+  }
+}
+
+int reorder_run(schur_handle_s* h, hipStream_t s, int n, double* S, int lds, double* Q, int ldq,
+                const int* select, double* wr, double* wi, int* m_out) {
+  if (n < 0 || n > 524288) return -1;
+  if (n == 0) { if (m_out) *m_out = 0; return 0; }
+  if (!S) return -2;
+  if (lds < std::max(1, n)) return -3;
+  if (Q && ldq < std::max(1, n)) return -5;
+  if (!select) return -6;
+  if (!wr) return -7;
+  if (!wi) return -8;
+  if (!is_device_ptr(S) || (Q && !is_device_ptr(Q)) || !is_device_ptr(wr) || !is_device_ptr(wi))
+    return -103;
+  try {
+    HCHECK(hipSetDevice(h->device));
+    std::memset(&h->stats, 0, sizeof(h->stats));
+    int rc = alloc_ws(h, n);
+    if (rc) return rc;
+    // block structure from S's subdiagonal
+    std::vector<double> sub(std::max(1, n - 1), 0.0);
+    if (n > 1) {
+      HCHECK(hipMemcpy2DAsync(sub.data(), sizeof(double), S + 1, sizeof(double) * (lds + 1),
+                              sizeof(double), n - 1, hipMemcpyDeviceToHost, s));
+      HCHECK(hipStreamSynchronize(s));
+    }
+    std::vector<int> bsz;
+    std::vector<char> bsel;
+    std::vector<unsigned char> rows(n, 0);
+    int m = 0;
+    for (int k = 0; k < n;) {
+      const int sz = (k + 1 < n && sub[k] != 0.0) ? 2 : 1;
+      const bool on = select[k] != 0 || (sz == 2 && select[k + 1] != 0);
+      bsz.push_back(sz);
+      bsel.push_back(on ? 1 : 0);
+      for (int q = 0; q < sz; ++q) rows[k + q] = on ? 1 : 0;
+      if (on) m += sz;
+      k += sz;
+    }
+    if (m_out) *m_out = m;
+    std::vector<std::vector<RWin>> chains;
+    std::vector<int> start;
+    plan_reorder(n, bsz, bsel, SMALL_Z_MAX, chains, start);
+    int T = 0;
+    for (size_t c = 0; c < chains.size(); ++c) T = std::max(T, start[c] + (int)chains[c].size());
+    // windows per time step (top to bottom = chains in order)
+    std::vector<std::vector<RWin>> steps(T);
+    for (size_t c = 0; c < chains.size(); ++c)
+      for (size_t t = 0; t < chains[c].size(); ++t) steps[start[c] + t].push_back(chains[c][t]);
+    size_t total = 0, maxw = 1;
+    for (const auto& st : steps) { total += st.size(); maxw = std::max(maxw, st.size()); }
+    // device buffers: row flags (+ info), tasks and panel descriptors of the
+    // whole schedule, U slots for the widest time step
+    unsigned char* seld = (unsigned char*)grow(h->b_rsel, (size_t)n + 64, true);
+    int* infod = (int*)(seld + (((size_t)n + 15) & ~(size_t)15));
+    std::memcpy(h->b_rsel.host, rows.data(), (size_t)n);
+    std::memset((unsigned char*)h->b_rsel.host + (((size_t)n + 15) & ~(size_t)15), 0, sizeof(int));
+    HCHECK(hipMemcpyAsync(seld, h->b_rsel.host, (((size_t)n + 15) & ~(size_t)15) + sizeof(int),
+                          hipMemcpyHostToDevice, s));
+    double* uslots =
+        (double*)grow(h->b_ru, sizeof(double) * (size_t)UPAD * UPAD * maxw, false);
+    ReorderTask* td = (ReorderTask*)grow(h->b_rtask, sizeof(ReorderTask) * std::max<size_t>(1, total), true);
+    WinB* wd = (WinB*)grow(h->b_rwin, sizeof(WinB) * std::max<size_t>(1, total), true);
+    ReorderTask* th = (ReorderTask*)h->b_rtask.host;
+    WinB* wh = (WinB*)h->b_rwin.host;
+    std::vector<int> tr_t(T, 0), tcq_t(T, 0);
+    std::vector<size_t> off(T + 1, 0);
+    for (int t = 0; t < T; ++t) {
+      off[t + 1] = off[t] + steps[t].size();
+      int tr = 0, tcq = 0;
+      for (size_t q = 0; q < steps[t].size(); ++q) {
+        const RWin& rw = steps[t][q];
+        if (rw.w < 1 || rw.w > SMALL_Z_MAX || rw.a < 0 || rw.a + rw.w > n)
+          throw HipErr{hipErrorInvalidValue};
+        const size_t k = off[t] + q;
+        double* slot = uslots + q * (size_t)UPAD * UPAD;
+        ReorderTask& rt = th[k];
+        std::memset(&rt, 0, sizeof(rt));
+        rt.S = S; rt.lds = lds; rt.a = rw.a; rt.w = rw.w; rt.sel = seld;
+        rt.Ut = slot; rt.ldut = UPAD; rt.info = infod;
+        WinB& w = wh[k];
+        std::memset(&w, 0, sizeof(w));
+        w.c.H = S; w.c.Q = Q; w.c.U = slot; w.c.st = nullptr;
+        w.c.ldh = lds; w.c.ldq = ldq; w.c.n = n;
+        w.c.ktop = 0; w.c.kbot = n - 1; w.c.rtop = 0; w.c.cend = n;
+        w.c.p = rw.a; w.c.ws = rw.w;
+        fill_tiles_b(w, tr, tcq, h->stats);
+      }
+      tr_t[t] = tr;
+      tcq_t[t] = tcq;
+    }
+    if (total > 0) {
+      HCHECK(hipMemcpyAsync(td, th, sizeof(ReorderTask) * total, hipMemcpyHostToDevice, s));
+      HCHECK(hipMemcpyAsync(wd, wh, sizeof(WinB) * total, hipMemcpyHostToDevice, s));
+    }
+    const bool time = (h->opts.flags & SCHUR_FLAG_TIME_KERNELS) != 0;
+    hipEvent_t e0 = nullptr;
+    for (int t = 0; t < T; ++t) {
+      const int nw = (int)steps[t].size();
+      if (nw == 0) continue;
+      if (time) h->timer.begin(s, e0);
+      launch_reorder(td + off[t], nw, s);
+      HCHECK(hipGetLastError());
+      if (time) h->timer.end(s, e0, &h->stats.reorder_ms);
+      if (tr_t[t] > 0) {
+        if (time) h->timer.begin(s, e0);
+        launch_panel_row_b(wd + off[t], nw, tr_t[t], s);
+        HCHECK(hipGetLastError());
+        if (time) h->timer.end(s, e0, &h->stats.row_ms);
+        h->stats.row_launches += 1;
+      }
+      if (tcq_t[t] > 0) {
+        if (time) h->timer.begin(s, e0);
+        launch_panel_colq_b(wd + off[t], nw, tcq_t[t], s);
+        HCHECK(hipGetLastError());
+        if (time) h->timer.end(s, e0, &h->stats.colq_ms);
+        h->stats.colq_launches += 1;
+      }
+      h->stats.launches += 1 + (tr_t[t] > 0) + (tcq_t[t] > 0);
+      h->stats.reorder_windows += nw;
+    }
+    h->stats.reorder_steps = T;
+    // eigenvalues in the new diagonal order (the blocks are standard already)
+    launch_standardize(S, lds, Q, ldq, n, 1, wr, wi, h->blist, h->bcount, h->blist_cap, s);
+    HCHECK(hipGetLastError());
+    int info = 0;
+    HCHECK(hipMemcpyAsync(&info, infod, sizeof(int), hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    if (time) h->timer.harvest();
+    h->stats.gemm_ms = h->stats.row_ms + h->stats.colq_ms;
+    return info ? 1 : 0;
   } catch (const HipErr& e) {
     (void)hipGetLastError();
     return e.e == hipErrorOutOfMemory ? -101 : -102;
@@ -2246,6 +2579,45 @@ int schur_hessenberg(schur_handle_t h, void* stream, int n, double* A, int lda, 
                      int ldq) {
   if (!h) return -104;
   return hess_reduce(h, stream ? (hipStream_t)stream : h->stream, n, A, lda, Q, ldq);
+}
+
+int schur_eigenvectors(schur_handle_t h, void* stream, int n, const double* S, int lds,
+                       const double* Q, int ldq, double* X, int ldx) {
+  if (!h) return -104;
+  return evec_compute(h, stream ? (hipStream_t)stream : h->stream, n, S, lds, Q, ldq, X, ldx);
+}
+
+int schur_reorder(schur_handle_t h, void* stream, int n, double* S, int lds, double* Q, int ldq,
+                  const int* select, double* wr, double* wi, int* m) {
+  if (!h) return -104;
+  return reorder_run(h, stream ? (hipStream_t)stream : h->stream, n, S, lds, Q, ldq, select, wr,
+                     wi, m);
+}
+
+int schur_plan_reorder(int n, const int* bsize, const int* bsel, int nblocks, int* out, int cap) {
+  if (n < 0 || nblocks < 0 || (nblocks > 0 && (!bsize || !bsel))) return -1;
+  std::vector<int> bs(bsize, bsize + nblocks);
+  std::vector<char> sl(nblocks);
+  int tot = 0;
+  for (int i = 0; i < nblocks; ++i) {
+    if (bs[i] != 1 && bs[i] != 2) return -1;
+    sl[i] = bsel[i] ? 1 : 0;
+    tot += bs[i];
+  }
+  if (tot != n) return -1;
+  std::vector<std::vector<RWin>> chains;
+  std::vector<int> start;
+  plan_reorder(n, bs, sl, SMALL_Z_MAX, chains, start);
+  int k = 0;
+  for (size_t c = 0; c < chains.size(); ++c)
+    for (size_t t = 0; t < chains[c].size(); ++t, ++k)
+      if (out && k < cap) {
+        out[4 * k] = (int)c;
+        out[4 * k + 1] = start[c] + (int)t;
+        out[4 * k + 2] = chains[c][t].a;
+        out[4 * k + 3] = chains[c][t].w;
+      }
+  return k;
 }
 
 int schur_reduce_async(schur_handle_t h, void* stream, int n, double* H, int ldh, double* Q,

@@ -61,6 +61,21 @@ struct SplitCommit {
   int fix_below;               // 1: scale H(a+nw, a+nw-1) (no committed window below)
 };
 
+// One diagonal window S(a:a+w, a:a+w) of a real Schur form (standardised
+// 1x1 / 2x2 blocks; the window starts and ends at block boundaries) in
+// eigenvalue reordering.  The selected rows (flag 1 in sel[a .. a+w)) form
+// whole blocks; the window task moves them to the top of the window,
+// keeping their order, by swaps of adjacent diagonal blocks, and writes the
+// window's orthogonal factor (transposed) to Ut.  w <= SMALL_Z_MAX.
+struct ReorderTask {
+  double* S; int lds;
+  int a, w;
+  unsigned char* sel;          // per row of S: 1 = selected (updated in place)
+  double* Ut; int ldut;        // U^T of the window, zero padded to ldut x ldut
+  int* info;                   // set to 1 when a swap is rejected
+  int pad;
+};
+
 // One matrix of a batched deflation scan.
 struct DeflB {
   double* H; double* Q; double* wr; double* wi;
@@ -82,6 +97,7 @@ void launch_small_eig(const SmallTask& t, hipStream_t s);
 void launch_aed(const AedTask& t, hipStream_t s);
 void launch_aed_b(const AedTask* tasks, int count, hipStream_t s);
 void launch_split(const SplitTask* tasks, int count, hipStream_t s);
+void launch_reorder(const ReorderTask* tasks, int count, hipStream_t s);
 void launch_split_commit(const SplitCommit* cm, int count, const SplitTask* tasks, hipStream_t s);
 void launch_split_scan(double* H, int ldh, int n, unsigned char* zero, hipStream_t s);
 void launch_slot_ident(double* U, const int* sizes, int count, hipStream_t s);

@@ -18,6 +18,7 @@
 #include "kernels.h"
 #include "wave_solvers.h"
 #include "window_chase.h"
+#include "reorder_window.h"
 
 namespace schur {
 
@@ -52,6 +53,20 @@ __global__ __launch_bounds__(64) void k_aed(AedTask t0, const AedTask* tasks) {
   __shared__ int ibuf[6 * MAXM];
   __shared__ double stdbuf[7 * MAXM];
   aed_window<MAXM>(T, S, Z, vv, ibuf, stdbuf);
+}
+
+// One window of eigenvalue reordering per workgroup (one wavefront, window
+// and its accumulated orthogonal factor in LDS).
+template <int MAXM>
+__global__ __launch_bounds__(64) void k_reorder(const ReorderTask* tasks) {
+  const ReorderTask T = tasks[blockIdx.x];
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  __shared__ double S[LD * MAXM];
+  __shared__ double Z[LD * MAXM];
+  __shared__ int status[MAXM];
+  __shared__ int ibuf[4 * (MAXM / 2 + 1)];
+  __shared__ double pbuf[7 * MAXM + 16];   // swap plans, then the standardisation
+  reorder_window<MAXM>(T, S, Z, status, ibuf, pbuf);
 }
 
 // One window of a parallel early-deflation pass per workgroup (one wavefront,
@@ -873,6 +888,11 @@ void launch_aed(const AedTask& t, hipStream_t s) {
 void launch_aed_b(const AedTask* tasks, int count, hipStream_t s) {
   if (count > 0)
     hipLaunchKernelGGL((k_aed<SMALL_Z_MAX>), dim3(count), dim3(64), 0, s, AedTask{}, tasks);
+}
+
+void launch_reorder(const ReorderTask* tasks, int count, hipStream_t s) {
+  if (count > 0)
+    hipLaunchKernelGGL((k_reorder<SMALL_Z_MAX>), dim3(count), dim3(64), 0, s, tasks);
 }
 
 void launch_split(const SplitTask* tasks, int count, hipStream_t s) {

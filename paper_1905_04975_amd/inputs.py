@@ -27,6 +27,11 @@ Recipes (all numpy ``Generator(PCG64(seed))``):
   entries it matches the first two moments of every entry of the reduced
   form.  It stands in for ``paper_like`` at orders where the dense CPU
   reduction takes minutes (n = 16384).
+* ``schur_form(n, seed, offdiag=0.3)`` -- a standardised real Schur form:
+  diagonal blocks 1x1 (d ~ U(-2, 2)) and 2x2 [[a, b], [c, a]] with
+  a ~ U(-2, 2), b c < 0 (|b|, |c| ~ U(0.2, 2), half of the eigenvalues in
+  complex pairs, blocks in random order), entries above the blocks
+  offdiag * N(0, 1) / sqrt(n), zeros below.  Input of the eigenvector step.
 * ``batch_sizes(count, lo, hi, seed)`` -- matrix orders for batched runs.
 
 All matrices are returned column-major (Fortran order), float64.
@@ -104,6 +109,24 @@ def paper_like_law(n: int, seed: int) -> np.ndarray:
         df = np.arange(n - 1, 0, -1, dtype=np.float64)   # n-1, ..., 1
         h[np.arange(1, n), np.arange(n - 1)] = np.sqrt(rng.chisquare(df) / 3.0)
     return np.asfortranarray(h)
+
+
+def schur_form(n: int, seed: int, offdiag: float = 0.3) -> np.ndarray:
+    rng = _rng(seed)
+    S = np.triu(rng.standard_normal((n, n)), 1) * (offdiag / np.sqrt(max(n, 1)))
+    k = 0
+    while k < n:
+        if k + 1 < n and rng.uniform() < 0.5:
+            a = rng.uniform(-2.0, 2.0)
+            b = rng.uniform(0.2, 2.0) * (1.0 if rng.uniform() < 0.5 else -1.0)
+            c = -np.sign(b) * rng.uniform(0.2, 2.0)
+            S[k, k] = S[k + 1, k + 1] = a
+            S[k, k + 1], S[k + 1, k] = b, c
+            k += 2
+        else:
+            S[k, k] = rng.uniform(-2.0, 2.0)
+            k += 1
+    return np.asfortranarray(S)
 
 
 def batch_sizes(count: int, lo: int, hi: int, seed: int) -> np.ndarray:

@@ -50,7 +50,12 @@ class SchurStats(ctypes.Structure):
                 ("chase_flops", ctypes.c_double), ("small_launches", ctypes.c_int64),
                 ("aed_launches", ctypes.c_int64),
                 ("hess_panel_ms", ctypes.c_double), ("hess_gemv_bytes", ctypes.c_double),
-                ("hess_gemm_ms", ctypes.c_double), ("hess_gemm_flops", ctypes.c_double)]
+                ("hess_gemm_ms", ctypes.c_double), ("hess_gemm_flops", ctypes.c_double),
+                ("ev_solve_ms", ctypes.c_double), ("ev_gemm_ms", ctypes.c_double),
+                ("ev_gemm_flops", ctypes.c_double), ("ev_back_ms", ctypes.c_double),
+                ("ev_back_flops", ctypes.c_double),
+                ("reorder_ms", ctypes.c_double), ("reorder_windows", ctypes.c_int64),
+                ("reorder_steps", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -63,7 +68,8 @@ EXPORTS = ("schur_reduce", "schur_create", "schur_destroy", "schur_set_opts",
            "schur_server_create", "schur_server_destroy", "schur_submit", "schur_poll",
            "schur_server_get_stats", "schur_set_tuning", "schur_plan_sweep",
            "schur_plan_split", "schur_select_windows", "schur_split_weight",
-           "schur_reduce_noalloc", "schur_hessenberg")
+           "schur_reduce_noalloc", "schur_hessenberg", "schur_eigenvectors",
+           "schur_reorder", "schur_plan_reorder")
 
 TUNING_PATH = os.path.join(HERE, "tuning.json")
 
@@ -107,6 +113,14 @@ def load():
     lib.schur_get_stats.restype = ctypes.c_int
     lib.schur_reduce_async.argtypes = [vp, vp, ip, dp, ip, dp, ip, dp, dp, ctypes.POINTER(ip)]
     lib.schur_reduce_async.restype = ctypes.c_int
+    lib.schur_reorder.argtypes = [vp, vp, ip, dp, ip, dp, ip, ctypes.POINTER(ip), dp, dp,
+                                  ctypes.POINTER(ip)]
+    lib.schur_reorder.restype = ctypes.c_int
+    lib.schur_plan_reorder.argtypes = [ip, ctypes.POINTER(ip), ctypes.POINTER(ip), ip,
+                                       ctypes.POINTER(ip), ip]
+    lib.schur_plan_reorder.restype = ctypes.c_int
+    lib.schur_eigenvectors.argtypes = [vp, vp, ip, dp, ip, dp, ip, dp, ip]
+    lib.schur_eigenvectors.restype = ctypes.c_int
     lib.schur_hessenberg.argtypes = [vp, vp, ip, dp, ip, dp, ip]
     lib.schur_hessenberg.restype = ctypes.c_int
     lib.schur_reduce_noalloc.argtypes = [vp, ip, dp, ip, dp, ip, dp, dp]
@@ -187,6 +201,21 @@ class Handle:
     def hessenberg_async(self, stream, n, A, lda, Q, ldq):
         """C ``schur_hessenberg`` with raw device pointers; returns its code."""
         return load().schur_hessenberg(self._h, stream, int(n), A, int(lda), Q, int(ldq))
+
+    def eigenvectors_async(self, stream, n, S, lds, Q, ldq, X, ldx):
+        """C ``schur_eigenvectors`` with raw device pointers; returns its code."""
+        return load().schur_eigenvectors(self._h, stream, int(n), S, int(lds), Q, int(ldq), X,
+                                         int(ldx))
+
+    def reorder_async(self, stream, n, S, lds, Q, ldq, select, wr, wi):
+        """C ``schur_reorder`` with raw device pointers and a host selection
+        (sequence of n ints); returns (code, m)."""
+        IA = ctypes.c_int * max(1, n)
+        sel = IA(*[int(x) for x in select]) if n else IA()
+        m = ctypes.c_int(0)
+        rc = load().schur_reorder(self._h, stream, int(n), S, int(lds), Q, int(ldq), sel, wr, wi,
+                                  ctypes.byref(m))
+        return rc, m.value
 
     def reduce_batched(self, stream, ns, Hs, ldhs, Qs, ldqs, wrs, wis):
         count = len(ns)
@@ -296,6 +325,76 @@ def hessenberg(A, Q=None, want_q=True, handle=None, stream=None):
         torch.cuda.synchronize(dev)
         handle.close()
     return H, Qm, rc
+
+
+def eigenvectors(S, Q=None, handle=None, stream=None):
+    """Eigenvectors of the real Schur form ``S`` (CUDA/HIP float64), back-
+    transformed with ``Q`` when given (paper Sec. 2, Eqs. (5)-(6)).  Returns
+    ``(X, rc)`` with X in LAPACK's real layout (column-major tensor)."""
+    import torch
+
+    n = S.shape[0]
+    Sm, lds = _colmajor(S)
+    dev = Sm.device
+    qptr, ldq = None, 1
+    if Q is not None:
+        Qm, ldq = _colmajor(Q)
+        qptr = Qm.data_ptr()
+    X = torch.empty(n, n, dtype=torch.float64, device=dev).t()
+    own = handle is None
+    if own:
+        handle = Handle(dev.index or 0)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = handle.eigenvectors_async(stream, n, Sm.data_ptr(), lds, qptr, ldq, X.data_ptr(),
+                                   max(1, n))
+    if own:
+        torch.cuda.synchronize(dev)
+        handle.close()
+    return X, rc
+
+
+def reorder(S, select, Q=None, handle=None, stream=None):
+    """Reorder the real Schur form ``S`` (CUDA/HIP float64, column-major in
+    place) so that the selected eigenvalues lead (paper Sec. 2, Eq. (7));
+    ``Q`` accumulates.  Returns ``(S, Q, w, m, rc)``."""
+    import torch
+
+    n = S.shape[0]
+    Sm, lds = _colmajor(S)
+    dev = Sm.device
+    qptr, ldq, Qm = None, 1, None
+    if Q is not None:
+        Qm, ldq = _colmajor(Q)
+        qptr = Qm.data_ptr()
+    wr = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    wi = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    own = handle is None
+    if own:
+        handle = Handle(dev.index or 0)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    rc, m = handle.reorder_async(stream, n, Sm.data_ptr(), lds, qptr, ldq, list(select),
+                                 wr.data_ptr(), wi.data_ptr())
+    if own:
+        torch.cuda.synchronize(dev)
+        handle.close()
+    return Sm, Qm, torch.complex(wr[:n], wi[:n]), m, rc
+
+
+def plan_reorder(bsize, bsel):
+    """Host-only reordering schedule: list of (chain, time step, first row,
+    order) for blocks of orders ``bsize`` with selection flags ``bsel``."""
+    lib = load()
+    nb = len(bsize)
+    n = int(sum(bsize))
+    IA = ctypes.c_int * max(nb, 1)
+    k = lib.schur_plan_reorder(n, IA(*bsize), IA(*bsel), nb, None, 0)
+    if k < 0:
+        raise ValueError("bad reordering arguments")
+    buf = (ctypes.c_int * (4 * max(k, 1)))()
+    lib.schur_plan_reorder(n, IA(*bsize), IA(*bsel), nb, buf, k)
+    return [tuple(buf[4 * i:4 * i + 4]) for i in range(k)]
 
 
 def reduce_batched(Hs, want_q=True, handle=None, stream=None):

@@ -10,6 +10,8 @@ the oracle's sequential Francis double-shift steps with the same shifts
 (the multishift sweep and the sequence of double-shift steps agree in exact
 arithmetic; paper Sec. 3.2 describes the windowed, accumulated form).
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -247,3 +249,58 @@ def test_split_candidate_weight():
         assert schur.split_weight(1, 7, top, below) == 8.0
     assert schur.split_weight(1, 0, 1, 1) == 1.0
     assert schur.split_weight(1, 3, 1, 1) == 4.0
+
+
+def _random_blocks(n, seed, frac):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes, sel = [], []
+    r = 0
+    while r < n:
+        s = 2 if (r + 1 < n and rng.uniform() < 0.4) else 1
+        sizes.append(s)
+        sel.append(1 if rng.uniform() < frac else 0)
+        r += s
+    return sizes, sel
+
+
+@pytest.mark.parametrize("n,seed,frac", [(1, 1, 1.0), (7, 2, 0.5), (96, 3, 0.5), (97, 4, 0.3),
+                                         (300, 5, 0.5), (1000, 6, 0.2), (1000, 7, 0.8),
+                                         (2500, 8, 0.5)])
+def test_reorder_schedule(n, seed, frac):
+    """The reordering schedule, executed as the device does (time step by
+    time step; in each window the flagged rows move to the top, stably),
+    leaves every selected block at the top in diagonal order; windows of one
+    time step are disjoint, none is larger than 96 rows, and every window
+    starts and ends at block boundaries of the layout it meets."""
+    sizes, sel = _random_blocks(n, seed, frac)
+    plan = schur.plan_reorder(sizes, sel)
+    # layout: list of blocks (id, size, selected) in diagonal order
+    layout = [(i, s, f) for i, (s, f) in enumerate(zip(sizes, sel))]
+    steps = {}
+    for chain, t, a, w in plan:
+        steps.setdefault(t, []).append((a, w, chain))
+    for t in sorted(steps):
+        wins = sorted(steps[t])
+        for (a1, w1, _), (a2, _, _) in zip(wins, wins[1:]):
+            assert a1 + w1 <= a2
+        for a, w, _ in wins:
+            assert 1 <= w <= 96
+            starts, r = [], 0
+            for b in layout:
+                starts.append(r)
+                r += b[1]
+            assert a in starts and (a + w in starts or a + w == n)
+            i0 = starts.index(a)
+            i1 = starts.index(a + w) if a + w < n else len(layout)
+            inside = layout[i0:i1]
+            layout[i0:i1] = [b for b in inside if b[2]] + [b for b in inside if not b[2]]
+    want = [i for i, f in enumerate(sel) if f]
+    got = [b[0] for b in layout[:len(want)]]
+    assert got == want
+    assert all(not b[2] for b in layout[len(want):])
+
+
+def test_reorder_schedule_bad_arguments():
+    IA = ctypes.c_int * 2
+    assert schur.load().schur_plan_reorder(3, IA(1, 3), IA(1, 0), 2, None, 0) == -1
+    assert schur.load().schur_plan_reorder(4, IA(1, 2), IA(1, 0), 2, None, 0) == -1
