@@ -69,7 +69,7 @@ EXPORTS = ("schur_reduce", "schur_create", "schur_destroy", "schur_set_opts",
            "schur_server_get_stats", "schur_set_tuning", "schur_plan_sweep",
            "schur_plan_split", "schur_select_windows", "schur_split_weight",
            "schur_reduce_noalloc", "schur_hessenberg", "schur_eigenvectors",
-           "schur_reorder", "schur_plan_reorder")
+           "schur_reorder", "schur_plan_reorder", "schur_reduce_begin", "schur_reduce_end")
 
 TUNING_PATH = os.path.join(HERE, "tuning.json")
 
@@ -113,6 +113,10 @@ def load():
     lib.schur_get_stats.restype = ctypes.c_int
     lib.schur_reduce_async.argtypes = [vp, vp, ip, dp, ip, dp, ip, dp, dp, ctypes.POINTER(ip)]
     lib.schur_reduce_async.restype = ctypes.c_int
+    lib.schur_reduce_begin.argtypes = [vp, vp, ip, dp, ip, dp, ip, dp, dp, dp]
+    lib.schur_reduce_begin.restype = ctypes.c_int
+    lib.schur_reduce_end.argtypes = [vp, vp]
+    lib.schur_reduce_end.restype = ctypes.c_int
     lib.schur_reorder.argtypes = [vp, vp, ip, dp, ip, dp, ip, ctypes.POINTER(ip), dp, dp,
                                   ctypes.POINTER(ip)]
     lib.schur_reorder.restype = ctypes.c_int
@@ -207,11 +211,21 @@ class Handle:
         return load().schur_eigenvectors(self._h, stream, int(n), S, int(lds), Q, int(ldq), X,
                                          int(ldx))
 
+    def reduce_begin(self, stream, n, H, ldh, Q, ldq, wr, wi, info_dev=None):
+        """C ``schur_reduce_begin`` (returns at once; raw device pointers)."""
+        return load().schur_reduce_begin(self._h, stream, int(n), H, int(ldh), Q, int(ldq), wr,
+                                         wi, info_dev)
+
+    def reduce_end(self, stream):
+        """C ``schur_reduce_end``: the stream waits for the begun solve; its info."""
+        return load().schur_reduce_end(self._h, stream)
+
     def reorder_async(self, stream, n, S, lds, Q, ldq, select, wr, wi):
         """C ``schur_reorder`` with raw device pointers and a host selection
         (sequence of n ints); returns (code, m)."""
-        IA = ctypes.c_int * max(1, n)
-        sel = IA(*[int(x) for x in select]) if n else IA()
+        vals = [int(x) for x in select]
+        IA = ctypes.c_int * max(1, len(vals))
+        sel = IA(*vals)
         m = ctypes.c_int(0)
         rc = load().schur_reorder(self._h, stream, int(n), S, int(lds), Q, int(ldq), sel, wr, wi,
                                   ctypes.byref(m))
