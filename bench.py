@@ -505,6 +505,161 @@ def probe(H0, H, Q, wr, seed):
             / torch.linalg.norm(Hh).item()}
 
 
+def block_matrix(S_np, m):
+    """Real block-diagonal L with S's eigenvalues for the first m columns of
+    an eigenvector matrix in LAPACK's layout: X L = S-image of X."""
+    import numpy as np
+
+    L = np.zeros((m, m))
+    k = 0
+    while k < m:
+        if k + 1 < S_np.shape[0] and S_np[k + 1, k] != 0.0:
+            wi = np.sqrt(abs(S_np[k, k + 1])) * np.sqrt(abs(S_np[k + 1, k]))
+            L[k, k] = S_np[k, k]
+            if k + 1 < m:
+                L[k + 1, k + 1] = S_np[k, k]
+                L[k, k + 1], L[k + 1, k] = wi, -wi
+            k += 2
+        else:
+            L[k, k] = S_np[k, k]
+            k += 1
+    return L
+
+
+def pipeline_measure(args, schur, inputs, dev, stream, H, Q, eye, wr, wi):
+    """The paper's route on its own test matrices (Sec. 5) at the same
+    order: a dense U(-1,1) matrix A (drawn on the device from a seeded
+    generator) is reduced to Hessenberg form (Eq. (3)), then to real Schur
+    form (Eq. (4)) with Q accumulating Q1 Q2, then the eigenvectors of A are
+    computed (Eqs. (5)-(6)).  Each step is timed with HIP events on the
+    stream and checked by probes (independent torch products)."""
+    import torch
+
+    n = args.n
+    g = torch.Generator(dev).manual_seed(inputs.SEED_PAPER_LIKE)
+    A0 = torch.rand(n, n, dtype=torch.float64, device=dev, generator=g).mul_(2.0).sub_(1.0)
+    H.copy_(A0)   # column-major working copy
+    Q.copy_(eye)
+    h = schur.Handle(0, flags=schur.FLAG_TIME_KERNELS)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    torch.cuda.synchronize(dev)
+    x = torch.randn(n, 2, dtype=torch.float64, device=dev,
+                    generator=torch.Generator(dev).manual_seed(3))
+    nA = torch.linalg.norm(A0).item()
+    nx = torch.linalg.norm(x).item()
+    # Hessenberg reduction
+    w0 = time.perf_counter()
+    ev[0].record(stream)
+    rc = h.hessenberg_async(stream.cuda_stream, n, H.data_ptr(), n, Q.data_ptr(), n)
+    ev[1].record(stream)
+    torch.cuda.synchronize(dev)
+    t_hess = time.perf_counter() - w0
+    if rc != 0:
+        raise RuntimeError("schur_hessenberg returned %d" % rc)
+    sth = h.stats()
+    r_hess = (torch.linalg.norm(A0 @ x - Q @ (H @ (Q.t() @ x))) / (nA * nx)).item()
+    below = torch.count_nonzero(torch.tril(H, -2)).item()
+    # Schur reduction of that Hessenberg form
+    w0 = time.perf_counter()
+    ev[2].record(stream)
+    info = h.reduce_async(stream.cuda_stream, n, H.data_ptr(), n, Q.data_ptr(), n, wr.data_ptr(),
+                          wi.data_ptr())
+    ev[3].record(stream)
+    torch.cuda.synchronize(dev)
+    t_schur = time.perf_counter() - w0
+    if info != 0:
+        raise RuntimeError("schur_reduce_async returned info=%d" % info)
+    sts = h.stats()
+    r_schur = (torch.linalg.norm(A0 @ x - Q @ (H @ (Q.t() @ x))) / (nA * nx)).item()
+    o_schur = (torch.linalg.norm(Q.t() @ (Q @ x) - x) / nx).item()
+    # eigenvectors of A
+    X = torch.empty(n, n, dtype=torch.float64, device=dev).t()
+    w0 = time.perf_counter()
+    ev[4].record(stream)
+    rc = h.eigenvectors_async(stream.cuda_stream, n, H.data_ptr(), n, Q.data_ptr(), n,
+                              X.data_ptr(), n)
+    ev[5].record(stream)
+    torch.cuda.synchronize(dev)
+    t_ev = time.perf_counter() - w0
+    if rc != 0:
+        raise RuntimeError("schur_eigenvectors returned %d" % rc)
+    ste = h.stats()
+    m = 256   # eigenvector check on the first m columns (before S is reordered)
+    S_lead = H[:m + 1, :m + 1].cpu().numpy()
+    L = torch.from_numpy(block_matrix(S_lead, m)).to(dev)
+    Xm = X[:, :m]
+    R = A0 @ Xm - Xm @ L
+    r_ev = (torch.linalg.norm(R, dim=0) / torch.linalg.norm(Xm, dim=0)).max().item() / nA
+    del X, Xm, R
+    # eigenvalue reordering (the paper's second Table 2 workload): a seeded
+    # random half of the eigenvalues to the top, Q accumulating
+    import numpy as np
+
+    sel = (np.random.Generator(np.random.PCG64(inputs.SEED_PAPER_LIKE)).uniform(size=n)
+           < 0.5).astype(int).tolist()
+    w0 = time.perf_counter()
+    rc, msel = h.reorder_async(stream.cuda_stream, n, H.data_ptr(), n, Q.data_ptr(), n, sel,
+                               wr.data_ptr(), wi.data_ptr())
+    torch.cuda.synchronize(dev)
+    t_ro = time.perf_counter() - w0
+    str_ = h.stats()
+    h.close()
+    if rc < 0:
+        raise RuntimeError("schur_reorder returned %d" % rc)
+    r_ro = (torch.linalg.norm(A0 @ x - Q @ (H @ (Q.t() @ x))) / (nA * nx)).item()
+    below_ro = torch.count_nonzero(torch.tril(H, -2)).item()
+    del A0
+    fam = family_lines(sts, "paper_like_n%d" % n)
+    gemv_s = sth["hess_panel_ms"] / 1e3
+    hess = {
+        "workload": "hessenberg_dense_uniform_n%d" % n, "seconds": t_hess,
+        "seconds_hip_events": ev[0].elapsed_time(ev[1]) / 1e3,
+        "panel_column_kernels_s": gemv_s,
+        "panel_products_s": sth["hess_gemm_ms"] / 1e3,
+        "roofline": {"kernel": "k_hgemv (+ the four column kernels of each column)",
+                     "bound": "hbm", "achieved": sth["hess_gemv_bytes"] / gemv_s / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": sth["hess_gemv_bytes"] / gemv_s / 1e9 / HBM_PEAK_GBS,
+                     "traffic": pmc_traffic("k_hgemv", "hessenberg_n%d" % n),
+                     "bytes_note": "8 bytes per trailing-matrix entry and column (the "
+                                   "matrix-vector products' algorithmic reads)"},
+        "products_tflops": sth["hess_gemm_flops"] / max(sth["hess_gemm_ms"], 1e-9) / 1e9,
+        "nominal_tflops": (10.0 / 3.0 + 4.0 / 3.0) * n ** 3 / t_hess / 1e12,
+        "check": {"residual_probe": r_hess, "nonzeros_below_subdiag": below},
+    }
+    paper = {
+        "workload": "paper_like_n%d" % n, "seed": inputs.SEED_PAPER_LIKE,
+        "input": ("Hessenberg form (computed above) of a dense U(-1,1) matrix drawn on the "
+                  "device (torch generator, seed %d)" % inputs.SEED_PAPER_LIKE),
+        "seconds_per_solve": t_schur, "seconds_hip_events": ev[2].elapsed_time(ev[3]) / 1e3,
+        "executed_tflops": counted_flops(sts) / t_schur / 1e12,
+        "nominal_tflops": 10.0 * n ** 3 / t_schur / 1e12,
+        "roofline": roofline_of(fam, sts), "families": fam,
+        "breakdown": breakdown_of(sts, t_schur),
+        "check": {"residual_probe_of_A": r_schur, "orthogonality_probe": o_schur},
+    }
+    eig = {
+        "workload": "eigenvectors_of_A_n%d" % n, "seconds": t_ev,
+        "seconds_hip_events": ev[4].elapsed_time(ev[5]) / 1e3,
+        "tile_solves_s": ste["ev_solve_ms"] / 1e3, "tile_updates_s": ste["ev_gemm_ms"] / 1e3,
+        "backtransform_s": ste["ev_back_ms"] / 1e3,
+        "update_tflops": ste["ev_gemm_flops"] / max(ste["ev_gemm_ms"], 1e-9) / 1e9,
+        "backtransform_tflops": ste["ev_back_flops"] / max(ste["ev_back_ms"], 1e-9) / 1e9,
+        "check": {"max_relative_residual_first_%d" % m: r_ev},
+    }
+    reo = {
+        "workload": "reorder_half_of_eigenvalues_n%d" % n, "seconds": t_ro, "info": rc,
+        "selected": msel, "windows": str_["reorder_windows"], "time_steps": str_["reorder_steps"],
+        "window_tasks_s": str_["reorder_ms"] / 1e3,
+        "products_s": (str_["row_ms"] + str_["colq_ms"]) / 1e3,
+        "products_tflops": str_["gemm_flops"] / max(str_["row_ms"] + str_["colq_ms"], 1e-9) / 1e9,
+        "check": {"residual_probe_of_A": r_ro, "nonzeros_below_subdiag": below_ro},
+    }
+    print("pipeline: hessenberg %.3f s, schur %.3f s, eigenvectors %.3f s, reorder %.3f s"
+          % (t_hess, t_schur, t_ev, t_ro), file=sys.stderr, flush=True)
+    return {"hessenberg": hess, "schur": paper, "eigenvectors": eig, "reorder": reo}
+
+
 def breakdown_of(st, seconds):
     keys = ("sweeps", "windows", "launches", "shifts_applied", "aed_windows", "aed_deflated",
             "split_passes", "split_windows", "split_accepted", "split_converged",
@@ -582,26 +737,8 @@ def main():
         sweep = sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream)
     paper = None
     if not paper_main and not args.no_paper_like:
-        # the paper's own test-matrix recipe (Sec. 5): the Hessenberg form of
-        # a dense U(-1,1) matrix, one solve with default options
         del H0
-        Hp = torch.from_numpy(inputs.paper_like_law(n, inputs.SEED_PAPER_LIKE)).to(dev)
-        hp = schur.Handle(0, flags=schur.FLAG_TIME_KERNELS)
-        solve_timed(schur, dev, stream, hp, Hp, H, Q, eye, wr, wi)   # warm-up
-        dtp, wtp, stp = solve_timed(schur, dev, stream, hp, Hp, H, Q, eye, wr, wi)
-        hp.close()
-        famp = family_lines(stp, "paper_like_n%d" % n)
-        paper = {
-            "workload": "paper_like_n%d" % n, "seed": inputs.SEED_PAPER_LIKE,
-            "input": "Hessenberg form of a dense U(-1,1) matrix (drawn from its distribution)",
-            "seconds_per_solve": wtp, "seconds_hip_events": dtp,
-            "executed_tflops": counted_flops(stp) / wtp / 1e12,
-            "nominal_tflops": 10.0 * n ** 3 / wtp / 1e12,
-            "roofline": roofline_of(famp, stp), "families": famp,
-            "breakdown": breakdown_of(stp, wtp),
-            "check": None if args.no_check else probe(Hp, H, Q, wr, 1),
-        }
-        print("paper_like: %.3f s, sweeps=%d" % (wtp, stp["sweeps"]), file=sys.stderr, flush=True)
+        paper = pipeline_measure(args, schur, inputs, dev, stream, H, Q, eye, wr, wi)
     row = table_row(n)
     out = {
         "metric": "Schur-reduction s & FP64 TFLOP/s at n=16384; batched solves/s; p99 latency",
@@ -642,7 +779,10 @@ def main():
         "roofline": roofline,
         "families": fam,
         "breakdown": breakdown_of(st0, sec),
-        "paper_like": paper,
+        "paper_like": paper["schur"] if paper else None,
+        "hessenberg": paper["hessenberg"] if paper else None,
+        "eigenvectors": paper["eigenvectors"] if paper else None,
+        "reorder": paper["reorder"] if paper else None,
         "sweep": sweep,
         "check": check,
         "gen_seconds": gen_s,

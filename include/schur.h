@@ -315,6 +315,28 @@ int schur_reduce_noalloc(void* stream, int n, double* H, int ldh, double* Q, int
                          double* wr, double* wi);
 
 /* --------------------------------------------------------------------------
+ * schur_reduce_begin / schur_reduce_end -- the Schur reduction of
+ * schur_reduce_async (paper Sec. 2, Eq. (4)) without holding the caller's
+ * thread.  schur_reduce_begin checks the arguments (host-side), marks the
+ * current point of `stream` and returns at once; a thread owned by the
+ * handle then runs the solve on the handle's own stream after that point
+ * (the sweep loop needs the host between sweeps, so it cannot be captured
+ * into one stream submission) and finally writes the info code to
+ * *info_dev (a DEVICE int, may be NULL) on that stream.  schur_reduce_end
+ * waits for that thread, makes `stream` wait for the solve's device work
+ * (an event wait: work enqueued on `stream` afterwards sees S, Q, wr, wi
+ * and *info_dev) and returns the info code.
+ *   arguments as schur_reduce_async; info_dev: device int or NULL
+ * Between the two calls the handle and the buffers must not be used
+ * otherwise (the handle is busy: a second begin returns -104).  begin
+ * returns 0 or an argument error (nothing started then); end returns the
+ * solve's info, or -104 when no solve was begun.
+ * ------------------------------------------------------------------------ */
+int schur_reduce_begin(schur_handle_t h, void* stream, int n, double* H, int ldh, double* Q,
+                       int ldq, double* wr, double* wi, int* info_dev);
+int schur_reduce_end(schur_handle_t h, void* stream);
+
+/* --------------------------------------------------------------------------
  * schur_reduce_batched -- many independent Hessenberg matrices of uneven
  * orders in one call.  n, ldh, ldq are HOST arrays of `count` ints; H, Q,
  * wr, wi are HOST arrays of `count` DEVICE pointers (Q[i] may be NULL,

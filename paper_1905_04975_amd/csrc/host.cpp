@@ -145,6 +145,13 @@ struct schur_handle_s {
   // runs on its large matrices (kept apart from the engine's own)
   schur_handle_s* side = nullptr;
   double* shm = nullptr;         // NS_MAX x NS_MAX copy of the trailing block
+  // schur_reduce_begin / _end: the thread that drives a solve begun on the
+  // handle, the caller's stream point it starts after, its completion on
+  // the handle's stream, its info code (and a pinned copy for the device)
+  std::thread* job = nullptr;
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+  int job_rc = 0;
+  int* job_info_h = nullptr;
 };
 
 namespace {
@@ -2521,7 +2528,15 @@ int schur_create(schur_handle_t* h, int device, const schur_opts* opts) {
 
 int schur_destroy(schur_handle_t h) {
   if (!h) return -104;
+  if (h->job) {   // a begun solve that was never ended
+    h->job->join();
+    delete h->job;
+    h->job = nullptr;
+  }
   (void)hipSetDevice(h->device);
+  if (h->ev_begin) (void)hipEventDestroy(h->ev_begin);
+  if (h->ev_end) (void)hipEventDestroy(h->ev_end);
+  if (h->job_info_h) (void)hipHostFree(h->job_info_h);
   if (h->stream) {
     (void)hipStreamSynchronize(h->stream);
     (void)hipStreamDestroy(h->stream);
@@ -2618,6 +2633,58 @@ int schur_plan_reorder(int n, const int* bsize, const int* bsel, int nblocks, in
         out[4 * k + 3] = chains[c][t].w;
       }
   return k;
+}
+
+int schur_reduce_begin(schur_handle_t h, void* stream, int n, double* H, int ldh, double* Q,
+                       int ldq, double* wr, double* wi, int* info_dev) {
+  if (!h) return -104;
+  if (h->job) return -104;   // a solve begun on this handle has not been ended
+  const int rc = check_args(n, H, ldh, Q, ldq, wr, wi);
+  if (rc != 0) return rc;
+  if (info_dev && !is_device_ptr(info_dev)) return -103;
+  try {
+    HCHECK(hipSetDevice(h->device));
+    if (!h->ev_begin) HCHECK(hipEventCreateWithFlags(&h->ev_begin, hipEventDisableTiming));
+    if (!h->ev_end) HCHECK(hipEventCreateWithFlags(&h->ev_end, hipEventDisableTiming));
+    if (!h->job_info_h &&
+        hipHostMalloc((void**)&h->job_info_h, sizeof(int), hipHostMallocDefault) != hipSuccess)
+      return -101;
+    // the solve starts after the work already on the caller's stream
+    HCHECK(hipEventRecord(h->ev_begin, (hipStream_t)stream));
+  } catch (const HipErr& e) {
+    (void)hipGetLastError();
+    return -102;
+  }
+  h->job_rc = 0;
+  h->job = new std::thread([h, n, H, ldh, Q, ldq, wr, wi, info_dev]() {
+    int r = -102;
+    if (hipSetDevice(h->device) == hipSuccess &&
+        hipStreamWaitEvent(h->stream, h->ev_begin, 0) == hipSuccess)
+      r = solve(h, h->stream, n, H, ldh, Q, ldq, wr, wi);
+    if (info_dev) {   // info on the device, ordered before the completion event
+      *h->job_info_h = r;
+      if (hipMemcpyAsync(info_dev, h->job_info_h, sizeof(int), hipMemcpyHostToDevice,
+                         h->stream) != hipSuccess)
+        r = -102;
+    }
+    if (hipEventRecord(h->ev_end, h->stream) != hipSuccess) r = -102;
+    (void)hipStreamSynchronize(h->stream);   // the pinned info copy has been read
+    h->job_rc = r;
+  });
+  return 0;
+}
+
+int schur_reduce_end(schur_handle_t h, void* stream) {
+  if (!h) return -104;
+  if (!h->job) return -104;
+  h->job->join();
+  delete h->job;
+  h->job = nullptr;
+  if (hipStreamWaitEvent((hipStream_t)stream, h->ev_end, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return -102;
+  }
+  return h->job_rc;
 }
 
 int schur_reduce_async(schur_handle_t h, void* stream, int n, double* H, int ldh, double* Q,
