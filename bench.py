@@ -61,14 +61,17 @@ def parse():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--sweep-ns", type=int, default=256,
                     help="shifts per sweep of the forced-sweep measurement (0: skip it)")
+    ap.add_argument("--panel-tile", type=int, default=0,
+                    help="panel tiles per workgroup of the sweep products (0: table/cost model)")
     ap.add_argument("--sweep-count", type=int, default=3,
                     help="sweeps timed by the forced-sweep measurement")
-    ap.add_argument("--workload", choices=["n16384", "paper_like", "batch", "serve", "sweep"],
+    ap.add_argument("--workload",
+                    choices=["n16384", "paper_like", "pipeline", "batch", "serve", "sweep"],
                     default="n16384")
     ap.add_argument("--no-paper-like", action="store_true",
                     help="skip the solve of the paper's test-matrix recipe")
     ap.add_argument("--count", type=int, default=2000, help="batch: number of matrices")
-    ap.add_argument("--plain-sample", type=int, default=60,
+    ap.add_argument("--plain-sample", type=int, default=200,
                     help="batch/serve: requests timed with per-matrix plain launches")
     ap.add_argument("--requests", type=int, default=240, help="serve: requests (first 10%% warm-up)")
     ap.add_argument("--rate", type=float, default=0.0, help="serve: arrivals/s (0: 0.7 x saturation)")
@@ -138,16 +141,27 @@ def bench_batch(args):
     H0 = [torch.from_numpy(H).to(dev) for H in mats]
     h = schur.Handle(0)
 
-    def run_batch():
+    def run_batch(hh=h):
         Hs = [H.clone() for H in H0]
         torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
-        Ss, Qs, ws, infos, rc = schur.reduce_batched(Hs, handle=h)
+        Ss, Qs, ws, infos, rc = schur.reduce_batched(Hs, handle=hh)
         torch.cuda.synchronize(dev)
         t = time.perf_counter() - t0
         if rc != 0:
             raise RuntimeError("batched solve failed: %d" % rc)
         return t, Ss, Qs
+
+    def worst(Ss, Qs):
+        worst_res = worst_orth = 0.0
+        for i in range(0, args.count, max(1, args.count // 50)):
+            Hh = torch.triu(H0[i], -1)
+            S, Q = Ss[i], Qs[i]
+            n = Hh.shape[0]
+            r = (torch.linalg.norm(Hh - Q @ S @ Q.t()) / torch.linalg.norm(Hh)).item()
+            o = torch.linalg.norm(Q.t() @ Q - torch.eye(n, dtype=torch.float64, device=dev)).item()
+            worst_res, worst_orth = max(worst_res, r), max(worst_orth, o)
+        return worst_res, worst_orth
 
     for _ in range(args.warmup):
         run_batch()
@@ -158,27 +172,51 @@ def bench_batch(args):
         print("batch step: %.3f s" % t, file=sys.stderr, flush=True)
     st = h.stats()
     # accuracy of a sample of the batch (checker)
-    worst_res = worst_orth = 0.0
-    for i in range(0, args.count, max(1, args.count // 50)):
-        Hh = torch.triu(H0[i], -1)
-        S, Q = Ss[i], Qs[i]
-        n = Hh.shape[0]
-        r = (torch.linalg.norm(Hh - Q @ S @ Q.t()) / torch.linalg.norm(Hh)).item()
-        o = torch.linalg.norm(Q.t() @ Q - torch.eye(n, dtype=torch.float64, device=dev)).item()
-        worst_res, worst_orth = max(worst_res, r), max(worst_orth, o)
-    # per-matrix plain launches (one schur_reduce per matrix) on a sample
-    k = min(args.plain_sample, args.count)
-    torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
-    for i in range(k):
+    worst_res, worst_orth = worst(Ss, Qs)
+    del Ss, Qs
+    # the same batch through the round engine (every matrix advanced sweep by
+    # sweep in shared launches, host-planned rounds), once after a warm-up
+    hr = schur.Handle(0, flags=schur.FLAG_BATCH_ROUNDS)
+    run_batch(hr)
+    t_rounds, Sr, Qr = run_batch(hr)
+    rounds_res, rounds_orth = worst(Sr, Qr)
+    st_r = hr.stats()
+    hr.close()
+    del Sr, Qr
+    print("batch rounds engine: %.3f s" % t_rounds, file=sys.stderr, flush=True)
+    # the persistent kernel alone, timed with HIP events
+    ht = schur.Handle(0, flags=schur.FLAG_TIME_KERNELS)
+    run_batch(ht)
+    stt = ht.stats()
+    ht.close()
+    # per-matrix plain launches (one schur_reduce per matrix): a stratified
+    # sample (every k-th matrix in order of size), each timed alone; the
+    # estimate for the whole batch sums the mean time of each size stratum
+    # over its members (no model of the time against n)
+    import numpy as np
+
+    order = np.argsort(sizes, kind="stable")
+    k = max(1, min(args.plain_sample, args.count))
+    strata = np.array_split(order, k)
+    plain_t, plain_res, plain_orth = [], 0.0, 0.0
+    for stratum in strata:
+        i = int(stratum[len(stratum) // 2])
         H = H0[i].clone()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
         S, Q, w, info = schur.reduce(H, handle=h)
-    torch.cuda.synchronize(dev)
-    tp = time.perf_counter() - t0
-    cost = sum(int(n) ** 3 for n in sizes)
-    cost_k = sum(int(n) ** 3 for n in sizes[:k])
-    plain_rate = k / tp
-    plain_scaled = args.count / (tp * cost / cost_k)
+        torch.cuda.synchronize(dev)
+        plain_t.append(time.perf_counter() - t0)
+        Hh = torch.triu(H0[i], -1)
+        n_i = Hh.shape[0]
+        plain_res = max(plain_res, (torch.linalg.norm(Hh - Q @ S @ Q.t())
+                                    / torch.linalg.norm(Hh)).item())
+        plain_orth = max(plain_orth, torch.linalg.norm(
+            Q.t() @ Q - torch.eye(n_i, dtype=torch.float64, device=dev)).item())
+        if info != 0:
+            raise RuntimeError("plain launch failed: %d" % info)
+    est_total = sum(plain_t[j] * len(strata[j]) for j in range(k))
+    plain_scaled = args.count / est_total
     t = sum(times) / len(times)
     out = {
         "metric": "batched solves/s (2000 random Hessenberg, orders U{32..512})",
@@ -188,11 +226,25 @@ def bench_batch(args):
         "config": {"workload": "schur_batched_random_hessenberg", "count": args.count,
                    "orders": "U{32..512}", "seed_sizes": inputs.SEED_BATCH_SIZES,
                    "schur_vectors": True},
-        "plain_launches": {"sample": k, "solves_per_s_sample": plain_rate,
-                           "solves_per_s_cost_scaled": plain_scaled,
-                           "speedup_cost_scaled": (args.count / t) / plain_scaled},
+        "plain_launches": {"sample": k, "sampling": "one matrix from the middle of each of "
+                                                     "%d size strata" % k,
+                           "solves_per_s_sample": k / sum(plain_t),
+                           "solves_per_s_stratified_estimate": plain_scaled,
+                           "speedup": (args.count / t) / plain_scaled,
+                           "check": {"max_residual": plain_res, "max_orthogonality": plain_orth}},
         "check": {"max_residual": worst_res, "max_orthogonality": worst_orth},
-        "stats": {k2: st[k2] for k2 in ("sweeps", "windows", "launches", "small_solves")},
+        "persistent_kernel": {
+            "matrices": stt["persist_jobs"], "launches": st["launches"],
+            "kernel_ms_hip_events": stt["persist_ms"],
+            "executed_tflops": (stt["gemm_flops"] + stt["chase_flops"] + stt["small_flops"]
+                                + stt["aed_flops"]) / max(stt["persist_ms"] * 1e-3, 1e-30) / 1e12,
+            "gemm_flops": stt["gemm_flops"]},
+        "rounds_engine": {"solves_per_s": args.count / t_rounds, "seconds": t_rounds,
+                          "launches": st_r["launches"],
+                          "speedup_of_persistent": (args.count / t) / (args.count / t_rounds),
+                          "check": {"max_residual": rounds_res, "max_orthogonality": rounds_orth}},
+        "stats": {k2: st[k2] for k2 in ("sweeps", "windows", "launches", "small_solves",
+                                        "aed_windows", "persist_jobs")},
     }
     print(json.dumps(out), flush=True)
 
@@ -257,7 +309,7 @@ def bench_serve(args):
     # FIFO plain launches on the same arrivals (sample): one request at a time
     import torch
 
-    k = min(args.plain_sample, args.requests)
+    k = min(args.plain_sample, args.requests, 60)
     h = schur.Handle(0)
     dev = torch.device("cuda:0")
     t_free = 0.0
@@ -321,6 +373,7 @@ def sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream):
     n = args.n
     dev = H0.device
     hs = schur.Handle(0, ns=args.sweep_ns, nb=args.nb, aed_nibble=-1, split_window=-1,
+                      panel_tile=args.panel_tile,
                       max_sweeps=args.sweep_count, flags=schur.FLAG_TIME_KERNELS)
     H.copy_(H0)
     Q.copy_(eye)
@@ -365,6 +418,7 @@ def sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream):
         / FP64_MFMA_PEAK_TFLOPS,
         "k_panel_colq": gl("k_panel_colq", st["colq_ms"], st["colq_launches"], st["colq_flops"]),
         "k_panel_row": gl("k_panel_row", st["row_ms"], st["row_launches"], st["row_flops"]),
+        "k_chase": family_lines(st, "sweep").get("k_chase"),
         "residual_probe": res,
     }
     print("sweep: %d sweeps of %d shifts, %.3f s, GEMM %.2f TFLOP/s" %
@@ -373,7 +427,7 @@ def sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream):
     return out
 
 
-KERNEL_SOURCES = ("kernels.hip", "wave_solvers.h", "window_chase.h", "device_common.h",
+KERNEL_SOURCES = ("kernels.hip", "wave_solvers.h", "window_chase.h", "device_common.h", "wg_ops.h",
                   "schur_internal.h")
 
 
@@ -443,6 +497,15 @@ def family_lines(st, workload):
                      "flops_per_launch": flops / launches}
         if traffic is not None:
             out[name]["hbm_gbs_from_traffic"] = traffic / (avg_ms * 1e-3) / 1e9
+        if name == "k_chase":
+            # the window task's own measures: chain steps per second and the
+            # algorithmic HBM rate (window in and out, U out: 24 ws^2 bytes)
+            out[name]["windows"] = st["windows"]
+            out[name]["chain_steps"] = st["chain_steps"]
+            out[name]["chain_steps_per_s"] = st["chain_steps"] / (ms * 1e-3)
+            out[name]["algorithmic_bytes_per_launch"] = st["chase_bytes"] / launches
+            out[name]["hbm_gbs_algorithmic"] = st["chase_bytes"] / (ms * 1e-3) / 1e9
+            out[name]["hbm_frac_algorithmic"] = out[name]["hbm_gbs_algorithmic"] / HBM_PEAK_GBS
     return out
 
 
@@ -702,9 +765,22 @@ def main():
     gen_s = time.time() - t0
     hdl = schur.Handle(0, ns=args.ns, nb=args.nb, step=args.step_len, aed_window=args.aed_window,
                        aed_nibble=args.aed_nibble, split_window=args.split_window,
-                       flags=schur.FLAG_TIME_KERNELS)
+                       panel_tile=args.panel_tile, flags=schur.FLAG_TIME_KERNELS)
     stream = torch.cuda.current_stream(dev)
 
+    if args.workload == "pipeline":
+        # only the paper's route on a dense U(-1,1) matrix (for profiling)
+        del H0
+        pl = pipeline_measure(args, schur, inputs, dev, stream, H, Q, eye, wr, wi)
+        print(json.dumps({"metric": "paper route at n=%d: Hessenberg, Schur, eigenvectors, "
+                                    "reordering (s)" % n,
+                          "value": sum(pl[k]["seconds" if k != "schur" else "seconds_per_solve"]
+                                       for k in pl),
+                          "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
+                          "data": "synthetic",
+                          "config": {"workload": "paper_route_dense_uniform", "n": n}, **pl}),
+              flush=True)
+        return
     if args.workload == "sweep":
         # only the forced-sweep measurement (for profiling the sweep kernels)
         sw = sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream)

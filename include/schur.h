@@ -23,8 +23,9 @@
  *     H is H[i + j*ldh], 0-based;
  *   - pointers named H, Q, wr, wi are DEVICE pointers (memory of the current
  *     HIP device, e.g. a torch tensor's data_ptr()), unless stated otherwise;
- *   - streams are passed as `void*` holding a hipStream_t (NULL = the
- *     handle's own stream);
+ *   - streams are passed as `void*` holding a hipStream_t; NULL is the null
+ *     (default) stream itself, so work the caller queued there (for example
+ *     on PyTorch's default stream) is ordered before the call's work;
  *   - return value `info`:
  *         0      success
  *        -i      argument i is illegal (1-based position in the argument
@@ -89,10 +90,15 @@ typedef struct schur_opts {
                     /* batched calls use them; the server does not             */
   int split_min_n;  /* smallest order that starts with those passes;          */
                     /* 0 = 2048                                                */
-  int reserved[1];
+  int panel_tile;   /* panel products of the sweeps: tiles (64 columns or rows of */
+                    /* the panel) per workgroup, i.e. the workgroup's output   */
+                    /* tile is ws x 64*panel_tile; 1..8, 0 = by table, else a  */
+                    /* per-launch cost model                                   */
 } schur_opts;
 
 #define SCHUR_FLAG_TIME_KERNELS 1   /* time each kernel family with HIP events */
+#define SCHUR_FLAG_BATCH_ROUNDS 2   /* schur_reduce_batched: every matrix through the  */
+                                    /* round engine (no persistent kernel)             */
 
 /* Counters of the last solve on a handle. */
 typedef struct schur_stats {
@@ -154,6 +160,12 @@ typedef struct schur_stats {
   double reorder_ms;        /* summed duration of the window tasks (TIME)       */
   int64_t reorder_windows;  /* windows processed                                */
   int64_t reorder_steps;    /* time steps (launches of window tasks)            */
+  double chase_bytes;       /* algorithmic HBM bytes of the window chases: the  */
+                            /* window read and written back and its factor U   */
+                            /* written, 24 ws^2 per window of order ws         */
+  /* schur_reduce_batched */
+  double persist_ms;        /* duration of the persistent kernel (TIME)         */
+  int64_t persist_jobs;     /* matrices it solved                               */
 } schur_stats;
 
 /* --------------------------------------------------------------------------
@@ -165,7 +177,8 @@ typedef struct schur_stats {
  *            Schur vectors, the Q products are skipped)
  *   ldq      >= max(1, n) when Q != NULL
  *   wr, wi   device, n doubles each
- * Uses a per-device default handle and its stream; blocks until done.
+ * Uses a per-device default handle; runs on the null stream after the
+ * work already there and blocks until done.
  * ------------------------------------------------------------------------ */
 int schur_reduce(int n, double* H, int ldh, double* Q, int ldq, double* wr, double* wi);
 
@@ -191,7 +204,7 @@ int schur_reduce_async(schur_handle_t h, void* stream, int n, double* H, int ldh
  * schur_hessenberg -- Hessenberg reduction A = Q1 H Q1^T (paper Sec. 2,
  * Eq. (3)), the step before the Schur reduction: H = schur_hessenberg(A),
  * then schur_reduce(H, Q) with the same Q gives A = (Q1 Q2) S (Q1 Q2)^T.
- *   h        handle (its workspace; stream NULL = the handle's stream)
+ *   h        handle (its workspace; stream NULL = the null stream)
  *   n        order, n >= 0
  *   A        device, lda x n; in: dense A; out: H (upper Hessenberg, exact
  *            zeros below the first subdiagonal)
@@ -214,7 +227,7 @@ int schur_hessenberg(schur_handle_t h, void* stream, int n, double* A, int lda, 
  * backtransform (paper Sec. 2, Eqs. (5) and (6)), the step after the Schur
  * reduction: with S and Q = Q1 Q2 from schur_hessenberg and schur_reduce,
  * X holds the eigenvectors of A.
- *   h        handle (its workspace; stream NULL = the handle's stream)
+ *   h        handle (its workspace; stream NULL = the null stream)
  *   n        order, n >= 0
  *   S        device, lds x n, read only: a standardised real Schur form (as
  *            schur_reduce returns it: 2x2 blocks with equal diagonal and
@@ -251,7 +264,7 @@ int schur_eigenvectors(schur_handle_t h, void* stream, int n, const double* S, i
  * their diagonal order; Q <- Q Q3.  With S and Q = Q1 Q2 from the previous
  * steps, the first m columns of Q span the invariant subspace of A for the
  * selected eigenvalues.
- *   h        handle (its workspace; stream NULL = the handle's stream)
+ *   h        handle (its workspace; stream NULL = the null stream)
  *   n        order, n >= 0
  *   S        device, lds x n; in: a standardised real Schur form (as
  *            schur_reduce returns it); out: S'
@@ -341,9 +354,14 @@ int schur_reduce_end(schur_handle_t h, void* stream);
  * orders in one call.  n, ldh, ldq are HOST arrays of `count` ints; H, Q,
  * wr, wi are HOST arrays of `count` DEVICE pointers (Q[i] may be NULL,
  * or Q itself NULL for no Schur vectors).  info is a HOST array of `count`
- * ints receiving each matrix's info.  Matrices of order <= 96 are solved one
- * per workgroup in a single launch; larger ones are advanced sweep by sweep
- * with the windows and panel tiles of all of them in shared launches.
+ * ints receiving each matrix's info.  Matrices of order <= 1024 are solved by
+ * one persistent launch: a grid of one workgroup per CU takes them from a
+ * queue, largest first, and each workgroup runs a whole Schur reduction on
+ * the device (early deflation, shifts, bulge chains chased through LDS
+ * windows, FP64 MFMA panel products; paper Sec. 3.2) with no host round
+ * trip.  Larger matrices (or all of them, with SCHUR_FLAG_BATCH_ROUNDS) are
+ * advanced sweep by sweep with the windows and panel tiles of all of them in
+ * shared launches (matrices of order <= 96 one per workgroup).
  * Returns 0 when every matrix succeeded, else the first nonzero info.
  * ------------------------------------------------------------------------ */
 int schur_reduce_batched(schur_handle_t h, void* stream, int count, const int* n,
@@ -354,16 +372,18 @@ int schur_reduce_batched(schur_handle_t h, void* stream, int count, const int* n
  * Tuning table (written by the autotuner).  For a matrix (or active block)
  * of order n, the first entry with n <= nmax[i] supplies the shifts per
  * sweep, bulges per window chain, chain steps per window (0 = largest that
- * fits), the early-deflation window (nw: 0 = from ns, < 0 = off, else
- * 4..96) and its sweep-skip percentage (nibble: 0 = 14, < 0 = always sweep,
- * else 1..100) whenever the handle's options leave them 0; nw and nibble may
+ * fits; with the bulges it sets the diagonal window's order), the
+ * early-deflation window (nw: 0 = from ns, < 0 = off, else 4..96), its
+ * sweep-skip percentage (nibble: 0 = 14, < 0 = always sweep, else 1..100)
+ * and the panel products' tiles per workgroup (tile: 0 = cost model, else
+ * 1..8) whenever the handle's options leave them 0; nw, nibble and tile may
  * be NULL for all 0.  Arrays of `count` entries, nmax strictly ascending;
  * host memory, read during the call.  Process-wide; count = 0 restores the
  * built-in table.  Returns 0, -1 (count < 0) or -2 (an entry out of range).
  * Host-only, no device work.
  * ------------------------------------------------------------------------ */
 int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, const int* step,
-                     const int* nw, const int* nibble);
+                     const int* nw, const int* nibble, const int* tile);
 
 /* --------------------------------------------------------------------------
  * Sweep schedule (host-only diagnostic of the planner, no device work):

@@ -59,6 +59,24 @@ __device__ __forceinline__ void wave_sync() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Barrier of the one-wavefront solvers (small-block QR, early-deflation and
+// reordering windows).  Their own kernels run one wavefront per workgroup,
+// where it is __syncthreads().  A kernel that runs them on the first
+// wavefront of a larger workgroup defines SCHUR_SOLVER_WAVE_SYNC before the
+// includes: then it drains the wavefront's outstanding memory operations
+// (what the barrier's fence does for a lone wavefront) and orders the lanes,
+// without waiting for the other wavefronts.
+#ifdef SCHUR_SOLVER_WAVE_SYNC
+__device__ __forceinline__ void solver_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+#else
+__device__ __forceinline__ void solver_sync() { __syncthreads(); }
+#endif
+
 // Value of v held by lane src of the wavefront (src uniform, 0..63): two
 // v_readlane_b32 into scalar registers, no LDS round trip.
 __device__ __forceinline__ double lane_read(double v, int src) {

@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "../../include/schur.h"
+#include "batch.h"
 #include "evec.h"
 #include "hess.h"
 #include "kernels.h"
@@ -139,6 +140,9 @@ struct schur_handle_s {
   Grow b_evy, b_evb;
   // reordering: row flags + info, window tasks, panel descriptors, U slots
   Grow b_rsel, b_rtask, b_rwin, b_ru;
+  // persistent batched kernel: jobs, queue order, results (info, counters),
+  // per-workgroup scratch and the queue counter
+  Grow b_pjob, b_pord, b_pres, b_pscr;
   // nested solve of a trailing block larger than SMALL_EIG_MAX (shifts only)
   schur_handle_s* sub = nullptr;
   // buffers of the parallel early-deflation passes that the batched engine
@@ -173,16 +177,17 @@ bool is_device_ptr(const void* p) {
 struct TuneRow {
   int nmax, ns, nb, step, nw;   // nw: early-deflation window (0: from ns, < 0: off)
   int nibble;                   // sweep-skip percentage after a window (0: default)
+  int tile;                     // panel tiles (64 columns or rows) per workgroup (0: model)
 };
 // built-in table: plain double-shift sweeps for small orders, then more
 // shifts per sweep as the order grows; early-deflation windows of 64 rows
 // for large orders, followed by another window rather than a sweep once it
 // deflates more than 7 % (measured at n = 16384: 64 rows beat 48 and 96;
 // 7 % needs no sweep, 14 % a few)
-const TuneRow kBuiltinTune[] = {{299, 2, 1, 0, 0, 0},
-                                {2999, 32, 16, 0, 0, 0},
-                                {5999, 64, 16, 0, 64, 7},
-                                {1 << 30, 128, 16, 0, 64, 7}};
+const TuneRow kBuiltinTune[] = {{299, 2, 1, 0, 0, 0, 0},
+                                {2999, 32, 16, 0, 0, 0, 0},
+                                {5999, 64, 16, 0, 64, 7, 0},
+                                {1 << 30, 128, 16, 0, 64, 7, 0}};
 std::mutex g_tune_mu;
 std::vector<TuneRow> g_tune(std::begin(kBuiltinTune), std::end(kBuiltinTune));
 
@@ -199,6 +204,7 @@ struct Params {
   int nibble;  // skip the sweep after a window that deflated > nibble % of nw (-1: never)
   int split_nw;     // window order of the parallel early-deflation passes (0: none)
   int split_min_n;  // smallest order that runs them
+  int tile;         // panel tiles per workgroup of the sweep's products (0: cost model)
   bool time;
 };
 
@@ -246,6 +252,8 @@ Params resolve(const schur_opts& o, int n) {
                                                               : SMALL_Z_MAX);
   if (p.split_nw < 3) p.split_nw = 0;
   p.split_min_n = o.split_min_n > 0 ? o.split_min_n : kSplitMinN;
+  const int tl = o.panel_tile != 0 ? o.panel_tile : tr.tile;
+  p.tile = tl > 0 ? std::min(tl, PANEL_TPB) : 0;
   if (aw < 0) p.nw = 0;
   else if (aw > 0) p.nw = std::min(aw, SMALL_Z_MAX);
   else p.nw = std::min(SMALL_Z_MAX, std::max(16, p.ns + p.ns / 2));
@@ -309,6 +317,7 @@ void free_ws(schur_handle_s* h) {
   free_grow(h->b_hvy); free_grow(h->b_ht); free_grow(h->b_hp); free_grow(h->b_hy);
   free_grow(h->b_hw); free_grow(h->b_evy); free_grow(h->b_evb);
   free_grow(h->b_rsel); free_grow(h->b_rtask); free_grow(h->b_rwin); free_grow(h->b_ru);
+  free_grow(h->b_pjob); free_grow(h->b_pord); free_grow(h->b_pres); free_grow(h->b_pscr);
   if (h->U) (void)hipFree(h->U);
   if (h->refl) (void)hipFree(h->refl);
   if (h->st) (void)hipFree(h->st);
@@ -493,7 +502,8 @@ struct Solver {
   // workgroup + the fixed cost of a workgroup, about half a tile), so that
   // the windows' ragged tile counts leave few CUs idle in the last round.
   template <typename TilesOf>
-  static int tiles_per_block(int nwin, TilesOf tiles_of) {
+  int tiles_per_block(int nwin, TilesOf tiles_of) const {
+    if (P.tile > 0) return P.tile;   // fixed by the options or the tuning table
     constexpr int kCUs = 256;
     int best = 1;
     double best_cost = 1e300;
@@ -806,6 +816,7 @@ struct Solver {
         h->stats.windows += 1;
         h->stats.chain_steps += pl.tau1 - pl.tau0;
         h->stats.chase_flops += chase_work(pl.ws, pl.nb, pl.tau1 - pl.tau0);
+        h->stats.chase_bytes += 24.0 * (double)pl.ws * (double)pl.ws;
       }
       hipEvent_t e0 = nullptr;
       if (P.time) h->timer.begin(s, e0);
@@ -1170,7 +1181,7 @@ int solve(schur_handle_s* h, hipStream_t s, int n, double* H, int ldh, double* Q
     rc = alloc_ws(h, n);
     if (rc) return rc;
     std::memset(&h->stats, 0, sizeof(h->stats));
-    Solver sv{h, s ? s : h->stream, resolve(h->opts, n), n, H, ldh, Q, ldq, wr, wi};
+    Solver sv{h, s, resolve(h->opts, n), n, H, ldh, Q, ldq, wr, wi};
     return sv.run();
   } catch (const HipErr& e) {
     (void)hipGetLastError();
@@ -2128,6 +2139,7 @@ struct BatchEngine {
             h->stats.windows += 1;
             h->stats.chain_steps += pl.tau1 - pl.tau0;
             h->stats.chase_flops += chase_work(pl.ws, pl.nb, pl.tau1 - pl.tau0);
+            h->stats.chase_bytes += 24.0 * (double)pl.ws * (double)pl.ws;
           }
         }
         tr_t[t] = tr;
@@ -2265,6 +2277,104 @@ bool batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<
   return ok;
 }
 
+// Matrices of order up to this go to the persistent kernel (one workgroup
+// per matrix, the whole solve on the device); larger ones to the round
+// engine, which spreads one matrix's windows and panel tiles over the GPU.
+constexpr int kPersistMaxN = 1024;
+
+// One job of the persistent kernel: the options resolved for order n, in the
+// kernel's ranges (at most 128 shifts, 8 bulges per window chain).
+void fill_job(PJob& J, const schur_opts& o, int n, double* H, int ldh, double* Q, int ldq,
+              double* wr, double* wi, int* info, double* counters) {
+  const Params P = resolve(o, std::max(1, n));
+  std::memset(&J, 0, sizeof(J));
+  J.H = H; J.Q = Q; J.wr = wr; J.wi = wi;
+  J.ldh = ldh; J.ldq = Q ? ldq : 1; J.n = n;
+  J.ns = std::max(2, std::min(P.ns, SMALL_EIG_MAX) & ~1);
+  J.nb = std::max(1, std::min(P.nb, PB_NBMAX));
+  J.step = P.step;
+  J.nw = P.nw;
+  J.nibble = P.nibble;
+  J.nmin = P.nmin;
+  J.exc_period = P.exc_period;
+  J.max_sweeps = P.max_sweeps;
+  J.info = info;
+  J.counters = counters;
+}
+
+// queue order: largest first, so that the last workgroups to finish hold
+// small matrices
+void order_jobs(const PJob* jobs, int* order, int cnt) {
+  for (int j = 0; j < cnt; ++j) order[j] = j;
+  std::stable_sort(order, order + cnt, [&](int a, int b) { return jobs[a].n > jobs[b].n; });
+}
+
+int device_cus(int device) {
+  int cus = 0;
+  HCHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+  return std::max(1, cus);
+}
+
+// The persistent batched kernel over the matrices idx[] of a batched call:
+// one launch, taken largest first; writes their info codes to info[idx[j]].
+void solve_persistent(schur_handle_s* h, hipStream_t s, const std::vector<int>& idx,
+                      const int* n, double* const* H, const int* ldh, double* const* Q,
+                      const int* ldq, double* const* wr, double* const* wi, int* info) {
+  const int cnt = (int)idx.size();
+  if (cnt == 0) return;
+  const int grid = std::min(cnt, device_cus(h->device));
+  grow(h->b_pjob, sizeof(PJob) * cnt, true);
+  grow(h->b_pord, sizeof(int) * cnt, true);
+  const size_t res_bytes = sizeof(double) * PB_COUNTERS * cnt + sizeof(int) * cnt;
+  grow(h->b_pres, res_bytes, true);
+  grow(h->b_pscr, sizeof(PScratch) * grid + 256, false);
+  PJob* jh = (PJob*)h->b_pjob.host;
+  int* oh = (int*)h->b_pord.host;
+  double* cnt_d = (double*)h->b_pres.dev;
+  int* info_d = (int*)(cnt_d + (size_t)PB_COUNTERS * cnt);
+  for (int j = 0; j < cnt; ++j) {
+    const int i = idx[j];
+    double* qi = Q ? Q[i] : nullptr;
+    fill_job(jh[j], h->opts, n[i], H[i], ldh[i], qi, (qi && ldq) ? ldq[i] : 1, wr[i], wi[i],
+             info_d + j, cnt_d + (size_t)PB_COUNTERS * j);
+  }
+  order_jobs(jh, oh, cnt);
+  HCHECK(hipMemcpyAsync(h->b_pjob.dev, jh, sizeof(PJob) * cnt, hipMemcpyHostToDevice, s));
+  HCHECK(hipMemcpyAsync(h->b_pord.dev, oh, sizeof(int) * cnt, hipMemcpyHostToDevice, s));
+  PScratch* scr = (PScratch*)h->b_pscr.dev;
+  int* next = (int*)((char*)h->b_pscr.dev + sizeof(PScratch) * grid);
+  const bool time = (h->opts.flags & SCHUR_FLAG_TIME_KERNELS) != 0;
+  hipEvent_t e0 = nullptr;
+  if (time) h->timer.begin(s, e0);
+  launch_batch_persistent((const PJob*)h->b_pjob.dev, (const int*)h->b_pord.dev, cnt, next, scr,
+                          grid, s);
+  HCHECK(hipGetLastError());
+  if (time) h->timer.end(s, e0, &h->stats.persist_ms);
+  HCHECK(hipMemcpyAsync(h->b_pres.host, h->b_pres.dev, res_bytes, hipMemcpyDeviceToHost, s));
+  HCHECK(hipStreamSynchronize(s));
+  if (time) h->timer.harvest();
+  const double* ch = (const double*)h->b_pres.host;
+  const int* ih = (const int*)(ch + (size_t)PB_COUNTERS * cnt);
+  schur_stats& st = h->stats;
+  for (int j = 0; j < cnt; ++j) {
+    info[idx[j]] = ih[j];
+    const double* c = ch + (size_t)PB_COUNTERS * j;
+    st.sweeps += (int64_t)c[PB_SWEEPS];
+    st.windows += (int64_t)c[PB_WINDOWS];
+    st.chain_steps += (int64_t)c[PB_CHAIN_STEPS];
+    st.aed_windows += (int64_t)c[PB_AED_WINDOWS];
+    st.aed_deflated += (int64_t)c[PB_AED_DEFLATED];
+    st.small_solves += (int64_t)c[PB_SMALL];
+    st.shifts_applied += (int64_t)c[PB_SHIFTS];
+    st.gemm_flops += c[PB_GEMM_FLOPS];
+    st.chase_flops += c[PB_CHASE_FLOPS];
+    st.small_flops += c[PB_SMALL_FLOPS];
+    st.aed_flops += c[PB_AED_FLOPS];
+  }
+  st.persist_jobs += cnt;
+  st.launches += 2;
+}
+
 int solve_batched(schur_handle_s* h, hipStream_t s, int count, const int* n, double* const* H,
                   const int* ldh, double* const* Q, const int* ldq, double* const* wr,
                   double* const* wi, int* info) {
@@ -2274,16 +2384,20 @@ int solve_batched(schur_handle_s* h, hipStream_t s, int count, const int* n, dou
     if (rc) return rc;
     std::memset(&h->stats, 0, sizeof(h->stats));
     BatchEngine b;
-    b.init(h, s ? s : h->stream, count);
+    b.init(h, s, count);
     b.time = (h->opts.flags & SCHUR_FLAG_TIME_KERNELS) != 0;
-    std::vector<int> pre(count, 0);
+    std::vector<int> pre(count, 0), pinfo(count, 0), pidx;
+    const bool rounds_only = (h->opts.flags & SCHUR_FLAG_BATCH_ROUNDS) != 0;
     for (int i = 0; i < count; ++i) {
       double* qi = Q ? Q[i] : nullptr;
       const int lq = (qi && ldq) ? ldq[i] : 1;
       pre[i] = check_args(n[i], H[i], ldh[i], qi, lq, wr[i], wi[i]);
       if (pre[i] == 0 && n[i] > 65536) pre[i] = -1;
-      if (pre[i] == 0) b.add(i, n[i], H[i], ldh[i], qi, lq, wr[i], wi[i], (uint64_t)i);
+      if (pre[i] != 0 || n[i] == 0) continue;
+      if (!rounds_only && n[i] <= kPersistMaxN) pidx.push_back(i);
+      else b.add(i, n[i], H[i], ldh[i], qi, lq, wr[i], wi[i], (uint64_t)i);
     }
+    solve_persistent(h, b.s, pidx, n, H, ldh, Q, ldq, wr, wi, pinfo.data());
     int64_t guard = 0;
     while (b.any_active()) {
       b.round();
@@ -2292,7 +2406,7 @@ int solve_batched(schur_handle_s* h, hipStream_t s, int count, const int* n, dou
     b.settle();
     int first = 0;
     for (int i = 0; i < count; ++i) {
-      const int r = pre[i] != 0 ? pre[i] : b.M[i].info;
+      const int r = pre[i] != 0 ? pre[i] : (b.M[i].used ? b.M[i].info : pinfo[i]);
       if (info) info[i] = r;
       if (r != 0 && first == 0) first = r;
     }
@@ -2375,6 +2489,20 @@ struct schur_server_s {
   int slots = 1024;
   uint64_t next_ticket = 1;
   schur_server_stats st{};
+  // requests of order <= kPersistMaxN: one persistent launch per group of
+  // requests admitted together, on a small pool of streams, so that groups
+  // admitted while others run overlap with them on the device
+  static constexpr int kLanes = 4;
+  hipStream_t lane[kLanes] = {};
+  int lane_next = 0;
+  struct Group {
+    std::vector<Request*> reqs;
+    hipStream_t s = nullptr;
+    char* host = nullptr;   // pinned: jobs and queue order, then the info codes
+    size_t off_info = 0;
+    hipEvent_t ev = nullptr;
+  };
+  std::vector<Group> groups;
 };
 
 namespace {
@@ -2395,6 +2523,65 @@ void free_request_host(Request* r) {
   r->ev = nullptr;
 }
 
+// One persistent launch for the requests of order <= kPersistMaxN admitted
+// together: their device buffers, input copies, the launch, result copies
+// to pinned memory and the frees, all in order on one stream of the pool;
+// an event marks the group's completion.
+void launch_group(schur_server_s* S, const std::vector<Request*>& reqs) {
+  schur_server_s::Group G;
+  G.reqs = reqs;
+  G.s = S->lane[S->lane_next++ % schur_server_s::kLanes];
+  const int cnt = (int)reqs.size();
+  const int grid = std::min(cnt, device_cus(S->h->device));
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t off_ord = up(sizeof(PJob) * cnt);
+  G.off_info = up(off_ord + sizeof(int) * cnt);
+  const size_t off_scr = up(G.off_info + sizeof(int) * cnt);
+  const size_t off_next = off_scr + sizeof(PScratch) * grid;
+  char* dev = nullptr;
+  HCHECK(hipMallocAsync((void**)&dev, off_next + 256, G.s));
+  HCHECK(hipHostMalloc((void**)&G.host, off_scr, hipHostMallocDefault));
+  PJob* jh = (PJob*)G.host;
+  int* oh = (int*)(G.host + off_ord);
+  for (int j = 0; j < cnt; ++j) {
+    Request* r = reqs[j];
+    const int n = r->n;
+    const size_t nn = (size_t)n * n;
+    HCHECK(hipMallocAsync((void**)&r->dH, sizeof(double) * std::max<size_t>(1, nn), G.s));
+    if (r->want_q)
+      HCHECK(hipMallocAsync((void**)&r->dQ, sizeof(double) * std::max<size_t>(1, nn), G.s));
+    HCHECK(hipMallocAsync((void**)&r->dw, sizeof(double) * 2 * std::max(1, n), G.s));
+    HCHECK(hipMemcpyAsync(r->dH, r->hH, sizeof(double) * nn, hipMemcpyHostToDevice, G.s));
+    if (r->want_q) launch_set_identity(r->dQ, n, n, G.s);
+    fill_job(jh[j], S->h->opts, n, r->dH, std::max(1, n), r->dQ, std::max(1, n), r->dw,
+             r->dw + std::max(1, n), (int*)(dev + G.off_info) + j, nullptr);
+  }
+  order_jobs(jh, oh, cnt);
+  HCHECK(hipMemcpyAsync(dev, G.host, G.off_info, hipMemcpyHostToDevice, G.s));
+  launch_batch_persistent((const PJob*)dev, (const int*)(dev + off_ord), cnt,
+                          (int*)(dev + off_next), (PScratch*)(dev + off_scr), grid, G.s);
+  HCHECK(hipGetLastError());
+  HCHECK(hipMemcpyAsync(G.host + G.off_info, dev + G.off_info, sizeof(int) * cnt,
+                        hipMemcpyDeviceToHost, G.s));
+  for (Request* r : reqs) {
+    const int n = r->n;
+    const size_t nn = (size_t)n * n;
+    HCHECK(hipMemcpyAsync(r->hH, r->dH, sizeof(double) * nn, hipMemcpyDeviceToHost, G.s));
+    if (r->want_q)
+      HCHECK(hipMemcpyAsync(r->hQ, r->dQ, sizeof(double) * nn, hipMemcpyDeviceToHost, G.s));
+    HCHECK(hipMemcpyAsync(r->hw, r->dw, sizeof(double) * 2 * std::max(1, n),
+                          hipMemcpyDeviceToHost, G.s));
+    HCHECK(hipFreeAsync(r->dH, G.s));
+    if (r->dQ) HCHECK(hipFreeAsync(r->dQ, G.s));
+    HCHECK(hipFreeAsync(r->dw, G.s));
+    r->dH = r->dQ = r->dw = nullptr;
+  }
+  HCHECK(hipFreeAsync(dev, G.s));
+  HCHECK(hipEventCreateWithFlags(&G.ev, hipEventDisableTiming));
+  HCHECK(hipEventRecord(G.ev, G.s));
+  S->groups.push_back(G);
+}
+
 void server_loop(schur_server_s* S) {
   hipStream_t s = S->h->stream;
   try {
@@ -2403,7 +2590,8 @@ void server_loop(schur_server_s* S) {
       std::vector<Request*> admitted;
       {
         std::unique_lock<std::mutex> lk(S->mu);
-        const bool idle = S->queue.empty() && !S->eng.any_active() && S->draining.empty();
+        const bool idle = S->queue.empty() && !S->eng.any_active() && S->draining.empty() &&
+                          S->groups.empty();
         if (idle) {
           if (S->stop) break;
           S->cv.wait_for(lk, std::chrono::milliseconds(2));
@@ -2422,18 +2610,22 @@ void server_loop(schur_server_s* S) {
             continue;
           }
           if (S->in_use + r->bytes > S->budget && !empty_gpu) break;
-          const int slot = S->eng.free_slot();
-          if (slot < 0) break;
+          const bool small = r->n <= kPersistMaxN;
+          const int slot = small ? -1 : S->eng.free_slot();
+          if (!small && slot < 0) break;
           S->queue.pop_front();
           r->slot = slot;
-          S->eng.M[slot].used = true;          // reserve; filled below
+          if (!small) S->eng.M[slot].used = true;   // reserve; filled below
           S->in_use += r->bytes;
           r->state = Request::RESIDENT;
           admitted.push_back(r);
         }
       }
-      // device state of the admitted requests (stream-ordered allocations)
+      // device state of the admitted requests (stream-ordered allocations);
+      // the small ones go out as one persistent launch
+      std::vector<Request*> group;
       for (Request* r : admitted) {
+        if (r->slot < 0) { group.push_back(r); continue; }
         const int n = r->n;
         const size_t nn = (size_t)n * n;
         HCHECK(hipMallocAsync((void**)&r->dH, sizeof(double) * std::max<size_t>(1, nn), s));
@@ -2446,10 +2638,12 @@ void server_loop(schur_server_s* S) {
                    r->dw + std::max(1, n), r->ticket);
         S->resident[r->slot] = r;
       }
+      if (!group.empty()) launch_group(S, group);
       {
         std::lock_guard<std::mutex> lk(S->mu);
-        const int64_t res = (int64_t)std::count_if(S->resident.begin(), S->resident.end(),
-                                                   [](Request* r) { return r != nullptr; });
+        int64_t res = (int64_t)std::count_if(S->resident.begin(), S->resident.end(),
+                                             [](Request* r) { return r != nullptr; });
+        for (const auto& G : S->groups) res += (int64_t)G.reqs.size();
         S->st.resident = res;
         S->st.peak_resident = std::max(S->st.peak_resident, res);
         S->st.bytes_in_use = (double)S->in_use;
@@ -2499,7 +2693,29 @@ void server_loop(schur_server_s* S) {
         S->st.completed += 1;
       }
       S->draining.swap(keep);
-      if (!S->draining.empty() && !S->eng.any_active()) {
+      // finished persistent groups
+      std::vector<schur_server_s::Group> running;
+      for (auto& G : S->groups) {
+        const hipError_t q = hipEventQuery(G.ev);
+        if (q == hipErrorNotReady) { running.push_back(G); continue; }
+        HCHECK(q);
+        const int* infos = (const int*)(G.host + G.off_info);
+        {
+          std::lock_guard<std::mutex> lk(S->mu);
+          for (size_t j = 0; j < G.reqs.size(); ++j) {
+            Request* r = G.reqs[j];
+            r->info = infos[j];
+            r->t_done = now_s();
+            r->state = Request::DONE;
+            S->in_use -= r->bytes;
+            S->st.completed += 1;
+          }
+        }
+        HCHECK(hipHostFree(G.host));
+        HCHECK(hipEventDestroy(G.ev));
+      }
+      S->groups.swap(running);
+      if ((!S->draining.empty() || !S->groups.empty()) && !S->eng.any_active()) {
         std::unique_lock<std::mutex> lk(S->mu);
         if (S->queue.empty()) S->cv.wait_for(lk, std::chrono::microseconds(200));
       }
@@ -2582,7 +2798,8 @@ int schur_reduce(int n, double* H, int ldh, double* Q, int ldq, double* wr, doub
     h = g_default[dev];
   }
   std::lock_guard<std::mutex> lk(g_mu);
-  return solve(h, h->stream, n, H, ldh, Q, ldq, wr, wi);
+  // on the null stream: after whatever the caller queued there
+  return solve(h, nullptr, n, H, ldh, Q, ldq, wr, wi);
 }
 
 int schur_reduce_noalloc(void* stream, int n, double* H, int ldh, double* Q, int ldq,
@@ -2593,19 +2810,19 @@ int schur_reduce_noalloc(void* stream, int n, double* H, int ldh, double* Q, int
 int schur_hessenberg(schur_handle_t h, void* stream, int n, double* A, int lda, double* Q,
                      int ldq) {
   if (!h) return -104;
-  return hess_reduce(h, stream ? (hipStream_t)stream : h->stream, n, A, lda, Q, ldq);
+  return hess_reduce(h, (hipStream_t)stream, n, A, lda, Q, ldq);
 }
 
 int schur_eigenvectors(schur_handle_t h, void* stream, int n, const double* S, int lds,
                        const double* Q, int ldq, double* X, int ldx) {
   if (!h) return -104;
-  return evec_compute(h, stream ? (hipStream_t)stream : h->stream, n, S, lds, Q, ldq, X, ldx);
+  return evec_compute(h, (hipStream_t)stream, n, S, lds, Q, ldq, X, ldx);
 }
 
 int schur_reorder(schur_handle_t h, void* stream, int n, double* S, int lds, double* Q, int ldq,
                   const int* select, double* wr, double* wi, int* m) {
   if (!h) return -104;
-  return reorder_run(h, stream ? (hipStream_t)stream : h->stream, n, S, lds, Q, ldq, select, wr,
+  return reorder_run(h, (hipStream_t)stream, n, S, lds, Q, ldq, select, wr,
                      wi, m);
 }
 
@@ -2715,12 +2932,16 @@ int schur_server_create(schur_server_t* out, int device, size_t hbm_budget_bytes
     HCHECK(hipSetDevice(device));
     if (alloc_ws(S->h, 2) != 0) throw HipErr{hipErrorOutOfMemory};
     S->eng.init(S->h, S->h->stream, S->slots);
+    for (int k = 0; k < schur_server_s::kLanes; ++k)
+      HCHECK(hipStreamCreateWithFlags(&S->lane[k], hipStreamNonBlocking));
     // the passes run on the host thread that drives the rounds: they would
     // stall every other resident request for their duration
     S->eng.allow_split = false;
     S->resident.assign(S->slots, nullptr);
     HCHECK(hipStreamSynchronize(S->h->stream));
   } catch (const HipErr&) {
+    for (int k = 0; k < schur_server_s::kLanes; ++k)
+      if (S->lane[k]) (void)hipStreamDestroy(S->lane[k]);
     schur_destroy(S->h);
     delete S;
     return -101;
@@ -2738,6 +2959,17 @@ int schur_server_destroy(schur_server_t S) {
   }
   S->cv.notify_all();
   if (S->th.joinable()) S->th.join();
+  (void)hipSetDevice(S->h->device);
+  for (int k = 0; k < schur_server_s::kLanes; ++k) {
+    if (!S->lane[k]) continue;
+    (void)hipStreamSynchronize(S->lane[k]);
+    (void)hipStreamDestroy(S->lane[k]);
+  }
+  for (auto& G : S->groups) {   // left by a failed loop: their streams are drained
+    if (G.host) (void)hipHostFree(G.host);
+    if (G.ev) (void)hipEventDestroy(G.ev);
+  }
+  S->groups.clear();
   for (auto& kv : S->all) { free_request_host(kv.second); delete kv.second; }
   S->all.clear();
   schur_destroy(S->h);
@@ -2824,7 +3056,7 @@ int schur_server_get_stats(schur_server_t S, schur_server_stats* out) {
 }
 
 int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, const int* step,
-                     const int* nw, const int* nibble) {
+                     const int* nw, const int* nibble, const int* tile) {
   if (count < 0) return -1;
   std::vector<TuneRow> t;
   if (count == 0) {
@@ -2837,7 +3069,9 @@ int schur_set_tuning(int count, const int* nmax, const int* ns, const int* nb, c
       if (ns[i] < 2 || ns[i] > NS_MAX || nb[i] < 1 || nb[i] > NBMAX || step[i] < 0 ||
           w > SMALL_Z_MAX || (w > 0 && w < 4) || nib > 100 || (i > 0 && nmax[i] <= nmax[i - 1]))
         return -2;
-      t.push_back(TuneRow{nmax[i], ns[i] & ~1, nb[i], step[i], w, nib});
+      const int tl = tile ? tile[i] : 0;
+      if (tl < 0 || tl > PANEL_TPB) return -2;
+      t.push_back(TuneRow{nmax[i], ns[i] & ~1, nb[i], step[i], w, nib, tl});
     }
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);

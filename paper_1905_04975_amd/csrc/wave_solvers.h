@@ -1,8 +1,9 @@
 // wave_solvers.h -- one-wavefront LDS solvers of the Schur engine: the
 // small-block Francis double-shift QR and the aggressive-early-deflation
-// window step.  Included by kernels.hip; written against the HIP device
-// API only (threadIdx, __syncthreads, __shfl_xor, __ballot), so the same
-// source also runs under a CPU emulation of one wavefront in the tests.
+// window step.  Included by kernels.hip and batch_kernels.hip; written
+// against the HIP device API only (threadIdx, __syncthreads through
+// solver_sync, __shfl_xor, __ballot), so the same source also runs under a
+// CPU emulation of one wavefront in the tests.
 #pragma once
 #include "schur_internal.h"
 #include "device_common.h"
@@ -121,7 +122,7 @@ __device__ void chase_reg(double* S, double* Zs, int m_in, int l_in, int i_in, d
     cA = far ? n2 : lA;
     cB = far ? n3 : lB;
   }
-  __syncthreads();
+  solver_sync();
 }
 
 // The same chase for 64 < m <= 128: lane q owns columns q and q + 64 in the
@@ -239,7 +240,7 @@ __device__ void chase_reg2(double* S, double* Zs, int m_in, int l_in, int i_in, 
     cA1 = far1 ? n21 : lA1;
     cB1 = far1 ? n31 : lB1;
   }
-  __syncthreads();
+  solver_sync();
 }
 
 // Francis double-shift iteration on the m x m block already in LDS (S, and Z
@@ -281,9 +282,9 @@ __device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
         break;
       }
     }
-    __syncthreads();
+    solver_sync();
     if (l > 0 && lane == 0) Sx(l, l - 1) = 0.0;
-    __syncthreads();
+    solver_sync();
 
     if (l == i) {
       if (lane == 0 && T.wr) { T.wr[i] = Sx(i, i); T.wi[i] = 0.0; }
@@ -292,7 +293,7 @@ __device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
     }
     if (l == i - 1) {
       const Std2 o = standardize2(Sx(i - 1, i - 1), Sx(i - 1, i), Sx(i, i - 1), Sx(i, i));
-      __syncthreads();
+      solver_sync();
       if (WANTZ && !(o.cs == 1.0 && o.sn == 0.0)) {
         for (int c = i + 1 + lane; c < m; c += 64) {
           const double x = Sx(i - 1, c), y = Sx(i, c);
@@ -320,7 +321,7 @@ __device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
           T.wr[i] = o.wr2;     T.wi[i] = o.wi2;
         }
       }
-      __syncthreads();
+      solver_sync();
       i -= 2; its = 0;
       continue;
     }
@@ -352,7 +353,7 @@ __device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
     double x, y, z;
     first_column(Sx(l, l), Sx(l, l + 1), Sx(l + 1, l), Sx(l + 1, l + 1), Sx(l + 2, l + 1), s, t,
                  x, y, z);
-    __syncthreads();   // every lane has read the corner before the first left update
+    solver_sync();   // every lane has read the corner before the first left update
     if (WANTZ && m <= 64) {
       chase_reg<MAXM>(S, Zs, m, l, i, x, y, z);
       continue;
@@ -386,7 +387,7 @@ __device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
         Sx(r + 1, c) = a2 - tv2 * w;
         Sx(r3, c) = (nr == 3) ? a3 - tv3 * w : a2 - tv2 * w;   // r3 = r + 1 for two rows
       }
-      __syncthreads();
+      solver_sync();
       if (r > l && lane == 0) {
         Sx(r, r - 1) = h.beta;
         Sx(r + 1, r - 1) = 0.0;
@@ -424,10 +425,10 @@ __device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
           if (nr == 3) Zx(qz, r + 2) = z3 - tv3 * wz;
         }
       }
-      __syncthreads();
+      solver_sync();
     }
   }
-  __syncthreads();
+  solver_sync();
   return info;
 }
 
@@ -442,7 +443,7 @@ __device__ void small_load(const SmallTask& T, double* S, double* Zs) {
   if (WANTZ)
     for (int c = 0; c < m; ++c)
       for (int r = lane; r < m; r += 64) Zs[r + c * LD] = (r == c) ? 1.0 : 0.0;
-  __syncthreads();
+  solver_sync();
 }
 
 // Whole small-block solve: load, iterate, then the Schur form back in place
@@ -473,7 +474,7 @@ __device__ void small_qr(const SmallTask& T, double* S, double* Zs) {
     if (T.Qacc) {
       // Qacc <- Qacc Z, rows by lanes, 16 columns at a time; the block's LDS
       // copy (already written back) is the staging area
-      __syncthreads();
+      solver_sync();
       for (int r = lane; r < m; r += 64) {
         for (int c0 = 0; c0 < m; c0 += 16) {
           double acc[16];
@@ -490,7 +491,7 @@ __device__ void small_qr(const SmallTask& T, double* S, double* Zs) {
             if (c0 + j < m) Sx(r, c0 + j) = acc[j];
         }
       }
-      __syncthreads();
+      solver_sync();
       for (int c = 0; c < m; ++c)
         for (int r = lane; r < m; r += 64) T.Qacc[r + (size_t)c * T.ldqacc] = Sx(r, c);
     }
@@ -726,7 +727,7 @@ __device__ void aed_std_all(double* S, double* Zs, int LD, int m, int lo, double
       blk[4 * (i - lo) + 3] = o.d;
     }
   }
-  __syncthreads();
+  solver_sync();
   // row pairs: column c meets the blocks starting at i <= c
   for (int c = lo + lane; c < m; c += 64) {
     for (int i = lo; i + 1 < m && i <= c; ++i) {
@@ -737,7 +738,7 @@ __device__ void aed_std_all(double* S, double* Zs, int LD, int m, int lo, double
       Sx(i + 1, c) = cs * y - sn * x;
     }
   }
-  __syncthreads();
+  solver_sync();
   // column pairs: row r of S meets the blocks with i + 1 >= r; all rows of Z
   for (int q = lane; q < 2 * m; q += 64) {
     const bool inS = q < m;
@@ -752,7 +753,7 @@ __device__ void aed_std_all(double* S, double* Zs, int LD, int m, int lo, double
       base[r + (i + 1) * LD] = cs * y - sn * x;
     }
   }
-  __syncthreads();
+  solver_sync();
   // the blocks exactly in standard form (a complex pair with equal diagonal,
   // or two real eigenvalues with a zero subdiagonal)
   for (int i = lo + lane; i + 1 < m; i += 64) {
@@ -762,7 +763,7 @@ __device__ void aed_std_all(double* S, double* Zs, int LD, int m, int lo, double
     Sx(i + 1, i) = blk[4 * (i - lo) + 2];
     Sx(i + 1, i + 1) = blk[4 * (i - lo) + 3];
   }
-  __syncthreads();
+  solver_sync();
 }
 
 // Householder reflector from a column held one entry per lane-slot:
@@ -777,9 +778,9 @@ __device__ void aed_reflector(double alpha, double* vv, int L, double& tau, doub
   if (tmax == 0.0) {
     tau = 0.0;
     beta = alpha;
-    __syncthreads();
+    solver_sync();
     if (lane == 0) vv[0] = 1.0;
-    __syncthreads();
+    solver_sync();
     return;
   }
   const int e = ilogb(fmax(fabs(alpha), tmax));
@@ -797,10 +798,10 @@ __device__ void aed_reflector(double alpha, double* vv, int L, double& tau, doub
   tau = -ds * (ds * r);
   beta = ldexp(bs, e);
   const double f = bs * r;
-  __syncthreads();
+  solver_sync();
   for (int i = 1 + lane; i < L; i += 64) vv[i] = ldexp(vv[i], -e) * f;
   if (lane == 0) vv[0] = 1.0;
-  __syncthreads();
+  solver_sync();
 }
 
 // The whole early-deflation step on one window; S, Z (LD x MAXM each), vv
@@ -878,7 +879,7 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
   if (lane == 0) {
     sh_nmv = 0; sh_bot = m - 1; sh_left = m; sh_tgt = 0;
   }
-  __syncthreads();
+  solver_sync();
   const double tiny = 2.2250738585072014e-308;
   const double smlnum = tiny * ((double)m / kUlp);
   int rounds = 0;
@@ -927,7 +928,7 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
       if (foo == 0.0) foo = fabs(s);
       defl = spk <= fmax(smlnum, kUlp * foo);
     }
-    __syncthreads();
+    solver_sync();
     // ---- plans, one lane per swap
     if (lane < nsw) {
       const int k = sw_k[lane], pp = sw_p[lane], rr = mv_sz[sw_j[lane]];
@@ -947,7 +948,7 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
       pl_d[2 * lane + 1] = Sx(k + pp + rr - 1, k + pp + rr - 1);   // B's
       sw_ok[lane] = ok ? 1 : 0;
     }
-    __syncthreads();
+    solver_sync();
     const bool bad = lane < nsw && sw_ok[lane] == 0;
     if (__ballot(bad) != 0ull) break;   // uniform: nothing of this round is applied
     if (nsw > 0) {
@@ -990,7 +991,7 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
           }
         }
       }
-      __syncthreads();
+      solver_sync();
       // right: rows -xr..k+N-1 of S, then rows 0..zrows-1 of Z (one index
       // space; ra below is the S row relative to the block)
       if (mine) {
@@ -1035,7 +1036,7 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
         }
       }
     }
-    __syncthreads();
+    solver_sync();
     // ---- bookkeeping: each swap's lane moves its block; the last lane
     // records the bottom test (disjoint rows and entries)
     if (lane < nsw) {
@@ -1058,9 +1059,9 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
       }
       sh_left = left - bs;
     }
-    __syncthreads();
+    solver_sync();
   }
-  __syncthreads();
+  solver_sync();
   return sh_bot + 1;
 }
 
@@ -1089,7 +1090,7 @@ __device__ void aed_write_vt(double* S, const double* Z, int LD, int nw, double*
       for (int u = 0; u < 4; ++u)
         if (i0 + u < nw) Sx(i0 + u, j) = acc[u] - ((i0 + u == j) ? 1.0 : 0.0);
     }
-  __syncthreads();
+  solver_sync();
   for (int j = lane; j < ldut; j += 64) {
     for (int r0 = 0; r0 < ldut; r0 += 4) {
       double val[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1180,7 +1181,7 @@ __device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, i
     spike = s * Zx(0, 0);
   } else if (nu > 1) {
     for (int i = lane; i < nu; i += 64) vv[i] = s * Zx(0, i);
-    __syncthreads();
+    solver_sync();
     const double alpha = vv[0];
     double tau, beta;
     aed_reflector(alpha, vv, nu, tau, beta);
@@ -1192,7 +1193,7 @@ __device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, i
         w *= tau;
         for (int i = 0; i < nu; ++i) Sx(i, c) -= vv[i] * w;
       }
-      __syncthreads();
+      solver_sync();
       for (int q = lane; q < nu + nw; q += 64) {     // columns 0..nu-1 of S rows < nu, and of Z
         double* base = (q < nu) ? S : Z;
         const int row = (q < nu) ? q : q - nu;
@@ -1201,14 +1202,14 @@ __device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, i
         w *= tau;
         for (int j = 0; j < nu; ++j) base[row + j * LD] -= w * vv[j];
       }
-      __syncthreads();
+      solver_sync();
     }
     // ---- Hessenberg form of the undeflated part
     for (int j = 0; j + 2 < nu; ++j) {
       const int L = nu - j - 1;                       // rows j+1 .. nu-1
       const double a0 = Sx(j + 1, j);
       for (int i = 1 + lane; i < L; i += 64) vv[i] = Sx(j + 1 + i, j);
-      __syncthreads();
+      solver_sync();
       double tj, bj;
       aed_reflector(a0, vv, L, tj, bj);
       if (tj == 0.0) continue;
@@ -1220,7 +1221,7 @@ __device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, i
         w *= tj;
         for (int i = 0; i < L; ++i) Sx(j + 1 + i, c) -= vv[i] * w;
       }
-      __syncthreads();
+      solver_sync();
       for (int q = lane; q < nu + nw; q += 64) {     // right: columns j+1..nu-1
         double* base = (q < nu) ? S : Z;
         const int row = (q < nu) ? q : q - nu;
@@ -1229,7 +1230,7 @@ __device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, i
         w *= tj;
         for (int i = 0; i < L; ++i) base[row + (j + 1 + i) * LD] -= w * vv[i];
       }
-      __syncthreads();
+      solver_sync();
     }
   }
 
@@ -1237,7 +1238,7 @@ __device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, i
   for (int c = 0; c < nw; ++c)
     for (int r = lane; r <= c + 1 && r < nw; r += 64) Hw[r + (size_t)c * T.ldh] = Sx(r, c);
   if (lane == 0 && kwtop > T.ktop) T.H[kwtop + (size_t)(kwtop - 1) * T.ldh] = spike;
-  __syncthreads();
+  solver_sync();
   aed_write_vt(S, Z, LD, nw, T.Ut, T.ldut);
 }
 
@@ -1276,7 +1277,7 @@ __device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, i
 __device__ void flip_tail(double* S, double* Z, int LD, int nw, int lo) {
   const int lane = threadIdx.x;
   const int d = nw - lo;
-  __syncthreads();
+  solver_sync();
   if (d <= 1) return;
   for (int idx = lane; idx < d * d; idx += 64) {
     const int r = idx % d, c = idx / d;
@@ -1299,7 +1300,7 @@ __device__ void flip_tail(double* S, double* Z, int LD, int nw, int lo) {
     *p1 = *p2;
     *p2 = t;
   }
-  __syncthreads();
+  solver_sync();
 }
 
 // Reflector I - tau vv vv^T (vv[0] = 1, L entries) applied to rows
@@ -1314,7 +1315,7 @@ __device__ void refl_apply(double* S, double* Z, int LD, const double* vv, doubl
     w *= tau;
     for (int i = 0; i < L; ++i) S[(r0 + i) + c * LD] -= vv[i] * w;
   }
-  __syncthreads();
+  solver_sync();
   const int ns = xr + rend;
   for (int q = lane; q < ns + zrows; q += 64) {
     double* base = (q < ns) ? S + (q - xr) : Z + (q - ns);
@@ -1323,7 +1324,7 @@ __device__ void refl_apply(double* S, double* Z, int LD, const double* vv, doubl
     w *= tau;
     for (int j = 0; j < L; ++j) base[(r0 + j) * LD] -= w * vv[j];
   }
-  __syncthreads();
+  solver_sync();
 }
 
 // The m x m quasi-triangular block B = S(0:m, 0:m) is coupled to the rest of
@@ -1336,11 +1337,11 @@ __device__ double spike_reduce(double* S, double* Z, int LD, int m, int ncols, i
                                int srow, double* vv) {
   const int lane = threadIdx.x;
   auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
-  __syncthreads();
+  solver_sync();
   if (m <= 0) return 0.0;
   if (m == 1) return Z[srow];
   for (int i = lane; i < m; i += 64) vv[i] = Z[srow + i * LD];
-  __syncthreads();
+  solver_sync();
   const double alpha = vv[0];
   double tau, beta;
   aed_reflector(alpha, vv, m, tau, beta);
@@ -1349,7 +1350,7 @@ __device__ double spike_reduce(double* S, double* Z, int LD, int m, int ncols, i
     const int L = m - j - 1;   // rows j+1 .. m-1
     const double a0 = Sx(j + 1, j);
     for (int i = 1 + lane; i < L; i += 64) vv[i] = Sx(j + 1 + i, j);
-    __syncthreads();
+    solver_sync();
     double tj, bj;
     aed_reflector(a0, vv, L, tj, bj);
     if (tj == 0.0) continue;
@@ -1357,7 +1358,7 @@ __device__ double spike_reduce(double* S, double* Z, int LD, int m, int ncols, i
     for (int i = 2 + lane; i <= L; i += 64) Sx(j + i, j) = 0.0;
     refl_apply(S, Z, LD, vv, tj, j + 1, L, j + 1, ncols, xr, m, zrows);
   }
-  __syncthreads();
+  solver_sync();
   return beta;
 }
 
@@ -1427,7 +1428,7 @@ __device__ void split_window(const SplitTask& T, double* S, double* Z, double* v
     const int ldw = T.Wo ? T.ldwo : T.ldh;
     for (int c = 0; c < nw; ++c)
       for (int r = lane; r <= c + 1 && r < nw; r += 64) Wd[r + (size_t)c * ldw] = Sx(r, c);
-    __syncthreads();
+    solver_sync();
     aed_write_vt(S, Z, LD, nw, T.Ut, T.ldut);
     out.split = 1;
     out.nu = nu;

@@ -12,8 +12,10 @@ namespace schur {
 // ============================================================================
 // Window chase (the window task).  One workgroup per diagonal window.
 //
-// Thread layout: 1024 threads; group b (TPB = 64 or 32 consecutive threads,
-// inside one wavefront) owns bulge b of the window's chain.  One chain step
+// Thread layout: NT = 1024 threads (the sweep kernels) or 256 (the
+// persistent batched kernel); group b (TPB = 64 or 32 consecutive threads,
+// inside one wavefront) owns bulge b of the window's chain, so a window
+// carries at most NBMAX (1024 threads) or 8 (256 threads) bulges.  One chain step
 // advances every bulge by one row:
 //   B  left update of rows K+1..K+3 from the bulge column to the window end;
 //   C  right update of columns K+1..K+3 from the window top to row K+4;
@@ -24,36 +26,46 @@ namespace schur {
 // Bulges sit three rows apart, so all left updates of a step precede all
 // right updates (B, barrier, C, barrier).  Each thread issues all loads of
 // a phase before its stores.  The reflectors are logged in LDS; after the
-// window is written back, U is accumulated in the freed LDS with eight
+// window is written back, U is accumulated in the freed LDS with NT / 128
 // lanes of one wavefront per row (rows are independent).
 // ============================================================================
 constexpr int CHASE_THREADS = 1024;
 
-__device__ void chase_window(const WinCtx& d) {
-  __shared__ double W[LDW * WMAX];
-  __shared__ double R[REFL_LDS * 3];
+// W: LDW x WMAX doubles of LDS, R: 3 REFL_LDS doubles of LDS.
+template <int NT>
+__device__ void chase_window_t(const WinCtx& d, double* W, double* R) {
+  static_assert(NT == 1024 || NT == 256, "1024 or 256 threads");
+  constexpr int CG = NT / 128;       // column groups of the window load / store
+  constexpr int QL = WMAX / CG;      // columns per thread in them
+  constexpr int QB = QL < 16 ? QL : 16;   // loads in flight per batch
+  constexpr int J = NT / 128;        // lanes per row of the U accumulation
+  constexpr int NBT = NT == 1024 ? NBMAX : NT / 32;   // most bulges per window
+  constexpr int QU = (NBT + J - 1) / J;   // bulges per lane and chain step in it
   const int tid = threadIdx.x;
   const int p = d.p, ws = d.ws, nb = d.nb;
   const int ktop = d.ktop, kbot = d.kbot;
   const WinCtx& a = d;   // matrix fields
   auto Wx = [&](int r, int c) -> double& { return W[r + c * LDW]; };
 
-  // load the window: 8 columns per pass, all loads issued before the stores
+  // load the window: CG columns per pass, a batch of loads issued before
+  // its stores
   {
     const int r = tid & 127, c0 = tid >> 7;
-    double v[16];
+    for (int qb = 0; qb < QL; qb += QB) {
+      double v[QB];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = c0 + 8 * q;
-      v[q] = (r < ws && c < ws) ? a.H[(size_t)(p + r) + (size_t)(p + c) * a.ldh] : 0.0;
-    }
+      for (int q = 0; q < QB; ++q) {
+        const int c = c0 + CG * (qb + q);
+        v[q] = (r < ws && c < ws) ? a.H[(size_t)(p + r) + (size_t)(p + c) * a.ldh] : 0.0;
+      }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = c0 + 8 * q;
-      if (r < ws && c < ws) Wx(r, c) = v[q];
+      for (int q = 0; q < QB; ++q) {
+        const int c = c0 + CG * (qb + q);
+        if (r < ws && c < ws) Wx(r, c) = v[q];
+      }
     }
   }
-  const int lgt = (nb <= 16) ? 6 : 5;
+  const int lgt = (nb <= NT / 64) ? 6 : 5;
   const int tpb = 1 << lgt;
   const int b = tid >> lgt;
   const int t = tid & (tpb - 1);
@@ -170,19 +182,20 @@ __device__ void chase_window(const WinCtx& d) {
   {
     const int r = tid & 127, c0 = tid >> 7;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = c0 + 8 * q;
+    for (int q = 0; q < QL; ++q) {
+      const int c = c0 + CG * q;
       if (r < ws && c < ws) a.H[(size_t)(p + r) + (size_t)(p + c) * a.ldh] = Wx(r, c);
     }
   }
   __syncthreads();
 
-  // ---- accumulate U = P_1 P_2 ... ; row r by lanes j = 0..7 of its wave,
-  // lane j applying the reflectors of bulges j, j+8, j+16 of each chain step
+  // ---- accumulate U = P_1 P_2 ... ; row r by lanes j = 0..J-1 of its wave,
+  // lane j applying the reflectors of bulges j, j+J, j+2J, ... of each chain
+  // step (they touch disjoint columns)
   {
-    const int r = tid >> 3, j = tid & 7;
+    const int r = tid / J, j = tid % J;
     if (r < ws)
-      for (int c = j; c < ws; c += 8) Wx(r, c) = (r == c) ? 1.0 : 0.0;
+      for (int c = j; c < ws; c += J) Wx(r, c) = (r == c) ? 1.0 : 0.0;
     wave_sync();
     for (int tau = d.tau0; tau < d.tau1; ++tau) {
       int klead = ktop - 1 + tau;
@@ -190,11 +203,11 @@ __device__ void chase_window(const WinCtx& d) {
       const bool rowact = (r < ws) && (r <= klead + 3 - p);
       const double* rt = &R[3 * (tau - d.tau0) * nb];
       if (rowact) {
-        double u1[3], u2[3], u3[3], tv[3], v2[3], v3[3];
-        int kk[3];
+        double u1[QU], u2[QU], u3[QU], tv[QU], v2[QU], v3[QU];
+        int kk[QU];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const int bb = j + 8 * q;
+        for (int q = 0; q < QU; ++q) {
+          const int bb = j + J * q;
           tv[q] = (bb < nb) ? rt[3 * bb + 2] : 0.0;
           if (tv[q] != 0.0) {
             v2[q] = rt[3 * bb];
@@ -208,7 +221,7 @@ __device__ void chase_window(const WinCtx& d) {
           }
         }
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
+        for (int q = 0; q < QU; ++q) {
           if (tv[q] == 0.0) continue;
           const double w = tv[q] * (u1[q] + v2[q] * u2[q] + v3[q] * u3[q]);
           double* row = &Wx(r, kk[q] + 1);
@@ -226,11 +239,17 @@ __device__ void chase_window(const WinCtx& d) {
   {
     const int r = tid & 127, c0 = tid >> 7;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {   // Ut(r, c) = U(c, r)
-      const int c = c0 + 8 * q;
+    for (int q = 0; q < QL; ++q) {   // Ut(r, c) = U(c, r)
+      const int c = c0 + CG * q;
       Ut[r + (size_t)c * UPAD] = (r < ws && c < ws) ? Wx(c, r) : 0.0;
     }
   }
+}
+
+__device__ void chase_window(const WinCtx& d) {
+  __shared__ double W[LDW * WMAX];
+  __shared__ double R[REFL_LDS * 3];
+  chase_window_t<CHASE_THREADS>(d, W, R);
 }
 
 }  // namespace schur

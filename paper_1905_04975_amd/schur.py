@@ -26,7 +26,7 @@ class SchurOpts(ctypes.Structure):
                 ("exc_period", ctypes.c_int), ("flags", ctypes.c_int),
                 ("aed_window", ctypes.c_int), ("aed_nibble", ctypes.c_int),
                 ("split_window", ctypes.c_int), ("split_min_n", ctypes.c_int),
-                ("reserved", ctypes.c_int * 1)]
+                ("panel_tile", ctypes.c_int)]
 
 
 class SchurStats(ctypes.Structure):
@@ -55,13 +55,15 @@ class SchurStats(ctypes.Structure):
                 ("ev_gemm_flops", ctypes.c_double), ("ev_back_ms", ctypes.c_double),
                 ("ev_back_flops", ctypes.c_double),
                 ("reorder_ms", ctypes.c_double), ("reorder_windows", ctypes.c_int64),
-                ("reorder_steps", ctypes.c_int64)]
+                ("reorder_steps", ctypes.c_int64), ("chase_bytes", ctypes.c_double),
+                ("persist_ms", ctypes.c_double), ("persist_jobs", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 FLAG_TIME_KERNELS = 1
+FLAG_BATCH_ROUNDS = 2
 
 EXPORTS = ("schur_reduce", "schur_create", "schur_destroy", "schur_set_opts",
            "schur_get_stats", "schur_reduce_async", "schur_reduce_batched",
@@ -147,7 +149,7 @@ def load():
     lib.schur_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.schur_server_get_stats.restype = ctypes.c_int
     pi = ctypes.POINTER(ctypes.c_int)
-    lib.schur_set_tuning.argtypes = [ip, pi, pi, pi, pi, pi, pi]
+    lib.schur_set_tuning.argtypes = [ip, pi, pi, pi, pi, pi, pi, pi]
     lib.schur_set_tuning.restype = ctypes.c_int
     lib.schur_plan_sweep.argtypes = [ip, ip, ip, ip, ip, pi, ip]
     lib.schur_plan_sweep.restype = ctypes.c_int
@@ -255,7 +257,7 @@ class Handle:
 
 
 def make_opts(ns=0, nb=0, step=0, nmin=0, max_sweeps=0, exc_period=0, flags=0, aed_window=0,
-              aed_nibble=0, split_window=0, split_min_n=0):
+              aed_nibble=0, split_window=0, split_min_n=0, panel_tile=0):
     o = SchurOpts()
     o.ns, o.nb, o.step, o.nmin = int(ns), int(nb), int(step), int(nmin)
     o.max_sweeps, o.exc_period, o.flags = int(max_sweeps), int(exc_period), int(flags)
@@ -263,6 +265,7 @@ def make_opts(ns=0, nb=0, step=0, nmin=0, max_sweeps=0, exc_period=0, flags=0, a
     o.aed_nibble = int(aed_nibble)
     o.split_window = int(split_window)
     o.split_min_n = int(split_min_n)
+    o.panel_tile = int(panel_tile)
     return o
 
 
@@ -519,7 +522,8 @@ def set_tuning(rows):
     rc = lib.schur_set_tuning(k, IA(*[r["nmax"] for r in rows]), IA(*[r["ns"] for r in rows]),
                               IA(*[r["nb"] for r in rows]), IA(*[r.get("step", 0) for r in rows]),
                               IA(*[r.get("nw", 0) for r in rows]),
-                              IA(*[r.get("nibble", 0) for r in rows]))
+                              IA(*[r.get("nibble", 0) for r in rows]),
+                              IA(*[r.get("tile", 0) for r in rows]))
     if rc != 0:
         raise ValueError("invalid tuning table (rc=%d)" % rc)
 

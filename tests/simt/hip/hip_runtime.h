@@ -2,8 +2,8 @@
 // kernels use, so that their device source runs on the host: one workgroup
 // is a set of std::threads; __syncthreads is a barrier over all of them,
 // the wavefront barrier one over the 64 threads of a wavefront, and
-// __shfl_xor / __ballot / readlane exchange values through memory between
-// barriers.
+// __shfl_xor / __ballot / readlane / the FP64 MFMA exchange values through
+// memory between wavefront barriers.
 // Threads run freely between barriers, which is stricter than lock-step
 // wavefronts: a kernel that relied on lock-step without a barrier shows a
 // race here.  Every __shared__ object lands in one section that the driver
@@ -40,3 +40,15 @@ void simt_wave_barrier();
 #define __builtin_amdgcn_rcp(x) (1.0 / (x))
 #define __builtin_amdgcn_readlane(v, l) simt_readlane((v), (l))
 #define __builtin_amdgcn_readfirstlane(v) simt_readlane((v), 0)
+#define __builtin_amdgcn_s_waitcnt(x) ((void)0)
+#define __builtin_amdgcn_sched_barrier(x) ((void)0)
+#define __noinline__ __attribute__((noinline))
+using std::max;
+using std::min;
+// FP64 MFMA 16x16x4 of one wavefront (lanes exchange operands through memory)
+typedef double simt_d4 __attribute__((ext_vector_type(4)));
+simt_d4 simt_mfma_f64_16x16x4(double a, double b, simt_d4 c);
+#define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) simt_mfma_f64_16x16x4((a), (b), (c))
+inline int atomicOr(int* p, int v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+inline unsigned atomicOr(unsigned* p, unsigned v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }

@@ -1,9 +1,10 @@
-// Host driver that runs the device source of two LDS kernels on the CPU
-// (see hip/hip_runtime.h): the window chase of a sweep time step, the
-// small-block solver and the early-deflation window step.  Test
+// Host driver that runs the device source of the LDS kernels on the CPU
+// (see hip/hip_runtime.h): the window chase of a sweep time step (1024 or
+// 256 threads), the small-block solver, the early-deflation window step and
+// the whole-matrix driver of the persistent batched kernel.  Test
 // infrastructure.
 //
-//   simt_kernels chase in.bin out.bin
+//   simt_kernels chase|chase256 in.bin out.bin
 //     in : int n, ktop, kbot, nst, nwin; double H[n*n] (column-major);
 //          double st[nst]; nwin x int (p, ws, tau0, tau1, nb, shift0)
 //     out: double H[n*n]; nwin x double Ut[128*128]
@@ -18,9 +19,14 @@
 //     in : int n, ktop, kbot, nw; double H[n*n]
 //     out: int nd, nu; double H[n*n]; double Ut[128*128]; double sr[96], si[96];
 //          double wr[n], wi[n]
+// The one-wavefront solvers use the wavefront-level barrier here, as in the
+// persistent batched kernel (for a workgroup of one wavefront it is the same
+// as the workgroup barrier).
+#define SCHUR_SOLVER_WAVE_SYNC 1
 #include "hip/hip_runtime.h"
 #include "wave_solvers.h"
 #include "window_chase.h"
+#include "batch_solve.h"
 
 #include <atomic>
 
@@ -67,13 +73,13 @@ int g_ball[1024];
 void __syncthreads() { g_all.wait(); }
 void simt_wave_barrier() { g_wave[threadIdx.x >> 6].wait(); }
 
-// only used by one-wavefront kernels (workgroup = one wavefront)
+// exchanges within the calling thread's wavefront
 double __shfl_xor(double x, int o, int) {
   const int l = threadIdx.x;
   g_shfl[l] = x;
-  __syncthreads();
+  simt_wave_barrier();
   const double r = g_shfl[l ^ o];
-  __syncthreads();
+  simt_wave_barrier();
   return r;
 }
 
@@ -86,19 +92,38 @@ int simt_readlane(int v, int src) {
   const int l = threadIdx.x;
   const unsigned k = g_rdl_calls++ & 1u;
   g_rdl[k][l] = v;
-  __syncthreads();
-  return g_rdl[k][src];
+  simt_wave_barrier();
+  return g_rdl[k][(l & ~63) + src];
 }
 
 unsigned long long __ballot(int p) {
-  const int l = threadIdx.x;
+  const int l = threadIdx.x, base = l & ~63;
   g_ball[l] = p != 0;
-  __syncthreads();
+  simt_wave_barrier();
   unsigned long long m = 0;
   for (int i = 0; i < 64; ++i)
-    if (g_ball[i]) m |= 1ull << i;
-  __syncthreads();
+    if (g_ball[base + i]) m |= 1ull << i;
+  simt_wave_barrier();
   return m;
+}
+
+// D = C + A B of the wavefront: A(i, k) in lane i + 16 k, B(k, j) in lane
+// j + 16 k, D(i, j) in lane j + 16 (i % 4), element i / 4
+double g_ma[1024], g_mb[1024];
+simt_d4 simt_mfma_f64_16x16x4(double a, double b, simt_d4 c) {
+  const int t = threadIdx.x, base = t & ~63, l = t & 63;
+  g_ma[t] = a;
+  g_mb[t] = b;
+  simt_wave_barrier();
+  simt_d4 d;
+  for (int e = 0; e < 4; ++e) {
+    const int i = (l >> 4) + 4 * e, j = l & 15;
+    double acc = c[e];
+    for (int k = 0; k < 4; ++k) acc += g_ma[base + i + 16 * k] * g_mb[base + j + 16 * k];
+    d[e] = acc;
+  }
+  simt_wave_barrier();
+  return d;
 }
 
 extern char __start_simt_lds[], __stop_simt_lds[];
@@ -125,12 +150,18 @@ bool rd(FILE* f, T* p, size_t n) { return fread(p, sizeof(T), n, f) == n; }
 
 using namespace schur;
 
+// LDS of the 256-thread window chase and of the persistent driver
+__shared__ double g_cw[LDW * WMAX];
+__shared__ double g_cr[3 * REFL_LDS];
+__shared__ double g_pb_lds[PB_LDS_D];
+__shared__ PShared g_pb_sh;
+
 int main(int argc, char** argv) {
   if (argc != 4) return 2;
   const std::string mode = argv[1];
   FILE* f = fopen(argv[2], "rb");
   if (!f) return 2;
-  if (mode == "chase") {
+  if (mode == "chase" || mode == "chase256") {
     int hdr[5];
     if (!rd(f, hdr, 5)) return 2;
     const int n = hdr[0], ktop = hdr[1], kbot = hdr[2], nst = hdr[3], nwin = hdr[4];
@@ -147,7 +178,10 @@ int main(int argc, char** argv) {
       c.ldh = n; c.ldq = n; c.n = n; c.ktop = ktop; c.kbot = kbot; c.rtop = 0; c.cend = n;
       c.p = wd[6 * w]; c.ws = wd[6 * w + 1]; c.tau0 = wd[6 * w + 2]; c.tau1 = wd[6 * w + 3];
       c.nb = wd[6 * w + 4];
-      run_workgroup(CHASE_THREADS, w, [c] { chase_window(c); });
+      if (mode == "chase")
+        run_workgroup(CHASE_THREADS, w, [c] { chase_window(c); });
+      else
+        run_workgroup(PB_THREADS, w, [c] { chase_window_t<PB_THREADS>(c, g_cw, g_cr); });
     }
     FILE* g = fopen(argv[3], "wb");
     fwrite(H.data(), sizeof(double), H.size(), g);
@@ -249,6 +283,37 @@ int main(int argc, char** argv) {
     fwrite(Zo.data(), sizeof(double), Zo.size(), g);
     fwrite(wr.data(), sizeof(double), m, g);
     fwrite(wi.data(), sizeof(double), m, g);
+    fclose(g);
+    return 0;
+  }
+  if (mode == "pbsolve") {
+    // in : int n, wantq, ns, nb, nw, nibble, nmin, max_sweeps; double H[n*n]
+    // out: int info; double counters[PB_COUNTERS]; double H[n*n], Q[n*n], wr[n], wi[n]
+    int hdr[8];
+    if (!rd(f, hdr, 8)) return 2;
+    const int n = hdr[0];
+    std::vector<double> H((size_t)n * n), Q((size_t)n * n, 0.0), wr(n, NAN), wi(n, NAN);
+    if (!rd(f, H.data(), H.size())) return 2;
+    fclose(f);
+    for (int i = 0; i < n; ++i) Q[i + (size_t)i * n] = 1.0;
+    static std::vector<double> scratch(sizeof(PScratch) / sizeof(double), NAN);
+    std::vector<double> cnt(PB_COUNTERS, NAN);
+    int info = -99;
+    PJob J{};
+    J.H = H.data(); J.Q = hdr[1] ? Q.data() : nullptr; J.wr = wr.data(); J.wi = wi.data();
+    J.ldh = n; J.ldq = n; J.n = n;
+    J.ns = hdr[2]; J.nb = hdr[3]; J.step = 0; J.nw = hdr[4]; J.nibble = hdr[5]; J.nmin = hdr[6];
+    J.exc_period = 6; J.max_sweeps = hdr[7];
+    J.info = &info; J.counters = cnt.data();
+    PScratch* X = (PScratch*)scratch.data();
+    run_workgroup(PB_THREADS, 0, [J, X] { pb_solve(J, g_pb_lds, g_pb_sh, X); });
+    FILE* g = fopen(argv[3], "wb");
+    fwrite(&info, sizeof(int), 1, g);
+    fwrite(cnt.data(), sizeof(double), cnt.size(), g);
+    fwrite(H.data(), sizeof(double), H.size(), g);
+    fwrite(Q.data(), sizeof(double), Q.size(), g);
+    fwrite(wr.data(), sizeof(double), n, g);
+    fwrite(wi.data(), sizeof(double), n, g);
     fclose(g);
     return 0;
   }

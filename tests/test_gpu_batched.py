@@ -2,7 +2,10 @@
 
 Each matrix of the batch must meet the same bar as a solo solve (backward
 error, orthogonality, structure, eigenvalues against the oracle), and its
-eigenvalues must agree with the solo solve of the same matrix.
+eigenvalues must agree with the solo solve of the same matrix.  Matrices of
+order <= 1024 go to the persistent kernel (one workgroup per matrix, the
+whole solve on the device), larger ones to the round engine; the tests run
+both engines (FLAG_BATCH_ROUNDS sends every matrix to the round engine).
 """
 import numpy as np
 import pytest
@@ -20,21 +23,27 @@ def _to_dev(H):
     return torch.from_numpy(np.asfortranarray(H)).to("cuda:0")
 
 
-def test_batched_mixed_sizes(gpu_lib):
+def _flags(lib, engine):
+    return lib.FLAG_BATCH_ROUNDS if engine == "rounds" else 0
+
+
+@pytest.mark.parametrize("engine", ["persistent", "rounds"])
+def test_batched_mixed_sizes(gpu_lib, engine):
     import torch
 
     sizes = [1, 2, 3, 5, 31, 32, 33, 64, 65, 95, 96, 97, 130, 200, 257, 300, 512]
     rng = np.random.default_rng(4)
     sizes += list(rng.integers(32, 400, size=23))
-    print("case batched %d matrices, orders %d..%d" % (len(sizes), min(sizes), max(sizes)),
-          flush=True)
+    print("case batched %s %d matrices, orders %d..%d" % (engine, len(sizes), min(sizes),
+                                                          max(sizes)), flush=True)
     mats = [inputs.hessenberg_normal(int(n), 40000 + i) for i, n in enumerate(sizes)]
-    h = gpu_lib.Handle(0)
+    h = gpu_lib.Handle(0, flags=_flags(gpu_lib, engine))
     Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(H) for H in mats], handle=h)
     torch.cuda.synchronize()
     st = h.stats()
     assert rc == 0 and all(i == 0 for i in infos), infos
     assert st["small_solves"] > 0 and st["windows"] > 0
+    assert st["persist_jobs"] == (len(sizes) if engine == "persistent" else 0)
     for H, S, Q, w in zip(mats, Ss, Qs, ws):
         S, Q, w = S.cpu().numpy(), Q.cpu().numpy(), w.cpu().numpy()
         n = H.shape[0]
@@ -79,12 +88,13 @@ def test_batched_equals_solo(gpu_lib):
     h.close()
 
 
-def test_batched_prescribed_and_no_q(gpu_lib):
+@pytest.mark.parametrize("engine", ["persistent", "rounds"])
+def test_batched_prescribed_and_no_q(gpu_lib, engine):
     import torch
 
-    print("case batched prescribed, no Q", flush=True)
+    print("case batched prescribed, no Q, %s" % engine, flush=True)
     cases = [inputs.prescribed(n, 60 + n) for n in (48, 120, 256, 410)]
-    h = gpu_lib.Handle(0)
+    h = gpu_lib.Handle(0, flags=_flags(gpu_lib, engine))
     Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(H) for H, _ in cases], want_q=False,
                                                     handle=h)
     torch.cuda.synchronize()
@@ -96,14 +106,15 @@ def test_batched_prescribed_and_no_q(gpu_lib):
     h.close()
 
 
-def test_batched_bad_member_reported(gpu_lib):
+@pytest.mark.parametrize("engine", ["persistent", "rounds"])
+def test_batched_bad_member_reported(gpu_lib, engine):
     import torch
 
-    print("case batched with a non-finite member", flush=True)
+    print("case batched with a non-finite member, %s" % engine, flush=True)
     good = inputs.hessenberg_normal(50, 1)
     bad = inputs.hessenberg_normal(60, 2)
     bad[5, 7] = np.inf
-    h = gpu_lib.Handle(0)
+    h = gpu_lib.Handle(0, flags=_flags(gpu_lib, engine))
     Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(good), _to_dev(bad)], handle=h)
     torch.cuda.synchronize()
     assert infos[0] == 0 and infos[1] == -2 and rc == -2
@@ -132,16 +143,17 @@ def test_batched_slow_block_converges(gpu_lib):
 
 
 def test_batched_large_members_use_passes(gpu_lib):
-    """Members from order 256 on (forced; 2048 by default) start with the
-    parallel early-deflation passes on a side handle, then join the rounds;
-    every member meets the bar and its spectrum matches its solo solve."""
+    """Round engine: members from order 256 on (forced; 2048 by default)
+    start with the parallel early-deflation passes on a side handle, then
+    join the rounds; every member meets the bar and its spectrum matches its
+    solo solve."""
     import torch
 
     sizes = [300, 40, 520, 97, 700, 260]
     mats = [inputs.hessenberg_normal(n, 42000 + i) for i, n in enumerate(sizes)]
     mats[5] = inputs.prescribed(260, 42005)[0]
     print("case batched with passes, orders %s" % sizes, flush=True)
-    h = gpu_lib.Handle(0, split_min_n=256)
+    h = gpu_lib.Handle(0, split_min_n=256, flags=gpu_lib.FLAG_BATCH_ROUNDS)
     Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(H) for H in mats], handle=h)
     torch.cuda.synchronize()
     st = h.stats()
@@ -161,14 +173,16 @@ def test_batched_large_members_use_passes(gpu_lib):
         assert np.all(cost[r, c] <= checks.kappa_tolerance(H, wref[c], kappa[c], factor=100.0)), n
 
 
-def test_batched_passes_without_q(gpu_lib):
-    """Members with the passes and no Schur vectors: the same S and spectrum
-    as with them (the Q products never feed back into H)."""
+@pytest.mark.parametrize("engine", ["persistent", "rounds"])
+def test_batched_passes_without_q(gpu_lib, engine):
+    """Members without Schur vectors: the same S and spectrum as with them
+    (the Q products never feed back into H); the round engine runs the
+    passes on its large members here."""
     import torch
 
-    print("case batched with passes, no Q", flush=True)
+    print("case batched without Q, %s" % engine, flush=True)
     mats = [inputs.hessenberg_normal(n, 43000 + i) for i, n in enumerate((300, 520, 64))]
-    h = gpu_lib.Handle(0, split_min_n=256)
+    h = gpu_lib.Handle(0, split_min_n=256, flags=_flags(gpu_lib, engine))
     Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(H) for H in mats], handle=h)
     S0, Q0, w0, infos0, rc0 = gpu_lib.reduce_batched([_to_dev(H) for H in mats], want_q=False,
                                                      handle=h)
@@ -179,3 +193,51 @@ def test_batched_passes_without_q(gpu_lib):
         S, Q, w = S.cpu().numpy(), Q.cpu().numpy(), w.cpu().numpy()
         assert checks.residual(H, Q, S) <= 1e-12 and checks.orthogonality(Q) <= 1e-12
         assert np.array_equal(Sn.cpu().numpy(), S) and np.array_equal(wn.cpu().numpy(), w)
+
+
+def test_persistent_result_independent_of_the_batch(gpu_lib):
+    """A matrix is solved by one workgroup from start to end, so its result
+    does not depend on what else is in the batch: bit for bit the same alone
+    and among others (in another position of the queue)."""
+    import torch
+
+    print("case persistent alone vs in a batch", flush=True)
+    mats = [inputs.hessenberg_normal(n, 44000 + i) for i, n in enumerate((230, 77, 512, 301, 1))]
+    h = gpu_lib.Handle(0)
+    Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(H) for H in mats], handle=h)
+    torch.cuda.synchronize()
+    assert rc == 0
+    for k in (0, 3):
+        S1, Q1, w1, i1, rc1 = gpu_lib.reduce_batched([_to_dev(mats[k])], handle=h)
+        torch.cuda.synchronize()
+        assert rc1 == 0
+        assert torch.equal(S1[0], Ss[k]) and torch.equal(Q1[0], Qs[k]) and torch.equal(w1[0], ws[k])
+    h.close()
+
+
+def test_persistent_and_rounds_split_at_order_1024(gpu_lib):
+    """Orders 1024 and 1025 side by side: the first goes to the persistent
+    kernel, the second to the round engine; both meet the bar, and the
+    persistent result has the spectrum of the round engine's."""
+    import torch
+
+    print("case persistent 1024 + rounds 1025", flush=True)
+    mats = [inputs.prescribed(1024, 45000)[0], inputs.hessenberg_normal(1025, 45001)]
+    h = gpu_lib.Handle(0)
+    Ss, Qs, ws, infos, rc = gpu_lib.reduce_batched([_to_dev(H) for H in mats], handle=h)
+    torch.cuda.synchronize()
+    st = h.stats()
+    assert rc == 0 and st["persist_jobs"] == 1
+    for H, S, Q, w in zip(mats, Ss, Qs, ws):
+        S, Q, w = S.cpu().numpy(), Q.cpu().numpy(), w.cpu().numpy()
+        assert checks.structure_errors(S, w.real, w.imag) == []
+        assert checks.residual(H, Q, S) <= 1e-12 and checks.orthogonality(Q) <= 1e-12
+    hr = gpu_lib.Handle(0, flags=gpu_lib.FLAG_BATCH_ROUNDS)
+    Sr, Qr, wr_, ir, rcr = gpu_lib.reduce_batched([_to_dev(mats[0])], handle=hr)
+    torch.cuda.synchronize()
+    assert rcr == 0 and hr.stats()["persist_jobs"] == 0
+    exact = inputs.prescribed(1024, 45000)[1]
+    for w in (ws[0].cpu().numpy(), wr_[0].cpu().numpy()):
+        assert np.all(checks.match_eigs(w, exact) <= checks.eig_rel_tol(exact, mats[0], 1e-9))
+    hr.close()
+    h.close()

@@ -2,7 +2,11 @@
 
 Requests of different orders and kinds are submitted while others are on
 the GPU; each result must meet the accuracy bar and agree with the same
-matrix solved alone (eigenvalues to rounding; backward error and
+matrix solved alone.  Requests of order <= 1024 are solved by persistent
+launches (one workgroup per matrix, the whole solve on the device), so
+their results are the same bit for bit in the mix, alone and through
+schur_reduce_batched; larger ones advance in the round engine's shared
+launches and agree to rounding (eigenvalues; backward error and
 orthogonality to the stated tolerance).  A tiny HBM budget forces requests
 to wait for admission; results stay correct.
 """
@@ -68,8 +72,20 @@ def test_served_mix_equals_alone(gpu_lib):
     for H, (S, Q, w, info, lat), (S1, Q1, w1, info1, lat1) in zip(mats, mixed, alone):
         _check(H, S, Q, w, info)
         _check(H, S1, Q1, w1, info1)
-        assert checks.match_eigs(w, w1).max() <= 1e-10 * np.linalg.norm(H)
+        assert np.array_equal(S, S1) and np.array_equal(Q, Q1) and np.array_equal(w, w1)
         assert lat > 0.0
+    # and through the batched entry point (same options, same kernel)
+    import torch
+
+    h = gpu_lib.Handle(0)
+    Sb, Qb, wb, ib, rc = gpu_lib.reduce_batched(
+        [torch.from_numpy(np.asfortranarray(H)).to("cuda:0") for H in mats], handle=h)
+    torch.cuda.synchronize()
+    h.close()
+    assert rc == 0
+    for (S, Q, w, info, lat), S2, Q2, w2 in zip(mixed, Sb, Qb, wb):
+        assert np.array_equal(S, S2.cpu().numpy()) and np.array_equal(Q, Q2.cpu().numpy())
+        assert np.array_equal(w, w2.cpu().numpy())
 
 
 def test_budget_forces_queueing(gpu_lib):
@@ -92,12 +108,13 @@ def test_budget_forces_queueing(gpu_lib):
 
 
 def test_served_large_requests_equal_alone(gpu_lib):
-    """Larger requests, random and prescribed, among small ones (with the
-    parallel-pass threshold lowered: the server still runs no passes, so the
-    option must not change its results): every result meets the bar and
-    equals the one alone."""
-    sizes = [(700, "normal"), (90, "normal"), (600, "prescribed"), (150, "prescribed"),
-             (520, "normal")]
+    """Requests above order 1024 (the round engine), random and prescribed,
+    among small ones (persistent launches), with the parallel-pass
+    threshold lowered (the server still runs no passes, so the option must
+    not change its results): every result meets the bar and equals the one
+    alone, the small ones bit for bit."""
+    sizes = [(700, "normal"), (90, "normal"), (1100, "prescribed"), (150, "prescribed"),
+             (1300, "normal"), (520, "normal")]
     mats = [inputs.hessenberg_normal(n, 51000 + i) if kind == "normal"
             else inputs.prescribed(n, 51000 + i)[0] for i, (n, kind) in enumerate(sizes)]
     print("case served larger requests", flush=True)
@@ -114,3 +131,5 @@ def test_served_large_requests_equal_alone(gpu_lib):
         _check(H, S, Q, w, info)
         _check(H, S1, Q1, w1, info1)
         assert checks.match_eigs(w, w1).max() <= 1e-10 * np.linalg.norm(H)
+        if H.shape[0] <= 1024:
+            assert np.array_equal(S, S1) and np.array_equal(w, w1)

@@ -5,9 +5,14 @@ above and below it; paper Sec. 3.2, AED) against the oracle's spectrum.
 The passes run by default from n = 2048; here they are forced on smaller
 matrices so that the oracle and LAPACK condition numbers stay affordable.
 Checked as for every Schur form: backward error and orthogonality <= 1e-12,
-exact structure, eigenvalues (condition weighted on random matrices, 1e-9
-relative on a prescribed normal spectrum), and the same result as with the
-passes off on what is unique (the spectrum)."""
+exact structure, and the same result as with the passes off on what is
+unique (the spectrum).  Eigenvalues: on the random N(0,1) matrices the
+condition numbers are so large (medians far above 1e19) that the
+condition-weighted bound rarely binds, so that check is informational
+there; the decisive eigenvalue check is the localised, well-conditioned
+tridiagonal input (condition numbers below 100, exact eigenvalues from the
+symmetric matrix it is similar to), which the passes really split, and the
+prescribed normal spectrum, which they do not."""
 import numpy as np
 import pytest
 
@@ -149,3 +154,46 @@ def test_split_passes_padded_leading_dimensions(gpu_lib):
     S1, Q1, w1, info1, st1 = _run(gpu_lib, H, split_min_n=64)
     assert info1 == 0
     assert np.array_equal(S1, S) and np.array_equal(Q1, Q) and np.array_equal(w1, w)
+
+
+@pytest.mark.parametrize("n,seed,forced", [(1500, 71, True), (2400, 72, False)])
+def test_split_passes_localised_well_conditioned(gpu_lib, n, seed, forced):
+    """A tridiagonal D T D^-1 with strongly localised eigenvectors: windows
+    inside the matrix split their blocks.  Its eigenvalues
+    are exactly those of the symmetric T (similarity by a diagonal), and
+    first-order perturbation theory bounds the error of each computed one by
+    kappa_i times the backward error, itself held to 1e-12 ||H||_F."""
+    import scipy.linalg as sla
+
+    print("case split passes localised n=%d seed=%d forced=%s" % (n, seed, forced), flush=True)
+    H = inputs.anderson(n, seed)
+    kw = dict(split_min_n=64) if forced else {}
+    S, Q, w, info, st = _run(gpu_lib, H, **kw)
+    _check_schur(H, S, Q, w, info)
+    print("passes %d windows %d accepted %d converged %d" % (
+        st["split_passes"], st["split_windows"], st["split_accepted"], st["split_converged"]),
+        flush=True)
+    # interior windows split their blocks (free rows inside the windows)
+    assert st["split_passes"] > 0 and st["split_accepted"] >= 4
+    d = np.diag(H).copy()
+    off = np.sqrt(np.diag(H, -1) * np.diag(H, 1))   # T's off-diagonal (exactly 1 here)
+    exact = sla.eigh_tridiagonal(d, off, eigvals_only=True)
+    wref, kappa = checks.eig_condition(H)
+    assert kappa.max() < 100.0      # the bound below is far from vacuous
+    # kappa of each computed eigenvalue: that of its LAPACK match
+    err_ref = checks.match_eigs(wref, exact)
+    assert err_ref.max() < 1e-12 * np.linalg.norm(H)
+    from scipy.optimize import linear_sum_assignment
+
+    r, c = linear_sum_assignment(np.abs(w[:, None] - wref[None, :]))
+    k_of_w = np.empty(n)
+    k_of_w[r] = kappa[c]
+    err = np.empty(n)
+    r2, c2 = linear_sum_assignment(np.abs(w[:, None] - exact[None, :]))
+    err[r2] = np.abs(w[r2] - exact[c2])
+    bound = 2.0 * k_of_w * 1e-12 * np.linalg.norm(H)
+    assert (err <= bound).all(), float((err / bound).max())
+    # the spectrum does not depend on the route: passes off
+    S0, Q0, w0, info0, st0 = _run(gpu_lib, H, split_window=-1)
+    _check_schur(H, S0, Q0, w0, info0)
+    assert checks.match_eigs(w, w0).max() <= bound.max()

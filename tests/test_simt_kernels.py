@@ -11,6 +11,9 @@ missing barrier shows up here, on the CPU.
   step, with the panel products done in numpy) must reproduce the oracle's
   sequential Francis double-shift steps with the same shifts (paper Sec. 3.2:
   the multishift sweep is that sequence, applied window by window);
+* the window chase with 256 threads equals the 1024-thread one bit for bit;
+* the whole-matrix driver of the persistent batched kernel gives a real
+  Schur form with the oracle's spectrum;
 * early deflation (paper Sec. 3.2): the returned V is orthogonal and
   V^T W V is the returned window; the undeflated part is Hessenberg, the
   deflated part quasi-triangular with no coupling back; the spike is
@@ -27,6 +30,7 @@ import pytest
 
 import oracle
 from paper_1905_04975_amd import inputs, schur
+from tests import checks
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -372,3 +376,91 @@ def test_split_window(driver, tmp_path, case):
     cost = np.abs(ev0[:, None] - ev1[None, :])
     r, c = linear_sum_assignment(cost)
     assert cost[r, c].max() <= 1e-8 * np.linalg.norm(W)
+
+
+@pytest.mark.parametrize("n,ktop,kbot,npair,nb,seed", [
+    (160, 0, 159, 1, 1, 3), (220, 0, 219, 6, 3, 4), (300, 10, 280, 8, 8, 5), (150, 0, 149, 5, 5, 8)])
+def test_chase_256_threads_equals_1024(driver, tmp_path, n, ktop, kbot, npair, nb, seed):
+    """The window chase with 256 threads (the persistent batched kernel's
+    layout: 32 lanes per bulge, two lanes per row of U) does exactly the
+    arithmetic of the 1024-thread chase: the same H and U bit for bit."""
+    H0 = inputs.hessenberg_normal(n, seed)
+    rng = np.random.default_rng(seed)
+    st = []
+    for _ in range(npair):
+        a, b = rng.uniform(-1, 1, 2)
+        st += [2 * a, a * a + b * b]
+    plan = schur.plan_sweep(ktop, kbot, npair, nb, 0)
+    t0 = min(r[0] for r in plan)
+    wins = [(p, ws, a0, a1, b, g) for (tt, g, p, ws, a0, a1, b) in plan if tt == t0]
+    payload = [np.array([n, ktop, kbot, len(st), len(wins)], dtype=np.int32),
+               np.asfortranarray(H0).ravel(order="F"), np.asarray(st, dtype=np.float64),
+               np.array([v for w in wins for v in w], dtype=np.int32)]
+    a = _call(driver, "chase", payload, tmp_path)
+    b = _call(driver, "chase256", payload, tmp_path)
+    assert a == b
+
+
+def _pbsolve(driver, tmp_path, H, wantq=True, ns=16, nb=8, nw=24, nibble=14, nmin=96,
+             max_sweeps=1000):
+    n = H.shape[0]
+    raw = _call(driver, "pbsolve",
+                [np.array([n, int(wantq), ns, nb, nw, nibble, nmin, max_sweeps], dtype=np.int32),
+                 np.asfortranarray(H).ravel(order="F")], tmp_path)
+    info = int(np.frombuffer(raw[:4], dtype=np.int32)[0])
+    x = np.frombuffer(raw[4:], dtype=np.float64)
+    cnt, x = x[:11], x[11:]
+    S = x[:n * n].reshape(n, n, order="F")
+    Q = x[n * n:2 * n * n].reshape(n, n, order="F")
+    w = x[2 * n * n:2 * n * n + n] + 1j * x[2 * n * n + n:]
+    return info, cnt, S, Q, w
+
+
+@pytest.mark.parametrize("n,ns,nb,nw,kind", [
+    (60, 16, 8, 24, "normal"),      # whole matrix in the small solver
+    (97, 16, 4, 24, "normal"),      # one sweep level above it
+    (150, 16, 8, 24, "normal"),
+    (180, 32, 8, 32, "prescribed"),  # two bulge groups per sweep
+    (130, 12, 6, 0, "normal"),      # no early deflation: trailing-block shifts
+])
+def test_persistent_driver(driver, tmp_path, n, ns, nb, nw, kind):
+    """The device-side driver of the persistent batched kernel (one
+    workgroup, the whole solve: deflation scans, small-block solver, early
+    deflation, shifts, bulge groups chased window by window, MFMA panel
+    products) run on the CPU: a real Schur form with Q (backward error and
+    orthogonality, standardised blocks, eigenvalues of the blocks), the
+    oracle's spectrum (exact spectrum on the prescribed input), and the same
+    S without Q."""
+    if kind == "normal":
+        H = inputs.hessenberg_normal(n, 300 + n)
+        exact = None
+    else:
+        H, exact = inputs.prescribed(n, 300 + n)
+    info, cnt, S, Q, w = _pbsolve(driver, tmp_path, H, True, ns, nb, nw)
+    assert info == 0
+    assert not np.isnan(S).any() and not np.isnan(Q).any()
+    assert checks.structure_errors(S, w.real, w.imag) == []
+    assert checks.residual(H, Q, S) <= 1e-13
+    assert checks.orthogonality(Q) <= 1e-13
+    if n > 96:
+        assert cnt[0] > 0 and cnt[1] > 0   # sweeps, windows
+    _, _, wr, wi, oinfo, _ = oracle.schur(H)
+    assert oinfo == 0
+    if exact is not None:
+        assert np.all(checks.match_eigs(w, exact) <= checks.eig_rel_tol(exact, H, 1e-9))
+    else:
+        wref, kappa = checks.eig_condition(H)
+        from scipy.optimize import linear_sum_assignment
+        cost = np.abs((wr + 1j * wi)[:, None] - w[None, :])
+        r, c = linear_sum_assignment(cost)
+        ko = kappa[np.argmin(np.abs((wr + 1j * wi)[r][:, None] - wref[None, :]), axis=1)]
+        assert np.all(cost[r, c] <= checks.kappa_tolerance(H, wref, ko, factor=200.0))
+    info0, _, S0, _, w0 = _pbsolve(driver, tmp_path, H, False, ns, nb, nw)
+    assert info0 == 0 and np.array_equal(S0, S) and np.array_equal(w0, w)
+
+
+def test_persistent_driver_reports_non_finite_input(driver, tmp_path):
+    H = inputs.hessenberg_normal(40, 5)
+    H[3, 10] = np.nan
+    info, cnt, S, Q, w = _pbsolve(driver, tmp_path, H)
+    assert info == -2
