@@ -136,6 +136,7 @@ def bench_batch(args):
     from paper_1905_04975_amd import inputs, schur
 
     dev = torch.device("cuda:0")
+    torch.cuda.set_stream(torch.cuda.Stream(dev))   # as in the main bench
     sizes = inputs.batch_sizes(args.count, 32, 512, inputs.SEED_BATCH_SIZES)
     mats = [inputs.hessenberg_normal(int(n), inputs.SEED_BATCH_BASE + i) for i, n in enumerate(sizes)]
     H0 = [torch.from_numpy(H).to(dev) for H in mats]
@@ -264,7 +265,8 @@ def bench_serve(args):
             pool.append(inputs.hessenberg_normal(n, inputs.SEED_SERVE_BASE + i))
         else:
             pool.append(inputs.prescribed(n, inputs.SEED_SERVE_BASE + i)[0])
-    srv = schur.Server(0, budget_bytes=int(args.budget_gb * (1 << 30)))
+    budget = int(args.budget_gb * (1 << 30))
+    srv = None
 
     def drain(pending, done, t_end=None):
         for tk in list(pending):
@@ -273,8 +275,8 @@ def bench_serve(args):
                 done[tk] = (pending[tk][1], r[3], r[4])
                 del pending[tk]
 
-    # saturation: submit a block of requests at once
-    if args.rate <= 0:
+    def saturation():
+        # a block of 24 requests submitted at once: completions per second
         pending, done = {}, {}
         t0 = time.perf_counter()
         for i in range(24):
@@ -283,7 +285,18 @@ def bench_serve(args):
         while pending:
             drain(pending, done)
             time.sleep(0.001)
-        mu = 24 / (time.perf_counter() - t0)
+        return 24 / (time.perf_counter() - t0)
+
+    # the same block through a server that sends every request to the round
+    # engine (no persistent launches), for comparison
+    srv = schur.Server(0, budget_bytes=budget, flags=schur.FLAG_BATCH_ROUNDS)
+    saturation()
+    mu_rounds = saturation()
+    srv.close()
+    srv = schur.Server(0, budget_bytes=budget)
+    if args.rate <= 0:
+        saturation()
+        mu = saturation()
         rate = 0.7 * mu
     else:
         mu, rate = None, args.rate
@@ -305,6 +318,13 @@ def bench_serve(args):
     srv.close()
     warm = args.requests // 10
     lat = np.array(sorted(v[2] for v in done.values() if v[0] >= warm))
+    by_order = {}
+    for name, keep in (("n<=1024", lambda m: m <= 1024), ("n>1024", lambda m: m > 1024)):
+        x = np.array([v[2] for v in done.values()
+                      if v[0] >= warm and keep(pool[v[0] % len(pool)].shape[0])])
+        if x.size:
+            by_order[name] = {"requests": int(x.size), "p50": float(np.percentile(x, 50)),
+                              "p99": float(np.percentile(x, 99))}
     infos = [v[1] for v in done.values()]
     # FIFO plain launches on the same arrivals (sample): one request at a time
     import torch
@@ -332,10 +352,11 @@ def bench_serve(args):
         "ms_per_step": 1e3 * wall, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "schur_serving_mix", "requests": args.requests,
-                   "rate_per_s": rate, "saturation_per_s": mu, "budget_gb": args.budget_gb,
+                   "rate_per_s": rate, "saturation_per_s": mu,
+                   "saturation_round_engine_only_per_s": mu_rounds, "budget_gb": args.budget_gb,
                    "mix": "half random N(0,1), half prescribed spectrum"},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                      "mean": float(lat.mean())},
+                      "mean": float(lat.mean()), "by_order": by_order},
         "fifo_plain_launches": {"sample": k,
                                 "p50": float(np.percentile(lat_plain, 50)),
                                 "p99": float(np.percentile(lat_plain, 99)),
@@ -363,33 +384,42 @@ def table_row(n):
 def sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream):
     """Forced multishift sweeps on the same matrix: `--sweep-ns` shifts per
     sweep (the trailing block of that order gives them), a sweep after every
-    early-deflation window, stopped after `--sweep-count` sweeps.  Reports
-    the sweep kernels (window chase, row-panel and column-panel/Q products)
-    with HIP-event times; the partial reduction is still an orthogonal
+    early-deflation window, stopped after `--sweep-count` sweeps.  Run twice:
+    as the library runs them (the Q products on a second stream, overlapping
+    the window chase; `seconds`), and with every kernel on the solve stream
+    (`SCHUR_FLAG_ONE_STREAM`), where each kernel's HIP-event duration is its
+    own, for the rates of the sweep kernels (window chase, row-panel and
+    column-panel/Q products).  The partial reduction is still an orthogonal
     similarity, which the probe checks."""
     import torch
     from paper_1905_04975_amd import schur
 
     n = args.n
     dev = H0.device
-    hs = schur.Handle(0, ns=args.sweep_ns, nb=args.nb, aed_nibble=-1, split_window=-1,
-                      panel_tile=args.panel_tile,
-                      max_sweeps=args.sweep_count, flags=schur.FLAG_TIME_KERNELS)
-    H.copy_(H0)
-    Q.copy_(eye)
-    torch.cuda.synchronize(dev)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    info = hs.reduce_async(stream.cuda_stream, n, H.data_ptr(), n, Q.data_ptr(), n,
-                           wr.data_ptr(), wi.data_ptr())
-    e1.record(stream)
-    torch.cuda.synchronize(dev)
-    st = hs.stats()
-    hs.close()
-    if info < 0:
-        raise RuntimeError("forced-sweep run failed: info=%d" % info)
-    nsw = max(1, st["sweeps"])
+
+    def run(flags):
+        hs = schur.Handle(0, ns=args.sweep_ns, nb=args.nb, aed_nibble=-1, split_window=-1,
+                          panel_tile=args.panel_tile, max_sweeps=args.sweep_count,
+                          flags=schur.FLAG_TIME_KERNELS | flags)
+        H.copy_(H0)
+        Q.copy_(eye)
+        torch.cuda.synchronize(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        info = hs.reduce_async(stream.cuda_stream, n, H.data_ptr(), n, Q.data_ptr(), n,
+                               wr.data_ptr(), wi.data_ptr())
+        e1.record(stream)
+        torch.cuda.synchronize(dev)
+        st = hs.stats()
+        hs.close()
+        if info < 0:
+            raise RuntimeError("forced-sweep run failed: info=%d" % info)
+        return info, e0.elapsed_time(e1) / 1e3, st
+
+    info1, sec1, st1 = run(schur.FLAG_ONE_STREAM)
+    info, sec, st = run(0)
+    nsw = max(1, st1["sweeps"])
 
     def gl(name, ms, launches, flops):
         avg = ms / max(1, launches)
@@ -398,7 +428,7 @@ def sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream):
                 "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS, "avg_launch_ms": avg,
                 "launches": launches, "flops_per_launch": flops / max(1, launches)}
 
-    gemm_ms = st["row_ms"] + st["colq_ms"]
+    gemm_ms = st1["row_ms"] + st1["colq_ms"]
     res = None
     if not args.no_check:
         x = torch.randn(n, 2, dtype=torch.float64, device=dev,
@@ -409,20 +439,21 @@ def sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream):
     out = {
         "shifts_per_sweep": args.sweep_ns, "sweeps": st["sweeps"],
         "shifts_applied": st["shifts_applied"], "stop_info": info,
-        "seconds": e0.elapsed_time(e1) / 1e3,
-        "ms_per_sweep": {"chase": st["chase_ms"] / nsw, "row_panel": st["row_ms"] / nsw,
-                         "colq_panel": st["colq_ms"] / nsw, "shifts": st["shift_ms"] / nsw,
-                         "aed": st["aed_ms"] / nsw},
-        "gemm_tflops": st["gemm_flops"] / max(gemm_ms * 1e-3, 1e-30) / 1e12,
-        "gemm_frac_of_fp64_mfma_peak": st["gemm_flops"] / max(gemm_ms * 1e-3, 1e-30) / 1e12
+        "seconds": sec,
+        "seconds_one_stream": sec1,
+        "ms_per_sweep_one_stream": {"chase": st1["chase_ms"] / nsw, "row_panel": st1["row_ms"] / nsw,
+                                    "colq_panel": st1["colq_ms"] / nsw,
+                                    "shifts": st1["shift_ms"] / nsw, "aed": st1["aed_ms"] / nsw},
+        "gemm_tflops": st1["gemm_flops"] / max(gemm_ms * 1e-3, 1e-30) / 1e12,
+        "gemm_frac_of_fp64_mfma_peak": st1["gemm_flops"] / max(gemm_ms * 1e-3, 1e-30) / 1e12
         / FP64_MFMA_PEAK_TFLOPS,
-        "k_panel_colq": gl("k_panel_colq", st["colq_ms"], st["colq_launches"], st["colq_flops"]),
-        "k_panel_row": gl("k_panel_row", st["row_ms"], st["row_launches"], st["row_flops"]),
-        "k_chase": family_lines(st, "sweep").get("k_chase"),
+        "k_panel_colq": gl("k_panel_colq", st1["colq_ms"], st1["colq_launches"], st1["colq_flops"]),
+        "k_panel_row": gl("k_panel_row", st1["row_ms"], st1["row_launches"], st1["row_flops"]),
+        "k_chase": family_lines(st1, "sweep").get("k_chase"),
         "residual_probe": res,
     }
-    print("sweep: %d sweeps of %d shifts, %.3f s, GEMM %.2f TFLOP/s" %
-          (st["sweeps"], args.sweep_ns, out["seconds"], out["gemm_tflops"]), file=sys.stderr,
+    print("sweep: %d sweeps of %d shifts, %.3f s (%.3f s on one stream), GEMM %.2f TFLOP/s" %
+          (st["sweeps"], args.sweep_ns, sec, sec1, out["gemm_tflops"]), file=sys.stderr,
           flush=True)
     return out
 
@@ -748,6 +779,10 @@ def main():
     from paper_1905_04975_amd import inputs, schur
 
     dev = torch.device("cuda:0")
+    # every step on one created stream (default priority): the library's
+    # kernels, their HIP events and torch's own work are in one stream order
+    # without the null stream's implicit synchronisation
+    torch.cuda.set_stream(torch.cuda.Stream(dev))
     n = args.n
     t0 = time.time()
     paper_main = args.workload == "paper_like"

@@ -97,8 +97,12 @@ typedef struct schur_opts {
 } schur_opts;
 
 #define SCHUR_FLAG_TIME_KERNELS 1   /* time each kernel family with HIP events */
-#define SCHUR_FLAG_BATCH_ROUNDS 2   /* schur_reduce_batched: every matrix through the  */
-                                    /* round engine (no persistent kernel)             */
+#define SCHUR_FLAG_BATCH_ROUNDS 2   /* schur_reduce_batched and the server: every      */
+                                    /* matrix through the round engine (no persistent  */
+                                    /* kernel)                                         */
+#define SCHUR_FLAG_ONE_STREAM 4     /* single solves: the Q products on the solve      */
+                                    /* stream too (no overlap with the window chase),  */
+                                    /* so each kernel's timed duration is its own      */
 
 /* Counters of the last solve on a handle. */
 typedef struct schur_stats {
@@ -435,8 +439,13 @@ double schur_split_weight(int split, int nf, int top, int below);
  * the batched engine (one sweep per resident matrix per round) the thread
  * admits queued requests while the device bytes of the resident ones (H, Q,
  * wr, wi) stay within `hbm_budget_bytes`, so requests that arrive while
- * others are on the GPU join the next round.  Finished results are copied
- * to pinned host memory; latency = submit to results on the host.
+ * others are on the GPU join the next round.  Requests of order <= 256 (all
+ * of them go to the round engine with SCHUR_FLAG_BATCH_ROUNDS in the
+ * options) are instead solved by a persistent launch per group admitted
+ * together, on one of two streams of the server: each by one workgroup from
+ * start to end, so its result is the one it gets alone, bit for bit.
+ * Finished results are copied to pinned host memory (blocks reused from
+ * request to request); latency = submit to results on the host.
  * ------------------------------------------------------------------------ */
 typedef struct schur_server_s* schur_server_t;
 

@@ -17,11 +17,12 @@ n = 1024 a random N(0,1) Hessenberg matrix; from n = 2048 on the Hessenberg
 form of a dense U(-1,1) matrix (drawn from its distribution), because on
 random Hessenberg matrices of these orders the parallel early-deflation
 passes do the work and no sweep runs.  With ``--batched`` the buckets up to
-512 are timed instead as batches (``schur_reduce_batched``) of matrices with
-orders spread around the bucket, by solves per second -- the regime where
-such orders occur.  The panel products' tile (64 x 64 outputs per MFMA tile,
-tiles per workgroup picked per launch by a cost model) is not a tuning
-parameter.
+512 are timed instead as batches (``schur_reduce_batched``, i.e. the
+persistent kernel, which takes at most 8 bulges per window chain) of
+matrices with orders spread around the bucket, by solves per second -- the
+regime where such orders occur.  For single solves from n = 512 on, the
+panel products' tiles per workgroup (64 columns or rows each; 0 keeps the
+per-launch cost model) are tried last, with the best sweep parameters.
 
     python -m paper_1905_04975_amd.autotune [--quick] [--batched] [--out path]
 """
@@ -198,6 +199,8 @@ def main():
             mats = [inputs.hessenberg_normal(int(m), 9100 + n + k) for k, m in enumerate(orders)]
             recipes[str(n)] = "batch of 200 hessenberg_normal, orders U[n/1.41, 1.41 n]"
             for c in candidates(n, args.quick):
+                if c["nb"] > 8:   # the persistent kernel caps the bulges per chain at 8
+                    continue
                 ok, rate = time_batched(schur, torch, mats, c, 2)
                 t = 1.0 / rate if rate > 0 else math.inf
                 results.append((c, ok, t))

@@ -575,8 +575,11 @@ struct Solver {
   void launch_q(const SweepArgs& aq, int tq, int buf) {
     if (one_stream) {
       if (tq > 0) {
+        hipEvent_t e0 = nullptr;
+        if (P.time) h->timer.begin(s, e0);
         launch_panel_colq(aq, tq, s);
         HCHECK(hipGetLastError());
+        if (P.time) h->timer.end(s, e0, &h->stats.colq_ms);
         h->stats.colq_launches += 1;
         h->stats.gemm_launches += 1;
         h->stats.launches += 1;
@@ -1182,6 +1185,7 @@ int solve(schur_handle_s* h, hipStream_t s, int n, double* H, int ldh, double* Q
     if (rc) return rc;
     std::memset(&h->stats, 0, sizeof(h->stats));
     Solver sv{h, s, resolve(h->opts, n), n, H, ldh, Q, ldq, wr, wi};
+    sv.one_stream = (h->opts.flags & SCHUR_FLAG_ONE_STREAM) != 0;
     return sv.run();
   } catch (const HipErr& e) {
     (void)hipGetLastError();
@@ -2468,6 +2472,8 @@ struct Request {
   int last_small_top = -1;
   double t_submit = 0, t_done = 0;
   hipEvent_t ev = nullptr;
+  void* hblock = nullptr;   // the pinned block holding hH, hQ, hw, hctrl
+  size_t hcap = 0;
   enum State { QUEUED, RESIDENT, DRAINING, DONE } state = QUEUED;
 };
 
@@ -2489,20 +2495,33 @@ struct schur_server_s {
   int slots = 1024;
   uint64_t next_ticket = 1;
   schur_server_stats st{};
-  // requests of order <= kPersistMaxN: one persistent launch per group of
+  // requests of order <= kServePersistMaxN: one persistent launch per group of
   // requests admitted together, on a small pool of streams, so that groups
   // admitted while others run overlap with them on the device
-  static constexpr int kLanes = 4;
+  // (groups on one stream run in stream order; each group's pinned staging
+  // comes from the pool below and its completion event from a free list, so
+  // no host allocation or free, which can wait for the device, happens per
+  // group).  Two streams: with the round engine's stream and its second
+  // stream they need four hardware queues, the runtime's default, so a long
+  // persistent launch never sits in front of the round engine's kernels.
+  static constexpr int kLanes = 2;
   hipStream_t lane[kLanes] = {};
   int lane_next = 0;
+  std::vector<hipEvent_t> free_events;
   struct Group {
     std::vector<Request*> reqs;
-    hipStream_t s = nullptr;
-    char* host = nullptr;   // pinned: jobs and queue order, then the info codes
+    void* host = nullptr;   // pinned (pool): jobs and queue order, then the info codes
+    size_t host_cap = 0;
     size_t off_info = 0;
     hipEvent_t ev = nullptr;
   };
   std::vector<Group> groups;
+  // pinned host blocks of finished requests, reused by later ones of the
+  // same size class (a pinned allocation or free can wait for the device)
+  std::mutex pool_mu;
+  std::map<size_t, std::vector<void*>> pool;
+  size_t pooled = 0;
+  static constexpr size_t kPoolMax = (size_t)8 << 30;
 };
 
 namespace {
@@ -2512,25 +2531,69 @@ size_t request_bytes(int n, bool want_q) {
   return sizeof(double) * (nn + (want_q ? nn : 0) + 2 * (size_t)n) + sizeof(Ctrl);
 }
 
-void free_request_host(Request* r) {
-  if (r->hH) (void)hipHostFree(r->hH);
-  if (r->hQ) (void)hipHostFree(r->hQ);
-  if (r->hw) (void)hipHostFree(r->hw);
-  if (r->hctrl) (void)hipHostFree(r->hctrl);
+// size class of a pinned block: the next power of two from 4 KiB
+size_t pin_class(size_t bytes) {
+  size_t c = 4096;
+  while (c < bytes) c <<= 1;
+  return c;
+}
+
+void* pin_get(schur_server_s* S, size_t bytes, size_t* cap) {
+  *cap = pin_class(bytes);
+  {
+    std::lock_guard<std::mutex> lk(S->pool_mu);
+    auto it = S->pool.find(*cap);
+    if (it != S->pool.end() && !it->second.empty()) {
+      void* p = it->second.back();
+      it->second.pop_back();
+      S->pooled -= *cap;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, *cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+  return p;
+}
+
+void pin_put(schur_server_s* S, void* p, size_t cap) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(S->pool_mu);
+    if (S->pooled + cap <= schur_server_s::kPoolMax) {
+      S->pool[cap].push_back(p);
+      S->pooled += cap;
+      return;
+    }
+  }
+  (void)hipHostFree(p);
+}
+
+void free_request_host(schur_server_s* S, Request* r) {
+  pin_put(S, r->hblock, r->hcap);
   if (r->ev) (void)hipEventDestroy(r->ev);
+  r->hblock = nullptr;
   r->hH = r->hQ = r->hw = nullptr;
   r->hctrl = nullptr;
   r->ev = nullptr;
 }
 
-// One persistent launch for the requests of order <= kPersistMaxN admitted
+// Served requests up to this order go to persistent launches, larger ones to
+// the round engine.  Lower than kPersistMaxN: a request alone on one CU
+// finishes later than in the round engine once its order is in the hundreds,
+// and a served mix has few such requests at once to fill the CUs (measured
+// on the serving bench, orders log-uniform in [64, 4096]: saturation 12.9
+// solves/s with 256, 10.2 with 1024, 12.8 with every request in the round
+// engine).
+constexpr int kServePersistMaxN = 256;
+
+// One persistent launch for the requests of order <= kServePersistMaxN admitted
 // together: their device buffers, input copies, the launch, result copies
 // to pinned memory and the frees, all in order on one stream of the pool;
 // an event marks the group's completion.
 void launch_group(schur_server_s* S, const std::vector<Request*>& reqs) {
   schur_server_s::Group G;
   G.reqs = reqs;
-  G.s = S->lane[S->lane_next++ % schur_server_s::kLanes];
+  hipStream_t gs = S->lane[S->lane_next++ % schur_server_s::kLanes];
   const int cnt = (int)reqs.size();
   const int grid = std::min(cnt, device_cus(S->h->device));
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -2539,46 +2602,54 @@ void launch_group(schur_server_s* S, const std::vector<Request*>& reqs) {
   const size_t off_scr = up(G.off_info + sizeof(int) * cnt);
   const size_t off_next = off_scr + sizeof(PScratch) * grid;
   char* dev = nullptr;
-  HCHECK(hipMallocAsync((void**)&dev, off_next + 256, G.s));
-  HCHECK(hipHostMalloc((void**)&G.host, off_scr, hipHostMallocDefault));
-  PJob* jh = (PJob*)G.host;
-  int* oh = (int*)(G.host + off_ord);
+  HCHECK(hipMallocAsync((void**)&dev, off_next + 256, gs));
+  char* host = (char*)pin_get(S, off_scr, &G.host_cap);
+  if (!host) throw HipErr{hipErrorOutOfMemory};
+  G.host = host;
+  PJob* jh = (PJob*)host;
+  int* oh = (int*)(host + off_ord);
   for (int j = 0; j < cnt; ++j) {
     Request* r = reqs[j];
     const int n = r->n;
     const size_t nn = (size_t)n * n;
-    HCHECK(hipMallocAsync((void**)&r->dH, sizeof(double) * std::max<size_t>(1, nn), G.s));
+    HCHECK(hipMallocAsync((void**)&r->dH, sizeof(double) * std::max<size_t>(1, nn), gs));
     if (r->want_q)
-      HCHECK(hipMallocAsync((void**)&r->dQ, sizeof(double) * std::max<size_t>(1, nn), G.s));
-    HCHECK(hipMallocAsync((void**)&r->dw, sizeof(double) * 2 * std::max(1, n), G.s));
-    HCHECK(hipMemcpyAsync(r->dH, r->hH, sizeof(double) * nn, hipMemcpyHostToDevice, G.s));
-    if (r->want_q) launch_set_identity(r->dQ, n, n, G.s);
+      HCHECK(hipMallocAsync((void**)&r->dQ, sizeof(double) * std::max<size_t>(1, nn), gs));
+    HCHECK(hipMallocAsync((void**)&r->dw, sizeof(double) * 2 * std::max(1, n), gs));
+    HCHECK(hipMemcpyAsync(r->dH, r->hH, sizeof(double) * nn, hipMemcpyHostToDevice, gs));
+    if (r->want_q) launch_set_identity(r->dQ, n, n, gs);
     fill_job(jh[j], S->h->opts, n, r->dH, std::max(1, n), r->dQ, std::max(1, n), r->dw,
              r->dw + std::max(1, n), (int*)(dev + G.off_info) + j, nullptr);
   }
   order_jobs(jh, oh, cnt);
-  HCHECK(hipMemcpyAsync(dev, G.host, G.off_info, hipMemcpyHostToDevice, G.s));
+  HCHECK(hipMemcpyAsync(dev, host, G.off_info, hipMemcpyHostToDevice, gs));
   launch_batch_persistent((const PJob*)dev, (const int*)(dev + off_ord), cnt,
-                          (int*)(dev + off_next), (PScratch*)(dev + off_scr), grid, G.s);
+                          (int*)(dev + off_next), (PScratch*)(dev + off_scr), grid, gs);
   HCHECK(hipGetLastError());
-  HCHECK(hipMemcpyAsync(G.host + G.off_info, dev + G.off_info, sizeof(int) * cnt,
-                        hipMemcpyDeviceToHost, G.s));
+  HCHECK(hipMemcpyAsync(host + G.off_info, dev + G.off_info, sizeof(int) * cnt,
+                        hipMemcpyDeviceToHost, gs));
   for (Request* r : reqs) {
     const int n = r->n;
     const size_t nn = (size_t)n * n;
-    HCHECK(hipMemcpyAsync(r->hH, r->dH, sizeof(double) * nn, hipMemcpyDeviceToHost, G.s));
+    HCHECK(hipMemcpyAsync(r->hH, r->dH, sizeof(double) * nn, hipMemcpyDeviceToHost, gs));
     if (r->want_q)
-      HCHECK(hipMemcpyAsync(r->hQ, r->dQ, sizeof(double) * nn, hipMemcpyDeviceToHost, G.s));
+      HCHECK(hipMemcpyAsync(r->hQ, r->dQ, sizeof(double) * nn, hipMemcpyDeviceToHost, gs));
     HCHECK(hipMemcpyAsync(r->hw, r->dw, sizeof(double) * 2 * std::max(1, n),
-                          hipMemcpyDeviceToHost, G.s));
-    HCHECK(hipFreeAsync(r->dH, G.s));
-    if (r->dQ) HCHECK(hipFreeAsync(r->dQ, G.s));
-    HCHECK(hipFreeAsync(r->dw, G.s));
+                          hipMemcpyDeviceToHost, gs));
+    HCHECK(hipFreeAsync(r->dH, gs));
+    if (r->dQ) HCHECK(hipFreeAsync(r->dQ, gs));
+    HCHECK(hipFreeAsync(r->dw, gs));
     r->dH = r->dQ = r->dw = nullptr;
   }
-  HCHECK(hipFreeAsync(dev, G.s));
-  HCHECK(hipEventCreateWithFlags(&G.ev, hipEventDisableTiming));
-  HCHECK(hipEventRecord(G.ev, G.s));
+  HCHECK(hipFreeAsync(dev, gs));
+  if (S->free_events.empty()) {
+    hipEvent_t e = nullptr;
+    HCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    S->free_events.push_back(e);
+  }
+  G.ev = S->free_events.back();
+  S->free_events.pop_back();
+  HCHECK(hipEventRecord(G.ev, gs));
   S->groups.push_back(G);
 }
 
@@ -2610,7 +2681,8 @@ void server_loop(schur_server_s* S) {
             continue;
           }
           if (S->in_use + r->bytes > S->budget && !empty_gpu) break;
-          const bool small = r->n <= kPersistMaxN;
+          const bool small = r->n <= kServePersistMaxN &&
+                             (S->h->opts.flags & SCHUR_FLAG_BATCH_ROUNDS) == 0;
           const int slot = small ? -1 : S->eng.free_slot();
           if (!small && slot < 0) break;
           S->queue.pop_front();
@@ -2699,7 +2771,7 @@ void server_loop(schur_server_s* S) {
         const hipError_t q = hipEventQuery(G.ev);
         if (q == hipErrorNotReady) { running.push_back(G); continue; }
         HCHECK(q);
-        const int* infos = (const int*)(G.host + G.off_info);
+        const int* infos = (const int*)((char*)G.host + G.off_info);
         {
           std::lock_guard<std::mutex> lk(S->mu);
           for (size_t j = 0; j < G.reqs.size(); ++j) {
@@ -2711,8 +2783,8 @@ void server_loop(schur_server_s* S) {
             S->st.completed += 1;
           }
         }
-        HCHECK(hipHostFree(G.host));
-        HCHECK(hipEventDestroy(G.ev));
+        pin_put(S, G.host, G.host_cap);
+        S->free_events.push_back(G.ev);
       }
       S->groups.swap(running);
       if ((!S->draining.empty() || !S->groups.empty()) && !S->eng.any_active()) {
@@ -2966,11 +3038,16 @@ int schur_server_destroy(schur_server_t S) {
     (void)hipStreamDestroy(S->lane[k]);
   }
   for (auto& G : S->groups) {   // left by a failed loop: their streams are drained
-    if (G.host) (void)hipHostFree(G.host);
+    pin_put(S, G.host, G.host_cap);
     if (G.ev) (void)hipEventDestroy(G.ev);
   }
   S->groups.clear();
-  for (auto& kv : S->all) { free_request_host(kv.second); delete kv.second; }
+  for (hipEvent_t e : S->free_events) (void)hipEventDestroy(e);
+  S->free_events.clear();
+  for (auto& kv : S->all) { free_request_host(S, kv.second); delete kv.second; }
+  for (auto& kv : S->pool)
+    for (void* p : kv.second) (void)hipHostFree(p);
+  S->pool.clear();
   S->all.clear();
   schur_destroy(S->h);
   delete S;
@@ -2989,21 +3066,25 @@ int schur_submit(schur_server_t S, int n, const double* H_host, int ldh, int wan
   r->want_q = want_q != 0;
   r->bytes = request_bytes(n, r->want_q);
   const size_t nn = (size_t)n * n;
-  if (hipHostMalloc((void**)&r->hH, sizeof(double) * std::max<size_t>(1, nn), hipHostMallocDefault) != hipSuccess ||
-      (r->want_q && hipHostMalloc((void**)&r->hQ, sizeof(double) * std::max<size_t>(1, nn), hipHostMallocDefault) != hipSuccess) ||
-      hipHostMalloc((void**)&r->hw, sizeof(double) * 2 * std::max(1, n), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&r->hctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
-      hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
-    free_request_host(r);
+  // one pinned block: S (or H), Q, (wr, wi), the control block
+  const size_t dh = std::max<size_t>(1, nn), dq = r->want_q ? dh : 0,
+               dw = 2 * (size_t)std::max(1, n);
+  r->hblock = pin_get(S, sizeof(double) * (dh + dq + dw) + sizeof(Ctrl), &r->hcap);
+  if (!r->hblock || hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
+    free_request_host(S, r);
     delete r;
     return -101;
   }
+  r->hH = (double*)r->hblock;
+  r->hQ = r->want_q ? r->hH + dh : nullptr;
+  r->hw = r->hH + dh + dq;
+  r->hctrl = (Ctrl*)(r->hw + dw);
   std::memset(r->hctrl, 0, sizeof(Ctrl));
   for (int c = 0; c < n; ++c)
     std::memcpy(r->hH + (size_t)c * n, H_host + (size_t)c * ldh, sizeof(double) * n);
   {
     std::lock_guard<std::mutex> lk(S->mu);
-    if (S->error) { free_request_host(r); delete r; return S->error; }
+    if (S->error) { free_request_host(S, r); delete r; return S->error; }
     r->ticket = S->next_ticket++;
     r->t_submit = now_s();
     if (n == 0) { r->state = Request::DONE; r->t_done = r->t_submit; S->st.completed += 1; }
@@ -3042,7 +3123,7 @@ int schur_poll(schur_server_t S, uint64_t ticket, double* S_host, int lds, doubl
   }
   if (info) *info = r->info;
   if (latency_s) *latency_s = r->t_done - r->t_submit;
-  free_request_host(r);
+  free_request_host(S, r);
   delete r;
   return 0;
 }

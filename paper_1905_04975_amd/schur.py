@@ -64,6 +64,7 @@ class SchurStats(ctypes.Structure):
 
 FLAG_TIME_KERNELS = 1
 FLAG_BATCH_ROUNDS = 2
+FLAG_ONE_STREAM = 4
 
 EXPORTS = ("schur_reduce", "schur_create", "schur_destroy", "schur_set_opts",
            "schur_get_stats", "schur_reduce_async", "schur_reduce_batched",

@@ -2,7 +2,7 @@
 
 Requests of different orders and kinds are submitted while others are on
 the GPU; each result must meet the accuracy bar and agree with the same
-matrix solved alone.  Requests of order <= 1024 are solved by persistent
+matrix solved alone.  Requests of order <= 256 are solved by persistent
 launches (one workgroup per matrix, the whole solve on the device), so
 their results are the same bit for bit in the mix, alone and through
 schur_reduce_batched; larger ones advance in the round engine's shared
@@ -72,7 +72,9 @@ def test_served_mix_equals_alone(gpu_lib):
     for H, (S, Q, w, info, lat), (S1, Q1, w1, info1, lat1) in zip(mats, mixed, alone):
         _check(H, S, Q, w, info)
         _check(H, S1, Q1, w1, info1)
-        assert np.array_equal(S, S1) and np.array_equal(Q, Q1) and np.array_equal(w, w1)
+        assert checks.match_eigs(w, w1).max() <= 1e-10 * np.linalg.norm(H)
+        if H.shape[0] <= 256:
+            assert np.array_equal(S, S1) and np.array_equal(Q, Q1) and np.array_equal(w, w1)
         assert lat > 0.0
     # and through the batched entry point (same options, same kernel)
     import torch
@@ -83,9 +85,12 @@ def test_served_mix_equals_alone(gpu_lib):
     torch.cuda.synchronize()
     h.close()
     assert rc == 0
-    for (S, Q, w, info, lat), S2, Q2, w2 in zip(mixed, Sb, Qb, wb):
-        assert np.array_equal(S, S2.cpu().numpy()) and np.array_equal(Q, Q2.cpu().numpy())
-        assert np.array_equal(w, w2.cpu().numpy())
+    for H, (S, Q, w, info, lat), S2, Q2, w2 in zip(mats, mixed, Sb, Qb, wb):
+        if H.shape[0] <= 256:
+            assert np.array_equal(S, S2.cpu().numpy()) and np.array_equal(Q, Q2.cpu().numpy())
+            assert np.array_equal(w, w2.cpu().numpy())
+        else:
+            assert checks.match_eigs(w, w2.cpu().numpy()).max() <= 1e-10 * np.linalg.norm(H)
 
 
 def test_budget_forces_queueing(gpu_lib):
@@ -108,8 +113,8 @@ def test_budget_forces_queueing(gpu_lib):
 
 
 def test_served_large_requests_equal_alone(gpu_lib):
-    """Requests above order 1024 (the round engine), random and prescribed,
-    among small ones (persistent launches), with the parallel-pass
+    """Larger requests (the round engine), random and prescribed, among
+    small ones (persistent launches), with the parallel-pass
     threshold lowered (the server still runs no passes, so the option must
     not change its results): every result meets the bar and equals the one
     alone, the small ones bit for bit."""
@@ -131,5 +136,5 @@ def test_served_large_requests_equal_alone(gpu_lib):
         _check(H, S, Q, w, info)
         _check(H, S1, Q1, w1, info1)
         assert checks.match_eigs(w, w1).max() <= 1e-10 * np.linalg.norm(H)
-        if H.shape[0] <= 1024:
+        if H.shape[0] <= 256:
             assert np.array_equal(S, S1) and np.array_equal(w, w1)
