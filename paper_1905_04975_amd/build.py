@@ -23,7 +23,8 @@ COMMON = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
-SOURCES = ["kernels.hip", "batch_kernels.hip", "hess_kernels.hip", "evec_kernels.hip", "host.cpp"]
+SOURCES = ["kernels.hip", "batch_kernels.hip", "split_kernels.hip", "hess_kernels.hip", "evec_kernels.hip",
+           "host.cpp"]
 
 
 def build(verbose: bool = False) -> str:

@@ -68,20 +68,6 @@ __global__ __launch_bounds__(64) void k_reorder(const ReorderTask* tasks) {
   reorder_window<MAXM>(T, S, Z, status, ibuf, pbuf);
 }
 
-// One window of a parallel early-deflation pass per workgroup (one wavefront,
-// window and Schur vectors in LDS).
-template <int MAXM>
-__global__ __launch_bounds__(64) void k_split(const SplitTask* tasks) {
-  const SplitTask T = tasks[blockIdx.x];
-  constexpr int LD = SmallSmem<MAXM>::LD;
-  __shared__ double S[LD * MAXM];
-  __shared__ double Z[LD * MAXM];
-  __shared__ double vv[MAXM];
-  __shared__ int ibuf[6 * MAXM];
-  __shared__ double pbuf[7 * MAXM];
-  split_window<MAXM>(T, S, Z, vv, ibuf, pbuf);
-}
-
 // Chosen windows of a pass (disjoint) written from their output slots into
 // H (the Hessenberg part), and the coupling entries at their ends scaled:
 // above by this window's and the committed neighbour's factors, below by
@@ -499,11 +485,6 @@ void launch_aed_b(const AedTask* tasks, int count, hipStream_t s) {
 void launch_reorder(const ReorderTask* tasks, int count, hipStream_t s) {
   if (count > 0)
     hipLaunchKernelGGL((k_reorder<SMALL_Z_MAX>), dim3(count), dim3(64), 0, s, tasks);
-}
-
-void launch_split(const SplitTask* tasks, int count, hipStream_t s) {
-  if (count > 0)
-    hipLaunchKernelGGL((k_split<SMALL_Z_MAX>), dim3(count), dim3(64), 0, s, tasks);
 }
 
 void launch_split_commit(const SplitCommit* cm, int count, const SplitTask* tasks, hipStream_t s) {

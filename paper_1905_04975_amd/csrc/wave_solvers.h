@@ -43,6 +43,7 @@ struct SmallSmem {
 template <int MAXM>
 __device__ void chase_reg(double* S, double* Zs, int m_in, int l_in, int i_in, double x,
                           double y, double z) {
+  static_assert((MAXM & 1) == 0, "row MAXM of the LDS block is padding");
   constexpr int LD = SmallSmem<MAXM>::LD;
   // the bounds are the same in every lane: in scalar registers, the position
   // loop and the lane numbers of lane_read are scalar too
@@ -54,8 +55,13 @@ __device__ void chase_reg(double* S, double* Zs, int m_in, int l_in, int i_in, d
   const int qc = inm ? q : m - 1;   // clamped: every lane issues valid loads
   auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
   auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
-  // left operands S(r..r+2, q) and Z(q, r..r+2) of the first position
-  double cA = Sx(l, qc), cB = Sx(l + 1, qc), cC = Sx(l + 2, qc);
+  // left operands S(r..r+2, q) and Z(q, r..r+2) of the first position; the
+  // first two rows are kept as loaded (lA, lB) beside this lane's previous
+  // left-update results (pA, pB) and chosen only where the left update uses
+  // them, so that the wait for the loads falls after the reflector
+  double lA = Sx(l, qc), lB = Sx(l + 1, qc), cC = Sx(l + 2, qc);
+  double pA = 0.0, pB = 0.0;
+  bool far = false;
   double zA = Zx(qc, l), zB = Zx(qc, l + 1), zC = Zx(qc, l + 2);
   double o1 = 0.0;   // S(q, r-1) from this row's last right update
   wave_sync();       // every lane has read its operands before any lane stores
@@ -70,57 +76,59 @@ __device__ void chase_reg(double* S, double* Zs, int m_in, int l_in, int i_in, d
     const Refl h = make_reflector_fast(three ? 3 : 2, x, y, z);
     const double tv2 = h.tau * h.v2, tv3 = h.tau * h.v3;
 
-    // ---- left update: rows r..r+2, columns r..m-1 (column lane q)
+    // ---- left update: rows r..r+2 of every column (column lane q).  No
+    // branches: columns left of the bulge hold exact zeros in these rows (the
+    // block is Hessenberg and the bulge column is set below), so updating
+    // them rewrites zeros; lanes past the block store to the padding row
+    // MAXM (never read); a 2-row reflector stores its second row twice.
+    // Each position is then one straight-line block, and each wait for LDS
+    // sits where a loaded value is used.
+    const double cA = far ? pA : lA, cB = far ? pB : lB;
     const double a3 = three ? cC : 0.0;
     const double wl = cA + h.v2 * cB + h.v3 * a3;
     const double n2 = cB - tv2 * wl, n3 = a3 - tv3 * wl;
-    if (inm && q >= r) {
-      Sx(r, q) = cA - h.tau * wl;
-      Sx(r + 1, q) = n2;
-      if (three) Sx(r + 2, q) = n3;
-    }
-    if (r > l && q == 0) {   // the bulge column: beta above two zeros
-      Sx(r, r - 1) = h.beta;
-      Sx(r + 1, r - 1) = 0.0;
-      if (three) Sx(r + 2, r - 1) = 0.0;
+    {
+      const bool bc = r > l && q == r - 1;   // the bulge column: beta above two zeros
+      Sx(inm ? r : MAXM, qc) = bc ? h.beta : cA - h.tau * wl;
+      Sx(inm ? r + 1 : MAXM, qc) = bc ? 0.0 : n2;
+      Sx(inm ? r2 : MAXM, qc) = bc ? 0.0 : (three ? n3 : n2);
     }
     wave_sync();   // the left stores precede the right update's loads
 
-    // ---- right update: columns r..r+2 of rows 0..min(r+3, i), all rows of Z
-    const int rlast = (r + 3 < i) ? r + 3 : i;
+    // ---- right update: columns r..r+2 of every row (rows below min(r+3, i)
+    // hold zeros there and rewrite them), all rows of Z
     const double s1 = Sx(qc, r), s2 = Sx(qc, r + 1), t3 = Sx(qc, r2);
     const double s3 = three ? t3 : 0.0;
     const double z3 = three ? zC : 0.0;
     const double wr = s1 + h.v2 * s2 + h.v3 * s3;
     const double wz = zA + h.v2 * zB + h.v3 * z3;
     const double e1 = s1 - h.tau * wr;
-    if (q <= rlast) {
-      Sx(q, r) = e1;
-      Sx(q, r + 1) = s2 - tv2 * wr;
-      if (three) Sx(q, r + 2) = s3 - tv3 * wr;
-    }
+    const double e2 = s2 - tv2 * wr;
+    const int qs = inm ? q : MAXM;   // lanes past the block: the padding row
+    Sx(qs, r) = e1;
+    Sx(qs, r + 1) = e2;
+    Sx(qs, r2) = three ? s3 - tv3 * wr : e2;
     o1 = e1;
     const double f2 = zB - tv2 * wz, f3 = z3 - tv3 * wz;
-    if (inm) {
-      Zx(q, r) = zA - h.tau * wz;
-      Zx(q, r + 1) = f2;
-      if (three) Zx(q, r + 2) = f3;
-    }
+    Zx(qs, r) = zA - h.tau * wz;
+    Zx(qs, r + 1) = f2;
+    Zx(qs, r2) = three ? f3 : f2;
     zA = f2;
     zB = f3;
     wave_sync();   // this position's stores precede the loads below
     // operands of position r+1: S(r+1..r+3, q) as just stored, Z(q, r+3)
     // untouched so far (indices clamped to the block)
     const int r3 = (r + 3 < m - 1) ? r + 3 : m - 1;
-    const double lA = Sx(r + 1, qc), lB = Sx((r + 2 < m - 1) ? r + 2 : m - 1, qc);
+    lA = Sx(r + 1, qc);
+    lB = Sx((r + 2 < m - 1) ? r + 2 : m - 1, qc);
     cC = Sx(r3, qc);
     zC = Zx(qc, r3);
     // columns right of the next bulge were changed by this left update only:
     // its results (equal to the loaded values) stay in the registers that
     // were stored from, which the compiler then does not reuse early
-    const bool far = q >= r + 3;
-    cA = far ? n2 : lA;
-    cB = far ? n3 : lB;
+    far = q >= r + 3;
+    pA = n2;
+    pB = n3;
   }
   solver_sync();
 }
@@ -131,6 +139,7 @@ __device__ void chase_reg(double* S, double* Zs, int m_in, int l_in, int i_in, d
 template <int MAXM>
 __device__ void chase_reg2(double* S, double* Zs, int m_in, int l_in, int i_in, double x,
                            double y, double z) {
+  static_assert((MAXM & 1) == 0, "row MAXM of the LDS block is padding");
   constexpr int LD = SmallSmem<MAXM>::LD;
   const int m = __builtin_amdgcn_readfirstlane(m_in);
   const int l = __builtin_amdgcn_readfirstlane(l_in);
@@ -145,8 +154,12 @@ __device__ void chase_reg2(double* S, double* Zs, int m_in, int l_in, int i_in, 
   auto bulge = [&](double o0, double o1, int row) -> double {
     return (row < 64) ? lane_read(o0, row) : lane_read(o1, row - 64);
   };
-  double cA0 = Sx(l, q), cB0 = Sx(l + 1, q), cC0 = Sx(l + 2, q);
-  double cA1 = Sx(l, qbc), cB1 = Sx(l + 1, qbc), cC1 = Sx(l + 2, qbc);
+  // first two rows as loaded (l*) and this lane's previous left-update
+  // results (p*), chosen where the left update uses them (see chase_reg)
+  double lA0 = Sx(l, q), lB0 = Sx(l + 1, q), cC0 = Sx(l + 2, q);
+  double lA1 = Sx(l, qbc), lB1 = Sx(l + 1, qbc), cC1 = Sx(l + 2, qbc);
+  double pA0 = 0.0, pB0 = 0.0, pA1 = 0.0, pB1 = 0.0;
+  bool far0 = false, far1 = false;
   double zA0 = Zx(q, l), zB0 = Zx(q, l + 1), zC0 = Zx(q, l + 2);
   double zA1 = Zx(qbc, l), zB1 = Zx(qbc, l + 1), zC1 = Zx(qbc, l + 2);
   double o0 = 0.0, o1 = 0.0;   // S(q, r-1), S(q+64, r-1) from the last right update
@@ -163,31 +176,29 @@ __device__ void chase_reg2(double* S, double* Zs, int m_in, int l_in, int i_in, 
     const double tv2 = h.tau * h.v2, tv3 = h.tau * h.v3;
 
     // ---- left update: rows r..r+2, columns q and q+64 (from r on)
+    const double cA0 = far0 ? pA0 : lA0, cB0 = far0 ? pB0 : lB0;
+    const double cA1 = far1 ? pA1 : lA1, cB1 = far1 ? pB1 : lB1;
     const double a30 = three ? cC0 : 0.0, a31 = three ? cC1 : 0.0;
     const double wl0 = cA0 + h.v2 * cB0 + h.v3 * a30;
     const double wl1 = cA1 + h.v2 * cB1 + h.v3 * a31;
     const double n20 = cB0 - tv2 * wl0, n30 = a30 - tv3 * wl0;
     const double n21 = cB1 - tv2 * wl1, n31 = a31 - tv3 * wl1;
-    if (q >= r) {
-      Sx(r, q) = cA0 - h.tau * wl0;
-      Sx(r + 1, q) = n20;
-      if (three) Sx(r + 2, q) = n30;
-    }
-    if (inb && qb >= r) {
-      Sx(r, qb) = cA1 - h.tau * wl1;
-      Sx(r + 1, qb) = n21;
-      if (three) Sx(r + 2, qb) = n31;
-    }
-    if (r > l && q == 0) {   // the bulge column: beta above two zeros
-      Sx(r, r - 1) = h.beta;
-      Sx(r + 1, r - 1) = 0.0;
-      if (three) Sx(r + 2, r - 1) = 0.0;
+    // every lane stores every entry, without branches (see chase_reg); the
+    // second slot of lanes past the block stores to the padding row MAXM
+    {
+      const bool bc0 = r > l && q == r - 1, bc1 = r > l && qb == r - 1;   // bulge column
+      Sx(r, q) = bc0 ? h.beta : cA0 - h.tau * wl0;
+      Sx(r + 1, q) = bc0 ? 0.0 : n20;
+      Sx(r2, q) = bc0 ? 0.0 : (three ? n30 : n20);
+      Sx(inb ? r : MAXM, qbc) = bc1 ? h.beta : cA1 - h.tau * wl1;
+      Sx(inb ? r + 1 : MAXM, qbc) = bc1 ? 0.0 : n21;
+      Sx(inb ? r2 : MAXM, qbc) = bc1 ? 0.0 : (three ? n31 : n21);
     }
     wave_sync();   // the left stores precede the right update's loads
 
-    // ---- right update: columns r..r+2 of rows q, q+64 (up to min(r+3, i)),
-    // and of rows q, q+64 of Z
-    const int rlast = (r + 3 < i) ? r + 3 : i;
+    // ---- right update: columns r..r+2 of rows q, q+64 (rows below
+    // min(r+3, i) hold zeros there and rewrite them), and of rows q, q+64
+    // of Z
     const double s10 = Sx(q, r), s20 = Sx(q, r + 1), t30 = Sx(q, r2);
     const double s11 = Sx(qbc, r), s21 = Sx(qbc, r + 1), t31 = Sx(qbc, r2);
     const double s30 = three ? t30 : 0.0, s31 = three ? t31 : 0.0;
@@ -197,28 +208,24 @@ __device__ void chase_reg2(double* S, double* Zs, int m_in, int l_in, int i_in, 
     const double wz0 = zA0 + h.v2 * zB0 + h.v3 * z30;
     const double wz1 = zA1 + h.v2 * zB1 + h.v3 * z31;
     const double e10 = s10 - h.tau * wr0, e11 = s11 - h.tau * wr1;
-    if (q <= rlast) {
-      Sx(q, r) = e10;
-      Sx(q, r + 1) = s20 - tv2 * wr0;
-      if (three) Sx(q, r + 2) = s30 - tv3 * wr0;
-    }
-    if (inb && qb <= rlast) {
-      Sx(qb, r) = e11;
-      Sx(qb, r + 1) = s21 - tv2 * wr1;
-      if (three) Sx(qb, r + 2) = s31 - tv3 * wr1;
-    }
+    const double e20 = s20 - tv2 * wr0, e21 = s21 - tv2 * wr1;
+    Sx(q, r) = e10;
+    Sx(q, r + 1) = e20;
+    Sx(q, r2) = three ? s30 - tv3 * wr0 : e20;
+    const int qs1 = inb ? qb : MAXM;   // second slot past the block: the padding row
+    Sx(qs1, r) = e11;
+    Sx(qs1, r + 1) = e21;
+    Sx(qs1, r2) = three ? s31 - tv3 * wr1 : e21;
     o0 = e10;
     o1 = e11;
     const double f20 = zB0 - tv2 * wz0, f30 = z30 - tv3 * wz0;
     const double f21 = zB1 - tv2 * wz1, f31 = z31 - tv3 * wz1;
     Zx(q, r) = zA0 - h.tau * wz0;
     Zx(q, r + 1) = f20;
-    if (three) Zx(q, r + 2) = f30;
-    if (inb) {
-      Zx(qb, r) = zA1 - h.tau * wz1;
-      Zx(qb, r + 1) = f21;
-      if (three) Zx(qb, r + 2) = f31;
-    }
+    Zx(q, r2) = three ? f30 : f20;
+    Zx(qs1, r) = zA1 - h.tau * wz1;
+    Zx(qs1, r + 1) = f21;
+    Zx(qs1, r2) = three ? f31 : f21;
     zA0 = f20;
     zB0 = f30;
     zA1 = f21;
@@ -228,19 +235,145 @@ __device__ void chase_reg2(double* S, double* Zs, int m_in, int l_in, int i_in, 
     // of the next bulge keep this left update's results from the registers
     const int r3 = (r + 3 < m - 1) ? r + 3 : m - 1;
     const int rb = (r + 2 < m - 1) ? r + 2 : m - 1;
-    const double lA0 = Sx(r + 1, q), lB0 = Sx(rb, q);
-    const double lA1 = Sx(r + 1, qbc), lB1 = Sx(rb, qbc);
+    lA0 = Sx(r + 1, q);
+    lB0 = Sx(rb, q);
+    lA1 = Sx(r + 1, qbc);
+    lB1 = Sx(rb, qbc);
     cC0 = Sx(r3, q);
     cC1 = Sx(r3, qbc);
     zC0 = Zx(q, r3);
     zC1 = Zx(qbc, r3);
-    const bool far0 = q >= r + 3, far1 = qb >= r + 3;
-    cA0 = far0 ? n20 : lA0;
-    cB0 = far0 ? n30 : lB0;
-    cA1 = far1 ? n21 : lA1;
-    cB1 = far1 ? n31 : lB1;
+    far0 = q >= r + 3;
+    far1 = qb >= r + 3;
+    pA0 = n20;
+    pB0 = n30;
+    pA1 = n21;
+    pB1 = n31;
   }
   solver_sync();
+}
+
+// Chain of kb double-shift bulges over rows/cols l..i of the m x m block in
+// LDS with Schur vectors, one bulge per wavefront of the workgroup (kb <= the
+// wavefronts; the others idle through the barriers).  Bulge b, chased by
+// wavefront b, enters at the top three positions after bulge b-1, so at step
+// k it is at position p = l + k - 3b; (s, t) is this wavefront's shift pair
+// as (sum, product).  A step is two phases, each closed by a workgroup
+// barrier: every bulge's reflector from the left (rows p..p+2, lane q owning
+// columns q and q + 64), then from the right (columns p..p+2 of S and of Z,
+// lane q owning rows q and q + 64).  In a phase the bulges touch disjoint
+// rows (left) or disjoint columns (right); where the left update of one
+// bulge meets the right update of the bulge ahead (rows p-3..p-1 of columns
+// p..p+2) the two commute, and a bulge's own column, read before its left
+// update, is untouched by the others since its last right update.  So the
+// result is that of kb single-bulge sweeps one after the other with the
+// shift pairs fixed beforehand (the multishift sweep of the paper, Sec. 2,
+// at the scale of one workgroup): no step waits for the chase of another
+// bulge.  NS = 1 for m <= 64, 2 for 64 < m <= 128.  Updates run over every
+// column and row of the block without branches, as in chase_reg (entries
+// outside a bulge's reach hold exact zeros and are rewritten as zeros);
+// lanes past the block store to the padding row MAXM.
+template <int NS, int MAXM>
+__device__ void chase_multi(double* S, double* Zs, int m_in, int l_in, int i_in, int kb_in,
+                            double s, double t) {
+  static_assert((MAXM & 1) == 0, "row MAXM of the LDS block is padding");
+  static_assert(NS == 1 || NS == 2, "one or two columns per lane");
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  const int m = __builtin_amdgcn_readfirstlane(m_in);
+  const int l = __builtin_amdgcn_readfirstlane(l_in);
+  const int i = __builtin_amdgcn_readfirstlane(i_in);
+  const int kb = __builtin_amdgcn_readfirstlane(kb_in);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int q = threadIdx.x & 63;
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
+  int cc[NS], cs[NS];   // this lane's columns (rows), clamped; store index
+  bool in[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int c = q + 64 * k;
+    in[k] = c < m;
+    cc[k] = in[k] ? c : m - 1;
+    cs[k] = in[k] ? c : MAXM;
+  }
+  auto bulge = [](double o0, double o1, int row) -> double {
+    if (NS == 1 || row < 64) return lane_read(o0, row);
+    return lane_read(o1, row - 64);
+  };
+  double o[NS], zA[NS], zB[NS], zc[NS];   // S(q, p-1); Z(q, p), Z(q, p+1), Z(q, p+2)
+#pragma unroll
+  for (int k = 0; k < NS; ++k) { o[k] = 0.0; zA[k] = 0.0; zB[k] = 0.0; zc[k] = 0.0; }
+  const int nsteps = (i - l) + 3 * (kb - 1);
+  for (int stp = 0; stp < nsteps; ++stp) {
+    const int p = l + stp - 3 * w;
+    const bool act = w < kb && p >= l && p <= i - 1;   // uniform over the wavefront
+    const bool three = p <= i - 2;
+    const int p2 = three ? p + 2 : p + 1;   // the third row / column, or a valid stand-in
+    Refl h{};
+    double tv2 = 0.0, tv3 = 0.0;
+    if (act) {
+      // operands first (the bulge ahead changed them in the last step), the
+      // reflector while they arrive
+      double a1[NS], a2[NS], a3[NS];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        a1[k] = Sx(p, cc[k]);
+        a2[k] = Sx(p + 1, cc[k]);
+        a3[k] = Sx(p2, cc[k]);
+        zc[k] = Zx(cc[k], p2);
+      }
+      double x, y, z;
+      if (p == l) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          zA[k] = Zx(cc[k], l);
+          zB[k] = Zx(cc[k], l + 1);
+        }
+        first_column(Sx(l, l), Sx(l, l + 1), Sx(l + 1, l), Sx(l + 1, l + 1), Sx(l + 2, l + 1), s,
+                     t, x, y, z);
+        wave_sync();   // the corner (other lanes' columns) is read before the left stores
+      } else {
+        x = bulge(o[0], o[NS - 1], p);
+        y = bulge(o[0], o[NS - 1], p + 1);
+        z = three ? bulge(o[0], o[NS - 1], p + 2) : 0.0;
+      }
+      h = make_reflector_fast(three ? 3 : 2, x, y, z);
+      tv2 = h.tau * h.v2;
+      tv3 = h.tau * h.v3;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const double c3 = three ? a3[k] : 0.0;
+        const double wl = a1[k] + h.v2 * a2[k] + h.v3 * c3;
+        const double n2 = a2[k] - tv2 * wl, n3 = c3 - tv3 * wl;
+        const bool bc = p > l && q + 64 * k == p - 1;   // the bulge column: beta above two zeros
+        Sx(in[k] ? p : MAXM, cc[k]) = bc ? h.beta : a1[k] - h.tau * wl;
+        Sx(in[k] ? p + 1 : MAXM, cc[k]) = bc ? 0.0 : n2;
+        Sx(in[k] ? p2 : MAXM, cc[k]) = bc ? 0.0 : (three ? n3 : n2);
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const double s1 = Sx(cc[k], p), s2 = Sx(cc[k], p + 1), t3 = Sx(cc[k], p2);
+        const double s3 = three ? t3 : 0.0, z3 = three ? zc[k] : 0.0;
+        const double wr = s1 + h.v2 * s2 + h.v3 * s3;
+        const double wz = zA[k] + h.v2 * zB[k] + h.v3 * z3;
+        const double e1 = s1 - h.tau * wr, e2 = s2 - tv2 * wr;
+        Sx(cs[k], p) = e1;
+        Sx(cs[k], p + 1) = e2;
+        Sx(cs[k], p2) = three ? s3 - tv3 * wr : e2;
+        o[k] = e1;
+        const double f2 = zB[k] - tv2 * wz, f3 = z3 - tv3 * wz;
+        Zx(cs[k], p) = zA[k] - h.tau * wz;
+        Zx(cs[k], p + 1) = f2;
+        Zx(cs[k], p2) = three ? f3 : f2;
+        zA[k] = f2;
+        zB[k] = f3;
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // Francis double-shift iteration on the m x m block already in LDS (S, and Z
@@ -432,6 +565,220 @@ __device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
   return info;
 }
 
+// LDS scratch of the multi-wavefront iteration: the copy of the trailing
+// block (order <= 8), its eigenvalues, the shift pairs and their count.
+constexpr int SMALL_MW_AUX = SmallSmem<8>::LD * 8 + 16 + 2 * 4 + 1;
+
+// Shift pairs for a chain of nsh / 2 bulges (nsh <= 8): the eigenvalues of
+// the trailing nsh x nsh block S(i-nsh+1..i, i-nsh+1..i), from the small
+// Francis iteration on a copy in aux, as (sum, product) pairs in
+// aux[SMALL_MW_SH + 2b], aux[SMALL_MW_SH + 2b + 1]: complex conjugate pairs
+// first, then the real eigenvalues two at a time, each group by decreasing
+// modulus; the number of pairs goes to aux[SMALL_MW_SH + 8] (0 when the copy
+// did not converge).  One wavefront.
+constexpr int SMALL_MW_SH = SmallSmem<8>::LD * 8 + 16;
+template <int MAXM>
+__device__ void trailing_shifts(const double* S, int i, int nsh, double* aux) {
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  constexpr int LB = SmallSmem<8>::LD;
+  double* const B = aux;
+  double* const er = aux + LB * 8;
+  double* const ei = er + 8;
+  double* const sh = aux + SMALL_MW_SH;
+  const int lane = threadIdx.x & 63;
+  const int i0 = i - nsh + 1;
+  {
+    const int r = lane & 7, c = lane >> 3;
+    if (r < nsh && c < nsh) B[r + c * LB] = (r <= c + 1) ? S[(i0 + r) + (i0 + c) * LD] : 0.0;
+  }
+  solver_sync();
+  SmallTask t{};
+  t.m = nsh;
+  t.wr = er;
+  t.wi = ei;
+  const int info = small_iter<false, 8>(t, B, nullptr);
+  if (lane == 0) {
+    int np = 0;
+    unsigned used = 0;
+    if (info == 0) {
+      for (int it = 0; it < nsh; ++it) {   // complex pairs (positive imaginary parts)
+        int best = -1;
+        double bm = -1.0;
+        for (int k = 0; k < nsh; ++k) {
+          const double md = er[k] * er[k] + ei[k] * ei[k];
+          if (!((used >> k) & 1u) && ei[k] > 0.0 && md > bm) { bm = md; best = k; }
+        }
+        if (best < 0) break;
+        used |= 1u << best;
+        sh[2 * np] = er[best] + er[best];
+        sh[2 * np + 1] = bm;
+        ++np;
+      }
+      bool half = false;
+      double first = 0.0;
+      for (int it = 0; it < nsh; ++it) {   // real ones, two at a time
+        int best = -1;
+        double bm = -1.0;
+        for (int k = 0; k < nsh; ++k)
+          if (!((used >> k) & 1u) && ei[k] == 0.0 && fabs(er[k]) > bm) { bm = fabs(er[k]); best = k; }
+        if (best < 0) break;
+        used |= 1u << best;
+        if (!half) {
+          first = er[best];
+        } else {
+          sh[2 * np] = first + er[best];
+          sh[2 * np + 1] = first * er[best];
+          ++np;
+        }
+        half = !half;
+      }
+    }
+    sh[8] = (double)np;
+  }
+  solver_sync();
+}
+
+// The Francis iteration of small_iter (with Schur vectors) by a workgroup of
+// K wavefronts: the deflation checks and 2x2 standardisations as there, each
+// step a chain of up to K bulges (chase_multi) with shifts from the trailing
+// 2kb x 2kb block (trailing_shifts); kb = K while the active block has at
+// least 6 K rows, halved below, and one bulge (wavefront 0 alone, Francis or
+// exceptional shifts as in small_iter) for small active blocks and every
+// tenth step without deflation.  Needs the wavefront-local solver_sync
+// (SCHUR_SOLVER_WAVE_SYNC): the one-wavefront parts run on wavefront 0 while
+// the others wait at the workgroup barrier.  aux: SMALL_MW_AUX doubles of
+// LDS.  Every wavefront returns the same info.
+template <int MAXM, int K>
+__device__ int small_iter_mw(const SmallTask& T, double* S, double* Zs, double* aux) {
+#ifndef SCHUR_SOLVER_WAVE_SYNC
+  static_assert(K < 0, "the multi-wavefront iteration needs the wavefront-local solver_sync");
+#endif
+  static_assert(K == 2 || K == 4, "two or four wavefronts");
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  const int m = T.m;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
+  const double* const sh = aux + SMALL_MW_SH;
+
+  int i = m - 1, its = 0, info = 0;
+  const int itmax = T.itmax > 0 ? T.itmax : 30 * (m > 10 ? m : 10);
+  while (i >= 0) {
+    // ---- deflation search (every wavefront the same, reads only)
+    int l = 0;
+    for (int top = i; top >= 1; top -= 64) {
+      const int k = top - lane;
+      bool neg = false;
+      if (k >= 1) {
+        const double sub = fabs(Sx(k, k - 1));
+        double tst = fabs(Sx(k - 1, k - 1)) + fabs(Sx(k, k));
+        if (tst == 0.0) {
+          tst = fabs(Sx(k - 1, k));
+          if (k >= 2) tst += fabs(Sx(k - 1, k - 2));
+          if (k + 1 <= i) tst += fabs(Sx(k + 1, k));
+        }
+        neg = (sub <= kUlp * tst);
+      }
+      const unsigned long long mask = __ballot(neg);
+      if (mask) {
+        l = top - __builtin_ctzll(mask);
+        break;
+      }
+    }
+    __syncthreads();
+    if (w == 0 && l > 0 && lane == 0) Sx(l, l - 1) = 0.0;
+    __syncthreads();
+
+    if (l == i) {
+      if (w == 0 && lane == 0 && T.wr) { T.wr[i] = Sx(i, i); T.wi[i] = 0.0; }
+      i -= 1; its = 0;
+      continue;
+    }
+    if (l == i - 1) {
+      const Std2 o = standardize2(Sx(i - 1, i - 1), Sx(i - 1, i), Sx(i, i - 1), Sx(i, i));
+      __syncthreads();
+      if (w == 0) {
+        if (!(o.cs == 1.0 && o.sn == 0.0)) {
+          for (int c = i + 1 + lane; c < m; c += 64) {
+            const double x = Sx(i - 1, c), y = Sx(i, c);
+            Sx(i - 1, c) = o.cs * x + o.sn * y;
+            Sx(i, c) = o.cs * y - o.sn * x;
+          }
+          for (int r = lane; r < i - 1; r += 64) {
+            const double x = Sx(r, i - 1), y = Sx(r, i);
+            Sx(r, i - 1) = o.cs * x + o.sn * y;
+            Sx(r, i) = o.cs * y - o.sn * x;
+          }
+          for (int r = lane; r < m; r += 64) {
+            const double x = Zx(r, i - 1), y = Zx(r, i);
+            Zx(r, i - 1) = o.cs * x + o.sn * y;
+            Zx(r, i) = o.cs * y - o.sn * x;
+          }
+        }
+        if (lane == 0) {
+          Sx(i - 1, i - 1) = o.a; Sx(i - 1, i) = o.b;
+          Sx(i, i - 1) = o.c;     Sx(i, i) = o.d;
+          if (T.wr) {
+            T.wr[i - 1] = o.wr1; T.wi[i - 1] = o.wi1;
+            T.wr[i] = o.wr2;     T.wi[i] = o.wi2;
+          }
+        }
+      }
+      __syncthreads();
+      i -= 2; its = 0;
+      continue;
+    }
+    its += 1;
+    if (its > itmax) { info = i + 1; break; }
+
+    // ---- shifts: a chain of kb bulges, or one (Francis or exceptional)
+    int kb = K;
+    while (kb > 1 && i - l + 1 < 6 * kb) kb >>= 1;
+    if (its % 10 == 0) kb = 1;
+    double s = 0.0, t = 0.0;
+    if (kb > 1) {
+      if (w == 0) trailing_shifts<MAXM>(S, i, 2 * kb, aux);
+      __syncthreads();
+      const int np = (int)sh[8];
+      kb = np < kb ? np : kb;
+      if (w < kb) { s = sh[2 * w]; t = sh[2 * w + 1]; }
+    }
+    if (kb >= 2) {
+      if (m <= 64) chase_multi<1, MAXM>(S, Zs, m, l, i, kb, s, t);
+      else         chase_multi<2, MAXM>(S, Zs, m, l, i, kb, s, t);
+      continue;
+    }
+    if (w == 0) {
+      if (its % 10 == 0) {   // ad-hoc pair every 10 steps without deflation
+        double wv, e;
+        if ((its / 10) % 2 == 1) {
+          wv = fabs(Sx(i, i - 1)) + fabs(Sx(i - 1, i - 2));
+          e = Sx(i, i) + 0.75 * wv;
+        } else {
+          wv = fabs(Sx(l + 1, l)) + fabs(Sx(l + 2, l + 1));
+          e = Sx(l, l) + 0.75 * wv;
+        }
+        s = e + e;
+        t = e * e + 0.4375 * wv * wv;
+      } else {
+        const double a = Sx(i - 1, i - 1), b = Sx(i - 1, i), c = Sx(i, i - 1), d = Sx(i, i);
+        s = a + d;
+        t = a * d - b * c;
+      }
+      double x, y, z;
+      first_column(Sx(l, l), Sx(l, l + 1), Sx(l + 1, l), Sx(l + 1, l + 1), Sx(l + 2, l + 1), s, t,
+                   x, y, z);
+      solver_sync();   // every lane has read the corner before the first left update
+      if (m <= 64) chase_reg<MAXM>(S, Zs, m, l, i, x, y, z);
+      else         chase_reg2<MAXM>(S, Zs, m, l, i, x, y, z);
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  return info;
+}
+
 template <bool WANTZ, int MAXM>
 __device__ void small_load(const SmallTask& T, double* S, double* Zs) {
   constexpr int LD = SmallSmem<MAXM>::LD;
@@ -447,16 +794,28 @@ __device__ void small_load(const SmallTask& T, double* S, double* Zs) {
 }
 
 // Whole small-block solve: load, iterate, then the Schur form back in place
-// and Z (or Z^T, or Qacc Z) out.
-template <bool WANTZ, int MAXM>
-__device__ void small_qr(const SmallTask& T, double* S, double* Zs) {
+// and Z (or Z^T, or Qacc Z) out.  K > 1: a workgroup of K wavefronts
+// iterates (small_iter_mw, aux: SMALL_MW_AUX doubles of LDS); loading and
+// writing back are done by wavefront 0, from which the others return.
+template <bool WANTZ, int MAXM, int K = 1>
+__device__ void small_qr(const SmallTask& T, double* S, double* Zs, double* aux = nullptr) {
   constexpr int LD = SmallSmem<MAXM>::LD;
   const int m = T.m;
   const int lane = threadIdx.x;
   auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
   auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
-  small_load<WANTZ, MAXM>(T, S, Zs);
-  const int info = small_iter<WANTZ, MAXM>(T, S, Zs);
+  int info;
+  if constexpr (K > 1) {
+    static_assert(WANTZ, "the multi-wavefront iteration keeps the Schur vectors");
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (w == 0) small_load<WANTZ, MAXM>(T, S, Zs);
+    __syncthreads();
+    info = small_iter_mw<MAXM, K>(T, S, Zs, aux);
+    if (w != 0) return;
+  } else {
+    small_load<WANTZ, MAXM>(T, S, Zs);
+    info = small_iter<WANTZ, MAXM>(T, S, Zs);
+  }
   if (lane == 0 && T.info) *T.info = info;
   if (WANTZ) {
     // Schur form of the block back to global memory, Z^T into the U slot layout
@@ -1362,7 +1721,7 @@ __device__ double spike_reduce(double* S, double* Z, int LD, int m, int ncols, i
   return beta;
 }
 
-template <int MAXM>
+template <int MAXM, int K = 1>
 __device__ void split_window(const SplitTask& T, double* S, double* Z, double* vv, int* ibuf,
                              double* pbuf) {
   constexpr int LD = SmallSmem<MAXM>::LD;
@@ -1379,8 +1738,20 @@ __device__ void split_window(const SplitTask& T, double* S, double* Z, double* v
     const double sb = T.below ? T.H[(a + nw) + (size_t)(a + nw - 1) * T.ldh] : 0.0;
     SmallTask t{};
     t.A = Hw; t.lda = T.ldh; t.m = nw; t.itmax = T.itmax;
-    small_load<true, MAXM>(t, S, Z);
-    if (small_iter<true, MAXM>(t, S, Z) != 0) break;
+    int info;
+    if constexpr (K > 1) {
+      // K wavefronts iterate (pbuf is free until the reorderings below);
+      // the rest is wavefront 0's
+      const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+      if (w == 0) small_load<true, MAXM>(t, S, Z);
+      __syncthreads();
+      info = small_iter_mw<MAXM, K>(t, S, Z, pbuf);
+      if (w != 0) return;
+    } else {
+      small_load<true, MAXM>(t, S, Z);
+      info = small_iter<true, MAXM>(t, S, Z);
+    }
+    if (info != 0) break;
     // ---- 1. blocks coupled upward to the top
     const int nu = (st != 0.0) ? aed_reorder(S, Z, LD, nw, st, ibuf, pbuf) : 0;
     // ---- 2. they must not reach the coupling below

@@ -8,10 +8,10 @@
 //     in : int n, ktop, kbot, nst, nwin; double H[n*n] (column-major);
 //          double st[nst]; nwin x int (p, ws, tau0, tau1, nb, shift0)
 //     out: double H[n*n]; nwin x double Ut[128*128]
-//   simt_kernels small in.bin out.bin
+//   simt_kernels small|small2|small4 in.bin out.bin   (1, 2 or 4 wavefronts)
 //     in : int m; double A[m*m] (upper Hessenberg, m <= 96)
 //     out: int info; double S[m*m]; double Z[m*m]; double wr[m], wi[m]
-//   simt_kernels split in.bin out.bin
+//   simt_kernels split|split4 in.bin out.bin   (1 or 4 wavefronts)
 //     in : int n, a, nw, above, below; double H[n*n]
 //     out: int split, nu, nf, nb; double ftop, fbot; double H[n*n];
 //          double Ut[128*128]
@@ -228,7 +228,7 @@ int main(int argc, char** argv) {
     fclose(g);
     return 0;
   }
-  if (mode == "split") {
+  if (mode == "split" || mode == "split4") {
     constexpr int MAXM = SMALL_Z_MAX;
     constexpr int LD = SmallSmem<MAXM>::LD;
     int hdr[5];
@@ -247,9 +247,14 @@ int main(int argc, char** argv) {
     T.H = H.data(); T.ldh = n; T.a = hdr[1]; T.nw = hdr[2];
     T.above = hdr[3] ? 0 : -1; T.below = hdr[4]; T.itmax = 0;
     T.Ut = Ut.data(); T.ldut = UPAD; T.res = &res;
-    run_workgroup(64, 0, [T] {
-      split_window<MAXM>(T, S.data(), Z.data(), vv.data(), ib.data(), pb.data());
-    });
+    if (mode == "split")
+      run_workgroup(64, 0, [T] {
+        split_window<MAXM>(T, S.data(), Z.data(), vv.data(), ib.data(), pb.data());
+      });
+    else
+      run_workgroup(256, 0, [T] {
+        split_window<MAXM, 4>(T, S.data(), Z.data(), vv.data(), ib.data(), pb.data());
+      });
     FILE* g = fopen(argv[3], "wb");
     const int o[4] = {res.split, res.nu, res.nf, res.nb};
     fwrite(o, sizeof(int), 4, g);
@@ -260,7 +265,7 @@ int main(int argc, char** argv) {
     fclose(g);
     return 0;
   }
-  if (mode == "small") {
+  if (mode == "small" || mode == "small2" || mode == "small4") {
     constexpr int MAXM = SMALL_Z_MAX;
     constexpr int LD = SmallSmem<MAXM>::LD;
     int hdr[1];
@@ -269,14 +274,19 @@ int main(int argc, char** argv) {
     std::vector<double> A((size_t)m * m), Zo((size_t)m * m, NAN), wr(m, NAN), wi(m, NAN);
     if (!rd(f, A.data(), A.size())) return 2;
     fclose(f);
-    static std::vector<double> S(LD * MAXM), Z(LD * MAXM);
-    for (auto* v : {&S, &Z})
+    static std::vector<double> S(LD * MAXM), Z(LD * MAXM), aux(SMALL_MW_AUX);
+    for (auto* v : {&S, &Z, &aux})
       for (double& x : *v) x = NAN;
     int info = -99;
     SmallTask T{};
     T.A = A.data(); T.lda = m; T.m = m; T.Z = Zo.data(); T.ldz = m;
     T.wr = wr.data(); T.wi = wi.data(); T.info = &info; T.itmax = 0;
-    run_workgroup(64, 0, [T] { small_qr<true, MAXM>(T, S.data(), Z.data()); });
+    if (mode == "small")
+      run_workgroup(64, 0, [T] { small_qr<true, MAXM>(T, S.data(), Z.data()); });
+    else if (mode == "small2")
+      run_workgroup(128, 0, [T] { small_qr<true, MAXM, 2>(T, S.data(), Z.data(), aux.data()); });
+    else
+      run_workgroup(256, 0, [T] { small_qr<true, MAXM, 4>(T, S.data(), Z.data(), aux.data()); });
     FILE* g = fopen(argv[3], "wb");
     fwrite(&info, sizeof(int), 1, g);
     fwrite(A.data(), sizeof(double), A.size(), g);

@@ -238,13 +238,16 @@ def test_aed_window(driver, tmp_path, case):
         assert nd == nw and H2[kw, kw - 1] == 0.0
 
 
+@pytest.mark.parametrize("waves", [1, 2, 4])
 @pytest.mark.parametrize("m,seed,kind", [(5, 1, "normal"), (33, 2, "normal"), (64, 3, "normal"),
                                          (96, 4, "normal"), (40, 5, "prescribed"),
                                          (60, 6, "graded"), (65, 7, "normal"),
                                          (80, 8, "prescribed"), (90, 9, "graded")])
-def test_small_block_solver(driver, tmp_path, m, seed, kind):
-    """The single-wavefront Francis solver with Z: a standardised real Schur
-    form, H = Z S Z^T, and the eigenvalues of the oracle."""
+def test_small_block_solver(driver, tmp_path, m, seed, kind, waves):
+    """The small-block Francis solver with Z, on one wavefront (single
+    double-shift bulges) or on two or four (chains of bulges, one per
+    wavefront): a standardised real Schur form, H = Z S Z^T, and the
+    eigenvalues of the oracle."""
     from tests import checks
 
     if kind == "prescribed":
@@ -253,7 +256,8 @@ def test_small_block_solver(driver, tmp_path, m, seed, kind):
         A = _graded(m, seed, m // 2, -10)
     else:
         A = inputs.hessenberg_normal(m, seed)
-    raw = _call(driver, "small", [np.array([m], dtype=np.int32),
+    mode = {1: "small", 2: "small2", 4: "small4"}[waves]
+    raw = _call(driver, mode, [np.array([m], dtype=np.int32),
                                   np.asfortranarray(A).ravel(order="F")], tmp_path)
     info = int(np.frombuffer(raw[:4], dtype=np.int32)[0])
     x = np.frombuffer(raw[4:], dtype=np.float64)
@@ -276,9 +280,9 @@ def test_small_block_solver(driver, tmp_path, m, seed, kind):
     assert np.all(cost[r, c] <= checks.kappa_tolerance(A, lam_o[c], k[c], factor=200.0))
 
 
-def _split(driver, tmp_path, H, a, nw, above, below):
+def _split(driver, tmp_path, H, a, nw, above, below, waves=1):
     n = H.shape[0]
-    raw = _call(driver, "split", [np.array([n, a, nw, int(above), int(below)], dtype=np.int32),
+    raw = _call(driver, "split" if waves == 1 else "split4", [np.array([n, a, nw, int(above), int(below)], dtype=np.int32),
                                   np.asfortranarray(H).ravel(order="F")], tmp_path)
     split, nu, nf, nb = (int(v) for v in np.frombuffer(raw[:16], dtype=np.int32))
     ftop, fbot = np.frombuffer(raw[16:32], dtype=np.float64)
@@ -288,8 +292,9 @@ def _split(driver, tmp_path, H, a, nw, above, below):
     return split, nu, nf, nb, float(ftop), float(fbot), H2, U
 
 
+@pytest.mark.parametrize("waves", [1, 4])
 @pytest.mark.parametrize("case", ["mid_split", "mid_nosplit", "bottom", "top", "whole"])
-def test_split_window(driver, tmp_path, case):
+def test_split_window(driver, tmp_path, case, waves):
     """One window of a parallel early-deflation pass (paper Sec. 3.2, AED
     applied to windows inside the matrix): when it splits, V is orthogonal,
     V^T W V is the returned window with zero subdiagonal entries around the
@@ -308,7 +313,8 @@ def test_split_window(driver, tmp_path, case):
     else:
         H, a, nw, above, below = inputs.hessenberg_normal(80, 6), 0, 80, False, False
     n = H.shape[0]
-    split, nu, nf, nb, ftop, fbot, H2, Vfull = _split(driver, tmp_path, H, a, nw, above, below)
+    split, nu, nf, nb, ftop, fbot, H2, Vfull = _split(driver, tmp_path, H, a, nw, above, below,
+                                                      waves)
     if case == "mid_nosplit":
         assert split == 0
     else:
