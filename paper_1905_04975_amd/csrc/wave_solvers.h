@@ -303,6 +303,7 @@ __device__ void chase_multi(double* S, double* Zs, int m_in, int l_in, int i_in,
   double o[NS], zA[NS], zB[NS], zc[NS];   // S(q, p-1); Z(q, p), Z(q, p+1), Z(q, p+2)
 #pragma unroll
   for (int k = 0; k < NS; ++k) { o[k] = 0.0; zA[k] = 0.0; zB[k] = 0.0; zc[k] = 0.0; }
+  Refl hn{};   // the reflector of the next position, formed before the step's last barrier
   const int nsteps = (i - l) + 3 * (kb - 1);
   for (int stp = 0; stp < nsteps; ++stp) {
     const int p = l + stp - 3 * w;
@@ -312,8 +313,7 @@ __device__ void chase_multi(double* S, double* Zs, int m_in, int l_in, int i_in,
     Refl h{};
     double tv2 = 0.0, tv3 = 0.0;
     if (act) {
-      // operands first (the bulge ahead changed them in the last step), the
-      // reflector while they arrive
+      // operands first (the bulge ahead changed them in the last step)
       double a1[NS], a2[NS], a3[NS];
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
@@ -322,22 +322,20 @@ __device__ void chase_multi(double* S, double* Zs, int m_in, int l_in, int i_in,
         a3[k] = Sx(p2, cc[k]);
         zc[k] = Zx(cc[k], p2);
       }
-      double x, y, z;
       if (p == l) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
           zA[k] = Zx(cc[k], l);
           zB[k] = Zx(cc[k], l + 1);
         }
+        double x, y, z;
         first_column(Sx(l, l), Sx(l, l + 1), Sx(l + 1, l), Sx(l + 1, l + 1), Sx(l + 2, l + 1), s,
                      t, x, y, z);
         wave_sync();   // the corner (other lanes' columns) is read before the left stores
+        h = make_reflector_fast(three ? 3 : 2, x, y, z);
       } else {
-        x = bulge(o[0], o[NS - 1], p);
-        y = bulge(o[0], o[NS - 1], p + 1);
-        z = three ? bulge(o[0], o[NS - 1], p + 2) : 0.0;
+        h = hn;
       }
-      h = make_reflector_fast(three ? 3 : 2, x, y, z);
       tv2 = h.tau * h.v2;
       tv3 = h.tau * h.v3;
 #pragma unroll
@@ -353,13 +351,20 @@ __device__ void chase_multi(double* S, double* Zs, int m_in, int l_in, int i_in,
     }
     __syncthreads();
     if (act) {
+      // every slot's operands before any store (one LDS round trip)
+      double s1[NS], s2[NS], t3[NS];
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
-        const double s1 = Sx(cc[k], p), s2 = Sx(cc[k], p + 1), t3 = Sx(cc[k], p2);
-        const double s3 = three ? t3 : 0.0, z3 = three ? zc[k] : 0.0;
-        const double wr = s1 + h.v2 * s2 + h.v3 * s3;
+        s1[k] = Sx(cc[k], p);
+        s2[k] = Sx(cc[k], p + 1);
+        t3[k] = Sx(cc[k], p2);
+      }
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const double s3 = three ? t3[k] : 0.0, z3 = three ? zc[k] : 0.0;
+        const double wr = s1[k] + h.v2 * s2[k] + h.v3 * s3;
         const double wz = zA[k] + h.v2 * zB[k] + h.v3 * z3;
-        const double e1 = s1 - h.tau * wr, e2 = s2 - tv2 * wr;
+        const double e1 = s1[k] - h.tau * wr, e2 = s2[k] - tv2 * wr;
         Sx(cs[k], p) = e1;
         Sx(cs[k], p + 1) = e2;
         Sx(cs[k], p2) = three ? s3 - tv3 * wr : e2;
@@ -370,6 +375,16 @@ __device__ void chase_multi(double* S, double* Zs, int m_in, int l_in, int i_in,
         Zx(cs[k], p2) = three ? f3 : f2;
         zA[k] = f2;
         zB[k] = f3;
+      }
+      // the next position's reflector from this wavefront's own results
+      // (column p, rows p+1..p+3, which no other bulge touches before it is
+      // used), while the stores drain ahead of the barrier
+      if (p + 1 <= i - 1) {
+        const bool three1 = p + 1 <= i - 2;
+        const double x = bulge(o[0], o[NS - 1], p + 1);
+        const double y = bulge(o[0], o[NS - 1], p + 2);
+        const double z = three1 ? bulge(o[0], o[NS - 1], p + 3) : 0.0;
+        hn = make_reflector_fast(three1 ? 3 : 2, x, y, z);
       }
     }
     __syncthreads();
@@ -565,38 +580,132 @@ __device__ int small_iter(const SmallTask& T, double* S, double* Zs) {
   return info;
 }
 
-// LDS scratch of the multi-wavefront iteration: the copy of the trailing
-// block (order <= 8), its eigenvalues, the shift pairs and their count.
-constexpr int SMALL_MW_AUX = SmallSmem<8>::LD * 8 + 16 + 2 * 4 + 1;
+// LDS scratch of the multi-wavefront iteration: the eigenvalues of the
+// trailing block (order <= 8), the shift pairs and their count.
+constexpr int SMALL_MW_AUX = 16 + 2 * 4 + 1;
+
+// Eigenvalues of an n x n upper Hessenberg block (n <= 8) held one entry per
+// lane (entry (r, c) in lane r + 8c; zeros outside the block): the Francis
+// double-shift iteration of small_iter without Schur vectors (the same
+// deflation test, Francis and exceptional shifts, 2x2 standardisation).
+// A position's reflector comes from three lanes' entries (readlane); the
+// left update gathers each column's rows p..p+2 and the right update each
+// row's columns p..p+2 by lane permutes, so the whole iteration stays in
+// registers (no LDS round trip, no barrier).  Updates span the whole block
+// (entries outside a reflector's reach are zero or off the active block,
+// as in chase_reg).  er/ei written by lane 0; returns 0 or the 1-based end
+// of a block that did not converge.  One wavefront.
+__device__ int tiny_eigs8(double h, int n, double* er, double* ei) {
+  const int lane = threadIdx.x & 63;
+  const int row = lane & 7, col = lane >> 3;
+  auto at = [&](int r, int c) -> double { return lane_read(h, r + 8 * c); };
+  auto gather = [&](int src) -> double { return __shfl(h, src & 63, 64); };
+  int i = n - 1, its = 0, info = 0;
+  const int itmax = 30 * 10;
+  while (i >= 0) {
+    // ---- deflation: lane (k, k-1) tests subdiagonal entry k, 1 <= k <= i
+    {
+      const double dkm = gather(lane - 1), dk = gather(lane + 8);   // H(k-1,k-1), H(k,k)
+      const double up = gather(lane + 7), lft = gather(lane - 9), dn = gather(lane + 9);
+      const bool sub = row == col + 1 && row <= i;
+      double tst = fabs(dkm) + fabs(dk);
+      if (tst == 0.0) {
+        tst = fabs(up);
+        if (row >= 2) tst += fabs(lft);
+        if (row + 1 <= i) tst += fabs(dn);
+      }
+      const bool neg = sub && fabs(h) <= kUlp * tst;
+      const unsigned long long mask = __ballot(neg);
+      const int l = mask ? (63 - __builtin_clzll(mask) + 8) / 9 : 0;   // lane 9k - 8 -> k
+      if (l > 0 && row == l && col == l - 1) h = 0.0;
+      if (l == i) {
+        const double v = at(i, i);
+        if (lane == 0) { er[i] = v; ei[i] = 0.0; }
+        i -= 1; its = 0;
+        continue;
+      }
+      if (l == i - 1) {
+        const Std2 o = standardize2(at(i - 1, i - 1), at(i - 1, i), at(i, i - 1), at(i, i));
+        if (lane == 0) {
+          er[i - 1] = o.wr1; ei[i - 1] = o.wi1;
+          er[i] = o.wr2;     ei[i] = o.wi2;
+        }
+        i -= 2; its = 0;
+        continue;
+      }
+      its += 1;
+      if (its > itmax) { info = i + 1; break; }
+      // ---- shifts: trailing 2x2 (Francis) or the ad-hoc pair
+      double s, t;
+      if (its % 10 == 0) {
+        double wv, e;
+        if ((its / 10) % 2 == 1) {
+          wv = fabs(at(i, i - 1)) + fabs(at(i - 1, i - 2));
+          e = at(i, i) + 0.75 * wv;
+        } else {
+          wv = fabs(at(l + 1, l)) + fabs(at(l + 2, l + 1));
+          e = at(l, l) + 0.75 * wv;
+        }
+        s = e + e;
+        t = e * e + 0.4375 * wv * wv;
+      } else {
+        const double a = at(i - 1, i - 1), b = at(i - 1, i), c = at(i, i - 1), d = at(i, i);
+        s = a + d;
+        t = a * d - b * c;
+      }
+      double x, y, z;
+      first_column(at(l, l), at(l, l + 1), at(l + 1, l), at(l + 1, l + 1), at(l + 2, l + 1), s, t,
+                   x, y, z);
+      // ---- one double-shift step on rows/cols l..i
+      for (int p = l; p <= i - 1; ++p) {
+        const bool three = p <= i - 2;
+        const int p2 = three ? p + 2 : p + 1;
+        if (p > l) {
+          x = at(p, p - 1);
+          y = at(p + 1, p - 1);
+          z = three ? at(p2, p - 1) : 0.0;
+        }
+        const Refl r = make_reflector_fast(three ? 3 : 2, x, y, z);
+        const double tv2 = r.tau * r.v2, tv3 = r.tau * r.v3;
+        {   // left: rows p..p+2 of this lane's column
+          const double a1 = gather(p + 8 * col), a2 = gather(p + 1 + 8 * col), a3 = gather(p2 + 8 * col);
+          const double wl = a1 + r.v2 * a2 + r.v3 * (three ? a3 : 0.0);
+          const double cf = row == p ? r.tau : row == p + 1 ? tv2 : (three && row == p + 2) ? tv3 : 0.0;
+          h -= cf * wl;
+          if (p > l && col == p - 1 && row >= p && row <= p2) h = row == p ? r.beta : 0.0;
+        }
+        {   // right: columns p..p+2 of this lane's row
+          const double b1 = gather(row + 8 * p), b2 = gather(row + 8 * (p + 1)), b3 = gather(row + 8 * p2);
+          const double wr = b1 + r.v2 * b2 + r.v3 * (three ? b3 : 0.0);
+          const double cf = col == p ? r.tau : col == p + 1 ? tv2 : (three && col == p + 2) ? tv3 : 0.0;
+          h -= cf * wr;
+        }
+      }
+    }
+  }
+  return info;
+}
 
 // Shift pairs for a chain of nsh / 2 bulges (nsh <= 8): the eigenvalues of
-// the trailing nsh x nsh block S(i-nsh+1..i, i-nsh+1..i), from the small
-// Francis iteration on a copy in aux, as (sum, product) pairs in
-// aux[SMALL_MW_SH + 2b], aux[SMALL_MW_SH + 2b + 1]: complex conjugate pairs
-// first, then the real eigenvalues two at a time, each group by decreasing
-// modulus; the number of pairs goes to aux[SMALL_MW_SH + 8] (0 when the copy
-// did not converge).  One wavefront.
-constexpr int SMALL_MW_SH = SmallSmem<8>::LD * 8 + 16;
+// the trailing nsh x nsh block S(i-nsh+1..i, i-nsh+1..i) (tiny_eigs8) as
+// (sum, product) pairs in aux[SMALL_MW_SH + 2b], aux[SMALL_MW_SH + 2b + 1]:
+// complex conjugate pairs first, then the real eigenvalues two at a time,
+// each group by decreasing modulus; the number of pairs goes to
+// aux[SMALL_MW_SH + 8] (0 when the iteration did not converge).  One
+// wavefront.
+constexpr int SMALL_MW_SH = 16;
 template <int MAXM>
 __device__ void trailing_shifts(const double* S, int i, int nsh, double* aux) {
   constexpr int LD = SmallSmem<MAXM>::LD;
-  constexpr int LB = SmallSmem<8>::LD;
-  double* const B = aux;
-  double* const er = aux + LB * 8;
-  double* const ei = er + 8;
+  double* const er = aux;
+  double* const ei = aux + 8;
   double* const sh = aux + SMALL_MW_SH;
   const int lane = threadIdx.x & 63;
   const int i0 = i - nsh + 1;
-  {
-    const int r = lane & 7, c = lane >> 3;
-    if (r < nsh && c < nsh) B[r + c * LB] = (r <= c + 1) ? S[(i0 + r) + (i0 + c) * LD] : 0.0;
-  }
-  solver_sync();
-  SmallTask t{};
-  t.m = nsh;
-  t.wr = er;
-  t.wi = ei;
-  const int info = small_iter<false, 8>(t, B, nullptr);
+  const int r = lane & 7, c = lane >> 3;
+  const double h = (r < nsh && c < nsh && r <= c + 1) ? S[(i0 + r) + (i0 + c) * LD] : 0.0;
+  const int info = tiny_eigs8(h, nsh, er, ei);
+  wave_sync();
   if (lane == 0) {
     int np = 0;
     unsigned used = 0;
@@ -635,7 +744,7 @@ __device__ void trailing_shifts(const double* S, int i, int nsh, double* aux) {
     }
     sh[8] = (double)np;
   }
-  solver_sync();
+  wave_sync();
 }
 
 // The Francis iteration of small_iter (with Schur vectors) by a workgroup of
@@ -1427,50 +1536,73 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
 // V^T of a window into its panel slot (ldut x ldut, zero padded), after one
 // first-order re-orthogonalisation V <- V (I - E / 2), E = V^T V - I: V's
 // own rounding (it collected every rotation of the window) would otherwise
-// reach Q.  S (free once the window is written back) holds E.
-// (four independent sums per lane, rows unrolled, so loads run ahead)
+// reach Q.  S (free once the window is written back) holds E.  Both
+// products as FP64 MFMA 16 x 16 tiles (16x16x4 steps, operands straight
+// from LDS, zero outside the window), the tiles shared by the K wavefronts
+// of the workgroup (K = 1: the calling wavefront).
+typedef double wv_d4 __attribute__((ext_vector_type(4)));
+template <int K = 1>
 __device__ void aed_write_vt(double* S, const double* Z, int LD, int nw, double* Ut, int ldut) {
-  const int lane = threadIdx.x;
-  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  const int lane = threadIdx.x & 63;
+  const int w = K > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
+  const int kr = lane >> 4, kc = lane & 15;   // operand (k, i) / result (i % 4, j) of a lane
+  const int nt = (nw + 15) >> 4;
   auto Zx = [&](int r, int c) -> double { return Z[r + c * LD]; };
-  for (int j = lane; j < nw; j += 64)
-    for (int i0 = 0; i0 < nw; i0 += 4) {
-      int ic[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) ic[u] = (i0 + u < nw) ? i0 + u : nw - 1;
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-      for (int r = 0; r < nw; ++r) {
-        const double zj = Zx(r, j);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] += Zx(r, ic[u]) * zj;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (i0 + u < nw) Sx(i0 + u, j) = acc[u] - ((i0 + u == j) ? 1.0 : 0.0);
+  auto sync = [&]() {
+    if constexpr (K > 1) __syncthreads();
+    else solver_sync();
+  };
+  // ---- E = V^T V - I: E(i, j) = sum_r V(r, i) V(r, j)
+  for (int tix = w; tix < nt * nt; tix += K) {
+    const int I0 = (tix % nt) * 16, J0 = (tix / nt) * 16;
+    const int ia = I0 + kc, jb = J0 + kc;
+    const int iac = ia < nw ? ia : nw - 1, jbc = jb < nw ? jb : nw - 1;
+    wv_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < nw; k0 += 4) {
+      const int r = k0 + kr;
+      const int rc = r < nw ? r : nw - 1;
+      const double av = Zx(rc, iac), bv = Zx(rc, jbc);
+      const double a = (r < nw && ia < nw) ? av : 0.0;   // A(i, k) = V(k, i)
+      const double b = (r < nw && jb < nw) ? bv : 0.0;   // B(k, j) = V(k, j)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
-  solver_sync();
-  for (int j = lane; j < ldut; j += 64) {
-    for (int r0 = 0; r0 < ldut; r0 += 4) {
-      double val[4] = {0.0, 0.0, 0.0, 0.0};
-      if (j < nw && r0 < nw) {
-        int rc[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) rc[u] = (r0 + u < nw) ? r0 + u : nw - 1;
-        double corr[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int k = 0; k < nw; ++k) {
-          const double e = Sx(k, j);
-#pragma unroll
-          for (int u = 0; u < 4; ++u) corr[u] += Zx(rc[u], k) * e;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          val[u] = (r0 + u < nw) ? Zx(rc[u], j) - 0.5 * corr[u] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) Ut[j + (size_t)(r0 + u) * ldut] = val[u];   // Ut(j, r) = V(r, j)
+    for (int e = 0; e < 4; ++e) {
+      const int row = I0 + 4 * e + kr, col = J0 + kc;
+      if (row < nw && col < nw) S[row + col * LD] = acc[e] - (row == col ? 1.0 : 0.0);
     }
+  }
+  sync();
+  // ---- Ut(j, r) = (V - V E / 2)(r, j)
+  for (int tix = w; tix < nt * nt; tix += K) {
+    const int R0 = (tix % nt) * 16, J0 = (tix / nt) * 16;
+    const int ra = R0 + kc, jb = J0 + kc;
+    const int rac = ra < nw ? ra : nw - 1, jbc = jb < nw ? jb : nw - 1;
+    wv_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < nw; k0 += 4) {
+      const int k = k0 + kr;
+      const int kk = k < nw ? k : nw - 1;
+      const double av = Zx(rac, kk), bv = S[kk + jbc * LD];
+      const double a = (k < nw && ra < nw) ? av : 0.0;   // A(i, k) = V(R0 + i, k)
+      const double b = (k < nw && jb < nw) ? bv : 0.0;   // B(k, j) = E(k, J0 + j)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = R0 + 4 * e + kr, j = J0 + kc;
+      const double v = (r < nw && j < nw) ? Zx(r, j) - 0.5 * acc[e] : 0.0;
+      if (r < ldut && j < ldut) Ut[j + (size_t)r * ldut] = v;
+    }
+  }
+  // ---- zeros of the slot outside the tiles (ldut >= nw)
+  const int nt16 = nt * 16 < ldut ? nt * 16 : ldut;
+  const int wide = (ldut - nt16) * ldut;          // columns j >= nt16 of every row r
+  const int rest = (ldut - nt16) * nt16;          // rows r >= nt16, columns j < nt16
+  for (int x = w * 64 + lane; x < wide + rest; x += 64 * K) {
+    int j, r;
+    if (x < wide) { r = x / (ldut - nt16); j = nt16 + x % (ldut - nt16); }
+    else { const int y = x - wide; r = nt16 + y / nt16; j = y % nt16; }
+    Ut[j + (size_t)r * ldut] = 0.0;
   }
 }
 
@@ -1725,12 +1857,14 @@ template <int MAXM, int K = 1>
 __device__ void split_window(const SplitTask& T, double* S, double* Z, double* vv, int* ibuf,
                              double* pbuf) {
   constexpr int LD = SmallSmem<MAXM>::LD;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = K > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
   const int nw = T.nw, a = T.a;
   auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
   auto Zx = [&](int r, int c) -> double& { return Z[r + c * LD]; };
   SplitRes out;
   out.split = 0; out.nu = nw; out.nf = 0; out.nb = 0; out.ftop = 1.0; out.fbot = 1.0;
+  bool ok = false;
   do {   // every exit below is uniform over the wavefront
     if (nw < 1 || nw > MAXM) break;
     double* Hw = T.H + a + (size_t)a * T.ldh;
@@ -1741,17 +1875,15 @@ __device__ void split_window(const SplitTask& T, double* S, double* Z, double* v
     int info;
     if constexpr (K > 1) {
       // K wavefronts iterate (pbuf is free until the reorderings below);
-      // the rest is wavefront 0's
-      const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+      // steps 1-3 are wavefront 0's, the others wait for the write-back
       if (w == 0) small_load<true, MAXM>(t, S, Z);
       __syncthreads();
       info = small_iter_mw<MAXM, K>(t, S, Z, pbuf);
-      if (w != 0) return;
     } else {
       small_load<true, MAXM>(t, S, Z);
       info = small_iter<true, MAXM>(t, S, Z);
     }
-    if (info != 0) break;
+    if (info != 0 || w != 0) break;
     // ---- 1. blocks coupled upward to the top
     const int nu = (st != 0.0) ? aed_reorder(S, Z, LD, nw, st, ibuf, pbuf) : 0;
     // ---- 2. they must not reach the coupling below
@@ -1794,21 +1926,33 @@ __device__ void split_window(const SplitTask& T, double* S, double* Z, double* v
       fbot = spike_reduce(S + bs + bs * LD, Z + bs * LD, LD, nb, nb, bs, nw, nw - 1, vv);
       flip_tail(S, Z, LD, nw, bs);
     }
-    // ---- 4. the window back into H (or its output slot), V^T into its slot
-    double* Wd = T.Wo ? T.Wo : Hw;
-    const int ldw = T.Wo ? T.ldwo : T.ldh;
-    for (int c = 0; c < nw; ++c)
-      for (int r = lane; r <= c + 1 && r < nw; r += 64) Wd[r + (size_t)c * ldw] = Sx(r, c);
-    solver_sync();
-    aed_write_vt(S, Z, LD, nw, T.Ut, T.ldut);
     out.split = 1;
     out.nu = nu;
     out.nb = nb;
     out.nf = nw - nu - nb;
     out.ftop = ftop;
     out.fbot = fbot;
+    ok = true;
   } while (false);
-  if (lane == 0) *T.res = out;
+  if constexpr (K > 1) {
+    // wavefront 0's outcome to the others (ibuf is free after the reorderings)
+    if (threadIdx.x == 0) ibuf[0] = ok ? 1 : 0;
+    __syncthreads();
+    ok = ibuf[0] != 0;
+  } else {
+    solver_sync();
+  }
+  if (ok) {
+    // ---- 4. the window back into H (or its output slot), V^T into its slot
+    double* Wd = T.Wo ? T.Wo : T.H + a + (size_t)a * T.ldh;
+    const int ldw = T.Wo ? T.ldwo : T.ldh;
+    for (int c = w; c < nw; c += K)
+      for (int r = lane; r <= c + 1 && r < nw; r += 64) Wd[r + (size_t)c * ldw] = Sx(r, c);
+    if constexpr (K > 1) __syncthreads();
+    else solver_sync();
+    aed_write_vt<K>(S, Z, LD, nw, T.Ut, T.ldut);
+  }
+  if (threadIdx.x == 0) *T.res = out;
 }
 
 }  // namespace schur

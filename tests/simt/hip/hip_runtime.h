@@ -2,7 +2,7 @@
 // kernels use, so that their device source runs on the host: one workgroup
 // is a set of std::threads; __syncthreads is a barrier over all of them,
 // the wavefront barrier one over the 64 threads of a wavefront, and
-// __shfl_xor / __ballot / readlane / the FP64 MFMA exchange values through
+// __shfl_xor / __shfl / __ballot / readlane / the FP64 MFMA exchange values through
 // memory between wavefront barriers.
 // Threads run freely between barriers, which is stricter than lock-step
 // wavefronts: a kernel that relied on lock-step without a barrier shows a
@@ -32,6 +32,7 @@ extern thread_local simt_dim3 blockIdx;
 extern simt_dim3 blockDim;
 void __syncthreads();
 double __shfl_xor(double x, int o, int w);
+double __shfl(double x, int src, int w);
 unsigned long long __ballot(int p);
 int simt_readlane(int v, int src);
 void simt_wave_barrier();

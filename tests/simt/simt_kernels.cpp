@@ -11,6 +11,9 @@
 //   simt_kernels small|small2|small4 in.bin out.bin   (1, 2 or 4 wavefronts)
 //     in : int m; double A[m*m] (upper Hessenberg, m <= 96)
 //     out: int info; double S[m*m]; double Z[m*m]; double wr[m], wi[m]
+//   simt_kernels tiny in.bin out.bin   (eigenvalues of a block of order <= 8)
+//     in : int n; double A[n*n] (upper Hessenberg)
+//     out: int info; double wr[n], wi[n]
 //   simt_kernels split|split4 in.bin out.bin   (1 or 4 wavefronts)
 //     in : int n, a, nw, above, below; double H[n*n]
 //     out: int split, nu, nf, nb; double ftop, fbot; double H[n*n];
@@ -79,6 +82,15 @@ double __shfl_xor(double x, int o, int) {
   g_shfl[l] = x;
   simt_wave_barrier();
   const double r = g_shfl[l ^ o];
+  simt_wave_barrier();
+  return r;
+}
+
+double __shfl(double x, int src, int) {
+  const int l = threadIdx.x;
+  g_shfl[l] = x;
+  simt_wave_barrier();
+  const double r = g_shfl[(l & ~63) + (src & 63)];
   simt_wave_barrier();
   return r;
 }
@@ -293,6 +305,29 @@ int main(int argc, char** argv) {
     fwrite(Zo.data(), sizeof(double), Zo.size(), g);
     fwrite(wr.data(), sizeof(double), m, g);
     fwrite(wi.data(), sizeof(double), m, g);
+    fclose(g);
+    return 0;
+  }
+  if (mode == "tiny") {
+    // in : int n; double A[n*n] (upper Hessenberg, n <= 8)
+    // out: int info; double wr[n], wi[n]
+    int hdr[1];
+    if (!rd(f, hdr, 1)) return 2;
+    const int n = hdr[0];
+    std::vector<double> A((size_t)n * n), er(8, NAN), ei(8, NAN);
+    if (!rd(f, A.data(), A.size())) return 2;
+    fclose(f);
+    int info = -99;
+    run_workgroup(64, 0, [&] {
+      const int r = threadIdx.x & 7, c = threadIdx.x >> 3;
+      const double h = (r < n && c < n && r <= c + 1) ? A[r + (size_t)c * n] : 0.0;
+      const int o = tiny_eigs8(h, n, er.data(), ei.data());
+      if (threadIdx.x == 0) info = o;
+    });
+    FILE* g = fopen(argv[3], "wb");
+    fwrite(&info, sizeof(int), 1, g);
+    fwrite(er.data(), sizeof(double), n, g);
+    fwrite(ei.data(), sizeof(double), n, g);
     fclose(g);
     return 0;
   }

@@ -280,6 +280,56 @@ def test_small_block_solver(driver, tmp_path, m, seed, kind, waves):
     assert np.all(cost[r, c] <= checks.kappa_tolerance(A, lam_o[c], k[c], factor=200.0))
 
 
+@pytest.mark.parametrize("n,seed,kind", [(1, 1, "normal"), (2, 2, "normal"), (3, 3, "normal"),
+                                         (4, 4, "normal"), (5, 5, "prescribed"), (8, 6, "normal"),
+                                         (8, 7, "prescribed"), (8, 8, "graded"), (6, 9, "zero_sub"),
+                                         (8, 10, "companion")])
+def test_tiny_eigenvalue_iteration(driver, tmp_path, n, seed, kind):
+    """The register-resident eigenvalue iteration of blocks of order <= 8
+    (the shifts of a bulge chain): every eigenvalue within a condition-
+    weighted bound of numpy's, on random, prescribed-spectrum, graded,
+    already split and companion (known roots) inputs."""
+    from tests import checks
+
+    exact = None
+    if kind == "prescribed":
+        A, exact = inputs.prescribed(n, seed)
+    elif kind == "graded":
+        A = _graded(n, seed, n // 2, -10)
+    elif kind == "companion":
+        roots = np.array([-3.0, -1.5, -0.5, 0.25, 1.0, 2.0, 2.5, 4.0])[:n]
+        c = np.poly(roots)
+        A = np.zeros((n, n))
+        A[0, :] = -c[1:]
+        A[np.arange(1, n), np.arange(n - 1)] = 1.0
+        exact = roots.astype(complex)
+    else:
+        A = inputs.hessenberg_normal(n, seed)
+        if kind == "zero_sub":
+            A[3, 2] = 0.0
+    raw = _call(driver, "tiny", [np.array([n], dtype=np.int32),
+                                 np.asfortranarray(A).ravel(order="F")], tmp_path)
+    info = int(np.frombuffer(raw[:4], dtype=np.int32)[0])
+    x = np.frombuffer(raw[4:], dtype=np.float64)
+    lam = x[:n] + 1j * x[n:2 * n]
+    assert info == 0 and not np.isnan(lam).any()
+    # conjugate pairs come as (re, +im), (re, -im)
+    k = 0
+    while k < n:
+        if lam[k].imag != 0.0:
+            assert lam[k].imag > 0 and lam[k + 1] == np.conj(lam[k])
+            k += 2
+        else:
+            k += 1
+    ref = np.linalg.eigvals(A) if exact is None else np.asarray(exact)
+    w, kappa = checks.eig_condition(np.triu(A, -1))
+    kap = kappa[np.argmin(np.abs(ref[:, None] - w[None, :]), axis=1)]
+    from scipy.optimize import linear_sum_assignment
+    cost = np.abs(lam[:, None] - ref[None, :])
+    r, c = linear_sum_assignment(cost)
+    assert np.all(cost[r, c] <= checks.kappa_tolerance(A, ref[c], kap[c], factor=200.0))
+
+
 def _split(driver, tmp_path, H, a, nw, above, below, waves=1):
     n = H.shape[0]
     raw = _call(driver, "split" if waves == 1 else "split4", [np.array([n, a, nw, int(above), int(below)], dtype=np.int32),
