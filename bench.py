@@ -458,8 +458,8 @@ def sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream):
     return out
 
 
-KERNEL_SOURCES = ("kernels.hip", "wave_solvers.h", "window_chase.h", "device_common.h", "wg_ops.h",
-                  "schur_internal.h")
+KERNEL_SOURCES = ("kernels.hip", "mw_kernels.hip", "wave_solvers.h", "window_chase.h",
+                  "device_common.h", "wg_ops.h", "schur_internal.h")
 
 
 def kernel_source_hash():

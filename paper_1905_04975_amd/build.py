@@ -23,7 +23,7 @@ COMMON = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
-SOURCES = ["kernels.hip", "batch_kernels.hip", "split_kernels.hip", "hess_kernels.hip", "evec_kernels.hip",
+SOURCES = ["kernels.hip", "batch_kernels.hip", "mw_kernels.hip", "hess_kernels.hip", "evec_kernels.hip",
            "host.cpp"]
 
 

@@ -24,16 +24,6 @@
 namespace schur {
 
 template <int MAXM>
-__global__ __launch_bounds__(64) void k_small_z(SmallTask t0, const SmallTask* tasks) {
-  constexpr int LD = SmallSmem<MAXM>::LD;
-  __shared__ double S[LD * MAXM];
-  __shared__ double Z[LD * MAXM];
-  const SmallTask T = tasks ? tasks[blockIdx.x] : t0;
-  if (T.m <= 0 || T.m > MAXM) return;
-  small_qr<true, MAXM>(T, S, Z);
-}
-
-template <int MAXM>
 __global__ __launch_bounds__(64) void k_small_eig(SmallTask t0, const SmallTask* tasks) {
   constexpr int LD = SmallSmem<MAXM>::LD;
   __shared__ double S[LD * MAXM];
@@ -452,16 +442,6 @@ __global__ void k_std_blocks(double* H, int ldh, int n, const int* list, const i
 // ============================================================================
 // Host-side launch wrappers
 // ============================================================================
-void launch_small_z(const SmallTask& t, const SmallTask* tasks, int count, int maxm,
-                    hipStream_t s) {
-  if (maxm <= 32)
-    hipLaunchKernelGGL((k_small_z<32>), dim3(count), dim3(64), 0, s, t, tasks);
-  else if (maxm <= 64)
-    hipLaunchKernelGGL((k_small_z<64>), dim3(count), dim3(64), 0, s, t, tasks);
-  else
-    hipLaunchKernelGGL((k_small_z<SMALL_Z_MAX>), dim3(count), dim3(64), 0, s, t, tasks);
-}
-
 void launch_small_eig(const SmallTask& t, hipStream_t s) {
   if (t.m <= 32)
     hipLaunchKernelGGL((k_small_eig<32>), dim3(1), dim3(64), 0, s, t, (const SmallTask*)nullptr);
