@@ -1324,10 +1324,19 @@ __device__ __forceinline__ void swap_apply(double (&a)[4], const double* v, cons
 //   xr: rows above the block (rows -xr..-1 of S, same columns) that take the
 //   right transforms too; zrows: rows of Zs that take them; srow: the row of
 //   Zs whose entries, times s, form the spike (0 for a bottom window).
+// K > 1: a workgroup of K wavefronts (every one calls it): wavefront 0 keeps
+// the round's bookkeeping (swap list, bottom test, plans), all K apply the
+// swaps, with workgroup barriers between the phases.
+template <int K = 1>
 __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* ibuf,
                            double* pbuf, int xr = 0, int zrows = -1, int srow = 0) {
   if (zrows < 0) zrows = m;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = K > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
+  auto sync = [&]() {
+    if constexpr (K > 1) __syncthreads();
+    else solver_sync();
+  };
   auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
   auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
   int* status = ibuf;            // per row: 0 untested, 1 undeflatable
@@ -1342,12 +1351,14 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
   double* pl_v = pbuf;               // 8 per swap
   double* pl_t = pbuf + 8 * maxsw;   // 2 per swap
   double* pl_d = pbuf + 10 * maxsw;  // 2 per swap (restored 1x1 diagonals)
-  __shared__ int sh_nmv, sh_bot, sh_left, sh_tgt;
-  for (int i = lane; i < m; i += 64) status[i] = 0;
-  if (lane == 0) {
-    sh_nmv = 0; sh_bot = m - 1; sh_left = m; sh_tgt = 0;
+  __shared__ int sh_nmv, sh_bot, sh_left, sh_tgt, sh_nsw;
+  if (w == 0) {
+    for (int i = lane; i < m; i += 64) status[i] = 0;
+    if (lane == 0) {
+      sh_nmv = 0; sh_bot = m - 1; sh_left = m; sh_tgt = 0;
+    }
   }
-  solver_sync();
+  sync();
   const double tiny = 2.2250738585072014e-308;
   const double smlnum = tiny * ((double)m / kUlp);
   int rounds = 0;
@@ -1355,8 +1366,9 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
     const int nmv = sh_nmv, bot = sh_bot, left = sh_left;
     if (left == 0 || ++rounds > 4 * m + 16) break;   // the bound is never reached
     // ---- this round's swaps: moving blocks with an untested upper neighbour
+    // (wavefront 0)
     int nsw = 0;
-    for (int base = 0; base < nmv; base += 64) {
+    for (int base = 0; w == 0 && base < nmv; base += 64) {
       const int j = base + lane;
       bool go = false;
       int k = 0, as = 1;
@@ -1377,8 +1389,9 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
       }
       nsw += __builtin_popcountll(mask);
     }
+    if (w == 0 && lane == 0) sh_nsw = nsw;
     // ---- bottom block test (it meets no swap window of this round)
-    const bool test = status[bot] == 0;
+    const bool test = w == 0 && status[bot] == 0;
     const int bs = (test && bot >= 1 && status[bot - 1] == 0 && Sx(bot, bot - 1) != 0.0) ? 2 : 1;
     bool defl = false;
     if (test) {
@@ -1396,9 +1409,10 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
       if (foo == 0.0) foo = fabs(s);
       defl = spk <= fmax(smlnum, kUlp * foo);
     }
-    solver_sync();
-    // ---- plans, one lane per swap
-    if (lane < nsw) {
+    sync();
+    nsw = sh_nsw;
+    // ---- plans, one lane of wavefront 0 per swap
+    if (w == 0 && lane < nsw) {
       const int k = sw_k[lane], pp = sw_p[lane], rr = mv_sz[sw_j[lane]];
       SwapPlan pl;
       bool ok;
@@ -1416,14 +1430,15 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
       pl_d[2 * lane + 1] = Sx(k + pp + rr - 1, k + pp + rr - 1);   // B's
       sw_ok[lane] = ok ? 1 : 0;
     }
-    solver_sync();
+    sync();
     const bool bad = lane < nsw && sw_ok[lane] == 0;
     if (__ballot(bad) != 0ull) break;   // uniform: nothing of this round is applied
     if (nsw > 0) {
-      // lanes in groups of G per swap; a group walks its swap's columns
+      // threads in groups of G per swap; a group walks its swap's columns
       // (left) and rows (right) two at a time
-      const int G = 64 / nsw;
-      const int t = lane / G, sub = lane - t * G;
+      const int tid = w * 64 + lane;
+      const int G = 64 * K / nsw;
+      const int t = tid / G, sub = tid - t * G;
       const bool mine = t < nsw;
       int k = 0, pp = 1, rr = 1, N = 2;
       double v[8], tau[2];
@@ -1459,7 +1474,7 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
           }
         }
       }
-      solver_sync();
+      sync();
       // right: rows -xr..k+N-1 of S, then rows 0..zrows-1 of Z (one index
       // space; ra below is the S row relative to the block)
       if (mine) {
@@ -1504,10 +1519,10 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
         }
       }
     }
-    solver_sync();
-    // ---- bookkeeping: each swap's lane moves its block; the last lane
-    // records the bottom test (disjoint rows and entries)
-    if (lane < nsw) {
+    sync();
+    // ---- bookkeeping (wavefront 0): each swap's lane moves its block; the
+    // last lane records the bottom test (disjoint rows and entries)
+    if (w == 0 && lane < nsw) {
       const int j = sw_j[lane], k = sw_k[lane], pp = sw_p[lane], rr = mv_sz[j];
       mv_pos[j] = k;
       for (int i = 0; i < rr; ++i) status[k + i] = 1;
@@ -1527,9 +1542,9 @@ __device__ int aed_reorder(double* S, double* Zs, int LD, int m, double s, int* 
       }
       sh_left = left - bs;
     }
-    solver_sync();
+    sync();
   }
-  solver_sync();
+  sync();
   return sh_bot + 1;
 }
 
@@ -1862,10 +1877,17 @@ __device__ void split_window(const SplitTask& T, double* S, double* Z, double* v
   const int nw = T.nw, a = T.a;
   auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
   auto Zx = [&](int r, int c) -> double& { return Z[r + c * LD]; };
+  auto sync = [&]() {
+    if constexpr (K > 1) __syncthreads();
+    else solver_sync();
+  };
   SplitRes out;
   out.split = 0; out.nu = nw; out.nf = 0; out.nb = 0; out.ftop = 1.0; out.fbot = 1.0;
   bool ok = false;
-  do {   // every exit below is uniform over the wavefront
+  // every exit below is uniform over the workgroup; with K > 1 the
+  // iteration and the reorderings are the K wavefronts', the flips and the
+  // spike reductions wavefront 0's
+  do {
     if (nw < 1 || nw > MAXM) break;
     double* Hw = T.H + a + (size_t)a * T.ldh;
     const double st = (T.above >= 0) ? T.H[a + (size_t)(a - 1) * T.ldh] : 0.0;
@@ -1874,19 +1896,18 @@ __device__ void split_window(const SplitTask& T, double* S, double* Z, double* v
     t.A = Hw; t.lda = T.ldh; t.m = nw; t.itmax = T.itmax;
     int info;
     if constexpr (K > 1) {
-      // K wavefronts iterate (pbuf is free until the reorderings below);
-      // steps 1-3 are wavefront 0's, the others wait for the write-back
       if (w == 0) small_load<true, MAXM>(t, S, Z);
       __syncthreads();
-      info = small_iter_mw<MAXM, K>(t, S, Z, pbuf);
+      info = small_iter_mw<MAXM, K>(t, S, Z, pbuf);   // pbuf is free until the reorderings
     } else {
       small_load<true, MAXM>(t, S, Z);
       info = small_iter<true, MAXM>(t, S, Z);
     }
-    if (info != 0 || w != 0) break;
+    if (info != 0) break;
     // ---- 1. blocks coupled upward to the top
-    const int nu = (st != 0.0) ? aed_reorder(S, Z, LD, nw, st, ibuf, pbuf) : 0;
-    // ---- 2. they must not reach the coupling below
+    const int nu = (st != 0.0) ? aed_reorder<K>(S, Z, LD, nw, st, ibuf, pbuf) : 0;
+    // ---- 2. they must not reach the coupling below (read only: every
+    // wavefront reaches the same verdict)
     if (nu > 0 && sb != 0.0) {
       const double smlnum = 2.2250738585072014e-308 * ((double)nw / kUlp);
       bool bad = false;
@@ -1913,18 +1934,22 @@ __device__ void split_window(const SplitTask& T, double* S, double* Z, double* v
     // flipped block, whose spike row is the last row of Z)
     int nb = 0;
     if (sb != 0.0 && nu < nw) {
-      flip_tail(S, Z, LD, nw, nu);
-      nb = aed_reorder(S + nu + nu * LD, Z + nu * LD, LD, nw - nu, sb, ibuf, pbuf, nu, nw, nw - 1);
-      flip_tail(S, Z, LD, nw, nu);
+      if (w == 0) flip_tail(S, Z, LD, nw, nu);
+      sync();
+      nb = aed_reorder<K>(S + nu + nu * LD, Z + nu * LD, LD, nw - nu, sb, ibuf, pbuf, nu, nw,
+                          nw - 1);
+      if (w == 0) flip_tail(S, Z, LD, nw, nu);
     }
     const int bs = nw - nb;
     // ---- 3. coupled parts back to Hessenberg form
     double ftop = 0.0, fbot = 0.0;
-    if (nu > 0) ftop = spike_reduce(S, Z, LD, nu, nw, 0, nw, 0, vv);
-    if (nb > 0) {
-      flip_tail(S, Z, LD, nw, bs);
-      fbot = spike_reduce(S + bs + bs * LD, Z + bs * LD, LD, nb, nb, bs, nw, nw - 1, vv);
-      flip_tail(S, Z, LD, nw, bs);
+    if (w == 0) {
+      if (nu > 0) ftop = spike_reduce(S, Z, LD, nu, nw, 0, nw, 0, vv);
+      if (nb > 0) {
+        flip_tail(S, Z, LD, nw, bs);
+        fbot = spike_reduce(S + bs + bs * LD, Z + bs * LD, LD, nb, nb, bs, nw, nw - 1, vv);
+        flip_tail(S, Z, LD, nw, bs);
+      }
     }
     out.split = 1;
     out.nu = nu;
@@ -1934,25 +1959,17 @@ __device__ void split_window(const SplitTask& T, double* S, double* Z, double* v
     out.fbot = fbot;
     ok = true;
   } while (false);
-  if constexpr (K > 1) {
-    // wavefront 0's outcome to the others (ibuf is free after the reorderings)
-    if (threadIdx.x == 0) ibuf[0] = ok ? 1 : 0;
-    __syncthreads();
-    ok = ibuf[0] != 0;
-  } else {
-    solver_sync();
-  }
+  sync();
   if (ok) {
     // ---- 4. the window back into H (or its output slot), V^T into its slot
     double* Wd = T.Wo ? T.Wo : T.H + a + (size_t)a * T.ldh;
     const int ldw = T.Wo ? T.ldwo : T.ldh;
     for (int c = w; c < nw; c += K)
       for (int r = lane; r <= c + 1 && r < nw; r += 64) Wd[r + (size_t)c * ldw] = Sx(r, c);
-    if constexpr (K > 1) __syncthreads();
-    else solver_sync();
+    sync();
     aed_write_vt<K>(S, Z, LD, nw, T.Ut, T.ldut);
   }
-  if (threadIdx.x == 0) *T.res = out;
+  if (threadIdx.x == 0) *T.res = out;   // wavefront 0's results
 }
 
 }  // namespace schur
