@@ -1812,25 +1812,32 @@ __device__ void flip_tail(double* S, double* Z, int LD, int nw, int lo) {
 // Reflector I - tau vv vv^T (vv[0] = 1, L entries) applied to rows
 // r0..r0+L-1 of S over columns c0..ncols-1 (left), then to columns
 // r0..r0+L-1 over rows -xr..rend-1 of S and rows 0..zrows-1 of Z (right).
+// K > 1: by the K wavefronts of the workgroup (columns, then rows, split
+// over all threads, a workgroup barrier after each phase).
+template <int K = 1>
 __device__ void refl_apply(double* S, double* Z, int LD, const double* vv, double tau, int r0,
                            int L, int c0, int ncols, int xr, int rend, int zrows) {
-  const int lane = threadIdx.x;
-  for (int c = c0 + lane; c < ncols; c += 64) {
+  const int tid = K > 1 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+  auto sync = [&]() {
+    if constexpr (K > 1) __syncthreads();
+    else solver_sync();
+  };
+  for (int c = c0 + tid; c < ncols; c += 64 * K) {
     double w = 0.0;
     for (int i = 0; i < L; ++i) w += vv[i] * S[(r0 + i) + c * LD];
     w *= tau;
     for (int i = 0; i < L; ++i) S[(r0 + i) + c * LD] -= vv[i] * w;
   }
-  solver_sync();
+  sync();
   const int ns = xr + rend;
-  for (int q = lane; q < ns + zrows; q += 64) {
+  for (int q = tid; q < ns + zrows; q += 64 * K) {
     double* base = (q < ns) ? S + (q - xr) : Z + (q - ns);
     double w = 0.0;
     for (int j = 0; j < L; ++j) w += base[(r0 + j) * LD] * vv[j];
     w *= tau;
     for (int j = 0; j < L; ++j) base[(r0 + j) * LD] -= w * vv[j];
   }
-  solver_sync();
+  sync();
 }
 
 // The m x m quasi-triangular block B = S(0:m, 0:m) is coupled to the rest of
@@ -1838,33 +1845,60 @@ __device__ void refl_apply(double* S, double* Z, int LD, const double* vv, doubl
 // onto its first entry, then bring B back to Hessenberg form with reflectors
 // that leave row and column 0 alone.  Left transforms run over columns
 // 0..ncols-1, right transforms over rows -xr..m-1 of S and rows 0..zrows-1
-// of Z.  Returns the first entry of the reflected row.
+// of Z.  Returns the first entry of the reflected row.  K > 1: every
+// wavefront of the workgroup calls it; wavefront 0 forms the reflectors
+// (published through LDS), all apply them.
+template <int K = 1>
 __device__ double spike_reduce(double* S, double* Z, int LD, int m, int ncols, int xr, int zrows,
                                int srow, double* vv) {
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = K > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
   auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
-  solver_sync();
+  auto sync = [&]() {
+    if constexpr (K > 1) __syncthreads();
+    else solver_sync();
+  };
+  // a reflector's (tau, beta) for the other wavefronts, two buffers used in
+  // turn: a buffer is rewritten only after every wavefront passed the barrier
+  // that follows its last read
+  __shared__ double sh_tb[2][2];
+  int par = 0;
+  sync();
   if (m <= 0) return 0.0;
   if (m == 1) return Z[srow];
-  for (int i = lane; i < m; i += 64) vv[i] = Z[srow + i * LD];
-  solver_sync();
-  const double alpha = vv[0];
-  double tau, beta;
-  aed_reflector(alpha, vv, m, tau, beta);
-  if (tau != 0.0) refl_apply(S, Z, LD, vv, tau, 0, m, 0, ncols, xr, m, zrows);
+  if (w == 0) {
+    for (int i = lane; i < m; i += 64) vv[i] = Z[srow + i * LD];
+    solver_sync();
+    const double alpha = vv[0];
+    double t0, b0;
+    aed_reflector(alpha, vv, m, t0, b0);
+    if (lane == 0) { sh_tb[par][0] = t0; sh_tb[par][1] = b0; }
+  }
+  sync();
+  const double tau = sh_tb[par][0], beta = sh_tb[par][1];
+  par ^= 1;
+  if (tau != 0.0) refl_apply<K>(S, Z, LD, vv, tau, 0, m, 0, ncols, xr, m, zrows);
   for (int j = 0; j + 2 < m; ++j) {
     const int L = m - j - 1;   // rows j+1 .. m-1
-    const double a0 = Sx(j + 1, j);
-    for (int i = 1 + lane; i < L; i += 64) vv[i] = Sx(j + 1 + i, j);
-    solver_sync();
-    double tj, bj;
-    aed_reflector(a0, vv, L, tj, bj);
+    if (w == 0) {
+      const double a0 = Sx(j + 1, j);
+      for (int i = 1 + lane; i < L; i += 64) vv[i] = Sx(j + 1 + i, j);
+      solver_sync();
+      double tj, bj;
+      aed_reflector(a0, vv, L, tj, bj);
+      if (lane == 0) { sh_tb[par][0] = tj; sh_tb[par][1] = bj; }
+      if (tj != 0.0) {
+        if (lane == 0) Sx(j + 1, j) = bj;
+        for (int i = 2 + lane; i <= L; i += 64) Sx(j + i, j) = 0.0;
+      }
+    }
+    sync();
+    const double tj = sh_tb[par][0];
+    par ^= 1;
     if (tj == 0.0) continue;
-    if (lane == 0) Sx(j + 1, j) = bj;
-    for (int i = 2 + lane; i <= L; i += 64) Sx(j + i, j) = 0.0;
-    refl_apply(S, Z, LD, vv, tj, j + 1, L, j + 1, ncols, xr, m, zrows);
+    refl_apply<K>(S, Z, LD, vv, tj, j + 1, L, j + 1, ncols, xr, m, zrows);
   }
-  solver_sync();
+  sync();
   return beta;
 }
 
@@ -1885,8 +1919,8 @@ __device__ void split_window(const SplitTask& T, double* S, double* Z, double* v
   out.split = 0; out.nu = nw; out.nf = 0; out.nb = 0; out.ftop = 1.0; out.fbot = 1.0;
   bool ok = false;
   // every exit below is uniform over the workgroup; with K > 1 the
-  // iteration and the reorderings are the K wavefronts', the flips and the
-  // spike reductions wavefront 0's
+  // iteration, the reorderings and the spike reductions are the K
+  // wavefronts', the flips wavefront 0's
   do {
     if (nw < 1 || nw > MAXM) break;
     double* Hw = T.H + a + (size_t)a * T.ldh;
@@ -1943,13 +1977,11 @@ __device__ void split_window(const SplitTask& T, double* S, double* Z, double* v
     const int bs = nw - nb;
     // ---- 3. coupled parts back to Hessenberg form
     double ftop = 0.0, fbot = 0.0;
-    if (w == 0) {
-      if (nu > 0) ftop = spike_reduce(S, Z, LD, nu, nw, 0, nw, 0, vv);
-      if (nb > 0) {
-        flip_tail(S, Z, LD, nw, bs);
-        fbot = spike_reduce(S + bs + bs * LD, Z + bs * LD, LD, nb, nb, bs, nw, nw - 1, vv);
-        flip_tail(S, Z, LD, nw, bs);
-      }
+    if (nu > 0) ftop = spike_reduce<K>(S, Z, LD, nu, nw, 0, nw, 0, vv);
+    if (nb > 0) {
+      if (w == 0) flip_tail(S, Z, LD, nw, bs);
+      fbot = spike_reduce<K>(S + bs + bs * LD, Z + bs * LD, LD, nb, nb, bs, nw, nw - 1, vv);
+      if (w == 0) flip_tail(S, Z, LD, nw, bs);
     }
     out.split = 1;
     out.nu = nu;
