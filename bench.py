@@ -388,8 +388,9 @@ def sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream):
     as the library runs them (the Q products on a second stream, overlapping
     the window chase; `seconds`), and with every kernel on the solve stream
     (`SCHUR_FLAG_ONE_STREAM`), where each kernel's HIP-event duration is its
-    own, for the rates of the sweep kernels (window chase, row-panel and
-    column-panel/Q products).  The partial reduction is still an orthogonal
+    own, for the rates of the sweep kernels (window chase; the panel products
+    of a time step, there two launches: rows of H with Q, then columns of
+    H).  The partial reduction is still an orthogonal
     similarity, which the probe checks."""
     import torch
     from paper_1905_04975_amd import schur
@@ -447,8 +448,12 @@ def sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream):
         "gemm_tflops": st1["gemm_flops"] / max(gemm_ms * 1e-3, 1e-30) / 1e12,
         "gemm_frac_of_fp64_mfma_peak": st1["gemm_flops"] / max(gemm_ms * 1e-3, 1e-30) / 1e12
         / FP64_MFMA_PEAK_TFLOPS,
-        "k_panel_colq": gl("k_panel_colq", st1["colq_ms"], st1["colq_launches"], st1["colq_flops"]),
-        "k_panel_row": gl("k_panel_row", st1["row_ms"], st1["row_launches"], st1["row_flops"]),
+        # with every kernel on one stream a time step's panel products are two
+        # launches: the rows of H with Q (k_panel_rowq), then the columns of H
+        "k_panel_colq": gl("k_panel_colq (columns of H)", st1["colq_ms"], st1["colq_launches"],
+                           st1["colq_flops"]),
+        "k_panel_row": gl("k_panel_rowq (rows of H and Q)", st1["row_ms"], st1["row_launches"],
+                          st1["row_flops"]),
         "k_chase": family_lines(st1, "sweep").get("k_chase"),
         "residual_probe": res,
     }

@@ -102,7 +102,10 @@ typedef struct schur_opts {
                                     /* kernel)                                         */
 #define SCHUR_FLAG_ONE_STREAM 4     /* single solves: the Q products on the solve      */
                                     /* stream too (no overlap with the window chase),  */
-                                    /* so each kernel's timed duration is its own      */
+                                    /* so each kernel's timed duration is its own; a   */
+                                    /* time step's Q products share one launch with    */
+                                    /* its row-panel products (same result bit for     */
+                                    /* bit)                                            */
 
 /* Counters of the last solve on a handle. */
 typedef struct schur_stats {

@@ -126,10 +126,11 @@ __device__ inline void pb_solve(const PJob& J, double* lds, PShared& sh, PScratc
     if (kbot < 0) break;
     const int ktop = sh.ctrl.ktop;
     const int len = kbot - ktop + 1;
-    // ---- a small active block: one wavefront solves it with its Z
+    // ---- a small active block: the workgroup solves it with its Z (bulge
+    // chains on the four wavefronts)
     if (len <= J.nmin) {
       const bool whole = ktop == 0 && kbot == n - 1;
-      if (tid < 64) {
+      {
         SmallTask t{};
         t.A = H + ktop + (size_t)ktop * ldh;
         t.lda = ldh;
@@ -145,7 +146,7 @@ __device__ inline void pb_solve(const PJob& J, double* lds, PShared& sh, PScratc
           t.Zt = X->U;
           t.ldzt = UPAD;
         }
-        small_qr<true, SMALL_Z_MAX>(t, S96, Z96);
+        small_qr<true, SMALL_Z_MAX, PB_THREADS / 64>(t, S96, Z96, lds + 2 * LD96 * SMALL_Z_MAX);
       }
       __syncthreads();
       cnt[PB_SMALL] += 1;
@@ -172,7 +173,7 @@ __device__ inline void pb_solve(const PJob& J, double* lds, PShared& sh, PScratc
     bool aed_shifts = false;
     const int nw = min(J.nw, len - 1);
     if (nw >= 4) {
-      if (tid < 64) {
+      {
         AedTask t{};
         t.H = H; t.ldh = ldh;
         t.ktop = ktop; t.kbot = kbot; t.nw = nw;
@@ -181,7 +182,7 @@ __device__ inline void pb_solve(const PJob& J, double* lds, PShared& sh, PScratc
         t.wr = J.wr + (kbot - nw + 1); t.wi = J.wi + (kbot - nw + 1);
         t.ctrl = &sh.ctrl;
         t.itmax = 0;
-        aed_window<SMALL_Z_MAX>(t, S96, Z96, lds + 2 * LD96 * SMALL_Z_MAX,
+        aed_window<SMALL_Z_MAX, PB_THREADS / 64>(t, S96, Z96, lds + 2 * LD96 * SMALL_Z_MAX,
                                 (int*)(lds + 2 * LD96 * SMALL_Z_MAX + SMALL_Z_MAX),
                                 lds + 2 * LD96 * SMALL_Z_MAX + 4 * SMALL_Z_MAX);
       }

@@ -639,6 +639,45 @@ struct Solver {
     h->stats.launches += (tr > 0) + (tcq > 0);
   }
 
+  // The panel products of one time step.  Two streams: Q on the aux stream,
+  // rows then columns of H on the main one.  One stream: two launches, the
+  // rows of H with Q (different matrices, no order between them), then the
+  // columns of H.  (The rows and the columns of H meet in the blocks
+  // rows(A) x cols(B) of two windows A above B, so they stay in two
+  // launches in stream order.  Splitting Q between the two launches so that
+  // they carry equal tile counts measured slower.)
+  void launch_panels(const SweepArgs& a, const SweepArgs& aq, int tr, int tc, int tq, int buf) {
+    if (!one_stream) {
+      launch_q(aq, tq, buf);
+      launch_gemms(a, tr, tc);
+      return;
+    }
+    (void)buf;
+    // the Q products are timed with the rows of H
+    for (int w = 0; w < aq.nwin; ++w) {
+      const double fq = 2.0 * (double)aq.win[w].ws * (double)aq.win[w].ws * (a.Q ? (double)n : 0.0);
+      h->stats.row_flops += fq;
+      h->stats.colq_flops -= fq;
+    }
+    hipEvent_t e0 = nullptr;
+    if (tr + tq > 0) {
+      if (P.time) h->timer.begin(s, e0);
+      launch_panel_rowq(a, tr, aq, tq, s);
+      HCHECK(hipGetLastError());
+      if (P.time) h->timer.end(s, e0, &h->stats.row_ms);
+      h->stats.row_launches += 1;
+    }
+    if (tc > 0) {
+      if (P.time) h->timer.begin(s, e0);
+      launch_panel_colq(a, tc, s);
+      HCHECK(hipGetLastError());
+      if (P.time) h->timer.end(s, e0, &h->stats.colq_ms);
+      h->stats.colq_launches += 1;
+    }
+    h->stats.gemm_launches += (tr + tq > 0) + (tc > 0);
+    h->stats.launches += (tr + tq > 0) + (tc > 0);
+  }
+
   void sync_ctrl() {
     HCHECK(hipMemcpyAsync(h->ctrl_h, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HCHECK(hipStreamSynchronize(s));
@@ -678,8 +717,7 @@ struct Solver {
     a.win[0].slot = buf * MAXWIN;
     int tr, tc, tq;
     fill_gemm(a, aq, tr, tc, tq);
-    launch_q(aq, tq, buf);
-    launch_gemms(a, tr, tc);
+    launch_panels(a, aq, tr, tc, tq, buf);
   }
 
   // Early deflation on the bottom nw rows of [ktop, kbot]; applies the
@@ -722,8 +760,7 @@ struct Solver {
       a.nwin = 0;
       aq = a;
     }
-    launch_q(aq, tq, buf);   // records the slot's events even when idle
-    launch_gemms(a, tr, tc);
+    launch_panels(a, aq, tr, tc, tq, buf);   // records the slot's events even when idle
     h->stats.aed_deflated += nd;
     h->stats.aed_flops += aed_work(nw, nd > 0 ? *nu : 0);
     return nd;
@@ -830,8 +867,7 @@ struct Solver {
       h->stats.launches += 1;
       int tr, tc, tq;
       fill_gemm(a, aq, tr, tc, tq);
-      launch_q(aq, tq, buf);
-      launch_gemms(a, tr, tc);
+      launch_panels(a, aq, tr, tc, tq, buf);
     }
   }
 

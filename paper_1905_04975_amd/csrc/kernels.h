@@ -108,6 +108,8 @@ void launch_shift_prep(const double* wr, const double* wi, int ns, const int* sm
 void launch_chase(const SweepArgs& a, hipStream_t s);
 void launch_panel_row(const SweepArgs& a, int blocks, hipStream_t s);
 void launch_panel_colq(const SweepArgs& a, int blocks, hipStream_t s);
+void launch_panel_rowq(const SweepArgs& a, int row_blocks, const SweepArgs& aq, int q_blocks,
+                       hipStream_t s);
 void launch_check_finite(const double* H, int ldh, int n, Ctrl* ctrl, hipStream_t s);
 void launch_zero_lower(double* H, int ldh, int n, hipStream_t s);
 void launch_ctrl_reset(Ctrl* ctrl, hipStream_t s);

@@ -32,18 +32,6 @@ __global__ __launch_bounds__(64) void k_small_eig(SmallTask t0, const SmallTask*
   small_qr<false, MAXM>(T, S, nullptr);
 }
 
-template <int MAXM>
-__global__ __launch_bounds__(64) void k_aed(AedTask t0, const AedTask* tasks) {
-  const AedTask T = tasks ? tasks[blockIdx.x] : t0;
-  constexpr int LD = SmallSmem<MAXM>::LD;
-  __shared__ double S[LD * MAXM];
-  __shared__ double Z[LD * MAXM];
-  __shared__ double vv[MAXM];
-  __shared__ int ibuf[6 * MAXM];
-  __shared__ double stdbuf[7 * MAXM];
-  aed_window<MAXM>(T, S, Z, vv, ibuf, stdbuf);
-}
-
 // One window of eigenvalue reordering per workgroup (one wavefront, window
 // and its accumulated orthogonal factor in LDS).
 template <int MAXM>
@@ -209,6 +197,26 @@ __global__ __launch_bounds__(256, 1) void k_panel_colq(SweepArgs a) {
               t1);
   __shared__ double Xs[2 * WMAX * LDT];
   panel_colq_tiles(ctx_of(a, a.win[w]), t0, t1, a.win[w].tiles_c, Xs);
+}
+
+// Row panels of H and Q products of one time step in one launch (they touch
+// different matrices): blocks [0, nrb) as k_panel_row over a, the rest as
+// k_panel_colq over aq (Q tiles only).
+__global__ __launch_bounds__(256, 1) void k_panel_rowq(SweepArgs a, SweepArgs aq, int nrb) {
+  __shared__ double Xs[2 * WMAX * LDT];
+  const int b = blockIdx.x;
+  if (b < nrb) {
+    const int w = find_window(a, b, true);
+    int t0, t1;
+    block_tiles(b, a.win[w].base_r, a.win[w].tiles_r, a.tpb_r, t0, t1);
+    panel_row_tiles(ctx_of(a, a.win[w]), t0, t1, Xs);
+  } else {
+    const int bq = b - nrb;
+    const int w = find_window(aq, bq, false);
+    int t0, t1;
+    block_tiles(bq, aq.win[w].base_cq, aq.win[w].tiles_c + aq.win[w].tiles_q, aq.tpb_cq, t0, t1);
+    panel_colq_tiles(ctx_of(aq, aq.win[w]), t0, t1, aq.win[w].tiles_c, Xs);
+  }
 }
 
 __global__ __launch_bounds__(256, 1) void k_panel_row_b(const WinB* wins, int nwin) {
@@ -452,16 +460,6 @@ void launch_small_eig(const SmallTask& t, hipStream_t s) {
                        (const SmallTask*)nullptr);
 }
 
-void launch_aed(const AedTask& t, hipStream_t s) {
-  hipLaunchKernelGGL((k_aed<SMALL_Z_MAX>), dim3(1), dim3(64), 0, s, t,
-                     (const AedTask*)nullptr);
-}
-
-void launch_aed_b(const AedTask* tasks, int count, hipStream_t s) {
-  if (count > 0)
-    hipLaunchKernelGGL((k_aed<SMALL_Z_MAX>), dim3(count), dim3(64), 0, s, AedTask{}, tasks);
-}
-
 void launch_reorder(const ReorderTask* tasks, int count, hipStream_t s) {
   if (count > 0)
     hipLaunchKernelGGL((k_reorder<SMALL_Z_MAX>), dim3(count), dim3(64), 0, s, tasks);
@@ -506,6 +504,13 @@ void launch_panel_row(const SweepArgs& a, int blocks, hipStream_t s) {
 
 void launch_panel_colq(const SweepArgs& a, int blocks, hipStream_t s) {
   if (blocks > 0) hipLaunchKernelGGL(k_panel_colq, dim3(blocks), dim3(256), 0, s, a);
+}
+
+void launch_panel_rowq(const SweepArgs& a, int row_blocks, const SweepArgs& aq, int q_blocks,
+                       hipStream_t s) {
+  if (row_blocks + q_blocks > 0)
+    hipLaunchKernelGGL(k_panel_rowq, dim3(row_blocks + q_blocks), dim3(256), 0, s, a, aq,
+                       row_blocks);
 }
 
 void launch_small_tasks(const SmallTask* tasks, int count, int maxm, bool wantz, hipStream_t s) {

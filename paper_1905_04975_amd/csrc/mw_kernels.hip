@@ -1,9 +1,11 @@
 // mw_kernels.hip -- kernels whose Francis iteration runs on a workgroup of
 // four wavefronts, as chains of up to four bulges, one per wavefront
-// (small_iter_mw): the windows of the parallel early-deflation passes and
-// the whole small blocks with Schur vectors.  The one-wavefront parts around
-// the iteration (loading, reorderings, spike reductions) are wavefront 0's,
-// so the solvers' barrier is the wavefront-local one here.
+// (small_iter_mw): the windows of the parallel early-deflation passes, the
+// bottom early-deflation windows and the whole small blocks with Schur
+// vectors.  Their reorderings, spike reductions and V^T products are shared
+// by the four wavefronts too; the one-wavefront parts around them (loading,
+// flips, standardisation) are wavefront 0's, so the solvers' barrier is the
+// wavefront-local one here.
 #define SCHUR_SOLVER_WAVE_SYNC 1
 #include "schur_internal.h"
 #include "device_common.h"
@@ -48,6 +50,31 @@ void launch_small_z(const SmallTask& t, const SmallTask* tasks, int count, int m
     hipLaunchKernelGGL((k_small_z<64>), g, b, 0, s, t, tasks);
   else
     hipLaunchKernelGGL((k_small_z<SMALL_Z_MAX>), g, b, 0, s, t, tasks);
+}
+
+// One bottom early-deflation window per workgroup.
+template <int MAXM>
+__global__ __launch_bounds__(64 * SPLIT_WAVES) void k_aed(AedTask t0, const AedTask* tasks) {
+  const AedTask T = tasks ? tasks[blockIdx.x] : t0;
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  static_assert(7 * MAXM >= SMALL_MW_AUX, "the iteration's scratch lives in stdbuf");
+  __shared__ double S[LD * MAXM];
+  __shared__ double Z[LD * MAXM];
+  __shared__ double vv[MAXM];
+  __shared__ int ibuf[6 * MAXM];
+  __shared__ double stdbuf[7 * MAXM];
+  aed_window<MAXM, SPLIT_WAVES>(T, S, Z, vv, ibuf, stdbuf);
+}
+
+void launch_aed(const AedTask& t, hipStream_t s) {
+  hipLaunchKernelGGL((k_aed<SMALL_Z_MAX>), dim3(1), dim3(64 * SPLIT_WAVES), 0, s, t,
+                     (const AedTask*)nullptr);
+}
+
+void launch_aed_b(const AedTask* tasks, int count, hipStream_t s) {
+  if (count > 0)
+    hipLaunchKernelGGL((k_aed<SMALL_Z_MAX>), dim3(count), dim3(64 * SPLIT_WAVES), 0, s, AedTask{},
+                       tasks);
 }
 
 void launch_split(const SplitTask* tasks, int count, hipStream_t s) {

@@ -1621,159 +1621,6 @@ __device__ void aed_write_vt(double* S, const double* Z, int LD, int nw, double*
   }
 }
 
-template <int MAXM>
-__device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, int* ibuf,
-                           double* stdbuf) {
-  constexpr int LD = SmallSmem<MAXM>::LD;
-  const int lane = threadIdx.x;
-  const int nw = T.nw;
-  const int kwtop = T.kbot - nw + 1;
-  if (nw < 1 || nw > MAXM || kwtop < T.ktop) return;
-  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
-  auto Zx = [&](int r, int c) -> double& { return Z[r + c * LD]; };
-  double* Hw = T.H + kwtop + (size_t)kwtop * T.ldh;
-  const double s = (kwtop > T.ktop) ? T.H[kwtop + (size_t)(kwtop - 1) * T.ldh] : 0.0;
-
-  SmallTask st{};
-  st.A = Hw; st.lda = T.ldh; st.m = nw; st.itmax = T.itmax;
-  small_load<true, MAXM>(st, S, Z);
-  const int info = small_iter<true, MAXM>(st, S, Z);
-  if (info != 0) {   // window not in Schur form: no deflation, no shifts
-    if (lane == 0) { T.ctrl->aed_nd = 0; T.ctrl->aed_nu = 0; }
-    return;
-  }
-
-  // ---- deflation checks from the bottom, undeflatable blocks moved up
-  const int nu = aed_reorder(S, Z, LD, nw, s, ibuf, stdbuf);
-  const int nd = nw - nu;
-  // the deflated blocks are final: standard form now
-  if (nd > 0) aed_std_all(S, Z, LD, nw, nu, stdbuf);
-
-  // ---- eigenvalues: undeflated blocks give the next shifts, deflated ones
-  // are final (written when the caller asks for them)
-  for (int e = lane; e < nw; e += 64) {
-    const bool first = (e + 1 < nw) && Sx(e + 1, e) != 0.0;
-    const bool second = (e >= 1) && Sx(e, e - 1) != 0.0;
-    double wr = Sx(e, e), wi = 0.0;
-    if (first || second) {
-      const int b0 = first ? e : e - 1;
-      double re, im, r1, r2;
-      block_eigs(Sx(b0, b0), Sx(b0, b0 + 1), Sx(b0 + 1, b0), Sx(b0 + 1, b0 + 1), re, im, r1, r2);
-      if (e >= nu) {   // standard form: read off the block as the final S shows it
-        wr = Sx(e, e);
-        wi = sqrt(fabs(Sx(b0, b0 + 1))) * sqrt(fabs(Sx(b0 + 1, b0)));
-        if (second) wi = -wi;
-      } else if (im != 0.0) {
-        wr = re;
-        wi = first ? im : -im;
-      } else {
-        wr = first ? r1 : r2;
-      }
-    }
-    if (e < nu) {
-      T.sr[e] = wr;
-      T.si[e] = wi;
-    } else if (T.wr) {
-      T.wr[e] = wr;
-      T.wi[e] = wi;
-    }
-  }
-  if (lane == 0) { T.ctrl->aed_nd = nd; T.ctrl->aed_nu = nu; }
-  if (nd == 0) return;   // nothing deflated: H stays as it was
-
-  // ---- reflect the spike of the undeflated part onto its first entry
-  double spike = 0.0;
-  if (nu == 1) {
-    spike = s * Zx(0, 0);
-  } else if (nu > 1) {
-    for (int i = lane; i < nu; i += 64) vv[i] = s * Zx(0, i);
-    solver_sync();
-    const double alpha = vv[0];
-    double tau, beta;
-    aed_reflector(alpha, vv, nu, tau, beta);
-    spike = beta;
-    if (tau != 0.0) {
-      for (int c = lane; c < nw; c += 64) {          // rows 0..nu-1, all columns
-        double w = 0.0;
-        for (int i = 0; i < nu; ++i) w += vv[i] * Sx(i, c);
-        w *= tau;
-        for (int i = 0; i < nu; ++i) Sx(i, c) -= vv[i] * w;
-      }
-      solver_sync();
-      for (int q = lane; q < nu + nw; q += 64) {     // columns 0..nu-1 of S rows < nu, and of Z
-        double* base = (q < nu) ? S : Z;
-        const int row = (q < nu) ? q : q - nu;
-        double w = 0.0;
-        for (int j = 0; j < nu; ++j) w += base[row + j * LD] * vv[j];
-        w *= tau;
-        for (int j = 0; j < nu; ++j) base[row + j * LD] -= w * vv[j];
-      }
-      solver_sync();
-    }
-    // ---- Hessenberg form of the undeflated part
-    for (int j = 0; j + 2 < nu; ++j) {
-      const int L = nu - j - 1;                       // rows j+1 .. nu-1
-      const double a0 = Sx(j + 1, j);
-      for (int i = 1 + lane; i < L; i += 64) vv[i] = Sx(j + 1 + i, j);
-      solver_sync();
-      double tj, bj;
-      aed_reflector(a0, vv, L, tj, bj);
-      if (tj == 0.0) continue;
-      if (lane == 0) Sx(j + 1, j) = bj;
-      for (int i = 2 + lane; i <= L; i += 64) Sx(j + i, j) = 0.0;
-      for (int c = j + 1 + lane; c < nw; c += 64) {  // left: rows j+1..nu-1
-        double w = 0.0;
-        for (int i = 0; i < L; ++i) w += vv[i] * Sx(j + 1 + i, c);
-        w *= tj;
-        for (int i = 0; i < L; ++i) Sx(j + 1 + i, c) -= vv[i] * w;
-      }
-      solver_sync();
-      for (int q = lane; q < nu + nw; q += 64) {     // right: columns j+1..nu-1
-        double* base = (q < nu) ? S : Z;
-        const int row = (q < nu) ? q : q - nu;
-        double w = 0.0;
-        for (int i = 0; i < L; ++i) w += base[row + (j + 1 + i) * LD] * vv[i];
-        w *= tj;
-        for (int i = 0; i < L; ++i) base[row + (j + 1 + i) * LD] -= w * vv[i];
-      }
-      solver_sync();
-    }
-  }
-
-  // ---- write back: the window and its spike
-  for (int c = 0; c < nw; ++c)
-    for (int r = lane; r <= c + 1 && r < nw; r += 64) Hw[r + (size_t)c * T.ldh] = Sx(r, c);
-  if (lane == 0 && kwtop > T.ktop) T.H[kwtop + (size_t)(kwtop - 1) * T.ldh] = spike;
-  solver_sync();
-  aed_write_vt(S, Z, LD, nw, T.Ut, T.ldut);
-}
-
-
-// ============================================================================
-// Early deflation on many windows at once.  Windows tile the unreduced
-// blocks of H; each window W (order nw <= SMALL_Z_MAX) is coupled to the
-// rest of its block by one subdiagonal entry above it (st, row 0 of W) and
-// one below it (sb, last column of W).  With W = V T V^T in real Schur form
-// the couplings become st V(0, .) on the left and sb V(nw-1, .) below.
-//   1. blocks whose entries of st V(0, .) are not negligible move to the top
-//      of T (the bottom-window reordering, rows [0, nu));
-//   2. if every one of them has negligible entries in sb V(nw-1, .), the
-//      window splits its block: among the remaining blocks, those with
-//      negligible sb V(nw-1, .) entries stay on top (free: deflated), the
-//      others move to the bottom (rows [bs, nw)); this is the same
-//      reordering on the flipped block J T^T J, whose spike is the last row
-//      of V;
-//   3. each coupled part is brought back to Hessenberg form with its
-//      coupling reflected onto one entry (the upper part as after a bottom
-//      window, the lower one flipped), so that H stays Hessenberg with zero
-//      subdiagonal entries around the free part;
-//   4. the window and V^T go out; the caller applies V to the panels and to
-//      Q and scales the coupling entries by the reflected first entries.
-// A window that does not split is left untouched (V = I).  Every dropped
-// entry is below the early-deflation threshold, so each pass is a backward
-// stable orthogonal similarity, as a bottom window is (paper Sec. 3.2, AED).
-// ============================================================================
-
 // Anti-transpose of the trailing block T = S(lo:nw, lo:nw) in place
 // (T(r, c) <-> T(d-1-c, d-1-r), d = nw - lo), with the columns lo..nw-1 of
 // the rows above it (S(0:lo, .)) and of Z (all nw rows) put in reverse
@@ -1901,6 +1748,123 @@ __device__ double spike_reduce(double* S, double* Z, int LD, int m, int ncols, i
   sync();
   return beta;
 }
+
+// K > 1: every wavefront of a workgroup of K calls it: the iteration, the
+// reordering, the spike reduction and the write of V^T are the K
+// wavefronts', the standardisation and the eigenvalue output wavefront 0's
+// (the solvers' barrier must then be the wavefront-local one).
+template <int MAXM, int K = 1>
+__device__ void aed_window(const AedTask& T, double* S, double* Z, double* vv, int* ibuf,
+                           double* stdbuf) {
+  constexpr int LD = SmallSmem<MAXM>::LD;
+  const int lane = threadIdx.x & 63;
+  const int w = K > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
+  const int nw = T.nw;
+  const int kwtop = T.kbot - nw + 1;
+  if (nw < 1 || nw > MAXM || kwtop < T.ktop) return;
+  auto Sx = [&](int r, int c) -> double& { return S[r + c * LD]; };
+  auto sync = [&]() {
+    if constexpr (K > 1) __syncthreads();
+    else solver_sync();
+  };
+  double* Hw = T.H + kwtop + (size_t)kwtop * T.ldh;
+  const double s = (kwtop > T.ktop) ? T.H[kwtop + (size_t)(kwtop - 1) * T.ldh] : 0.0;
+
+  SmallTask st{};
+  st.A = Hw; st.lda = T.ldh; st.m = nw; st.itmax = T.itmax;
+  int info;
+  if constexpr (K > 1) {
+    if (w == 0) small_load<true, MAXM>(st, S, Z);
+    __syncthreads();
+    info = small_iter_mw<MAXM, K>(st, S, Z, stdbuf);   // stdbuf is free until the reordering
+  } else {
+    small_load<true, MAXM>(st, S, Z);
+    info = small_iter<true, MAXM>(st, S, Z);
+  }
+  if (info != 0) {   // window not in Schur form: no deflation, no shifts
+    if (threadIdx.x == 0) { T.ctrl->aed_nd = 0; T.ctrl->aed_nu = 0; }
+    return;
+  }
+
+  // ---- deflation checks from the bottom, undeflatable blocks moved up
+  const int nu = aed_reorder<K>(S, Z, LD, nw, s, ibuf, stdbuf);
+  const int nd = nw - nu;
+  if (w == 0) {
+    // the deflated blocks are final: standard form now
+    if (nd > 0) aed_std_all(S, Z, LD, nw, nu, stdbuf);
+
+    // ---- eigenvalues: undeflated blocks give the next shifts, deflated
+    // ones are final (written when the caller asks for them)
+    for (int e = lane; e < nw; e += 64) {
+      const bool first = (e + 1 < nw) && Sx(e + 1, e) != 0.0;
+      const bool second = (e >= 1) && Sx(e, e - 1) != 0.0;
+      double wr = Sx(e, e), wi = 0.0;
+      if (first || second) {
+        const int b0 = first ? e : e - 1;
+        double re, im, r1, r2;
+        block_eigs(Sx(b0, b0), Sx(b0, b0 + 1), Sx(b0 + 1, b0), Sx(b0 + 1, b0 + 1), re, im, r1, r2);
+        if (e >= nu) {   // standard form: read off the block as the final S shows it
+          wr = Sx(e, e);
+          wi = sqrt(fabs(Sx(b0, b0 + 1))) * sqrt(fabs(Sx(b0 + 1, b0)));
+          if (second) wi = -wi;
+        } else if (im != 0.0) {
+          wr = re;
+          wi = first ? im : -im;
+        } else {
+          wr = first ? r1 : r2;
+        }
+      }
+      if (e < nu) {
+        T.sr[e] = wr;
+        T.si[e] = wi;
+      } else if (T.wr) {
+        T.wr[e] = wr;
+        T.wi[e] = wi;
+      }
+    }
+    if (lane == 0) { T.ctrl->aed_nd = nd; T.ctrl->aed_nu = nu; }
+  }
+  if (nd == 0) return;   // nothing deflated: H stays as it was
+
+  // ---- the spike s V(0, 0:nu) reflected onto its first entry and the
+  // undeflated part back to Hessenberg form (the reflector of V(0, .) is
+  // that of s V(0, .), whose first entry is s times V(0, .)'s)
+  const double spike = nu >= 1 ? s * spike_reduce<K>(S, Z, LD, nu, nw, 0, nw, 0, vv) : 0.0;
+  sync();
+
+  // ---- write back: the window and its spike
+  for (int c = w; c < nw; c += K)
+    for (int r = lane; r <= c + 1 && r < nw; r += 64) Hw[r + (size_t)c * T.ldh] = Sx(r, c);
+  if (threadIdx.x == 0 && kwtop > T.ktop) T.H[kwtop + (size_t)(kwtop - 1) * T.ldh] = spike;
+  sync();
+  aed_write_vt<K>(S, Z, LD, nw, T.Ut, T.ldut);
+}
+
+
+// ============================================================================
+// Early deflation on many windows at once.  Windows tile the unreduced
+// blocks of H; each window W (order nw <= SMALL_Z_MAX) is coupled to the
+// rest of its block by one subdiagonal entry above it (st, row 0 of W) and
+// one below it (sb, last column of W).  With W = V T V^T in real Schur form
+// the couplings become st V(0, .) on the left and sb V(nw-1, .) below.
+//   1. blocks whose entries of st V(0, .) are not negligible move to the top
+//      of T (the bottom-window reordering, rows [0, nu));
+//   2. if every one of them has negligible entries in sb V(nw-1, .), the
+//      window splits its block: among the remaining blocks, those with
+//      negligible sb V(nw-1, .) entries stay on top (free: deflated), the
+//      others move to the bottom (rows [bs, nw)); this is the same
+//      reordering on the flipped block J T^T J, whose spike is the last row
+//      of V;
+//   3. each coupled part is brought back to Hessenberg form with its
+//      coupling reflected onto one entry (the upper part as after a bottom
+//      window, the lower one flipped), so that H stays Hessenberg with zero
+//      subdiagonal entries around the free part;
+//   4. the window and V^T go out; the caller applies V to the panels and to
+//      Q and scales the coupling entries by the reflected first entries.
+// A window that does not split is left untouched (V = I).  Every dropped
+// entry is below the early-deflation threshold, so each pass is a backward
+// stable orthogonal similarity, as a bottom window is (paper Sec. 3.2, AED).
+// ============================================================================
 
 template <int MAXM, int K = 1>
 __device__ void split_window(const SplitTask& T, double* S, double* Z, double* vv, int* ibuf,

@@ -244,6 +244,120 @@ __device__ void chase_window_t(const WinCtx& d, double* W, double* R) {
       Ut[r + (size_t)c * UPAD] = (r < ws && c < ws) ? Wx(c, r) : 0.0;
     }
   }
+  // ---- one first-order re-orthogonalisation, U^T <- (I - E / 2) U^T with
+  // E = U^T U - I, before U reaches the panels and Q: U collected every
+  // reflector of the window, and its departure from orthogonality would
+  // otherwise add up in Q over the sweep's windows.  Both products as FP64
+  // MFMA 16 x 16 tiles over the workgroup's wavefronts.  E is symmetric:
+  // its upper tiles from U in LDS, then E (both triangles) replaces U in
+  // LDS (U^T is in the slot).  The new U^T by column blocks of 16 in two
+  // halves of row tiles, one wavefront per half: a half's tiles read only
+  // its column block of the slot (held in registers, read by every half
+  // before any writes).
+  {
+    typedef double cw_d4 __attribute__((ext_vector_type(4)));
+    constexpr int NW = NT / 64;                     // wavefronts
+    constexpr int NTM = WMAX / 16;                  // tiles per side at most
+    constexpr int TPW = (NTM * (NTM + 1) / 2 + NW - 1) / NW;   // upper tiles per wavefront
+    const int wv = tid >> 6, lane = tid & 63, kr = lane >> 4, kc = lane & 15;
+    const int nt = (ws + 15) >> 4;
+    const int npair = nt * (nt + 1) / 2;
+    auto pair_of = [&](int q, int& I, int& J) {   // q = J (J + 1) / 2 + I, I <= J
+      J = 0;
+      while ((J + 1) * (J + 2) / 2 <= q) ++J;
+      I = q - J * (J + 1) / 2;
+    };
+    // the wavefront's tiles side by side in each k step: independent
+    // accumulation chains keep the MFMA pipeline busy
+    cw_d4 acc[TPW];
+    int ia[TPW], jb[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+      acc[u] = cw_d4{0.0, 0.0, 0.0, 0.0};
+      const int q = wv + NW * u;
+      int I = 0, J = 0;
+      if (q < npair) pair_of(q, I, J);
+      ia[u] = q < npair ? 16 * I + kc : ws;   // out of the window: zero operands
+      jb[u] = q < npair ? 16 * J + kc : ws;
+    }
+#pragma unroll 4
+    for (int s4 = 0; s4 < WMAX / 4; ++s4) {
+      const int k = 4 * s4 + kr;
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        if (wv + NW * u >= npair) continue;   // uniform over the wavefront
+        const double a = (k < ws && ia[u] < ws) ? Wx(k, ia[u]) : 0.0;   // A(i, k) = U(k, i)
+        const double b = (k < ws && jb[u] < ws) ? Wx(k, jb[u]) : 0.0;   // B(k, j) = U(k, j)
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+      }
+    }
+    __syncthreads();   // every read of U in LDS is done, and U^T is in the slot
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+      const int q = wv + NW * u;
+      if (q >= npair) continue;
+      int I, J;
+      pair_of(q, I, J);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = 16 * I + 4 * e + kr, col = 16 * J + kc;
+        if (row < ws && col < ws) {
+          const double v = acc[u][e] - (row == col ? 1.0 : 0.0);
+          Wx(row, col) = v;
+          Wx(col, row) = v;
+        }
+      }
+    }
+    __syncthreads();   // E in LDS
+    // jobs: (column block R, half h of its row tiles), h = 0: tiles 0..3,
+    // h = 1: tiles 4..7; each wavefront owns whole jobs, and a job reads
+    // only its own column block of the slot (rows of other jobs of the same
+    // block are written by another wavefront but never read by this one:
+    // bv holds the block's column, read before the barrier below)
+    const int nj = 2 * nt;
+    for (int jb0 = 0; jb0 < 2 * NTM; jb0 += NW) {
+      const int job = jb0 + wv;
+      const bool act = job < nj;
+      const int R = act ? job >> 1 : 0, h = job & 1;
+      const int rb = 16 * R + kc;
+      // the block's column of U^T in registers, every load in flight at once:
+      // bv[s] = U^T(4 s + kr, R0 + kc), the B operand of step s and, for
+      // s = 4 J + e, the old value of this lane's result entry (e) of tile J
+      double bv[WMAX / 4];
+#pragma unroll
+      for (int s4 = 0; s4 < WMAX / 4; ++s4) {
+        const int k = 4 * s4 + kr;
+        bv[s4] = (act && k < ws && rb < ws) ? Ut[k + (size_t)rb * UPAD] : 0.0;
+      }
+      __syncthreads();   // every job has read its column before any writes
+      if (act && 4 * h < nt) {
+        // the half's four row tiles, their accumulation chains interleaved
+        cw_d4 c[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) c[g] = cw_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < WMAX / 4; ++s4) {
+          const int k = 4 * s4 + kr;
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            const int ja = 16 * (4 * h + g) + kc;
+            const double av = (k < ws && ja < ws) ? Wx(ja, k) : 0.0;   // E(16 J + i, k)
+            c[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[s4], c[g], 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int J = 4 * h + g;
+            const int jr = 16 * J + 4 * e + kr;
+            const double old = h ? bv[16 + 4 * g + e] : bv[4 * g + e];
+            if (jr < ws && rb < ws) Ut[jr + (size_t)rb * UPAD] = old - 0.5 * c[g][e];
+          }
+        }
+      }
+    }
+  }
 }
 
 __device__ void chase_window(const WinCtx& d) {

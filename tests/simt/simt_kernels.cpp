@@ -18,7 +18,7 @@
 //     in : int n, a, nw, above, below; double H[n*n]
 //     out: int split, nu, nf, nb; double ftop, fbot; double H[n*n];
 //          double Ut[128*128]
-//   simt_kernels aed in.bin out.bin
+//   simt_kernels aed|aed4 in.bin out.bin   (1 or 4 wavefronts)
 //     in : int n, ktop, kbot, nw; double H[n*n]
 //     out: int nd, nu; double H[n*n]; double Ut[128*128]; double sr[96], si[96];
 //          double wr[n], wi[n]
@@ -201,7 +201,7 @@ int main(int argc, char** argv) {
     fclose(g);
     return 0;
   }
-  if (mode == "aed") {
+  if (mode == "aed" || mode == "aed4") {
     constexpr int MAXM = SMALL_Z_MAX;
     constexpr int LD = SmallSmem<MAXM>::LD;
     int hdr[4];
@@ -225,9 +225,14 @@ int main(int argc, char** argv) {
     const int kwtop = T.kbot - T.nw + 1;
     T.wr = wr.data() + kwtop; T.wi = wi.data() + kwtop;
     T.ctrl = &ctrl; T.itmax = 30;
-    run_workgroup(64, 0, [T] {
-      aed_window<MAXM>(T, S.data(), Z.data(), vv.data(), ib.data(), sb.data());
-    });
+    if (mode == "aed")
+      run_workgroup(64, 0, [T] {
+        aed_window<MAXM>(T, S.data(), Z.data(), vv.data(), ib.data(), sb.data());
+      });
+    else
+      run_workgroup(256, 0, [T] {
+        aed_window<MAXM, 4>(T, S.data(), Z.data(), vv.data(), ib.data(), sb.data());
+      });
     FILE* g = fopen(argv[3], "wb");
     const int o[2] = {ctrl.aed_nd, ctrl.aed_nu};
     fwrite(o, sizeof(int), 2, g);

@@ -152,6 +152,23 @@ def test_bitwise_repeatable(gpu_lib):
     assert np.array_equal(a[2], b[2])
 
 
+@pytest.mark.parametrize("n,ns,nb,seed", [(1500, 64, 8, 21), (2600, 128, 16, 22)])
+def test_one_stream_panels_equal_two_streams(gpu_lib, n, ns, nb, seed):
+    """With every kernel on one stream the panel products of a time step
+    are two launches (rows of H with the top rows of Q, then columns of H
+    with the rest of Q) instead of three on two streams: the same tiles,
+    so the same result bit for bit."""
+    print("case one stream n=%d ns=%d" % (n, ns), flush=True)
+    H = inputs.hessenberg_normal(n, seed)
+    opts = dict(ns=ns, nb=nb, aed_window=-1, split_window=-1)
+    a = _run(gpu_lib, H, **opts)
+    b = _run(gpu_lib, H, flags=gpu_lib.FLAG_ONE_STREAM, **opts)
+    assert a[3] == 0 and b[3] == 0
+    assert a[4]["sweeps"] > 0 and a[4]["sweeps"] == b[4]["sweeps"]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    _check_schur(H, b[0], b[1], b[2], b[3])
+
+
 def test_special_inputs(gpu_lib):
     print("case special inputs", flush=True)
     # upper triangular: already in Schur form

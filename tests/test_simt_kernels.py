@@ -124,9 +124,9 @@ def test_chase_sweep_equals_sequential_double_shift_steps(driver, tmp_path, n, k
     assert not np.tril(H, -2).any()
 
 
-def _aed(driver, tmp_path, H, ktop, kbot, nw):
+def _aed(driver, tmp_path, H, ktop, kbot, nw, waves=1):
     n = H.shape[0]
-    raw = _call(driver, "aed", [np.array([n, ktop, kbot, nw], dtype=np.int32),
+    raw = _call(driver, "aed" if waves == 1 else "aed4", [np.array([n, ktop, kbot, nw], dtype=np.int32),
                                 np.asfortranarray(H).ravel(order="F")], tmp_path)
     nd, nu = np.frombuffer(raw[:8], dtype=np.int32)
     x = np.frombuffer(raw[8:], dtype=np.float64)
@@ -170,8 +170,9 @@ def _graded(n, seed, m, lo):
     return H
 
 
+@pytest.mark.parametrize("waves", [1, 4])
 @pytest.mark.parametrize("case", ["raw400", "conv256", "conv200", "graded", "all", "top"])
-def test_aed_window(driver, tmp_path, case):
+def test_aed_window(driver, tmp_path, case, waves):
     if case == "raw400":
         H, ktop, nw = inputs.hessenberg_normal(400, 5), 0, 48
     elif case == "conv256":
@@ -188,7 +189,7 @@ def test_aed_window(driver, tmp_path, case):
     n = H.shape[0]
     kbot = n - 1
     kw = kbot - nw + 1
-    nd, nu, H2, Vfull, sr, si, wr, wi = _aed(driver, tmp_path, H, ktop, kbot, nw)
+    nd, nu, H2, Vfull, sr, si, wr, wi = _aed(driver, tmp_path, H, ktop, kbot, nw, waves)
     assert nd + nu == nw and nd >= 0
     W = H[kw:, kw:]
     if nd == 0:
