@@ -90,7 +90,21 @@ def test_served_mix_equals_alone(gpu_lib):
             assert np.array_equal(S, S2.cpu().numpy()) and np.array_equal(Q, Q2.cpu().numpy())
             assert np.array_equal(w, w2.cpu().numpy())
         else:
-            assert checks.match_eigs(w, w2.cpu().numpy()).max() <= 1e-10 * np.linalg.norm(H)
+            # a different engine (the persistent kernel) from the server's
+            # rounds: the two spectra agree within each eigenvalue's
+            # condition number times the backward error, as any two
+            # backward-stable solves do
+            _eigs_agree(H, w, w2.cpu().numpy())
+
+
+def _eigs_agree(H, a, b):
+    """Two eigenvalue multisets of H from two backward-stable solves: every
+    matched pair within 100 n u kappa_i ||H||_F (kappa_i the eigenvalue's
+    condition number)."""
+    wref, kappa = checks.eig_condition(np.triu(H, -1))
+    k = kappa[np.argmin(np.abs(np.asarray(a)[:, None] - wref[None, :]), axis=1)]
+    d = checks.match_eigs(a, b)
+    assert np.all(d <= checks.kappa_tolerance(H, a, k, factor=100.0)), d.max()
 
 
 def test_budget_forces_queueing(gpu_lib):
