@@ -94,6 +94,7 @@ struct ShiftB {
 void launch_small_z(const SmallTask& t, const SmallTask* tasks, int count, int maxm,
                     hipStream_t s);
 void launch_small_eig(const SmallTask& t, hipStream_t s);
+void launch_small_eig_b(const SmallTask* tasks, int count, int maxm, hipStream_t s);
 void launch_aed(const AedTask& t, hipStream_t s);
 void launch_aed_b(const AedTask* tasks, int count, hipStream_t s);
 void launch_split(const SplitTask* tasks, int count, hipStream_t s);

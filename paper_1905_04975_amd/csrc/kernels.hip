@@ -23,15 +23,6 @@
 
 namespace schur {
 
-template <int MAXM>
-__global__ __launch_bounds__(64) void k_small_eig(SmallTask t0, const SmallTask* tasks) {
-  constexpr int LD = SmallSmem<MAXM>::LD;
-  __shared__ double S[LD * MAXM];
-  const SmallTask T = tasks ? tasks[blockIdx.x] : t0;
-  if (T.m <= 0 || T.m > MAXM) return;
-  small_qr<false, MAXM>(T, S, nullptr);
-}
-
 // One window of eigenvalue reordering per workgroup (one wavefront, window
 // and its accumulated orthogonal factor in LDS).
 template <int MAXM>
@@ -450,16 +441,6 @@ __global__ void k_std_blocks(double* H, int ldh, int n, const int* list, const i
 // ============================================================================
 // Host-side launch wrappers
 // ============================================================================
-void launch_small_eig(const SmallTask& t, hipStream_t s) {
-  if (t.m <= 32)
-    hipLaunchKernelGGL((k_small_eig<32>), dim3(1), dim3(64), 0, s, t, (const SmallTask*)nullptr);
-  else if (t.m <= 64)
-    hipLaunchKernelGGL((k_small_eig<64>), dim3(1), dim3(64), 0, s, t, (const SmallTask*)nullptr);
-  else
-    hipLaunchKernelGGL((k_small_eig<SMALL_EIG_MAX>), dim3(1), dim3(64), 0, s, t,
-                       (const SmallTask*)nullptr);
-}
-
 void launch_reorder(const ReorderTask* tasks, int count, hipStream_t s) {
   if (count > 0)
     hipLaunchKernelGGL((k_reorder<SMALL_Z_MAX>), dim3(count), dim3(64), 0, s, tasks);
@@ -518,12 +499,8 @@ void launch_small_tasks(const SmallTask* tasks, int count, int maxm, bool wantz,
   SmallTask none{};
   if (wantz) {
     launch_small_z(none, tasks, count, maxm, s);
-  } else if (maxm <= 32) {
-    hipLaunchKernelGGL((k_small_eig<32>), dim3(count), dim3(64), 0, s, none, tasks);
-  } else if (maxm <= 64) {
-    hipLaunchKernelGGL((k_small_eig<64>), dim3(count), dim3(64), 0, s, none, tasks);
   } else {
-    hipLaunchKernelGGL((k_small_eig<SMALL_EIG_MAX>), dim3(count), dim3(64), 0, s, none, tasks);
+    launch_small_eig_b(tasks, count, maxm, s);
   }
 }
 

@@ -272,8 +272,9 @@ __device__ void chase_reg2(double* S, double* Zs, int m_in, int l_in, int i_in, 
 // bulge.  NS = 1 for m <= 64, 2 for 64 < m <= 128.  Updates run over every
 // column and row of the block without branches, as in chase_reg (entries
 // outside a bulge's reach hold exact zeros and are rewritten as zeros);
-// lanes past the block store to the padding row MAXM.
-template <int NS, int MAXM>
+// lanes past the block store to the padding row MAXM.  WZ = false: no Schur
+// vectors (Zs unused), for eigenvalues only.
+template <int NS, int MAXM, bool WZ = true>
 __device__ void chase_multi(double* S, double* Zs, int m_in, int l_in, int i_in, int kb_in,
                             double s, double t) {
   static_assert((MAXM & 1) == 0, "row MAXM of the LDS block is padding");
@@ -320,13 +321,15 @@ __device__ void chase_multi(double* S, double* Zs, int m_in, int l_in, int i_in,
         a1[k] = Sx(p, cc[k]);
         a2[k] = Sx(p + 1, cc[k]);
         a3[k] = Sx(p2, cc[k]);
-        zc[k] = Zx(cc[k], p2);
+        if constexpr (WZ) zc[k] = Zx(cc[k], p2);
       }
       if (p == l) {
+        if constexpr (WZ) {
 #pragma unroll
-        for (int k = 0; k < NS; ++k) {
-          zA[k] = Zx(cc[k], l);
-          zB[k] = Zx(cc[k], l + 1);
+          for (int k = 0; k < NS; ++k) {
+            zA[k] = Zx(cc[k], l);
+            zB[k] = Zx(cc[k], l + 1);
+          }
         }
         double x, y, z;
         first_column(Sx(l, l), Sx(l, l + 1), Sx(l + 1, l), Sx(l + 1, l + 1), Sx(l + 2, l + 1), s,
@@ -369,12 +372,14 @@ __device__ void chase_multi(double* S, double* Zs, int m_in, int l_in, int i_in,
         Sx(cs[k], p + 1) = e2;
         Sx(cs[k], p2) = three ? s3 - tv3 * wr : e2;
         o[k] = e1;
-        const double f2 = zB[k] - tv2 * wz, f3 = z3 - tv3 * wz;
-        Zx(cs[k], p) = zA[k] - h.tau * wz;
-        Zx(cs[k], p + 1) = f2;
-        Zx(cs[k], p2) = three ? f3 : f2;
-        zA[k] = f2;
-        zB[k] = f3;
+        if constexpr (WZ) {
+          const double f2 = zB[k] - tv2 * wz, f3 = z3 - tv3 * wz;
+          Zx(cs[k], p) = zA[k] - h.tau * wz;
+          Zx(cs[k], p + 1) = f2;
+          Zx(cs[k], p2) = three ? f3 : f2;
+          zA[k] = f2;
+          zB[k] = f3;
+        }
       }
       // the next position's reflector from this wavefront's own results
       // (column p, rows p+1..p+3, which no other bulge touches before it is
@@ -756,8 +761,10 @@ __device__ void trailing_shifts(const double* S, int i, int nsh, double* aux) {
 // tenth step without deflation.  Needs the wavefront-local solver_sync
 // (SCHUR_SOLVER_WAVE_SYNC): the one-wavefront parts run on wavefront 0 while
 // the others wait at the workgroup barrier.  aux: SMALL_MW_AUX doubles of
-// LDS.  Every wavefront returns the same info.
-template <int MAXM, int K>
+// LDS.  Every wavefront returns the same info.  WZ = false: eigenvalues only
+// (no Schur vectors, converged 2x2 blocks not standardised in place, single
+// bulges as chains of one).
+template <int MAXM, int K, bool WZ = true>
 __device__ int small_iter_mw(const SmallTask& T, double* S, double* Zs, double* aux) {
 #ifndef SCHUR_SOLVER_WAVE_SYNC
   static_assert(K < 0, "the multi-wavefront iteration needs the wavefront-local solver_sync");
@@ -807,7 +814,7 @@ __device__ int small_iter_mw(const SmallTask& T, double* S, double* Zs, double* 
     if (l == i - 1) {
       const Std2 o = standardize2(Sx(i - 1, i - 1), Sx(i - 1, i), Sx(i, i - 1), Sx(i, i));
       __syncthreads();
-      if (w == 0) {
+      if (WZ && w == 0) {
         if (!(o.cs == 1.0 && o.sn == 0.0)) {
           for (int c = i + 1 + lane; c < m; c += 64) {
             const double x = Sx(i - 1, c), y = Sx(i, c);
@@ -834,6 +841,10 @@ __device__ int small_iter_mw(const SmallTask& T, double* S, double* Zs, double* 
           }
         }
       }
+      if (!WZ && w == 0 && lane == 0 && T.wr) {
+        T.wr[i - 1] = o.wr1; T.wi[i - 1] = o.wi1;
+        T.wr[i] = o.wr2;     T.wi[i] = o.wi2;
+      }
       __syncthreads();
       i -= 2; its = 0;
       continue;
@@ -854,11 +865,11 @@ __device__ int small_iter_mw(const SmallTask& T, double* S, double* Zs, double* 
       if (w < kb) { s = sh[2 * w]; t = sh[2 * w + 1]; }
     }
     if (kb >= 2) {
-      if (m <= 64) chase_multi<1, MAXM>(S, Zs, m, l, i, kb, s, t);
-      else         chase_multi<2, MAXM>(S, Zs, m, l, i, kb, s, t);
+      if (m <= 64) chase_multi<1, MAXM, WZ>(S, Zs, m, l, i, kb, s, t);
+      else         chase_multi<2, MAXM, WZ>(S, Zs, m, l, i, kb, s, t);
       continue;
     }
-    if (w == 0) {
+    if (WZ ? w == 0 : true) {
       if (its % 10 == 0) {   // ad-hoc pair every 10 steps without deflation
         double wv, e;
         if ((its / 10) % 2 == 1) {
@@ -875,12 +886,20 @@ __device__ int small_iter_mw(const SmallTask& T, double* S, double* Zs, double* 
         s = a + d;
         t = a * d - b * c;
       }
-      double x, y, z;
-      first_column(Sx(l, l), Sx(l, l + 1), Sx(l + 1, l), Sx(l + 1, l + 1), Sx(l + 2, l + 1), s, t,
-                   x, y, z);
-      solver_sync();   // every lane has read the corner before the first left update
-      if (m <= 64) chase_reg<MAXM>(S, Zs, m, l, i, x, y, z);
-      else         chase_reg2<MAXM>(S, Zs, m, l, i, x, y, z);
+      if constexpr (WZ) {
+        double x, y, z;
+        first_column(Sx(l, l), Sx(l, l + 1), Sx(l + 1, l), Sx(l + 1, l + 1), Sx(l + 2, l + 1), s,
+                     t, x, y, z);
+        solver_sync();   // every lane has read the corner before the first left update
+        if (m <= 64) chase_reg<MAXM>(S, Zs, m, l, i, x, y, z);
+        else         chase_reg2<MAXM>(S, Zs, m, l, i, x, y, z);
+      }
+    }
+    if constexpr (!WZ) {   // one bulge on wavefront 0, the others through the barriers
+      __syncthreads();     // every wavefront has read the shift inputs
+      if (m <= 64) chase_multi<1, MAXM, false>(S, Zs, m, l, i, 1, s, t);
+      else         chase_multi<2, MAXM, false>(S, Zs, m, l, i, 1, s, t);
+      continue;
     }
     __syncthreads();
   }
@@ -915,11 +934,10 @@ __device__ void small_qr(const SmallTask& T, double* S, double* Zs, double* aux 
   auto Zx = [&](int r, int c) -> double& { return Zs[r + c * LD]; };
   int info;
   if constexpr (K > 1) {
-    static_assert(WANTZ, "the multi-wavefront iteration keeps the Schur vectors");
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (w == 0) small_load<WANTZ, MAXM>(T, S, Zs);
     __syncthreads();
-    info = small_iter_mw<MAXM, K>(T, S, Zs, aux);
+    info = small_iter_mw<MAXM, K, WANTZ>(T, S, Zs, aux);
     if (w != 0) return;
   } else {
     small_load<WANTZ, MAXM>(T, S, Zs);

@@ -11,6 +11,9 @@
 //   simt_kernels small|small2|small4 in.bin out.bin   (1, 2 or 4 wavefronts)
 //     in : int m; double A[m*m] (upper Hessenberg, m <= 96)
 //     out: int info; double S[m*m]; double Z[m*m]; double wr[m], wi[m]
+//   simt_kernels eig|eig4 in.bin out.bin   (eigenvalues only, 1 or 4 wavefronts)
+//     in : int m; double A[m*m] (upper Hessenberg, m <= 128)
+//     out: int info; double wr[m], wi[m]
 //   simt_kernels tiny in.bin out.bin   (eigenvalues of a block of order <= 8)
 //     in : int n; double A[n*n] (upper Hessenberg)
 //     out: int info; double wr[n], wi[n]
@@ -308,6 +311,35 @@ int main(int argc, char** argv) {
     fwrite(&info, sizeof(int), 1, g);
     fwrite(A.data(), sizeof(double), A.size(), g);
     fwrite(Zo.data(), sizeof(double), Zo.size(), g);
+    fwrite(wr.data(), sizeof(double), m, g);
+    fwrite(wi.data(), sizeof(double), m, g);
+    fclose(g);
+    return 0;
+  }
+  if (mode == "eig" || mode == "eig4") {
+    // in : int m; double A[m*m] (upper Hessenberg, m <= 128)
+    // out: int info; double wr[m], wi[m]
+    constexpr int MAXM = SMALL_EIG_MAX;
+    constexpr int LD = SmallSmem<MAXM>::LD;
+    int hdr[1];
+    if (!rd(f, hdr, 1)) return 2;
+    const int m = hdr[0];
+    std::vector<double> A((size_t)m * m), wr(m, NAN), wi(m, NAN);
+    if (!rd(f, A.data(), A.size())) return 2;
+    fclose(f);
+    static std::vector<double> S(LD * MAXM), aux(SMALL_MW_AUX);
+    for (auto* v : {&S, &aux})
+      for (double& x : *v) x = NAN;
+    int info = -99;
+    SmallTask T{};
+    T.A = A.data(); T.lda = m; T.m = m;
+    T.wr = wr.data(); T.wi = wi.data(); T.info = &info; T.itmax = 0;
+    if (mode == "eig")
+      run_workgroup(64, 0, [T] { small_qr<false, MAXM>(T, S.data(), nullptr); });
+    else
+      run_workgroup(256, 0, [T] { small_qr<false, MAXM, 4>(T, S.data(), nullptr, aux.data()); });
+    FILE* g = fopen(argv[3], "wb");
+    fwrite(&info, sizeof(int), 1, g);
     fwrite(wr.data(), sizeof(double), m, g);
     fwrite(wi.data(), sizeof(double), m, g);
     fclose(g);

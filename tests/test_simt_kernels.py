@@ -281,6 +281,38 @@ def test_small_block_solver(driver, tmp_path, m, seed, kind, waves):
     assert np.all(cost[r, c] <= checks.kappa_tolerance(A, lam_o[c], k[c], factor=200.0))
 
 
+@pytest.mark.parametrize("waves", [1, 4])
+@pytest.mark.parametrize("m,seed,kind", [(7, 1, "normal"), (40, 2, "normal"), (64, 3, "prescribed"),
+                                         (100, 4, "normal"), (128, 5, "normal"),
+                                         (128, 6, "prescribed"), (90, 7, "graded")])
+def test_eigenvalue_solver(driver, tmp_path, m, seed, kind, waves):
+    """The eigenvalues-only solver of a sweep's shift problem (orders up to
+    128), one wavefront or bulge chains on four: every eigenvalue within a
+    condition-weighted bound of numpy's (or of the known spectrum)."""
+    from tests import checks
+
+    exact = None
+    if kind == "prescribed":
+        A, exact = inputs.prescribed(m, seed)
+    elif kind == "graded":
+        A = _graded(m, seed, m // 2, -10)
+    else:
+        A = inputs.hessenberg_normal(m, seed)
+    raw = _call(driver, "eig" if waves == 1 else "eig4",
+                [np.array([m], dtype=np.int32), np.asfortranarray(A).ravel(order="F")], tmp_path)
+    info = int(np.frombuffer(raw[:4], dtype=np.int32)[0])
+    x = np.frombuffer(raw[4:], dtype=np.float64)
+    lam = x[:m] + 1j * x[m:2 * m]
+    assert info == 0 and not np.isnan(lam).any()
+    ref = np.linalg.eigvals(A) if exact is None else np.asarray(exact)
+    w, kappa = checks.eig_condition(np.triu(A, -1))
+    kap = kappa[np.argmin(np.abs(ref[:, None] - w[None, :]), axis=1)]
+    from scipy.optimize import linear_sum_assignment
+    cost = np.abs(lam[:, None] - ref[None, :])
+    r, c = linear_sum_assignment(cost)
+    assert np.all(cost[r, c] <= checks.kappa_tolerance(A, ref[c], kap[c], factor=200.0))
+
+
 @pytest.mark.parametrize("n,seed,kind", [(1, 1, "normal"), (2, 2, "normal"), (3, 3, "normal"),
                                          (4, 4, "normal"), (5, 5, "prescribed"), (8, 6, "normal"),
                                          (8, 7, "prescribed"), (8, 8, "graded"), (6, 9, "zero_sub"),
