@@ -63,6 +63,8 @@ def parse():
                     help="shifts per sweep of the forced-sweep measurement (0: skip it)")
     ap.add_argument("--panel-tile", type=int, default=0,
                     help="panel tiles per workgroup of the sweep products (0: table/cost model)")
+    ap.add_argument("--sweep-mode", choices=("both", "one"), default="both",
+                    help="forced sweeps: both stream modes, or only the one-stream run (profiling)")
     ap.add_argument("--sweep-count", type=int, default=3,
                     help="sweeps timed by the forced-sweep measurement")
     ap.add_argument("--workload",
@@ -419,15 +421,22 @@ def sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream):
         return info, e0.elapsed_time(e1) / 1e3, st
 
     info1, sec1, st1 = run(schur.FLAG_ONE_STREAM)
-    info, sec, st = run(0)
+    if args.sweep_mode == "one":
+        info, sec, st = info1, sec1, st1
+    else:
+        info, sec, st = run(0)
     nsw = max(1, st1["sweeps"])
 
-    def gl(name, ms, launches, flops):
+    def gl(name, key, ms, launches, flops):
         avg = ms / max(1, launches)
         ach = flops / max(1, launches) / max(avg * 1e-3, 1e-30) / 1e12
-        return {"kernel": name, "bound": "mfma", "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS, "avg_launch_ms": avg,
-                "launches": launches, "flops_per_launch": flops / max(1, launches)}
+        out = {"kernel": name, "bound": "mfma", "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS,
+               "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS, "avg_launch_ms": avg,
+               "launches": launches, "flops_per_launch": flops / max(1, launches),
+               "traffic": pmc_traffic(key, "sweep")}
+        if out["traffic"] is not None:
+            out["hbm_gbs_from_traffic"] = out["traffic"] / max(avg * 1e-3, 1e-30) / 1e9
+        return out
 
     gemm_ms = st1["row_ms"] + st1["colq_ms"]
     res = None
@@ -450,10 +459,10 @@ def sweep_measure(args, hdl, H0, H, Q, eye, wr, wi, stream):
         / FP64_MFMA_PEAK_TFLOPS,
         # with every kernel on one stream a time step's panel products are two
         # launches: the rows of H with Q (k_panel_rowq), then the columns of H
-        "k_panel_colq": gl("k_panel_colq (columns of H)", st1["colq_ms"], st1["colq_launches"],
-                           st1["colq_flops"]),
-        "k_panel_row": gl("k_panel_rowq (rows of H and Q)", st1["row_ms"], st1["row_launches"],
-                          st1["row_flops"]),
+        "k_panel_colq": gl("k_panel_colq (columns of H)", "k_panel_colq", st1["colq_ms"],
+                           st1["colq_launches"], st1["colq_flops"]),
+        "k_panel_row": gl("k_panel_rowq (rows of H and Q)", "k_panel_rowq", st1["row_ms"],
+                          st1["row_launches"], st1["row_flops"]),
         "k_chase": family_lines(st1, "sweep").get("k_chase"),
         "residual_probe": res,
     }

@@ -271,7 +271,7 @@ __device__ inline void pb_solve(const PJob& J, double* lds, PShared& sh, PScratc
         c.H = H; c.Q = J.Q; c.U = X->U; c.st = X->st + 2 * sh0;
         c.ldh = ldh; c.ldq = J.ldq; c.n = n;
         c.ktop = ktop; c.kbot = kbot; c.rtop = 0; c.cend = n;
-        chase_window_t<PB_THREADS>(c, lds, lds + LDW * WMAX);
+        chase_window_t<PB_THREADS, false>(c, lds, lds + LDW * WMAX);
         pb_panels(c, lds, cnt);
         cnt[PB_WINDOWS] += 1;
         cnt[PB_CHAIN_STEPS] += c.tau1 - c.tau0;

@@ -32,7 +32,7 @@ namespace schur {
 constexpr int CHASE_THREADS = 1024;
 
 // W: LDW x WMAX doubles of LDS, R: 3 REFL_LDS doubles of LDS.
-template <int NT>
+template <int NT, bool REORTH = true>
 __device__ void chase_window_t(const WinCtx& d, double* W, double* R) {
   static_assert(NT == 1024 || NT == 256, "1024 or 256 threads");
   constexpr int CG = NT / 128;       // column groups of the window load / store
@@ -247,14 +247,15 @@ __device__ void chase_window_t(const WinCtx& d, double* W, double* R) {
   // ---- one first-order re-orthogonalisation, U^T <- (I - E / 2) U^T with
   // E = U^T U - I, before U reaches the panels and Q: U collected every
   // reflector of the window, and its departure from orthogonality would
-  // otherwise add up in Q over the sweep's windows.  Both products as FP64
+  // otherwise add up in Q over the sweep's windows.  The persistent kernel's
+  // matrices (order <= 1024) put few window products into Q; it skips it.  Both products as FP64
   // MFMA 16 x 16 tiles over the workgroup's wavefronts.  E is symmetric:
   // its upper tiles from U in LDS, then E (both triangles) replaces U in
   // LDS (U^T is in the slot).  The new U^T by column blocks of 16 in two
   // halves of row tiles, one wavefront per half: a half's tiles read only
   // its column block of the slot (held in registers, read by every half
   // before any writes).
-  {
+  if constexpr (REORTH) {
     typedef double cw_d4 __attribute__((ext_vector_type(4)));
     constexpr int NW = NT / 64;                     // wavefronts
     constexpr int NTM = WMAX / 16;                  // tiles per side at most
