@@ -179,10 +179,12 @@ typedef struct schur_stats {
  * schur_reduce -- synchronous Schur reduction (paper Sec. 2, Eq. (4)).
  *   n        order, n >= 0
  *   H        device, ldh x n; in: upper Hessenberg; out: S
- *   ldh      >= max(1, n)
+ *   ldh      max(1, n) <= ldh <= 1048576 (2^20: a panel tile of up to 128
+ *            columns is addressed through one buffer descriptor of under
+ *            2^30 bytes)
  *   Q        device, ldq x n or NULL; in: Q_in; out: Q_in Q2 (NULL: no
  *            Schur vectors, the Q products are skipped)
- *   ldq      >= max(1, n) when Q != NULL
+ *   ldq      max(1, n) <= ldq <= 1048576 when Q != NULL
  *   wr, wi   device, n doubles each
  * Uses a per-device default handle; runs on the null stream after the
  * work already there and blocks until done.
@@ -275,9 +277,9 @@ int schur_eigenvectors(schur_handle_t h, void* stream, int n, const double* S, i
  *   n        order, n >= 0
  *   S        device, lds x n; in: a standardised real Schur form (as
  *            schur_reduce returns it); out: S'
- *   lds      >= max(1, n)
+ *   lds      max(1, n) <= lds <= 1048576 (as ldh of schur_reduce)
  *   Q        device, ldq x n or NULL; in: Q_in; out: Q_in Q3
- *   ldq      >= max(1, n) when Q != NULL
+ *   ldq      max(1, n) <= ldq <= 1048576 when Q != NULL
  *   select   HOST, n ints: select[k] != 0 selects eigenvalue k (either row
  *            of a 2x2 block selects the pair)
  *   wr, wi   device, n doubles each: the eigenvalues of S' (diagonal order)

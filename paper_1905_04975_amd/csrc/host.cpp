@@ -1202,8 +1202,8 @@ int check_args(int n, double* H, int ldh, double* Q, int ldq, double* wr, double
   if (n < 0 || n > 524288) return -1;
   if (n == 0) return 0;
   if (!H) return -2;
-  if (ldh < std::max(1, n)) return -3;
-  if (Q && ldq < std::max(1, n)) return -5;
+  if (ldh < std::max(1, n) || ldh > LD_MAX) return -3;
+  if (Q && (ldq < std::max(1, n) || ldq > LD_MAX)) return -5;
   if (!wr) return -6;
   if (!wi) return -7;
   if (!is_device_ptr(H) || (Q && !is_device_ptr(Q)) || !is_device_ptr(wr) || !is_device_ptr(wi))
@@ -1530,8 +1530,8 @@ int reorder_run(schur_handle_s* h, hipStream_t s, int n, double* S, int lds, dou
   if (n < 0 || n > 524288) return -1;
   if (n == 0) { if (m_out) *m_out = 0; return 0; }
   if (!S) return -2;
-  if (lds < std::max(1, n)) return -3;
-  if (Q && ldq < std::max(1, n)) return -5;
+  if (lds < std::max(1, n) || lds > LD_MAX) return -3;
+  if (Q && (ldq < std::max(1, n) || ldq > LD_MAX)) return -5;
   if (!select) return -6;
   if (!wr) return -7;
   if (!wi) return -8;

@@ -5,6 +5,7 @@
 // LDS from the caller, so one kernel can run several of them over the same
 // LDS.
 #pragma once
+#include <type_traits>
 #include "schur_internal.h"
 #include "device_common.h"
 #include "kernels.h"
@@ -113,16 +114,46 @@ __device__ void shift_prep(const double* wr, const double* wi, int ns, const int
 //   D(i, j): lane = j + 16 (i % 4), element i / 4
 // ============================================================================
 constexpr int PT = GEMM_T;       // 64
+// s_waitcnt operand for vmcnt(0) alone (expcnt and lgkmcnt at their maxima)
+constexpr int PANEL_VMCNT0 = 0x0F70;
+
+// Tile accesses go through buffer instructions: one descriptor per tile
+// (base at the tile's first element, byte range PANEL_NREC) and a 32-bit
+// byte offset per lane.  A lane outside the tile gets an offset of at least
+// PANEL_OOB: its load returns 0 and its store is dropped, so the k loop
+// needs no exec masks, branches or 64-bit address arithmetic around its
+// loads and stores.  A valid offset is at most 127 ld 8 + 127 8 bytes (a
+// column-panel tile spans up to 128 window columns), under PANEL_NREC for
+// ld <= LD_MAX; the sum of two invalid parts, 2 PANEL_OOB, does not wrap.
+constexpr unsigned PANEL_OOB = 0x40000000u;
+constexpr int PANEL_NREC = 0x3FFFFFFF;
+static_assert(127ull * LD_MAX * 8 + 128 * 8 <= (unsigned long long)PANEL_NREC, "tile range");
+typedef unsigned panel_u2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t panel_rsrc(const double* base) {
+  // dword 3: 32-bit data format (needed for untyped loads and stores on gfx9)
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, PANEL_NREC,
+                                           0x00020000);
+}
+__device__ __forceinline__ double panel_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void panel_store(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(panel_u2, v), r, (int)off, 0, 0);
+}
+static_assert(UPAD / 4 == 32, "32 k steps of 4 carry a tile's 32 loads and 32 stores");
 constexpr int LDT = PT + 4;      // padded LDS leading dimension of panel tiles
 
 // Panel tiles are processed up to PANEL_TPB at a time by one workgroup of
 // four waves, one workgroup per CU (two 128 x 68 FP64 LDS buffers, 136 KiB,
 // passed in as Xs: 2 WMAX LDT doubles):
 //  * the window's U (or U^T) is read into registers once;
-//  * while tile t is multiplied from LDS, the wave issues, one per k step,
-//    the global loads of tile t+1 (into registers) and the global stores of
-//    the results of tile t-1 (kept in a second set of accumulators), so that
-//    HBM traffic and the FP64 MFMA work overlap instead of alternating;
+//  * while tile t is multiplied from LDS, the wave issues the global loads
+//    of tile t+1 (into registers, two per k step in the first half of the
+//    k loop, so that they have landed when the next pass needs them) and
+//    the global stores of the results of tile t-1 (kept in a second set of
+//    accumulators, one per k step), so that HBM traffic and the FP64 MFMA
+//    work overlap instead of alternating;
 //  * the operands of the next k step are read from LDS before the products
 //    of the current one are issued.
 // Each pass: tile t -> LDS, barrier, then the interleaved k loop.  One pass
@@ -140,7 +171,8 @@ __device__ void panel_row_tiles(const WinCtx& d, int t0, int t1, double* Xs) {
   const int kpad = (ws + 3) & ~3;
   const double* Ut = d.U;
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
+  // wave index in a scalar register: the tests on it below are uniform branches
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int i0 = wave * 32;
   const bool active = i0 < ws;
@@ -155,70 +187,96 @@ __device__ void panel_row_tiles(const WinCtx& d, int t0, int t1, double* Xs) {
   }
   double* const H = d.H;
   const size_t ldh = d.ldh;
+  const unsigned ldb = (unsigned)ldh * 8u;   // bytes per column
   // first column of tile t and its width
   auto col0 = [&](int t) { return p + ws + t * PT; };
   auto ncols = [&](int t) { return min(PT, d.cend - col0(t)); };
-  // rows past the window read row ws-1 and are zeroed on the way to LDS;
-  // columns past the panel are not read (uniform test per wave)
-  auto load_one = [&](double& dst, int c0, int nc, int e) {
-    const int r = lane + 64 * (e & 1), c = wave + 4 * (e >> 1);
-    dst = (c < nc) ? H[(size_t)(p + min(r, ws - 1)) + (size_t)(c0 + c) * ldh] : 0.0;
+  auto rsrc = [&](int t) { return panel_rsrc(H + (size_t)p + (size_t)col0(t) * ldh); };
+  // lane parts of the load offsets (window rows lane and lane + 64)
+  const unsigned rl0 = lane < ws ? lane * 8u : PANEL_OOB;
+  const unsigned rl1 = lane + 64 < ws ? (lane + 64) * 8u : PANEL_OOB;
+  auto load_one = [&](double& dst, __amdgpu_buffer_rsrc_t R, int nc, int e) {
+    const int c = wave + 4 * (e >> 1);
+    dst = panel_load(R, (c < nc ? (unsigned)c * ldb : PANEL_OOB) + ((e & 1) ? rl1 : rl0));
   };
-  auto store_one = [&](const d4 (&res)[2][4], int c0, int nc, int s) {
+  auto store_one = [&](const d4 (&res)[2][4], __amdgpu_buffer_rsrc_t R, int nc, int s) {
     const int ib = s >> 4, jb = (s >> 2) & 3, e = s & 3;
     const int row = i0 + ib * 16 + lk + 4 * e, col = jb * 16 + li;
-    if (row < ws && col < nc) H[(size_t)(p + row) + (size_t)(c0 + col) * ldh] = res[ib][jb][e];
+    const unsigned off = (row < ws && col < nc) ? (unsigned)row * 8u + (unsigned)col * ldb
+                                                : PANEL_OOB;
+    panel_store(R, off, res[ib][jb][e]);
   };
   double pre[32];
   {
-    const int c0 = col0(t0), nc = ncols(t0);
+    const __amdgpu_buffer_rsrc_t R = rsrc(t0);
+    const int nc = ncols(t0);
 #pragma unroll
-    for (int e = 0; e < 32; ++e) load_one(pre[e], c0, nc, e);
+    for (int e = 0; e < 32; ++e) load_one(pre[e], R, nc, e);
   }
   __builtin_amdgcn_s_waitcnt(0);   // U and the first tile are in registers
   d4 acc[2][4], accp[2][4];
+  for (int ib = 0; ib < 2; ++ib)   // stored (as dropped stores) before the first results exist
+    for (int jb = 0; jb < 4; ++jb) accp[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
   for (int t = t0; t <= t1; ++t) {
     const bool cur = t < t1, prev = t > t0 && active, next = t + 1 < t1;
     double* X = Xs + ((t - t0) & 1) * (WMAX * LDT);
+    // vmcnt(0) on every pass, also the last: nothing issued in an earlier
+    // pass is then pending inside the k loop, which keeps it free of waits
+    __builtin_amdgcn_s_waitcnt(PANEL_VMCNT0);
     if (cur) {
 #pragma unroll
-      for (int e = 0; e < 32; ++e) {
+      for (int e = 0; e < 32; ++e) {   // entries outside the tile were loaded as 0
         const int r = lane + 64 * (e & 1), c = wave + 4 * (e >> 1);
-        X[c + r * LDT] = r < ws ? pre[e] : 0.0;   // r < 128, c < 64: inside the buffer
+        X[c + r * LDT] = pre[e];   // r < 128, c < 64: inside the buffer
       }
       __syncthreads();
     }
-    const int cn0 = col0(t + 1), nnc = ncols(t + 1);
-    const int cp0 = col0(t - 1), npc = ncols(t - 1);
+    // neighbouring tiles; a width of 0 drops every access to one (no next
+    // tile to load, no results of a previous tile to store)
+    const __amdgpu_buffer_rsrc_t RN = rsrc(next ? t + 1 : t), RP = rsrc(prev ? t - 1 : t);
+    const int nnc = next ? ncols(t + 1) : 0, npc = prev ? ncols(t - 1) : 0;
     const bool mm = active && cur;
-    if (mm) {
-      for (int ib = 0; ib < 2; ++ib)
-        for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
-    }
-    double bn[4];
-    if (mm) {
+    // the k loop: MODE 0 loads and stores only, 1 products for the k steps
+    // below kpad, 2 products for all 32 steps (no test inside: the loop is
+    // one block in which the compiler interleaves memory operations with
+    // the products)
+    auto kloop = [&](auto mode) {
+      constexpr int MODE = decltype(mode)::value;
+      double bn[4];
+      if constexpr (MODE > 0) {
+        for (int ib = 0; ib < 2; ++ib)
+          for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int jb = 0; jb < 4; ++jb) bn[jb] = X[(jb * 16 + li) + lk * LDT];
-    }
+        for (int jb = 0; jb < 4; ++jb) bn[jb] = X[(jb * 16 + li) + lk * LDT];
+      }
 #pragma unroll
-    for (int ks = 0; ks < UPAD / 4; ++ks) {
-      if (next) load_one(pre[ks], cn0, nnc, ks);
-      if (prev) store_one(accp, cp0, npc, ks);
-      if (mm && 4 * ks < kpad) {
-        double b[4];
+      for (int ks = 0; ks < UPAD / 4; ++ks) {
+        if (ks < 16) {   // the next tile's loads in the first half of the k loop
+          load_one(pre[2 * ks], RN, nnc, 2 * ks);
+          load_one(pre[2 * ks + 1], RN, nnc, 2 * ks + 1);
+        }
+        store_one(accp, RP, npc, ks);
+        if constexpr (MODE > 0) {
+          if (MODE == 2 || 4 * ks < kpad) {
+            double b[4];
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) b[jb] = bn[jb];
-        const int kn = min(4 * ks + 4, kpad - 4) + lk;   // the last step re-reads a valid row
+            for (int jb = 0; jb < 4; ++jb) b[jb] = bn[jb];
+            const int kn = min(4 * ks + 4, kpad - 4) + lk;   // the last step re-reads a valid row
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) bn[jb] = X[(jb * 16 + li) + kn * LDT];
-        __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the products below
+            for (int jb = 0; jb < 4; ++jb) bn[jb] = X[(jb * 16 + li) + kn * LDT];
+            __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the products below
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
-          acc[0][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][0], b[jb], acc[0][jb], 0, 0, 0);
-          acc[1][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][1], b[jb], acc[1][jb], 0, 0, 0);
+            for (int jb = 0; jb < 4; ++jb) {
+              acc[0][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][0], b[jb], acc[0][jb], 0, 0, 0);
+              acc[1][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][1], b[jb], acc[1][jb], 0, 0, 0);
+            }
+          }
         }
       }
-    }
+    };
+    if (mm && kpad == UPAD) kloop(std::integral_constant<int, 2>());
+    else if (mm) kloop(std::integral_constant<int, 1>());
+    else kloop(std::integral_constant<int, 0>());
     if (mm) {
       for (int ib = 0; ib < 2; ++ib)
         for (int jb = 0; jb < 4; ++jb) accp[ib][jb] = acc[ib][jb];
@@ -238,7 +296,8 @@ __device__ void panel_colq_tiles(const WinCtx& d, int t0, int t1, int tiles_c, d
   const int kpad = (ws + 3) & ~3;
   const double* Ut = d.U;
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
+  // wave index in a scalar register: the tests on it below are uniform branches
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int j0 = wave * 32;
   const bool active = j0 < ws;
@@ -251,29 +310,33 @@ __device__ void panel_colq_tiles(const WinCtx& d, int t0, int t1, int tiles_c, d
       ub[ks][1] = Ut[(j0 + 16 + li) + (size_t)k * UPAD];
     }
   }
-  // tile t: first element (row r0, column p) and number of rows
-  struct Tile { double* base; size_t ld; int nr; };
+  // tile t: first element (row r0, column p), leading dimension in bytes
+  // and number of rows
+  struct Tile { __amdgpu_buffer_rsrc_t R; unsigned ldb; int nr; };
   auto tile = [&](int t) {
     Tile T;
     if (t < tiles_c) {
       const int r0 = d.rtop + t * PT;
-      T.base = d.H + (size_t)r0 + (size_t)p * d.ldh; T.ld = d.ldh; T.nr = min(PT, p - r0);
+      T.R = panel_rsrc(d.H + (size_t)r0 + (size_t)p * d.ldh);
+      T.ldb = (unsigned)d.ldh * 8u; T.nr = min(PT, p - r0);
     } else {
       const int r0 = (t - tiles_c) * PT;
-      T.base = d.Q + (size_t)r0 + (size_t)p * d.ldq; T.ld = d.ldq; T.nr = min(PT, d.n - r0);
+      T.R = panel_rsrc(d.Q + (size_t)r0 + (size_t)p * d.ldq);
+      T.ldb = (unsigned)d.ldq * 8u; T.nr = min(PT, d.n - r0);
     }
     return T;
   };
-  // rows past the tile read its last row and are zeroed on the way to LDS;
-  // columns past the window are not read (uniform test per wave)
   auto load_one = [&](double& dst, const Tile& T, int e) {
     const int c = wave + 4 * e;
-    dst = (c < ws) ? T.base[(size_t)min(lane, T.nr - 1) + (size_t)c * T.ld] : 0.0;
+    dst = panel_load(T.R, (lane < T.nr ? lane * 8u : PANEL_OOB) +
+                              (c < ws ? (unsigned)c * T.ldb : PANEL_OOB));
   };
   auto store_one = [&](const d4 (&res)[4][2], const Tile& T, int s) {
     const int ib = s >> 3, jb = (s >> 2) & 1, e = s & 3;
     const int row = ib * 16 + lk + 4 * e, col = j0 + jb * 16 + li;
-    if (row < T.nr && col < ws) T.base[(size_t)row + (size_t)col * T.ld] = res[ib][jb][e];
+    const unsigned off = (row < T.nr && col < ws) ? (unsigned)row * 8u + (unsigned)col * T.ldb
+                                                  : PANEL_OOB;
+    panel_store(T.R, off, res[ib][jb][e]);
   };
   double pre[32];
   {
@@ -283,46 +346,61 @@ __device__ void panel_colq_tiles(const WinCtx& d, int t0, int t1, int tiles_c, d
   }
   __builtin_amdgcn_s_waitcnt(0);   // U and the first tile are in registers
   d4 acc[4][2], accp[4][2];
+  for (int ib = 0; ib < 4; ++ib)   // as in the row panel
+    for (int jb = 0; jb < 2; ++jb) accp[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
   for (int t = t0; t <= t1; ++t) {
     const bool cur = t < t1, prev = t > t0 && active, next = t + 1 < t1;
     double* X = Xs + ((t - t0) & 1) * (WMAX * LDT);
+    __builtin_amdgcn_s_waitcnt(PANEL_VMCNT0);   // as in the row panel
     if (cur) {
-      const int nr_t = tile(t).nr;
 #pragma unroll
-      for (int e = 0; e < 32; ++e)   // inside the buffer
-        X[lane + (wave + 4 * e) * LDT] = lane < nr_t ? pre[e] : 0.0;
+      for (int e = 0; e < 32; ++e)   // inside the buffer; entries outside the tile are 0
+        X[lane + (wave + 4 * e) * LDT] = pre[e];
       __syncthreads();
     }
-    const Tile TN = tile(next ? t + 1 : t0), TP = tile(prev ? t - 1 : t0);
+    // neighbouring tiles; 0 rows drop every access to one
+    Tile TN = tile(next ? t + 1 : t0), TP = tile(prev ? t - 1 : t0);
+    if (!next) TN.nr = 0;
+    if (!prev) TP.nr = 0;
     const bool mm = active && cur;
-    if (mm) {
-      for (int ib = 0; ib < 4; ++ib)
-        for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
-    }
-    double an[4];
-    if (mm) {
+    // the k loop, MODE as in the row panel
+    auto kloop = [&](auto mode) {
+      constexpr int MODE = decltype(mode)::value;
+      double an[4];
+      if constexpr (MODE > 0) {
+        for (int ib = 0; ib < 4; ++ib)
+          for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int ib = 0; ib < 4; ++ib) an[ib] = X[(ib * 16 + li) + lk * LDT];
-    }
+        for (int ib = 0; ib < 4; ++ib) an[ib] = X[(ib * 16 + li) + lk * LDT];
+      }
 #pragma unroll
-    for (int ks = 0; ks < UPAD / 4; ++ks) {
-      if (next) load_one(pre[ks], TN, ks);
-      if (prev) store_one(accp, TP, ks);
-      if (mm && 4 * ks < kpad) {
-        double av[4];
+      for (int ks = 0; ks < UPAD / 4; ++ks) {
+        if (ks < 16) {
+          load_one(pre[2 * ks], TN, 2 * ks);
+          load_one(pre[2 * ks + 1], TN, 2 * ks + 1);
+        }
+        store_one(accp, TP, ks);
+        if constexpr (MODE > 0) {
+          if (MODE == 2 || 4 * ks < kpad) {
+            double av[4];
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) av[ib] = an[ib];
-        const int kn = min(4 * ks + 4, kpad - 4) + lk;   // the last step re-reads a valid row
+            for (int ib = 0; ib < 4; ++ib) av[ib] = an[ib];
+            const int kn = min(4 * ks + 4, kpad - 4) + lk;   // the last step re-reads a valid row
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) an[ib] = X[(ib * 16 + li) + kn * LDT];
-        __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the products below
+            for (int ib = 0; ib < 4; ++ib) an[ib] = X[(ib * 16 + li) + kn * LDT];
+            __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the products below
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
-          acc[ib][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ib], ub[ks][0], acc[ib][0], 0, 0, 0);
-          acc[ib][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ib], ub[ks][1], acc[ib][1], 0, 0, 0);
+            for (int ib = 0; ib < 4; ++ib) {
+              acc[ib][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ib], ub[ks][0], acc[ib][0], 0, 0, 0);
+              acc[ib][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ib], ub[ks][1], acc[ib][1], 0, 0, 0);
+            }
+          }
         }
       }
-    }
+    };
+    if (mm && kpad == UPAD) kloop(std::integral_constant<int, 2>());
+    else if (mm) kloop(std::integral_constant<int, 1>());
+    else kloop(std::integral_constant<int, 0>());
     if (mm) {
       for (int ib = 0; ib < 4; ++ib)
         for (int jb = 0; jb < 2; ++jb) accp[ib][jb] = acc[ib][jb];

@@ -50,6 +50,33 @@ using std::min;
 typedef double simt_d4 __attribute__((ext_vector_type(4)));
 simt_d4 simt_mfma_f64_16x16x4(double a, double b, simt_d4 c);
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) simt_mfma_f64_16x16x4((a), (b), (c))
+// Raw buffer descriptors: base and byte range.  A load at an offset past
+// the range returns 0 and such a store is dropped, as on the GPU; an access
+// that straddles the end of the range is a kernel bug and aborts.
+struct simt_rsrc {
+  char* base;
+  unsigned nrec;
+};
+typedef simt_rsrc __amdgpu_buffer_rsrc_t;
+typedef unsigned simt_u2 __attribute__((ext_vector_type(2)));
+inline simt_rsrc __builtin_amdgcn_make_buffer_rsrc(void* p, short stride, int nrec, int flags) {
+  if (stride != 0 || flags != 0x00020000) __builtin_trap();
+  return simt_rsrc{(char*)p, (unsigned)nrec};
+}
+inline simt_u2 __builtin_amdgcn_raw_buffer_load_b64(simt_rsrc r, int off, int soff, int aux) {
+  const unsigned o = (unsigned)off + (unsigned)soff;
+  simt_u2 v = {0u, 0u};
+  if (o >= r.nrec) return v;
+  if (o + 8u > r.nrec || aux != 0) __builtin_trap();
+  memcpy(&v, r.base + o, 8);
+  return v;
+}
+inline void __builtin_amdgcn_raw_buffer_store_b64(simt_u2 v, simt_rsrc r, int off, int soff, int aux) {
+  const unsigned o = (unsigned)off + (unsigned)soff;
+  if (o >= r.nrec) return;
+  if (o + 8u > r.nrec || aux != 0) __builtin_trap();
+  memcpy(r.base + o, &v, 8);
+}
 inline int atomicOr(int* p, int v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
 inline unsigned atomicOr(unsigned* p, unsigned v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
 inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }

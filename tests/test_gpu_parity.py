@@ -216,6 +216,9 @@ def test_argument_errors(gpu_lib):
     assert f(n, None, n, None, n, wr.data_ptr(), wi.data_ptr()) == -2
     assert f(n, H.data_ptr(), n - 1, None, n, wr.data_ptr(), wi.data_ptr()) == -3
     assert f(n, H.data_ptr(), n, H.data_ptr(), n - 1, wr.data_ptr(), wi.data_ptr()) == -5
+    # leading dimensions above 2^20 are refused before anything is read
+    assert f(n, H.data_ptr(), (1 << 20) + 1, None, n, wr.data_ptr(), wi.data_ptr()) == -3
+    assert f(n, H.data_ptr(), n, H.data_ptr(), (1 << 20) + 1, wr.data_ptr(), wi.data_ptr()) == -5
     assert f(n, H.data_ptr(), n, None, n, None, wi.data_ptr()) == -6
     assert f(n, H.data_ptr(), n, None, n, wr.data_ptr(), None) == -7
     host = np.zeros((n, n))

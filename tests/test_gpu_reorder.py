@@ -128,6 +128,8 @@ def test_reorder_argument_errors(gpu_lib):
     assert h.reorder_async(None, 4, None, 4, None, 1, sel, p, p)[0] == -2
     assert h.reorder_async(None, 4, p, 3, None, 1, sel, p, p)[0] == -3
     assert h.reorder_async(None, 4, p, 4, p, 3, sel, p, p)[0] == -5
+    assert h.reorder_async(None, 4, p, (1 << 20) + 1, None, 1, sel, p, p)[0] == -3
+    assert h.reorder_async(None, 4, p, 4, p, (1 << 20) + 1, sel, p, p)[0] == -5
     assert h.reorder_async(None, 4, p, 4, None, 1, sel, None, p)[0] == -7
     assert h.reorder_async(None, 4, p, 4, None, 1, sel, p, None)[0] == -8
     h.close()
