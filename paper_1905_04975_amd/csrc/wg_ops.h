@@ -114,8 +114,9 @@ __device__ void shift_prep(const double* wr, const double* wi, int ns, const int
 //   D(i, j): lane = j + 16 (i % 4), element i / 4
 // ============================================================================
 constexpr int PT = GEMM_T;       // 64
-// s_waitcnt operand for vmcnt(0) alone (expcnt and lgkmcnt at their maxima)
-constexpr int PANEL_VMCNT0 = 0x0F70;
+// s_waitcnt operand for vmcnt(32) alone (expcnt and lgkmcnt at their
+// maxima; vmcnt in bits 3:0 and 15:14)
+constexpr int PANEL_VMCNT32 = 0x8F70;
 
 // Tile accesses go through buffer instructions: one descriptor per tile
 // (base at the tile's first element, byte range PANEL_NREC) and a 32-bit
@@ -148,15 +149,18 @@ constexpr int LDT = PT + 4;      // padded LDS leading dimension of panel tiles
 // four waves, one workgroup per CU (two 128 x 68 FP64 LDS buffers, 136 KiB,
 // passed in as Xs: 2 WMAX LDT doubles):
 //  * the window's U (or U^T) is read into registers once;
-//  * while tile t is multiplied from LDS, the wave issues the global loads
-//    of tile t+1 (into registers, two per k step in the first half of the
-//    k loop, so that they have landed when the next pass needs them) and
-//    the global stores of the results of tile t-1 (kept in a second set of
-//    accumulators, one per k step), so that HBM traffic and the FP64 MFMA
-//    work overlap instead of alternating;
+//  * while tile t is multiplied from LDS, the wave issues the loads of tile
+//    t+1 (into registers) in the first half of the k loop and the stores of
+//    the results of tile t-1 (kept in a second set of accumulators) in the
+//    second half, two per k step, and in the last quarter writes tile t+1
+//    from its registers into the other LDS buffer: HBM traffic at an even
+//    rate, the LDS writes and the FP64 MFMA work overlap instead of
+//    alternating (measured: memory operations bunched into part of the loop,
+//    or the tile written to LDS between passes, are slower);
 //  * the operands of the next k step are read from LDS before the products
 //    of the current one are issued.
-// Each pass: tile t -> LDS, barrier, then the interleaved k loop.  One pass
+// Each pass: barrier (tile t is in LDS; every wave has finished reading tile
+// t-1, whose buffer takes tile t+1), then the interleaved k loop.  One pass
 // more than there are tiles stores the last results.
 
 // Row panel: Y(ws x 64) = U^T X for 64-column tiles of H(p:p+ws-1, right of
@@ -207,6 +211,12 @@ __device__ void panel_row_tiles(const WinCtx& d, int t0, int t1, double* Xs) {
     panel_store(R, off, res[ib][jb][e]);
   };
   double pre[32];
+  // element e of the registers into tile buffer X (entries outside the tile
+  // were loaded as 0)
+  auto lds_one = [&](double* X, int e) {
+    const int r = lane + 64 * (e & 1), c = wave + 4 * (e >> 1);
+    X[c + r * LDT] = pre[e];   // r < 128, c < 64: inside the buffer
+  };
   {
     const __amdgpu_buffer_rsrc_t R = rsrc(t0);
     const int nc = ncols(t0);
@@ -214,23 +224,19 @@ __device__ void panel_row_tiles(const WinCtx& d, int t0, int t1, double* Xs) {
     for (int e = 0; e < 32; ++e) load_one(pre[e], R, nc, e);
   }
   __builtin_amdgcn_s_waitcnt(0);   // U and the first tile are in registers
+#pragma unroll
+  for (int e = 0; e < 32; ++e) lds_one(Xs, e);
   d4 acc[2][4], accp[2][4];
   for (int ib = 0; ib < 2; ++ib)   // stored (as dropped stores) before the first results exist
     for (int jb = 0; jb < 4; ++jb) accp[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
   for (int t = t0; t <= t1; ++t) {
     const bool cur = t < t1, prev = t > t0 && active, next = t + 1 < t1;
     double* X = Xs + ((t - t0) & 1) * (WMAX * LDT);
-    // vmcnt(0) on every pass, also the last: nothing issued in an earlier
-    // pass is then pending inside the k loop, which keeps it free of waits
-    __builtin_amdgcn_s_waitcnt(PANEL_VMCNT0);
-    if (cur) {
-#pragma unroll
-      for (int e = 0; e < 32; ++e) {   // entries outside the tile were loaded as 0
-        const int r = lane + 64 * (e & 1), c = wave + 4 * (e >> 1);
-        X[c + r * LDT] = pre[e];   // r < 128, c < 64: inside the buffer
-      }
-      __syncthreads();
-    }
+    double* XN = Xs + ((t - t0 + 1) & 1) * (WMAX * LDT);
+    // the loads of the last pass were written to LDS inside it; its stores
+    // (the last 32 memory operations) may still be in flight
+    __builtin_amdgcn_s_waitcnt(PANEL_VMCNT32);
+    __syncthreads();
     // neighbouring tiles; a width of 0 drops every access to one (no next
     // tile to load, no results of a previous tile to store)
     const __amdgpu_buffer_rsrc_t RN = rsrc(next ? t + 1 : t), RP = rsrc(prev ? t - 1 : t);
@@ -251,11 +257,17 @@ __device__ void panel_row_tiles(const WinCtx& d, int t0, int t1, double* Xs) {
       }
 #pragma unroll
       for (int ks = 0; ks < UPAD / 4; ++ks) {
-        if (ks < 16) {   // the next tile's loads in the first half of the k loop
+        if (ks < 16) {   // loads of tile t+1, then stores of tile t-1
           load_one(pre[2 * ks], RN, nnc, 2 * ks);
           load_one(pre[2 * ks + 1], RN, nnc, 2 * ks + 1);
+        } else {
+          store_one(accp, RP, npc, 2 * ks - 32);
+          store_one(accp, RP, npc, 2 * ks - 31);
         }
-        store_one(accp, RP, npc, ks);
+        if (ks >= 24) {   // tile t+1 into the other buffer
+#pragma unroll
+          for (int q = 0; q < 4; ++q) lds_one(XN, 4 * (ks - 24) + q);
+        }
         if constexpr (MODE > 0) {
           if (MODE == 2 || 4 * ks < kpad) {
             double b[4];
@@ -339,25 +351,25 @@ __device__ void panel_colq_tiles(const WinCtx& d, int t0, int t1, int tiles_c, d
     panel_store(T.R, off, res[ib][jb][e]);
   };
   double pre[32];
+  // as in the row panel (inside the buffer)
+  auto lds_one = [&](double* X, int e) { X[lane + (wave + 4 * e) * LDT] = pre[e]; };
   {
     const Tile T = tile(t0);
 #pragma unroll
     for (int e = 0; e < 32; ++e) load_one(pre[e], T, e);
   }
   __builtin_amdgcn_s_waitcnt(0);   // U and the first tile are in registers
+#pragma unroll
+  for (int e = 0; e < 32; ++e) lds_one(Xs, e);
   d4 acc[4][2], accp[4][2];
   for (int ib = 0; ib < 4; ++ib)   // as in the row panel
     for (int jb = 0; jb < 2; ++jb) accp[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
   for (int t = t0; t <= t1; ++t) {
     const bool cur = t < t1, prev = t > t0 && active, next = t + 1 < t1;
     double* X = Xs + ((t - t0) & 1) * (WMAX * LDT);
-    __builtin_amdgcn_s_waitcnt(PANEL_VMCNT0);   // as in the row panel
-    if (cur) {
-#pragma unroll
-      for (int e = 0; e < 32; ++e)   // inside the buffer; entries outside the tile are 0
-        X[lane + (wave + 4 * e) * LDT] = pre[e];
-      __syncthreads();
-    }
+    double* XN = Xs + ((t - t0 + 1) & 1) * (WMAX * LDT);
+    __builtin_amdgcn_s_waitcnt(PANEL_VMCNT32);   // as in the row panel
+    __syncthreads();
     // neighbouring tiles; 0 rows drop every access to one
     Tile TN = tile(next ? t + 1 : t0), TP = tile(prev ? t - 1 : t0);
     if (!next) TN.nr = 0;
@@ -375,11 +387,17 @@ __device__ void panel_colq_tiles(const WinCtx& d, int t0, int t1, int tiles_c, d
       }
 #pragma unroll
       for (int ks = 0; ks < UPAD / 4; ++ks) {
-        if (ks < 16) {
+        if (ks < 16) {   // as in the row panel
           load_one(pre[2 * ks], TN, 2 * ks);
           load_one(pre[2 * ks + 1], TN, 2 * ks + 1);
+        } else {
+          store_one(accp, TP, 2 * ks - 32);
+          store_one(accp, TP, 2 * ks - 31);
         }
-        store_one(accp, TP, ks);
+        if (ks >= 24) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) lds_one(XN, 4 * (ks - 24) + q);
+        }
         if constexpr (MODE > 0) {
           if (MODE == 2 || 4 * ks < kpad) {
             double av[4];
