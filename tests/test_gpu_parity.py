@@ -169,6 +169,41 @@ def test_one_stream_panels_equal_two_streams(gpu_lib, n, ns, nb, seed):
     _check_schur(H, b[0], b[1], b[2], b[3])
 
 
+@pytest.mark.parametrize("ld", [1503, 1 << 20])
+def test_padded_leading_dimensions(gpu_lib, ld):
+    """Leading dimensions above n, up to the largest accepted (2^20: a panel
+    tile of 128 columns then spans nearly the whole byte range of its buffer
+    descriptor), give the result of ld = n bit for bit; the padding rows,
+    filled with NaN, are neither read into the result nor written."""
+    import torch
+
+    n, seed = 1500, 23
+    print("case padded ld=%d n=%d" % (ld, n), flush=True)
+    H = inputs.hessenberg_normal(n, seed)
+    opts = dict(ns=64, nb=8, aed_window=-1, split_window=-1)
+    a = _run(gpu_lib, H, **opts)
+    assert a[3] == 0 and a[4]["sweeps"] > 0
+    dev = torch.device("cuda:0")
+
+    def padded(M):
+        big = torch.full((n, ld), float("nan"), dtype=torch.float64, device=dev)
+        view = big.t()[:n, :]   # (n, n), column j at j * ld
+        view.copy_(torch.from_numpy(np.ascontiguousarray(M)).to(dev))
+        return big, view
+
+    Hb, Hv = padded(H)
+    Qb, Qv = padded(np.eye(n))
+    h = gpu_lib.Handle(0, **opts)
+    S, Qo, w, info = gpu_lib.reduce(Hv, Q=Qv, want_q=True, handle=h)
+    torch.cuda.synchronize()
+    h.close()
+    assert info == 0
+    assert np.array_equal(S.cpu().numpy(), a[0]) and np.array_equal(Qo.cpu().numpy(), a[1])
+    assert bool(torch.isnan(Hb[:, n:]).all()) and bool(torch.isnan(Qb[:, n:]).all())
+    del Hb, Qb, Hv, Qv, S, Qo
+    torch.cuda.empty_cache()
+
+
 def test_special_inputs(gpu_lib):
     print("case special inputs", flush=True)
     # upper triangular: already in Schur form
