@@ -243,9 +243,10 @@ __device__ void panel_row_tiles(const WinCtx& d, int t0, int t1, double* Xs) {
     const int nnc = next ? ncols(t + 1) : 0, npc = prev ? ncols(t - 1) : 0;
     const bool mm = active && cur;
     // the k loop: MODE 0 loads and stores only, 1 products for the k steps
-    // below kpad, 2 products for all 32 steps (no test inside: the loop is
-    // one block in which the compiler interleaves memory operations with
-    // the products)
+    // below kpad, 2 products for all 32 steps, 3 for the first 24 (kpad =
+    // 96: the order-96 early-deflation and AED windows).  Modes 2 and 3
+    // have no test inside: the loop is one block in which the compiler
+    // interleaves memory operations with the products.
     auto kloop = [&](auto mode) {
       constexpr int MODE = decltype(mode)::value;
       double bn[4];
@@ -269,11 +270,12 @@ __device__ void panel_row_tiles(const WinCtx& d, int t0, int t1, double* Xs) {
           for (int q = 0; q < 4; ++q) lds_one(XN, 4 * (ks - 24) + q);
         }
         if constexpr (MODE > 0) {
-          if (MODE == 2 || 4 * ks < kpad) {
+          if (MODE == 2 || (MODE == 3 && ks < 24) || (MODE == 1 && 4 * ks < kpad)) {
             double b[4];
 #pragma unroll
             for (int jb = 0; jb < 4; ++jb) b[jb] = bn[jb];
-            const int kn = min(4 * ks + 4, kpad - 4) + lk;   // the last step re-reads a valid row
+            const int kp = MODE == 2 ? UPAD : (MODE == 3 ? 96 : kpad);
+            const int kn = min(4 * ks + 4, kp - 4) + lk;   // the last step re-reads a valid row
 #pragma unroll
             for (int jb = 0; jb < 4; ++jb) bn[jb] = X[(jb * 16 + li) + kn * LDT];
             __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the products below
@@ -287,6 +289,7 @@ __device__ void panel_row_tiles(const WinCtx& d, int t0, int t1, double* Xs) {
       }
     };
     if (mm && kpad == UPAD) kloop(std::integral_constant<int, 2>());
+    else if (mm && kpad == 96) kloop(std::integral_constant<int, 3>());
     else if (mm) kloop(std::integral_constant<int, 1>());
     else kloop(std::integral_constant<int, 0>());
     if (mm) {
@@ -399,11 +402,12 @@ __device__ void panel_colq_tiles(const WinCtx& d, int t0, int t1, int tiles_c, d
           for (int q = 0; q < 4; ++q) lds_one(XN, 4 * (ks - 24) + q);
         }
         if constexpr (MODE > 0) {
-          if (MODE == 2 || 4 * ks < kpad) {
+          if (MODE == 2 || (MODE == 3 && ks < 24) || (MODE == 1 && 4 * ks < kpad)) {
             double av[4];
 #pragma unroll
             for (int ib = 0; ib < 4; ++ib) av[ib] = an[ib];
-            const int kn = min(4 * ks + 4, kpad - 4) + lk;   // the last step re-reads a valid row
+            const int kp = MODE == 2 ? UPAD : (MODE == 3 ? 96 : kpad);
+            const int kn = min(4 * ks + 4, kp - 4) + lk;   // the last step re-reads a valid row
 #pragma unroll
             for (int ib = 0; ib < 4; ++ib) an[ib] = X[(ib * 16 + li) + kn * LDT];
             __builtin_amdgcn_sched_barrier(0);   // keep these reads ahead of the products below
@@ -417,6 +421,7 @@ __device__ void panel_colq_tiles(const WinCtx& d, int t0, int t1, int tiles_c, d
       }
     };
     if (mm && kpad == UPAD) kloop(std::integral_constant<int, 2>());
+    else if (mm && kpad == 96) kloop(std::integral_constant<int, 3>());
     else if (mm) kloop(std::integral_constant<int, 1>());
     else kloop(std::integral_constant<int, 0>());
     if (mm) {
