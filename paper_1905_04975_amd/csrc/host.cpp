@@ -332,17 +332,21 @@ void free_ws(schur_handle_s* h) {
   h->blist_cap = 0;
 }
 
-// Panel tiles of one window of a batched panel launch (PANEL_TPB_BATCH tiles
-// per workgroup), appended after the workgroups counted so far.
-void fill_tiles_b(WinB& w, int& tr, int& tcq, schur_stats& st) {
+// Panel tiles of one window of a batched panel launch (tpb tiles per
+// workgroup: PANEL_TPB_WIDE where a launch carries many windows, so that each
+// workgroup reads its U once for more tiles; PANEL_TPB_BATCH in the round
+// engine, whose launches can hold only a few windows), appended after the
+// workgroups counted so far.
+void fill_tiles_b(WinB& w, int& tr, int& tcq, schur_stats& st, int tpb) {
   const int pe = w.c.p + w.c.ws - 1;
   w.tiles_r = std::max(0, (w.c.cend - pe - 1 + GEMM_T - 1) / GEMM_T);
   w.tiles_c = std::max(0, (w.c.p - w.c.rtop + GEMM_T - 1) / GEMM_T);
   w.tiles_q = w.c.Q ? (w.c.n + GEMM_T - 1) / GEMM_T : 0;
   w.base_r = tr;
   w.base_cq = tcq;
-  tr += panel_blocks(w.tiles_r, PANEL_TPB_BATCH);
-  tcq += panel_blocks(w.tiles_c + w.tiles_q, PANEL_TPB_BATCH);
+  w.tpb = tpb;
+  tr += panel_blocks(w.tiles_r, tpb);
+  tcq += panel_blocks(w.tiles_c + w.tiles_q, tpb);
   const double ws = w.c.ws;
   const double fr = 2.0 * ws * ws * (double)std::max(0, w.c.cend - pe - 1);
   const double fc = 2.0 * ws * ws * ((double)(w.c.p - w.c.rtop) + (w.c.Q ? (double)w.c.n : 0.0));
@@ -1066,7 +1070,7 @@ struct Solver {
         w.c.ldh = ldh; w.c.ldq = ldq; w.c.n = n;
         w.c.ktop = 0; w.c.kbot = n - 1; w.c.rtop = 0; w.c.cend = n;
         w.c.p = wins[i].a; w.c.ws = wins[i].nw;
-        fill_tiles_b(w, tr, tcq, h->stats);
+        fill_tiles_b(w, tr, tcq, h->stats, PANEL_TPB_WIDE);
       }
       WinB* wd = (WinB*)h->b_splw.dev;
       HCHECK(hipMemcpyAsync(wd, wh, sizeof(WinB) * ncm, hipMemcpyHostToDevice, s));
@@ -1609,7 +1613,7 @@ int reorder_run(schur_handle_s* h, hipStream_t s, int n, double* S, int lds, dou
         w.c.ldh = lds; w.c.ldq = ldq; w.c.n = n;
         w.c.ktop = 0; w.c.kbot = n - 1; w.c.rtop = 0; w.c.cend = n;
         w.c.p = rw.a; w.c.ws = rw.w;
-        fill_tiles_b(w, tr, tcq, h->stats);
+        fill_tiles_b(w, tr, tcq, h->stats, PANEL_TPB_WIDE);
       }
       tr_t[t] = tr;
       tcq_t[t] = tcq;
@@ -2213,7 +2217,9 @@ struct BatchEngine {
     }
   }
 
-  void fill_tiles(WinB& w, int& tr, int& tcq) { fill_tiles_b(w, tr, tcq, h->stats); }
+  void fill_tiles(WinB& w, int& tr, int& tcq) {
+    fill_tiles_b(w, tr, tcq, h->stats, PANEL_TPB_BATCH);
+  }
 
   // row-panel and column-panel/Q products of `nwin` windows (descriptors on
   // the device)
@@ -2291,7 +2297,7 @@ bool batch_blocks(schur_handle_s* h, hipStream_t s, const std::vector<std::pair<
     w.c.ldh = ldh; w.c.ldq = ldq; w.c.n = n;
     w.c.ktop = 0; w.c.kbot = n - 1; w.c.rtop = 0; w.c.cend = n;
     w.c.p = blocks[i].first; w.c.ws = sz[i];
-    fill_tiles_b(w, tr, tcq, h->stats);
+    fill_tiles_b(w, tr, tcq, h->stats, PANEL_TPB_WIDE);
   }
   WinB* wd = (WinB*)h->b_splw.dev;
   HCHECK(hipMemcpyAsync(wd, wh, sizeof(WinB) * cnt, hipMemcpyHostToDevice, s));

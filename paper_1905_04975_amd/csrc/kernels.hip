@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256, 1) void k_panel_rowq(SweepArgs a, SweepArgs aq
 __global__ __launch_bounds__(256, 1) void k_panel_row_b(const WinB* wins, int nwin) {
   const int w = find_window_b(wins, nwin, blockIdx.x, true);
   int t0, t1;
-  block_tiles(blockIdx.x, wins[w].base_r, wins[w].tiles_r, PANEL_TPB_BATCH, t0, t1);
+  block_tiles(blockIdx.x, wins[w].base_r, wins[w].tiles_r, wins[w].tpb, t0, t1);
   __shared__ double Xs[2 * WMAX * LDT];
   panel_row_tiles(wins[w].c, t0, t1, Xs);
 }
@@ -221,8 +221,8 @@ __global__ __launch_bounds__(256, 1) void k_panel_row_b(const WinB* wins, int nw
 __global__ __launch_bounds__(256, 1) void k_panel_colq_b(const WinB* wins, int nwin) {
   const int w = find_window_b(wins, nwin, blockIdx.x, false);
   int t0, t1;
-  block_tiles(blockIdx.x, wins[w].base_cq, wins[w].tiles_c + wins[w].tiles_q, PANEL_TPB_BATCH,
-              t0, t1);
+  block_tiles(blockIdx.x, wins[w].base_cq, wins[w].tiles_c + wins[w].tiles_q, wins[w].tpb, t0,
+              t1);
   __shared__ double Xs[2 * WMAX * LDT];
   panel_colq_tiles(wins[w].c, t0, t1, wins[w].tiles_c, Xs);
 }

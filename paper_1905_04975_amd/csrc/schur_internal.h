@@ -27,7 +27,8 @@ constexpr int SMALL_EIG_MAX = 128; // block order solved in LDS, eigenvalues onl
 constexpr int GEMM_T = 64;         // panel tile edge (rows or columns)
 constexpr int LD_MAX = 1 << 20;    // largest leading dimension (a panel tile's byte range)
 constexpr int PANEL_TPB = 8;       // most panel tiles per workgroup (one load of U)
-constexpr int PANEL_TPB_BATCH = 8; // panel tiles per workgroup of the batched launches
+constexpr int PANEL_TPB_BATCH = 4; // panel tiles per workgroup: launches of the round engine
+constexpr int PANEL_TPB_WIDE = 8;  // ... launches of many windows (passes, finish, reordering)
 constexpr int REFL_LDS = 1280;     // reflectors (chain step x bulge) logged in LDS per window
 
 // ---- one diagonal window of a sweep (a "window task") -----------------------
@@ -77,7 +78,7 @@ struct WinB {
   WinCtx c;
   int tiles_r, tiles_c, tiles_q;
   int base_r, base_cq;      // workgroup prefixes over the launch's windows (ascending)
-  int pad;
+  int tpb;                  // panel tiles per workgroup of this window
 };
 
 // workgroups of a panel launch that cover `tiles` tiles of one window, tpb
